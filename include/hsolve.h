@@ -1,0 +1,169 @@
+/*
+ * hsolve: hierarchical (LoRaSp / GC) factorization of a sparse SPD matrix on one
+ * MI355X (gfx950) GPU, used as a preconditioner inside PCG.
+ *
+ * The operation is the one of arXiv:1611.03189 (Yang, Pouransari, Darve, "Sparse
+ * hierarchical solvers with guaranteed convergence"):
+ *   - §2-§3: the problem A x = b with A sparse SPD (eq. Axb), block partition into
+ *     2^L red nodes by recursive bisection, pairwise merge into super nodes;
+ *   - §3.2 and Algorithm "Setup": for each super node, compression of its
+ *     well-separated block (eq. local_compression / compression_sw), extension
+ *     (eq. extended) and elimination (eq. extended_rearranged), level by level up
+ *     to an exact root;
+ *   - §6: the GC variant, which keeps the action of A on chosen vectors exact
+ *     (eq. compression_xy, eq. preserve);
+ *   - §3.3 and Algorithm "Solve" (Appendix A): z = A_H^{-1} r with P_ss and M_ss.
+ *
+ * Conventions for every call:
+ *   - Every function returns an hsolve_status and never throws or aborts.
+ *   - "host" pointers are ordinary CPU memory, "device" pointers are GPU memory of
+ *     the current HIP device (e.g. torch.cuda tensors' data_ptr()).
+ *   - The caller keeps ownership of every array it passes. hsolve_analyze copies the
+ *     pattern (and coordinates / preserved vectors); hsolve_factor copies the values.
+ *   - Dense vectors are column-major n x nrhs with a leading dimension >= n.
+ *   - All GPU work of a plan runs on the stream given in the options (NULL = the
+ *     default stream); calls return after that work has finished.
+ *   - A plan is not reentrant: calls on one plan must not overlap. Separate plans may
+ *     be used from separate host threads.
+ *   - Device memory for the factors is allocated by the library and released by
+ *     hsolve_destroy (or by the next hsolve_factor on the same plan).
+ */
+#ifndef HSOLVE_H
+#define HSOLVE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsolve_plan_s* hsolve_plan;
+
+typedef enum {
+    HSOLVE_OK = 0,
+    HSOLVE_NOT_CONVERGED = 1,      /* warning: x holds the last iterate, stats are filled */
+    HSOLVE_ERR_INVALID = -1,       /* bad sizes, unsorted / out-of-range CSR, NaN, bad options */
+    HSOLVE_ERR_NOT_SYMMETRIC = -2, /* the sparsity pattern is not symmetric */
+    HSOLVE_ERR_NOT_SPD = -3,       /* a pivot block (or S = U^T A_ss^-1 U) failed Cholesky;
+                                      stats.fail_level / fail_node name it */
+    HSOLVE_ERR_OOM = -4,           /* device allocation failed */
+    HSOLVE_ERR_DEVICE = -5,        /* a HIP runtime call failed */
+    HSOLVE_ERR_STATE = -6          /* call out of order (e.g. apply before factor) */
+} hsolve_status;
+
+enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
+enum { HSOLVE_PCG = 0 };
+
+typedef struct {
+    int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
+                               depth L is the integer nearest log2(n / leaf_size) */
+    double eps;             /* relative compression tolerance (>= 0; 0 = no truncation):
+                               keep singular values > eps * ||A_sw||_2 */
+    int variant;            /* HSOLVE_LORASP or HSOLVE_GC (default GC) */
+    int nvec;               /* GC: number of preserved vectors in phi (<= 8) */
+    const double* phi;      /* GC, host: n x nvec column-major, or NULL for the constant
+                               vector (GC-constant) */
+    int dim;                /* coordinate dimension 0..3 */
+    const double* coords;   /* host: n x dim, row-major (coords[i*dim + t]); NULL = use
+                               the unknown index as a 1-D coordinate */
+    double tol;             /* hsolve_solve: stop at ||b - A x||_2 <= tol ||b||_2 (1e-10) */
+    int max_iter;           /* hsolve_solve: iteration cap (1000) */
+    int krylov;             /* HSOLVE_PCG */
+    void* stream;           /* hipStream_t or NULL */
+} hsolve_options;
+
+typedef struct {
+    int iterations;             /* outer iterations of the last hsolve_solve (max over rhs) */
+    double rel_residual;        /* largest true ||b - A x||_2 / ||b||_2 over the rhs */
+    double t_analyze;           /* seconds, host wall clock */
+    double t_factor;
+    double t_solve;
+    int levels;                 /* tree depth L */
+    int colours;                /* elimination colours summed over levels */
+    int max_rank;               /* largest red-node size */
+    int64_t factor_bytes;       /* device bytes of the stored factors (apply data) */
+    double factor_flops;        /* counted algorithmic flops of the last factorization */
+    double apply_bytes;         /* algorithmic bytes read+written by one apply (1 rhs) */
+    int fail_level;             /* for HSOLVE_ERR_NOT_SPD: depth and node of the failure */
+    int fail_node;
+} hsolve_stats;
+
+/* Fill *opt with the defaults listed above. */
+void hsolve_default_options(hsolve_options* opt);
+
+/* Symbolic analysis (§2.1, §3, §3.1): clustering into 2^L leaves by recursive bisection,
+ * footprint adjacency per level, simulated elimination (block fill, neighbour and
+ * well-separated sets, colour order per level). Host only; no GPU work except the
+ * upload of the pattern.
+ *   n        number of unknowns (>= 1)
+ *   row_ptr  host, n+1 entries, row_ptr[0] = 0, nondecreasing
+ *   col_idx  host, row_ptr[n] entries, each row sorted ascending, in [0, n), and the
+ *            pattern structurally symmetric (HSOLVE_ERR_NOT_SYMMETRIC otherwise)
+ *   opt      host, may be NULL for defaults
+ *   out      receives the new plan (NULL on error) */
+hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
+                             const hsolve_options* opt, hsolve_plan* out);
+
+/* Numeric factorization (Algorithm "Setup"; §3.2 compression, extension, elimination;
+ * §6 GC compression). values: device, row_ptr[n] doubles in the pattern given to
+ * hsolve_analyze; A must be symmetric positive definite. Replaces any previous
+ * factorization of the plan. HSOLVE_ERR_NOT_SPD if a pivot block is not positive
+ * definite (the plan then has no factorization). */
+hsolve_status hsolve_factor(hsolve_plan plan, const double* values);
+
+/* Preconditioner application z = A_H^{-1} r (Algorithm "Solve"): forward
+ * substitution, restriction, parent-level solve, prolongation and backward substitution
+ * in reverse elimination order, level by level. r, z: device, n x nrhs column-major;
+ * r and z may not overlap. */
+hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
+                           int ldz);
+
+/* Solve A x = b by PCG preconditioned with A_H^{-1} (x0 = 0), per column, to the
+ * relative residual opt.tol. b, x: device, n x nrhs column-major. stats may be NULL.
+ * HSOLVE_NOT_CONVERGED if max_iter is reached first (x = last iterate). */
+hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb, double* x,
+                           int ldx, hsolve_stats* stats);
+
+/* y = A x with the matrix of the last hsolve_factor. x, y: device, n entries. */
+hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y);
+
+/* Counters of the plan (levels, colours, ranks, bytes, flops, timings). */
+hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats);
+
+/* Release the plan and all device memory it owns. NULL is accepted. */
+hsolve_status hsolve_destroy(hsolve_plan plan);
+
+/* Static, human-readable name of a status code. */
+const char* hsolve_status_string(hsolve_status s);
+
+/* ---- Introspection of the symbolic schedule (host arrays, caller-allocated) ---- */
+
+/* Tree depth L of the plan. */
+int hsolve_depth(hsolve_plan plan);
+
+/* Leaf order: perm[p] = original index of the unknown at position p (n entries), and
+ * leaf_off[i] = first position of leaf i (2^L + 1 entries). */
+hsolve_status hsolve_leaf_order(hsolve_plan plan, int32_t* perm, int32_t* leaf_off);
+
+/* Colour of every super node of level `depth` (2^depth entries; -1 = empty node) and
+ * the number of colours in *ncolours. Colours are processed in increasing order, nodes
+ * of one colour in increasing index. */
+hsolve_status hsolve_level_colours(hsolve_plan plan, int depth, int32_t* colour_of,
+                                   int32_t* ncolours);
+
+/* Neighbour set N(s) and well-separated set W(s) of super node `node` of level `depth`
+ * when it is eliminated, as ascending indices. Each list entry is 2*index + (1 if the
+ * partner was already a red node at that time, else 0). At most `cap` entries are
+ * written per list; *nn / *nw receive the full lengths. */
+hsolve_status hsolve_node_sets(hsolve_plan plan, int depth, int node, int32_t* nbrs,
+                               int32_t* nn, int32_t* ws, int32_t* nw, int cap);
+
+/* Red-node sizes (ranks k) of level `depth` after the last factorization
+ * (2^depth entries, 0 for empty nodes). */
+hsolve_status hsolve_ranks(hsolve_plan plan, int depth, int32_t* ranks);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HSOLVE_H */

@@ -199,6 +199,7 @@ class NodeFactor:
     nbrs: list                    # [(n, 'S' or 'R' at elimination time, A_ns)]
     W: list                       # well-separated partners (indices), for inspection
     U: np.ndarray                 # compression basis (m x k)
+    Wstate: list = None           # 'S' / 'R' of each well-separated partner at elimination
 
 
 @dataclass
@@ -362,6 +363,7 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
                 before = {j: cur.state[j] for j in cur.partners.get(s, ())}
                 nf = eliminate_node(cur, s, adj, eps, variant)
                 nf.nbrs = [(nb, before[nb], A) for (nb, _, A) in nf.nbrs]
+                nf.Wstate = [before[w] for w in nf.W]
                 nodes[s] = nf
             taken = set(colour)
             remaining = [s for s in remaining if s not in taken]

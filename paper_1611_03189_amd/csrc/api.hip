@@ -1,0 +1,248 @@
+// The extern "C" boundary (include/hsolve.h): argument checks, error translation,
+// timing. No exception crosses it.
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <new>
+
+#include "hs_internal.h"
+
+using hs::Error;
+using hs::Plan;
+
+struct hsolve_plan_s {
+    Plan P;
+    std::string last_error;
+};
+
+namespace {
+
+hsolve_status guard(hsolve_plan plan, const char* where, void (*fn)(void*), void* arg) {
+    try {
+        fn(arg);
+        return HSOLVE_OK;
+    } catch (const Error& e) {
+        if (plan) plan->last_error = std::string(where) + ": " + e.what;
+        if (std::getenv("HSOLVE_VERBOSE")) std::fprintf(stderr, "hsolve %s: %s\n", where, e.what.c_str());
+        return e.status;
+    } catch (const std::bad_alloc&) {
+        return HSOLVE_ERR_OOM;
+    } catch (...) {
+        return HSOLVE_ERR_DEVICE;
+    }
+}
+
+template <class F>
+hsolve_status run(hsolve_plan plan, const char* where, F&& f) {
+    return guard(plan, where, [](void* a) { (*static_cast<F*>(a))(); }, &f);
+}
+
+double seconds_since(std::chrono::steady_clock::time_point t0) {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+}
+
+}  // namespace
+
+extern "C" {
+
+void hsolve_default_options(hsolve_options* o) {
+    if (!o) return;
+    std::memset(o, 0, sizeof(*o));
+    o->leaf_size = 16;
+    o->eps = 1e-2;
+    o->variant = HSOLVE_GC;
+    o->nvec = 0;
+    o->phi = nullptr;
+    o->dim = 0;
+    o->coords = nullptr;
+    o->tol = 1e-10;
+    o->max_iter = 1000;
+    o->krylov = HSOLVE_PCG;
+    o->stream = nullptr;
+}
+
+hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
+                             const hsolve_options* opt, hsolve_plan* out) {
+    if (!out) return HSOLVE_ERR_INVALID;
+    *out = nullptr;
+    if (n < 1 || !row_ptr || !col_idx) return HSOLVE_ERR_INVALID;
+    hsolve_options o;
+    if (opt) o = *opt;
+    else hsolve_default_options(&o);
+    if (!(o.eps >= 0.0) || !std::isfinite(o.eps) || o.leaf_size < 1 ||
+        (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC) || o.dim < 0 || o.dim > 3 ||
+        o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
+        !(o.tol >= 0.0) || o.krylov != HSOLVE_PCG)
+        return HSOLVE_ERR_INVALID;
+    if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;
+    hsolve_plan plan = new (std::nothrow) hsolve_plan_s();
+    if (!plan) return HSOLVE_ERR_OOM;
+    auto t0 = std::chrono::steady_clock::now();
+    hsolve_status st = run(plan, "analyze", [&] {
+        Plan& P = plan->P;
+        P.n = n;
+        P.nnz = row_ptr[n];
+        P.opt = o;
+        P.stream = static_cast<hipStream_t>(o.stream);
+        P.row_ptr.assign(row_ptr, row_ptr + n + 1);
+        P.col_idx.assign(col_idx, col_idx + P.nnz);
+        if (o.coords && o.dim > 0) {
+            P.coords.assign(o.coords, o.coords + size_t(n) * o.dim);
+            for (double c : P.coords)
+                if (!std::isfinite(c)) throw Error{HSOLVE_ERR_INVALID, "non-finite coordinate"};
+        }
+        P.opt.coords = P.coords.empty() ? nullptr : P.coords.data();
+        if (o.variant == HSOLVE_GC) {
+            if (o.phi) {
+                P.nphi = o.nvec;
+                P.phi.assign(o.phi, o.phi + size_t(n) * o.nvec);
+                for (double v : P.phi)
+                    if (!std::isfinite(v)) throw Error{HSOLVE_ERR_INVALID, "non-finite phi"};
+            } else {
+                P.nphi = 1;
+                P.phi.assign(size_t(n), 1.0);
+            }
+        }
+        P.opt.phi = nullptr;
+        hs::analyze(P);
+        P.stats.levels = P.L;
+        P.stats.colours = P.total_colours;
+        P.stats.fail_level = P.stats.fail_node = -1;
+    });
+    if (st != HSOLVE_OK) {
+        delete plan;
+        return st;
+    }
+    plan->P.stats.t_analyze = seconds_since(t0);
+    *out = plan;
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_factor(hsolve_plan plan, const double* values) {
+    if (!plan || !values) return HSOLVE_ERR_INVALID;
+    return run(plan, "factor", [&] {
+        hs::upload_pattern(plan->P);
+        hs::factor(plan->P, values);
+    });
+}
+
+hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
+                           int ldz) {
+    if (!plan || !r || !z || nrhs < 1 || ldr < plan->P.n || ldz < plan->P.n)
+        return HSOLVE_ERR_INVALID;
+    if (!plan->P.factored) return HSOLVE_ERR_STATE;
+    return run(plan, "apply", [&] {
+        hs::apply(plan->P, nrhs, r, ldr, z, ldz);
+        HS_HIP(hipStreamSynchronize(plan->P.stream));
+    });
+}
+
+hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb, double* x,
+                           int ldx, hsolve_stats* stats) {
+    if (!plan || !b || !x || nrhs < 1 || ldb < plan->P.n || ldx < plan->P.n)
+        return HSOLVE_ERR_INVALID;
+    Plan& P = plan->P;
+    if (!P.factored) return HSOLVE_ERR_STATE;
+    bool converged = true;
+    auto t0 = std::chrono::steady_clock::now();
+    hsolve_status st = run(plan, "solve", [&] {
+        int its = 0;
+        double worst = 0.0;
+        for (int c = 0; c < nrhs; ++c) {
+            double rel = 0.0;
+            int it = hs::pcg(P, b + size_t(c) * ldb, x + size_t(c) * ldx, P.opt.tol,
+                             P.opt.max_iter, &rel);
+            if (!(rel <= P.opt.tol)) converged = false;
+            its = std::max(its, it);
+            worst = std::max(worst, rel);
+        }
+        HS_HIP(hipStreamSynchronize(P.stream));
+        P.stats.iterations = its;
+        P.stats.rel_residual = worst;
+    });
+    P.stats.t_solve = seconds_since(t0);
+    if (stats) *stats = P.stats;
+    if (st != HSOLVE_OK) return st;
+    return converged ? HSOLVE_OK : HSOLVE_NOT_CONVERGED;
+}
+
+hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y) {
+    if (!plan || !x || !y) return HSOLVE_ERR_INVALID;
+    if (!plan->P.factored) return HSOLVE_ERR_STATE;
+    return run(plan, "spmv", [&] {
+        hs::spmv(plan->P, x, y);
+        HS_HIP(hipStreamSynchronize(plan->P.stream));
+    });
+}
+
+hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats) {
+    if (!plan || !stats) return HSOLVE_ERR_INVALID;
+    *stats = plan->P.stats;
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_destroy(hsolve_plan plan) {
+    if (!plan) return HSOLVE_OK;
+    if (plan->P.d_row_ptr) (void)hipStreamSynchronize(plan->P.stream);   // GPU used
+    delete plan;
+    return HSOLVE_OK;
+}
+
+const char* hsolve_status_string(hsolve_status s) {
+    switch (s) {
+        case HSOLVE_OK: return "HSOLVE_OK";
+        case HSOLVE_NOT_CONVERGED: return "HSOLVE_NOT_CONVERGED";
+        case HSOLVE_ERR_INVALID: return "HSOLVE_ERR_INVALID";
+        case HSOLVE_ERR_NOT_SYMMETRIC: return "HSOLVE_ERR_NOT_SYMMETRIC";
+        case HSOLVE_ERR_NOT_SPD: return "HSOLVE_ERR_NOT_SPD";
+        case HSOLVE_ERR_OOM: return "HSOLVE_ERR_OOM";
+        case HSOLVE_ERR_DEVICE: return "HSOLVE_ERR_DEVICE";
+        case HSOLVE_ERR_STATE: return "HSOLVE_ERR_STATE";
+    }
+    return "HSOLVE_UNKNOWN_STATUS";
+}
+
+int hsolve_depth(hsolve_plan plan) { return plan ? plan->P.L : -1; }
+
+hsolve_status hsolve_leaf_order(hsolve_plan plan, int32_t* perm, int32_t* leaf_off) {
+    if (!plan) return HSOLVE_ERR_INVALID;
+    const Plan& P = plan->P;
+    if (perm) std::memcpy(perm, P.perm.data(), sizeof(int32_t) * P.n);
+    if (leaf_off) std::memcpy(leaf_off, P.leaf_off.data(), sizeof(int32_t) * P.leaf_off.size());
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_level_colours(hsolve_plan plan, int depth, int32_t* colour_of,
+                                   int32_t* ncolours) {
+    if (!plan || depth < 0 || depth >= int(plan->P.sym.size())) return HSOLVE_ERR_INVALID;
+    const hs::LevelSym& S = plan->P.sym[depth];
+    if (colour_of)
+        for (size_t i = 0; i < S.colour_of.size(); ++i) colour_of[i] = S.colour_of[i];
+    if (ncolours) *ncolours = int32_t(S.colours.size());
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_node_sets(hsolve_plan plan, int depth, int node, int32_t* nbrs, int32_t* nn,
+                               int32_t* ws, int32_t* nw, int cap) {
+    if (!plan || depth < 0 || depth >= int(plan->P.sym.size())) return HSOLVE_ERR_INVALID;
+    const hs::LevelSym& S = plan->P.sym[depth];
+    if (node < 0 || node >= int(S.N.size())) return HSOLVE_ERR_INVALID;
+    if (nn) *nn = int32_t(S.N[node].size());
+    if (nw) *nw = int32_t(S.W[node].size());
+    for (size_t i = 0; nbrs && i < S.N[node].size() && int(i) < cap; ++i)
+        nbrs[i] = 2 * S.N[node][i] + S.Nred[node][i];
+    for (size_t i = 0; ws && i < S.W[node].size() && int(i) < cap; ++i)
+        ws[i] = 2 * S.W[node][i] + S.Wred[node][i];
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_ranks(hsolve_plan plan, int depth, int32_t* ranks) {
+    if (!plan || !ranks || depth < 0 || depth >= int(plan->P.sym.size())) return HSOLVE_ERR_INVALID;
+    if (!plan->P.factored) return HSOLVE_ERR_STATE;
+    const hs::LevelNum& LN = plan->P.num[depth];
+    for (size_t i = 0; i < LN.ksz.size(); ++i) ranks[i] = LN.ksz[i];
+    return HSOLVE_OK;
+}
+
+}  // extern "C"

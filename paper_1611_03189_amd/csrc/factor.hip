@@ -1,0 +1,535 @@
+// Numeric factorization (Algorithm "Setup"), driven level by level and colour by colour.
+//
+// For every colour of a level all its super nodes are processed together (they share no
+// block, so this equals eliminating them one after the other, §3.2 "a given ordering"):
+//   A  compression (§3.2 eq. local_compression; §6 eq. compression_xy / preserve):
+//      gather A_sw, Gram matrix, [phi_s, A_sw phi_w] for GC, eigen-decomposition and
+//      truncation on the GPU; the ranks k come back to the host (they size the new blocks)
+//   B  elimination (§3.2 eq. extended_rearranged, K = L K2 L^T; Appendix A):
+//      A_ss^-1, Y = A_ss^-1 U, S = U^T Y, S^-1, P_ss = S^-1 Y^T, M_ss = A_ss^-1 - Y P_ss,
+//      T_N = A_Ns M_ss (kept for the solve), red-node blocks S^-1, A_ns P_ss^T, R,
+//      the preserved vector U^T phi_s, and the Schur update A_n1n2 -= T_n1 A_n2s^T
+//      (gathered per target block, contributions in index order).
+// At the end of a level the red nodes of sibling pairs are merged into the super nodes
+// of the parent level (Algorithm "Setup", merge step).
+#include <algorithm>
+#include <array>
+#include <chrono>
+#include <map>
+
+#include "hs_internal.h"
+
+namespace hs {
+
+namespace {
+
+struct Live {
+    std::unordered_map<uint64_t, Block> map;
+    Block* find(int i, int j) {
+        auto it = map.find(i <= j ? bkey(i, j) : bkey(j, i));
+        return it == map.end() ? nullptr : &it->second;
+    }
+    void put(int i, int j, const Block& b) { map[bkey(i, j)] = b; }   // i <= j
+    void erase(int i, int j) { map.erase(i <= j ? bkey(i, j) : bkey(j, i)); }
+};
+
+struct Batch {
+    std::vector<CopyTask> copies;
+    std::vector<GemmTask> gt;
+    std::vector<GemmTerm> terms;
+    std::vector<GemmTile> tiles;
+    std::vector<CholTask> chol;
+
+    void copy(const double* src, int lds, double* dst, int ldd, int rows, int cols, int trans) {
+        if (rows > 0 && cols > 0) copies.push_back(CopyTask{src, dst, lds, ldd, rows, cols, trans, 0});
+    }
+    void open(double* C, int ldc, int M, int N, double alpha, double beta) {
+        gt.push_back(GemmTask{C, ldc, M, N, int(terms.size()), int(terms.size()), 0, alpha, beta});
+    }
+    void term(const double* A, int lda, int tA, const double* B, int ldb, int tB, int K) {
+        if (K <= 0) return;
+        terms.push_back(GemmTerm{A, B, lda, ldb, K, tA, tB, 0});
+        gt.back().t_end = int(terms.size());
+    }
+    void close() {
+        const GemmTask& t = gt.back();
+        const int id = int(gt.size()) - 1;
+        for (int ti = 0; ti * 64 < t.M; ++ti)
+            for (int tj = 0; tj * 64 < t.N; ++tj) tiles.push_back(GemmTile{id, ti, tj, 0});
+    }
+    void gemm(double* C, int ldc, int M, int N, double alpha, double beta, const double* A,
+              int lda, int tA, const double* B, int ldb, int tB, int K) {
+        if (M <= 0 || N <= 0) return;
+        open(C, ldc, M, N, alpha, beta);
+        term(A, lda, tA, B, ldb, tB, K);
+        close();
+    }
+    void flush_copies(Plan& P) {
+        if (copies.empty()) return;
+        CopyTask* d = P.stage.upload_vec(copies, P.spool, P.stream);
+        launch_copy(d, int(copies.size()), P.stream);
+        copies.clear();
+    }
+    void flush_gemm(Plan& P) {
+        if (!tiles.empty()) {
+            GemmTask* dt = P.stage.upload_vec(gt, P.spool, P.stream);
+            GemmTerm* dterm = P.stage.upload_vec(terms, P.spool, P.stream);
+            GemmTile* dtile = P.stage.upload_vec(tiles, P.spool, P.stream);
+            launch_gemm(dt, dterm, dtile, int(tiles.size()), P.stream);
+        }
+        gt.clear();
+        terms.clear();
+        tiles.clear();
+    }
+    void flush_chol(Plan& P, int* d_fail) {
+        if (chol.empty()) return;
+        CholTask* d = P.stage.upload_vec(chol, P.spool, P.stream);
+        launch_chol_inv(d, int(chol.size()), d_fail, P.stream);
+        chol.clear();
+    }
+};
+
+size_t blk_bytes(int r, int c) { return ((size_t(r) * c * sizeof(double)) + 255) & ~size_t(255); }
+
+}  // namespace
+
+void factor(Plan& P, const double* d_values_in) {
+    using clk = std::chrono::steady_clock;
+    const auto t0 = clk::now();
+    hipStream_t st = P.stream;
+    const int L = P.L;
+    const int nlev = std::max(L, 1);
+    const bool gc = P.opt.variant == HSOLVE_GC;
+    const int p = P.nphi;
+    const double eps = P.opt.eps;
+
+    P.factored = false;
+    P.d_V = nullptr;
+    P.V_cols = 0;
+    P.d_krylov = nullptr;
+    P.krylov_cols = 0;
+    P.d_scalars = nullptr;
+    P.sched.clear();
+    HS_HIP(hipStreamSynchronize(st));
+    P.stage.reset();
+    P.fpool.reset();
+    P.lpool[0].reset();
+    P.lpool[1].reset();
+    P.spool.reset();
+    P.apool.reset();
+    HS_HIP(hipMemcpyAsync(P.d_values, d_values_in, size_t(P.nnz) * sizeof(double),
+                          hipMemcpyDeviceToDevice, st));
+
+    P.num.assign(nlev, LevelNum{});
+    Live lives[2];
+    std::vector<std::vector<double*>> phi_sup(nlev), phi_red(nlev);
+    double flops = 0.0;
+    int max_rank = 0;
+    int* h_flags = nullptr;     // pinned: fail flags of the level + ranks of the colour
+    HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), sizeof(int) * (size_t(2) << nlev) + 64,
+                         hipHostMallocDefault));
+    struct HostFree { int* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{h_flags};
+
+    for (int d = nlev - 1; d >= 0; --d) {
+        const LevelSym& S = P.sym[d];
+        const int nd = 1 << d;
+        LevelNum& LN = P.num[d];
+        LN.msz.assign(nd, 0);
+        LN.ksz.assign(nd, 0);
+        LN.node.assign(nd, NodeNum{});
+        const bool first = (d == nlev - 1);
+        for (int s = 0; s < nd; ++s) {
+            if (!S.super_nonempty[s]) continue;
+            if (L == 0) LN.msz[s] = P.n;
+            else if (first) LN.msz[s] = P.leaf_off[2 * s + 2] - P.leaf_off[2 * s];
+            else LN.msz[s] = P.num[d + 1].ksz[2 * s] + P.num[d + 1].ksz[2 * s + 1];
+        }
+        Live& live = lives[d & 1];
+        live.map.clear();
+        Pool& lp = P.lpool[d & 1];
+        lp.reset();
+        phi_sup[d].assign(nd, nullptr);
+        phi_red[d].assign(nd, nullptr);
+        P.spool.reset();
+        int* d_fail = lp.alloc_n<int>(nd);
+        HS_HIP(hipMemsetAsync(d_fail, 0, sizeof(int) * nd, st));
+        Batch B;
+
+        // ---- blocks of the level at its start: diagonal + upper partners, one zeroed region
+        size_t region = 0;
+        for (int s = 0; s < nd; ++s) {
+            if (!S.super_nonempty[s]) continue;
+            region += blk_bytes(LN.msz[s], LN.msz[s]);
+            for (int j : S.init_partners[s])
+                if (j > s) region += blk_bytes(LN.msz[s], LN.msz[j]);
+        }
+        char* base = static_cast<char*>(lp.alloc(region));
+        launch_fill(reinterpret_cast<double*>(base), 0.0, int64_t(region / sizeof(double)), st);
+        std::vector<int32_t> blk_begin(nd + 1, 0), blk_col, blk_ld;
+        std::vector<double*> blk_ptr;
+        {
+            size_t off = 0;
+            for (int s = 0; s < nd; ++s) {
+                blk_begin[s] = int32_t(blk_col.size());
+                if (!S.super_nonempty[s]) continue;
+                const int m = LN.msz[s];
+                Block b{reinterpret_cast<double*>(base + off), m, m, m};
+                off += blk_bytes(m, m);
+                live.put(s, s, b);
+                blk_col.push_back(s); blk_ld.push_back(m); blk_ptr.push_back(b.p);
+                for (int j : S.init_partners[s]) {
+                    if (j <= s) continue;
+                    Block c{reinterpret_cast<double*>(base + off), m, LN.msz[j], m};
+                    off += blk_bytes(m, LN.msz[j]);
+                    live.put(s, j, c);
+                    blk_col.push_back(j); blk_ld.push_back(m); blk_ptr.push_back(c.p);
+                }
+            }
+            blk_begin[nd] = int32_t(blk_col.size());
+        }
+        if (first) {
+            std::vector<int32_t> super_first(nd, 0);
+            if (L > 0)
+                for (int s = 0; s < nd; ++s) super_first[s] = P.leaf_off[2 * s];
+            launch_leaf_scatter(P.d_row_ptr, P.d_col_idx, P.d_values, P.d_iperm, P.d_pos_super, P.stage.upload_vec(super_first, P.spool, st),
+                                P.stage.upload_vec(blk_ptr, P.spool, st),
+                                P.stage.upload_vec(blk_ld, P.spool, st),
+                                P.stage.upload_vec(blk_col, P.spool, st),
+                                P.stage.upload_vec(blk_begin, P.spool, st), P.n, st);
+            if (gc) {
+                std::vector<double> h(size_t(P.n) * p);
+                size_t off = 0;
+                std::vector<size_t> node_off(nd, 0);
+                for (int s = 0; s < nd; ++s) {
+                    node_off[s] = off;
+                    const int m = LN.msz[s];
+                    const int p0 = (L == 0) ? 0 : P.leaf_off[2 * s];
+                    for (int c = 0; c < p; ++c)
+                        for (int i = 0; i < m; ++i)
+                            h[off + size_t(c) * m + i] = P.phi[size_t(P.perm[p0 + i]) + size_t(c) * P.n];
+                    off += size_t(m) * p;
+                }
+                double* dphi = P.stage.upload_vec(h, lp, st);
+                for (int s = 0; s < nd; ++s) phi_sup[d][s] = dphi + node_off[s];
+            }
+        } else {
+            Live& prev = lives[(d + 1) & 1];
+            const std::vector<int>& kc = P.num[d + 1].ksz;
+            for (int I = 0; I < nd; ++I) {
+                if (!S.super_nonempty[I]) continue;
+                std::vector<int> Js{I};
+                for (int j : S.init_partners[I])
+                    if (j > I) Js.push_back(j);
+                for (int J : Js) {
+                    Block* C = live.find(I, J);
+                    for (int a = 0; a < 2; ++a) {
+                        const int ca = 2 * I + a, ka = kc[ca];
+                        if (!ka) continue;
+                        const int roff = a ? kc[2 * I] : 0;
+                        for (int b = 0; b < 2; ++b) {
+                            const int cb = 2 * J + b, kb = kc[cb];
+                            if (!kb || (I == J && a > b)) continue;
+                            const int coff = b ? kc[2 * J] : 0;
+                            Block* ch = prev.find(ca, cb);
+                            if (!ch) continue;
+                            B.copy(ch->p, ch->ld, C->p + roff + size_t(coff) * C->ld, C->ld, ch->rows,
+                                   ch->cols, 0);
+                            if (I == J && a == 0 && b == 1)
+                                B.copy(ch->p, ch->ld, C->p + kc[2 * I], C->ld, ch->cols, ch->rows, 1);
+                        }
+                    }
+                }
+                if (gc) {
+                    const int m = LN.msz[I];
+                    double* f = lp.alloc_n<double>(size_t(m) * p);
+                    phi_sup[d][I] = f;
+                    int r0 = 0;
+                    for (int a = 0; a < 2; ++a) {
+                        const int ka = kc[2 * I + a];
+                        if (!ka) continue;
+                        B.copy(phi_red[d + 1][2 * I + a], ka, f + r0, m, ka, p, 0);
+                        r0 += ka;
+                    }
+                }
+            }
+            B.flush_copies(P);
+        }
+
+        // ---- colours
+        auto cursize = [&](int j, bool red) { return red ? LN.ksz[j] : LN.msz[j]; };
+        for (size_t c = 0; c < S.colours.size(); ++c) {
+            const std::vector<int>& nodes = S.colours[c];
+            P.spool.reset();    // stream order: the previous colour's kernels run first
+            // --- phase A: compression of the nodes with well-separated blocks
+            struct CompNode { int s, slot, wt; double *Asw, *U; };
+            std::vector<CompNode> comp;
+            std::vector<CompressTask> ctasks;
+            for (int s : nodes) {
+                if (S.W[s].empty()) continue;
+                const int m = LN.msz[s];
+                if (m > 1024)
+                    throw Error{HSOLVE_ERR_INVALID, "super node larger than 1024 unknowns at compression"};
+                int wt = 0;
+                for (size_t t = 0; t < S.W[s].size(); ++t) wt += cursize(S.W[s][t], S.Wred[s][t]);
+                double* Asw = P.spool.alloc_n<double>(size_t(m) * wt);
+                double* G = P.spool.alloc_n<double>(size_t(m) * m);
+                double* U = P.spool.alloc_n<double>(size_t(m) * m);
+                double* work = P.spool.alloc_n<double>(size_t(2) * m * m + 32 * size_t(m));
+                double* Z = nullptr;
+                int off = 0;
+                for (size_t t = 0; t < S.W[s].size(); ++t) {
+                    const int w = S.W[s][t];
+                    const int ws = cursize(w, S.Wred[s][t]);
+                    Block* b = live.find(s, w);
+                    if (!b) throw Error{HSOLVE_ERR_DEVICE, "internal: missing well-separated block"};
+                    if (s < w) B.copy(b->p, b->ld, Asw + size_t(off) * m, m, m, ws, 0);
+                    else B.copy(b->p, b->ld, Asw + size_t(off) * m, m, m, ws, 1);
+                    off += ws;
+                }
+                if (gc) {
+                    double* phiW = P.spool.alloc_n<double>(size_t(wt) * p);
+                    int r0 = 0;
+                    for (size_t t = 0; t < S.W[s].size(); ++t) {
+                        const int w = S.W[s][t];
+                        const bool red = S.Wred[s][t];
+                        const int ws = cursize(w, red);
+                        B.copy(red ? phi_red[d][w] : phi_sup[d][w], ws, phiW + r0, wt, ws, p, 0);
+                        r0 += ws;
+                    }
+                    Z = P.spool.alloc_n<double>(size_t(m) * 2 * p);
+                    B.copy(phi_sup[d][s], m, Z, m, m, p, 0);
+                    B.gemm(Z + size_t(p) * m, m, m, p, 1.0, 0.0, Asw, m, 0, phiW, wt, 0, wt);
+                    flops += 2.0 * m * wt * p;
+                }
+                B.gemm(G, m, m, m, 1.0, 0.0, Asw, m, 0, Asw, m, 1, wt);
+                flops += 2.0 * m * m * wt;
+                const int slot = int(comp.size());
+                comp.push_back(CompNode{s, slot, wt, Asw, U});
+                ctasks.push_back(CompressTask{G, Z, work, U, m, gc ? 2 * p : 0, wt, slot});
+            }
+            int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
+            B.flush_copies(P);
+            B.flush_gemm(P);
+            if (!ctasks.empty())
+                launch_compress(P.stage.upload_vec(ctasks, P.spool, st), int(ctasks.size()),
+                                P.opt.variant, eps, d_rank, st);
+            HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
+            if (!comp.empty())
+                HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size(),
+                                      hipMemcpyDeviceToHost, st));
+            HS_HIP(hipStreamSynchronize(st));
+            P.stage.reset();
+            for (int s = 0; s < nd; ++s)
+                if (h_flags[s]) {
+                    P.stats.fail_level = d;
+                    P.stats.fail_node = s;
+                    throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
+                }
+            for (const CompNode& cn : comp) {
+                const int k = h_flags[nd + cn.slot];
+                if (k < 0 || k > LN.msz[cn.s])
+                    throw Error{HSOLVE_ERR_DEVICE, "eigen-solver did not converge"};
+                LN.ksz[cn.s] = k;
+                max_rank = std::max(max_rank, k);
+            }
+            std::vector<const CompNode*> compof(nd, nullptr);
+            for (const CompNode& cn : comp) compof[cn.s] = &cn;
+
+            // --- phase B: elimination
+            std::vector<double*> AN(nodes.size()), Ysc(nodes.size());
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                nn.m = LN.msz[s];
+                nn.k = LN.ksz[s];
+                nn.ka = (first && L > 0) ? (P.leaf_off[2 * s + 1] - P.leaf_off[2 * s])
+                                         : (first ? nn.m : P.num[d + 1].ksz[2 * s]);
+                nn.ntot = 0;
+                nn.noff.clear();
+                for (size_t t = 0; t < S.N[s].size(); ++t) {
+                    nn.noff.push_back(nn.ntot);
+                    nn.ntot += cursize(S.N[s][t], S.Nred[s][t]);
+                }
+                nn.ldG = nn.m + nn.ntot + nn.k;
+                nn.Gm = P.fpool.alloc_n<double>(size_t(nn.ldG) * nn.m);
+                const int m = nn.m;
+                AN[q] = nn.ntot ? P.spool.alloc_n<double>(size_t(nn.ntot) * m) : nullptr;
+                for (size_t t = 0; t < S.N[s].size(); ++t) {
+                    const int nb = S.N[s][t];
+                    const int ns = cursize(nb, S.Nred[s][t]);
+                    Block* b = live.find(nb, s);
+                    if (!b) throw Error{HSOLVE_ERR_DEVICE, "internal: missing neighbour block"};
+                    if (nb < s) B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 0);
+                    else B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
+                }
+                Block* dg = live.find(s, s);
+                B.chol.push_back(CholTask{dg->p, nn.Gm, dg->ld, nn.ldG, m, s});
+                flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
+            }
+            B.flush_copies(P);
+            B.flush_chol(P, d_fail);
+            // Y = A_ss^-1 U, S = U^T Y
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                if (!nn.k) continue;
+                Ysc[q] = P.spool.alloc_n<double>(size_t(nn.m) * nn.k);
+                B.gemm(Ysc[q], nn.m, nn.m, nn.k, 1.0, 0.0, nn.Gm, nn.ldG, 0, compof[s]->U, nn.m, 0, nn.m);
+                flops += 2.0 * nn.m * nn.m * nn.k;
+            }
+            B.flush_gemm(P);
+            std::vector<double*> Ssc(nodes.size()), Sinv(nodes.size());
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                if (!nn.k) continue;
+                Ssc[q] = P.spool.alloc_n<double>(size_t(nn.k) * nn.k);
+                B.gemm(Ssc[q], nn.k, nn.k, nn.k, 1.0, 0.0, compof[s]->U, nn.m, 1, Ysc[q], nn.m, 0, nn.m);
+                flops += 2.0 * nn.m * nn.k * nn.k;
+            }
+            B.flush_gemm(P);
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                if (!nn.k) continue;
+                Sinv[q] = static_cast<double*>(lp.alloc(blk_bytes(nn.k, nn.k)));
+                B.chol.push_back(CholTask{Ssc[q], Sinv[q], nn.k, nn.k, nn.k, s});
+                flops += double(nn.k) * nn.k * nn.k;
+            }
+            B.flush_chol(P, d_fail);
+            // P_ss = S^-1 Y^T (rows m+ntot.. of Gm)
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                if (!nn.k) continue;
+                B.gemm(nn.Gm + nn.m + nn.ntot, nn.ldG, nn.k, nn.m, 1.0, 0.0, Sinv[q], nn.k, 0, Ysc[q],
+                       nn.m, 1, nn.k);
+                flops += 2.0 * nn.k * nn.k * nn.m;
+            }
+            B.flush_gemm(P);
+            // M_ss = A_ss^-1 - Y P_ss
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                if (!nn.k) continue;
+                B.gemm(nn.Gm, nn.ldG, nn.m, nn.m, -1.0, 1.0, Ysc[q], nn.m, 0, nn.Gm + nn.m + nn.ntot,
+                       nn.ldG, 0, nn.k);
+                flops += 2.0 * nn.m * nn.m * nn.k;
+            }
+            B.flush_gemm(P);
+            // T_N = A_Ns M_ss; red-node blocks L_nr = A_ns P_ss^T, R, S^-1; phi_r = U^T phi_s
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                NodeNum& nn = LN.node[s];
+                const int m = nn.m, k = nn.k;
+                if (nn.ntot) {
+                    B.gemm(nn.Gm + m, nn.ldG, nn.ntot, m, 1.0, 0.0, AN[q], nn.ntot, 0, nn.Gm, nn.ldG, 0, m);
+                    flops += 2.0 * nn.ntot * m * m;
+                }
+                if (!k) {
+                    for (int j : S.N[s]) live.erase(s, j);
+                    for (int j : S.W[s]) live.erase(s, j);
+                    live.erase(s, s);
+                    continue;
+                }
+                const double* Pm = nn.Gm + m + nn.ntot;
+                for (size_t t = 0; t < S.N[s].size(); ++t) {
+                    const int nb = S.N[s][t];
+                    const int ns = cursize(nb, S.Nred[s][t]);
+                    if (nb < s) {
+                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(ns, k)));
+                        live.put(nb, s, Block{blk, ns, k, ns});
+                        B.gemm(blk, ns, ns, k, 1.0, 0.0, AN[q] + nn.noff[t], nn.ntot, 0, Pm, nn.ldG, 1, m);
+                    } else {
+                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(k, ns)));
+                        live.put(s, nb, Block{blk, k, ns, k});
+                        B.gemm(blk, k, k, ns, 1.0, 0.0, Pm, nn.ldG, 0, AN[q] + nn.noff[t], nn.ntot, 1, m);
+                    }
+                    flops += 2.0 * ns * m * k;
+                }
+                const CompNode* cn = compof[s];
+                int off = 0;
+                for (size_t t = 0; t < S.W[s].size(); ++t) {
+                    const int w = S.W[s][t];
+                    const int ws = cursize(w, S.Wred[s][t]);
+                    const double* Aw = cn->Asw + size_t(off) * m;
+                    if (s < w) {
+                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(k, ws)));
+                        live.put(s, w, Block{blk, k, ws, k});
+                        B.gemm(blk, k, k, ws, 1.0, 0.0, cn->U, m, 1, Aw, m, 0, m);
+                    } else {
+                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(ws, k)));
+                        live.put(w, s, Block{blk, ws, k, ws});
+                        B.gemm(blk, ws, ws, k, 1.0, 0.0, Aw, m, 1, cn->U, m, 0, m);
+                    }
+                    flops += 2.0 * ws * m * k;
+                    off += ws;
+                }
+                live.put(s, s, Block{Sinv[q], k, k, k});
+                if (gc) {
+                    double* f = lp.alloc_n<double>(size_t(k) * p);
+                    phi_red[d][s] = f;
+                    B.gemm(f, k, k, p, 1.0, 0.0, cn->U, m, 1, phi_sup[d][s], m, 0, m);
+                }
+            }
+            B.flush_gemm(P);
+            // Schur complement on the neighbours, gathered per target block
+            std::map<uint64_t, std::vector<std::array<int, 3>>> targets;
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                const std::vector<int>& Nl = S.N[s];
+                for (size_t a = 0; a < Nl.size(); ++a)
+                    for (size_t b = a; b < Nl.size(); ++b)
+                        targets[bkey(Nl[a], Nl[b])].push_back({int(q), int(a), int(b)});
+            }
+            for (auto& [key, contrib] : targets) {
+                const int a = int(key >> 32), b = int(key & 0xffffffffu);
+                const int q0 = contrib[0][0];
+                const int s0 = nodes[q0];
+                const int sa = cursize(a, S.Nred[s0][contrib[0][1]]);
+                const int sb = cursize(b, S.Nred[s0][contrib[0][2]]);
+                Block* C = live.find(a, b);
+                bool fresh = false;
+                if (!C) {
+                    double* blk = static_cast<double*>(lp.alloc(blk_bytes(sa, sb)));
+                    live.put(a, b, Block{blk, sa, sb, sa});
+                    C = live.find(a, b);
+                    fresh = true;
+                }
+                B.open(C->p, C->ld, sa, sb, -1.0, fresh ? 0.0 : 1.0);
+                for (const auto& ct : contrib) {
+                    const int s = nodes[ct[0]];
+                    const NodeNum& nn = LN.node[s];
+                    B.term(nn.Gm + nn.m + nn.noff[ct[1]], nn.ldG, 0, AN[ct[0]] + nn.noff[ct[2]], nn.ntot, 1,
+                           nn.m);
+                    flops += 2.0 * sa * sb * nn.m;
+                }
+                B.close();
+            }
+            B.flush_gemm(P);
+        }
+        // end of level: surface pivot failures of the last colour
+        HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
+        HS_HIP(hipStreamSynchronize(st));
+        P.stage.reset();
+        for (int s = 0; s < nd; ++s)
+            if (h_flags[s]) {
+                P.stats.fail_level = d;
+                P.stats.fail_node = s;
+                throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
+            }
+    }
+    build_apply_schedule(P);
+    HS_HIP(hipStreamSynchronize(st));
+    P.factored = true;
+    P.stats.factor_flops = flops;
+    P.stats.max_rank = max_rank;
+    P.stats.levels = L;
+    P.stats.colours = P.total_colours;
+    P.stats.factor_bytes = int64_t(P.fpool.high_water());
+    P.stats.fail_level = -1;
+    P.stats.fail_node = -1;
+    P.stats.t_factor = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+}  // namespace hs

@@ -1,0 +1,276 @@
+// Internal data structures of the hsolve library (host side) and the launch wrappers of
+// its HIP kernels. Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/hsolve.h"
+
+namespace hs {
+
+// ---------------------------------------------------------------------------------
+// Errors
+// ---------------------------------------------------------------------------------
+struct Error {
+    hsolve_status status;
+    std::string what;
+};
+
+#define HS_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            throw ::hs::Error{e_ == hipErrorOutOfMemory ? HSOLVE_ERR_OOM               \
+                                                        : HSOLVE_ERR_DEVICE,          \
+                              std::string(#call) + ": " + hipGetErrorString(e_)};     \
+    } while (0)
+
+// ---------------------------------------------------------------------------------
+// Device memory: chunked bump allocators (256-byte aligned)
+// ---------------------------------------------------------------------------------
+class Pool {
+public:
+    explicit Pool(size_t chunk = size_t(64) << 20) : chunk_(chunk) {}
+    ~Pool();
+    Pool(const Pool&) = delete;
+    Pool& operator=(const Pool&) = delete;
+    void* alloc(size_t bytes);
+    template <class T> T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
+    void reset();      // reuse all chunks from the start (stream order keeps this safe)
+    void release();    // free every chunk
+    size_t high_water() const { return high_; }
+    size_t in_use() const;
+
+private:
+    struct Chunk { char* p; size_t size; };
+    std::vector<Chunk> chunks_;
+    size_t cur_ = 0, off_ = 0, chunk_, high_ = 0, used_before_ = 0;
+};
+
+// Pinned host staging + device copy of small task tables.
+class Staging {
+public:
+    ~Staging();
+    // copies `bytes` from src into pinned memory and enqueues an H2D copy into dst_pool;
+    // returns the device pointer
+    void* upload(const void* src, size_t bytes, Pool& dst_pool, hipStream_t s);
+    template <class T> T* upload_vec(const std::vector<T>& v, Pool& pool, hipStream_t s) {
+        if (v.empty()) return nullptr;
+        return static_cast<T*>(upload(v.data(), v.size() * sizeof(T), pool, s));
+    }
+    void reset() { off_ = 0; }   // only after a stream synchronisation
+
+private:
+    char* host_ = nullptr;
+    size_t cap_ = 0, off_ = 0;
+};
+
+// ---------------------------------------------------------------------------------
+// Symbolic schedule of one level (depth d): super nodes are the 2^d clusters of depth d
+// ---------------------------------------------------------------------------------
+struct LevelSym {
+    int d = 0;
+    std::vector<std::vector<int>> colours;
+    std::vector<int> colour_of;                 // -1 for empty super nodes
+    std::vector<std::vector<int>> N, W;         // neighbour / well-separated partners
+    std::vector<std::vector<uint8_t>> Nred, Wred;  // partner already red at elimination
+    std::vector<uint8_t> super_nonempty, red_nonempty;
+    std::vector<std::vector<int>> init_partners;   // block pattern when the level starts
+};
+
+// ---------------------------------------------------------------------------------
+// Dense blocks of the current matrix (column-major, canonical orientation i <= j)
+// ---------------------------------------------------------------------------------
+struct Block {
+    double* p = nullptr;
+    int rows = 0, cols = 0, ld = 0;
+};
+
+inline uint64_t bkey(int i, int j) {
+    return (uint64_t(uint32_t(i)) << 32) | uint32_t(j);
+}
+
+// ---------------------------------------------------------------------------------
+// Numeric factor of one eliminated super node, kept for the solve phase:
+// Gm = [M_ss (m rows); T_N = A_Ns M_ss (ntot rows); P_ss (k rows)], m columns,
+// column-major with ld = m + ntot + k.
+// ---------------------------------------------------------------------------------
+struct NodeNum {
+    int m = 0, k = 0, ntot = 0, ka = 0;
+    double* Gm = nullptr;
+    int ldG = 0;
+    std::vector<int> noff;     // row offset of each neighbour inside T_N
+};
+
+struct LevelNum {
+    std::vector<int> msz, ksz;          // super / red sizes (2^d)
+    std::vector<int64_t> red_off;       // start of each red segment in the solve vector
+    std::vector<NodeNum> node;
+};
+
+// ---------------------------------------------------------------------------------
+// Kernel task records (shared layout with kernels.hip)
+// ---------------------------------------------------------------------------------
+struct CopyTask {            // dst(i,j) = src(i,j) or src(j,i) (trans)
+    const double* src;
+    double* dst;
+    int lds, ldd, rows, cols, trans, pad;
+};
+
+struct GemmTask {            // C = beta C + alpha sum_t op(A_t) op(B_t), C is M x N
+    double* C;
+    int ldc, M, N, t_begin, t_end, pad;
+    double alpha, beta;
+};
+
+struct GemmTerm {
+    const double* A;
+    const double* B;
+    int lda, ldb, K, transA, transB, pad;
+};
+
+struct GemmTile {            // one 64 x 64 tile of a task
+    int task, ti, tj, pad;
+};
+
+struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1}
+    double* A;
+    double* Ainv;
+    int lda, ldi, m, id;
+};
+
+struct CompressTask {
+    const double* G;         // m x m Gram matrix A_sw A_sw^T (ld m), consumed
+    const double* Z;         // m x nz vectors to keep [phi_s, A_sw phi_w] (ld m), or null
+    double* work;            // scratch: 2 m^2 + 32 m doubles
+    double* U;               // out: m x k (ld m)
+    int m, nz, wt, id;
+};
+
+struct FwdTarget {           // V[dst + i] += sign * sum_c Gc[i, :] V[src_c + :]
+    long long dst;
+    int len, sign, c_begin, c_end;
+};
+
+struct FwdContrib {
+    const double* G;         // first row of the contributing rows, column-major
+    long long src;           // start of phi_s in V
+    int ldG, m;
+};
+
+struct BwdNode {             // x_s = Gm^T [phi_s; -x_N; x_r], written at dst
+    const double* G;
+    long long dst;
+    int ldG, m, rows, seg_begin, seg_end, pad;
+};
+
+struct BwdSeg {
+    long long off;
+    int len, sign;
+};
+
+// ---------------------------------------------------------------------------------
+// The plan
+// ---------------------------------------------------------------------------------
+struct Plan {
+    // pattern and options
+    int n = 0;
+    int64_t nnz = 0;
+    std::vector<int64_t> row_ptr;
+    std::vector<int32_t> col_idx;
+    hsolve_options opt{};
+    std::vector<double> coords, phi;   // copies (phi column-major n x nvec)
+    int nphi = 0;                      // preserved vectors (0 for LoRaSp)
+    hipStream_t stream = nullptr;
+
+    // tree
+    int L = 0;
+    std::vector<int32_t> perm, iperm, leaf_off;   // leaf order
+    std::vector<LevelSym> sym;                     // sym[d], d = 0 .. L-1
+    int total_colours = 0;
+
+    // device copies of the pattern
+    int64_t* d_row_ptr = nullptr;
+    int32_t* d_col_idx = nullptr;
+    double* d_values = nullptr;
+    int32_t* d_perm = nullptr;         // [perm (n) | iperm (n)]
+    int32_t* d_iperm = nullptr;        // = d_perm + n
+    int32_t* d_pos_super = nullptr;    // super node of the first level for each position
+
+    // numeric factor
+    bool factored = false;
+    std::vector<LevelNum> num;         // num[d]
+    int64_t vlen = 0;                  // length of one solve-vector column
+    Pool fpool{size_t(256) << 20};     // factor data (kept)
+    Pool lpool[2]{Pool(size_t(256) << 20), Pool(size_t(256) << 20)};  // live blocks by depth parity
+    Pool spool{size_t(128) << 20};     // per-step scratch
+    Pool apool{size_t(16) << 20};      // apply schedule + vectors
+    Staging stage;
+
+    // apply schedule (device), per level and colour
+    struct ColourSched {
+        FwdTarget* fwd_t = nullptr; int nfwd = 0; int max_len = 0;
+        FwdContrib* fwd_c = nullptr;
+        BwdNode* bwd_n = nullptr; int nbwd = 0;
+        BwdSeg* bwd_s = nullptr;
+    };
+    std::vector<std::vector<ColourSched>> sched;   // sched[d][c]
+    double* d_V = nullptr;
+    int V_cols = 0;
+    double* d_scalars = nullptr;                    // dot-product results
+    double* h_scalars = nullptr;                    // pinned
+    double* d_krylov = nullptr;                     // PCG vectors
+    int krylov_cols = 0;
+
+    hsolve_stats stats{};
+    ~Plan();
+};
+
+// analyze.hip (host only)
+void analyze(Plan& P);
+// runtime.hip
+void upload_pattern(Plan& P);
+// factor.hip
+void factor(Plan& P, const double* d_values);
+// solve.hip
+void build_apply_schedule(Plan& P);
+void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
+int pcg(Plan& P, const double* b, double* x, double tol, int max_iter, double* rel_out);
+void spmv(Plan& P, const double* x, double* y);
+
+// kernels.hip: launch wrappers (all asynchronous on stream s)
+void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
+void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
+                 int ntiles, hipStream_t s);
+void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, hipStream_t s);
+void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
+                     int* d_rank, hipStream_t s);
+void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                         const int32_t* iperm, const int32_t* pos_super,
+                         const int32_t* super_first, double* const* blk_ptr,
+                         const int32_t* blk_ld, const int32_t* blk_col,
+                         const int32_t* blk_begin, int n, hipStream_t s);
+void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, double* V, int64_t ldv,
+                int nrhs, hipStream_t s);
+void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, double* V, int64_t ldv,
+                int nrhs, int max_rows, hipStream_t s);
+void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, const int32_t* perm,
+                        int n, int nrhs, hipStream_t s);   // dst[p] = src[perm[p]]
+void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
+                         const int32_t* perm, int n, int nrhs, hipStream_t s); // dst[perm[p]] = src[p]
+void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                 const double* x, double* y, int n, hipStream_t s);
+void launch_dot2(const double* a, const double* b, const double* c, const double* d, int n,
+                 double* out, hipStream_t s);   // out[0] = a.b, out[1] = c.d
+void launch_axpy2(double* x, const double* p, double* r, const double* q, const double* alpha,
+                  int n, hipStream_t s);        // x += a p, r -= a q (a = alpha[0]/alpha[1])
+void launch_xpby(double* p, const double* z, const double* beta, int n, hipStream_t s);
+void launch_fill(double* p, double v, int64_t n, hipStream_t s);
+
+}  // namespace hs

@@ -1,0 +1,268 @@
+"""Thin Python binding of the hsolve C ABI (include/hsolve.h).
+
+Argument marshalling only: every step of the factorization and of the solve runs in the
+HIP library ``libhsolve.so`` built from ``csrc/`` (``python -m paper_1611_03189_amd.build``).
+PyTorch provides device memory and the stream. If the library is missing, importing the
+functions that need it raises ``RuntimeError``; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+from ctypes import POINTER, c_double, c_int, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libhsolve.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "hsolve.h")
+
+LORASP = 0
+GC = 1
+
+STATUS = {
+    0: "HSOLVE_OK", 1: "HSOLVE_NOT_CONVERGED", -1: "HSOLVE_ERR_INVALID",
+    -2: "HSOLVE_ERR_NOT_SYMMETRIC", -3: "HSOLVE_ERR_NOT_SPD", -4: "HSOLVE_ERR_OOM",
+    -5: "HSOLVE_ERR_DEVICE", -6: "HSOLVE_ERR_STATE",
+}
+
+
+class HSolveError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {STATUS.get(status, status)}")
+        self.status = status
+
+
+class NotSPD(HSolveError):
+    pass
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("leaf_size", c_int), ("eps", c_double), ("variant", c_int), ("nvec", c_int),
+        ("phi", POINTER(c_double)), ("dim", c_int), ("coords", POINTER(c_double)),
+        ("tol", c_double), ("max_iter", c_int), ("krylov", c_int), ("stream", c_void_p),
+    ]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [
+        ("iterations", c_int), ("rel_residual", c_double), ("t_analyze", c_double),
+        ("t_factor", c_double), ("t_solve", c_double), ("levels", c_int), ("colours", c_int),
+        ("max_rank", c_int), ("factor_bytes", c_int64), ("factor_flops", c_double),
+        ("apply_bytes", c_double), ("fail_level", c_int), ("fail_node", c_int),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_lib = None
+
+
+def exported_names() -> list[str]:
+    """Function names declared in include/hsolve.h."""
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(hsolve_[a-z_]+)\s*\(", text)))
+
+
+def load() -> ctypes.CDLL:
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1611_03189_amd.build`")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = c_void_p
+    sig = {
+        "hsolve_default_options": (None, [POINTER(Options)]),
+        "hsolve_analyze": (c_int, [c_int, POINTER(c_int64), POINTER(c_int32), POINTER(Options), POINTER(P)]),
+        "hsolve_factor": (c_int, [P, P]),
+        "hsolve_apply": (c_int, [P, c_int, P, c_int, P, c_int]),
+        "hsolve_solve": (c_int, [P, c_int, P, c_int, P, c_int, POINTER(Stats)]),
+        "hsolve_spmv": (c_int, [P, P, P]),
+        "hsolve_get_stats": (c_int, [P, POINTER(Stats)]),
+        "hsolve_destroy": (c_int, [P]),
+        "hsolve_status_string": (ctypes.c_char_p, [c_int]),
+        "hsolve_depth": (c_int, [P]),
+        "hsolve_leaf_order": (c_int, [P, POINTER(c_int32), POINTER(c_int32)]),
+        "hsolve_level_colours": (c_int, [P, c_int, POINTER(c_int32), POINTER(c_int32)]),
+        "hsolve_node_sets": (c_int, [P, c_int, c_int, POINTER(c_int32), POINTER(c_int32),
+                                     POINTER(c_int32), POINTER(c_int32), c_int]),
+        "hsolve_ranks": (c_int, [P, c_int, POINTER(c_int32)]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int, where: str):
+    if status == -3:
+        raise NotSPD(status, where)
+    if status not in (0, 1):
+        raise HSolveError(status, where)
+    return status
+
+
+def _i32p(a):
+    return a.ctypes.data_as(POINTER(c_int32))
+
+
+def _dev(t, torch):
+    """A contiguous float64 tensor on the current GPU (copies numpy / host input)."""
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    if not t.is_cuda:
+        t = t.cuda()
+    if t.dtype != torch.float64:
+        raise TypeError("hsolve works on float64 data")
+    return t.contiguous()
+
+
+class HSolver:
+    """One analysed sparse SPD pattern with (after :meth:`factor`) its hierarchical factor.
+
+    ``row_ptr``/``col_idx``: CSR pattern (host arrays, symmetric, sorted rows);
+    ``coords`` (n x dim) drive the bisection; ``variant`` is ``"gc"`` (default) or
+    ``"lorasp"``; ``phi`` (n x p) are the vectors GC preserves (default: constant).
+    """
+
+    def __init__(self, row_ptr, col_idx, coords=None, leaf: int = 16, eps: float = 1e-2,
+                 variant: str = "gc", phi=None, tol: float = 1e-10, max_iter: int = 1000,
+                 stream=None):
+        lib = load()
+        self._lib = lib
+        self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
+        self.n = len(self.row_ptr) - 1
+        opt = Options()
+        lib.hsolve_default_options(ctypes.byref(opt))
+        opt.leaf_size = int(leaf)
+        opt.eps = float(eps)
+        opt.variant = {"gc": GC, "lorasp": LORASP}[variant] if isinstance(variant, str) else int(variant)
+        opt.tol = float(tol)
+        opt.max_iter = int(max_iter)
+        self._keep = []
+        if coords is not None:
+            c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(self.n, -1))
+            self._keep.append(c)
+            opt.dim = c.shape[1]
+            opt.coords = c.ctypes.data_as(POINTER(c_double))
+        if phi is not None:
+            ph = np.asfortranarray(np.asarray(phi, dtype=np.float64).reshape(self.n, -1))
+            self._keep.append(ph)
+            opt.nvec = ph.shape[1]
+            opt.phi = ph.ctypes.data_as(POINTER(c_double))
+        self.stream = stream
+        opt.stream = c_void_p(stream.cuda_stream) if stream is not None else None
+        h = c_void_p()
+        _check(lib.hsolve_analyze(self.n, self.row_ptr.ctypes.data_as(POINTER(c_int64)),
+                                  _i32p(self.col_idx), ctypes.byref(opt), ctypes.byref(h)),
+               "hsolve_analyze")
+        self._h = h
+        self._keep.clear()          # analyze copied coordinates and phi
+        self.values = None
+
+    # -- lifecycle -----------------------------------------------------------------
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.hsolve_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    # -- numeric -------------------------------------------------------------------
+    def factor(self, values):
+        import torch
+        v = _dev(values, torch)
+        self.values = v
+        _check(self._lib.hsolve_factor(self._h, c_void_p(v.data_ptr())), "hsolve_factor")
+        return self
+
+    def apply(self, r, out=None):
+        import torch
+        r = _dev(r, torch)
+        vec = r.dim() == 1
+        R = r.reshape(self.n, -1) if vec else r
+        # column-major n x nrhs == a (nrhs, n) row-major tensor
+        Rc = R.t().contiguous()
+        Z = torch.empty_like(Rc) if out is None else out
+        _check(self._lib.hsolve_apply(self._h, Rc.shape[0], c_void_p(Rc.data_ptr()), self.n,
+                                      c_void_p(Z.data_ptr()), self.n), "hsolve_apply")
+        Z = Z.t()
+        return Z.reshape(-1) if vec else Z
+
+    def solve(self, b):
+        import torch
+        b = _dev(b, torch)
+        vec = b.dim() == 1
+        B = b.reshape(self.n, -1) if vec else b
+        Bc = B.t().contiguous()
+        X = torch.empty_like(Bc)
+        st = Stats()
+        status = _check(self._lib.hsolve_solve(self._h, Bc.shape[0], c_void_p(Bc.data_ptr()), self.n,
+                                               c_void_p(X.data_ptr()), self.n, ctypes.byref(st)),
+                        "hsolve_solve")
+        X = X.t()
+        d = st.as_dict()
+        d["converged"] = status == 0
+        return (X.reshape(-1) if vec else X), d
+
+    def spmv(self, x):
+        import torch
+        x = _dev(x, torch)
+        y = torch.empty_like(x)
+        _check(self._lib.hsolve_spmv(self._h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr())),
+               "hsolve_spmv")
+        return y
+
+    # -- introspection -------------------------------------------------------------
+    def stats(self) -> dict:
+        st = Stats()
+        _check(self._lib.hsolve_get_stats(self._h, ctypes.byref(st)), "hsolve_get_stats")
+        return st.as_dict()
+
+    @property
+    def depth(self) -> int:
+        return self._lib.hsolve_depth(self._h)
+
+    def leaf_order(self):
+        L = self.depth
+        perm = np.empty(self.n, dtype=np.int32)
+        off = np.empty((1 << L) + 1, dtype=np.int32)
+        _check(self._lib.hsolve_leaf_order(self._h, _i32p(perm), _i32p(off)), "hsolve_leaf_order")
+        return perm, off
+
+    def colours(self, depth: int):
+        col = np.empty(1 << depth, dtype=np.int32)
+        nc = c_int32()
+        _check(self._lib.hsolve_level_colours(self._h, depth, _i32p(col), ctypes.byref(nc)),
+               "hsolve_level_colours")
+        return col, nc.value
+
+    def node_sets(self, depth: int, node: int, cap: int = 4096):
+        nb = np.empty(cap, dtype=np.int32)
+        ws = np.empty(cap, dtype=np.int32)
+        nn, nw = c_int32(), c_int32()
+        _check(self._lib.hsolve_node_sets(self._h, depth, node, _i32p(nb), ctypes.byref(nn),
+                                          _i32p(ws), ctypes.byref(nw), cap), "hsolve_node_sets")
+        return nb[:nn.value].copy(), ws[:nw.value].copy()
+
+    def ranks(self, depth: int):
+        out = np.empty(1 << depth, dtype=np.int32)
+        _check(self._lib.hsolve_ranks(self._h, depth, _i32p(out)), "hsolve_ranks")
+        return out

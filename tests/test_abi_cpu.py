@@ -1,0 +1,98 @@
+"""C-ABI library checks that need no GPU: it loads, exports every declared symbol, and its
+host symbolic analysis (bisection, adjacency, simulated fill, colour order) produces
+exactly the integer schedule of the CPU oracle, which implements the same rules separately.
+"""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1611_03189_amd import hsolve as H
+from paper_1611_03189_amd import problems as pb
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return H.load()
+
+
+def test_library_exports_every_declared_symbol(lib):
+    names = H.exported_names()
+    assert "hsolve_analyze" in names and "hsolve_factor" in names
+    assert "hsolve_apply" in names and "hsolve_solve" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_status_strings(lib):
+    for code, name in H.STATUS.items():
+        assert lib.hsolve_status_string(code).decode() == name
+
+
+CASES = [
+    ("poisson2d_32_leaf16", lambda: pb.poisson(32, 2), 16, 1e-2, "gc"),
+    ("poisson2d_24_leaf8", lambda: pb.poisson(24, 2), 8, 0.1, "lorasp"),
+    ("lognormal2d_32_leaf8", lambda: pb.lognormal(32, 2, 2.0, 3), 8, 1e-2, "gc"),
+    ("poisson3d_12_leaf16", lambda: pb.poisson(12, 3), 16, 1e-2, "gc"),
+    ("poisson3d_16_leaf64", lambda: pb.poisson(16, 3), 64, 1e-2, "gc"),
+    ("chain_100_leaf5", lambda: pb.chain(100), 5, 0.1, "gc"),
+    ("poisson2d_20_nocoords", lambda: pb.poisson(20, 2), 8, 1e-2, "gc"),
+]
+
+
+@pytest.mark.parametrize("name,make,leaf,eps,variant", CASES, ids=[c[0] for c in CASES])
+def test_schedule_matches_oracle(name, make, leaf, eps, variant):
+    p = make()
+    coords = None if name.endswith("nocoords") else p.coords
+    F = O.factor(p.row_ptr, p.col_idx, p.values, coords, leaf=leaf, eps=eps,
+                 variant=O.GC if variant == "gc" else O.LORASP)
+    with H.HSolver(p.row_ptr, p.col_idx, coords=coords, leaf=leaf, eps=eps, variant=variant) as S:
+        assert S.depth == F.L
+        perm, off = S.leaf_order()
+        assert np.array_equal(perm, np.concatenate(F.leaves))
+        assert np.array_equal(np.diff(off), [len(c) for c in F.leaves])
+        for d, lev in F.levels.items():
+            col, nc = S.colours(d)
+            assert nc == len(lev.colours)
+            for ci, members in enumerate(lev.colours):
+                assert sorted(np.nonzero(col == ci)[0].tolist()) == members
+            for s, nf in lev.nodes.items():
+                nb, ws = S.node_sets(d, s)
+                exp_nb = [2 * n + (st == "R") for (n, st, _) in nf.nbrs]
+                exp_ws = [2 * w + (st == "R") for w, st in zip(nf.W, nf.Wstate)]
+                assert nb.tolist() == exp_nb, (d, s)
+                assert ws.tolist() == exp_ws, (d, s)
+            # nodes the oracle never eliminated (empty) have no colour in the library
+            empty = set(range(1 << d)) - set(lev.nodes)
+            assert all(col[e] == -1 for e in empty)
+
+
+def test_analyze_rejects_bad_input(lib):
+    p = pb.poisson(6, 2)
+    with pytest.raises(H.HSolveError) as e:
+        H.HSolver(p.row_ptr, p.col_idx[::-1].copy(), coords=p.coords)
+    assert e.value.status == -1                      # unsorted rows
+    rp, ci = p.row_ptr.copy(), p.col_idx.copy()
+    assert ci[:3].tolist() == [0, 1, 6]
+    ci[2] = 7                                        # (0,7) without (7,0); row 0 stays sorted
+    with pytest.raises(H.HSolveError) as e:
+        H.HSolver(rp, ci, coords=p.coords)
+    assert e.value.status == -2
+    with pytest.raises(H.HSolveError) as e:
+        H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, eps=-1.0)
+    assert e.value.status == -1
+    bad = p.col_idx.copy()
+    bad[-1] = p.n + 5
+    with pytest.raises(H.HSolveError):
+        H.HSolver(p.row_ptr, bad, coords=p.coords)
+
+
+def test_state_errors_without_factor(lib):
+    p = pb.poisson(6, 2)
+    with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords) as S:
+        dummy = ctypes.c_void_p(1)
+        assert lib.hsolve_apply(S._h, 1, dummy, p.n, dummy, p.n) == -6
+        assert lib.hsolve_solve(S._h, 1, dummy, p.n, dummy, p.n, None) == -6
+        assert lib.hsolve_ranks(S._h, 0, np.zeros(1, np.int32).ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int32))) == -6

@@ -1,0 +1,178 @@
+"""GPU (HIP, gfx950) path vs the FP64 CPU oracle, through the C ABI.
+
+Bar (FP64 path): rank vectors equal level by level, and ||z_gpu - z_oracle|| /
+||z_oracle|| <= 1e-10 for z = A_H^{-1} r on the same seeded r. Properties that hold at any
+size are checked at the full workload sizes (GC invariant A_H^{-1} A 1 = 1, PCG reaching
+1e-10 true residual). Each case prints its name before touching the GPU.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1611_03189_amd import problems as pb
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_03189_amd import hsolve as H  # noqa: E402
+
+TOL = 1e-10
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def run_pair(p, leaf, eps, variant, nrhs=2, seed=7, phi=None, coords="grid"):
+    c = p.coords if coords == "grid" else None
+    F = O.factor(p.row_ptr, p.col_idx, p.values, c, leaf=leaf, eps=eps,
+                 variant=O.GC if variant == "gc" else O.LORASP, phi=phi)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=c, leaf=leaf, eps=eps, variant=variant, phi=phi)
+    S.factor(torch.from_numpy(p.values).cuda())
+    r = pb.rhs(p.n, nrhs, seed)
+    z_ref = O.apply(F, r)
+    z = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+    return F, S, r, z_ref, z
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+PARITY = [
+    ("c1_poisson2d_32_leaf16_gc", lambda: pb.poisson(32, 2), 16, 1e-2, "gc"),
+    ("c1_poisson2d_32_leaf16_lorasp", lambda: pb.poisson(32, 2), 16, 1e-2, "lorasp"),
+    ("poisson2d_30_ragged_leaf8_gc", lambda: pb.poisson(30, 2), 8, 0.05, "gc"),
+    ("lognormal2d_48_s2_leaf8_gc", lambda: pb.lognormal(48, 2, 2.0, 1002), 8, 1e-2, "gc"),
+    ("poisson3d_12_leaf16_gc", lambda: pb.poisson(12, 3), 16, 1e-2, "gc"),
+    ("poisson3d_16_leaf64_gc", lambda: pb.poisson(16, 3), 64, 1e-2, "gc"),
+    ("poisson3d_16_leaf64_eps1e-4", lambda: pb.poisson(16, 3), 64, 1e-4, "gc"),
+    ("poisson3d_8_leaf8_lorasp", lambda: pb.poisson(8, 3), 8, 0.1, "lorasp"),
+    ("chain_300_leaf6_gc", lambda: pb.chain(300), 6, 0.1, "gc"),
+    ("single_leaf_n20", lambda: pb.poisson(20, 1), 64, 1e-2, "gc"),
+]
+
+
+@pytest.mark.parametrize("name,make,leaf,eps,variant", PARITY, ids=[c[0] for c in PARITY])
+def test_apply_matches_oracle(name, make, leaf, eps, variant):
+    say(name)
+    p = make()
+    F, S, r, z_ref, z = run_pair(p, leaf, eps, variant)
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
+    assert rel(z, z_ref) <= TOL, (name, rel(z, z_ref))
+    S.close()
+
+
+@pytest.mark.parametrize("variant", ["gc", "lorasp"])
+def test_eps_zero_exact_on_gpu(variant):
+    say("eps0", variant)
+    p = pb.poisson(16, 2)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8, eps=0.0, variant=variant)
+    S.factor(torch.from_numpy(p.values).cuda())
+    b = pb.rhs(p.n, 1, 5)[:, 0]
+    x = np.linalg.solve(p.dense(), b)
+    z = S.apply(torch.from_numpy(b).cuda()).cpu().numpy()
+    assert rel(z, x) < 1e-14 * np.linalg.cond(p.dense())
+    S.close()
+
+
+def test_gc_eigenvector_phi_on_gpu():
+    say("gc_eigenvector_p2")
+    N = 24
+    p = pb.poisson(N, 2)
+    lam, V = np.linalg.eigh(p.dense())
+    phi = np.asfortranarray(V[:, :2])
+    F, S, r, z_ref, z = run_pair(p, 8, 0.2, "gc", phi=phi)
+    assert rel(z, z_ref) <= TOL
+    for j in range(2):
+        zj = S.apply(torch.from_numpy(p.dense() @ phi[:, j]).cuda()).cpu().numpy()
+        assert np.max(np.abs(zj - phi[:, j])) < 1e-10
+    S.close()
+
+
+def test_multiple_rhs_equal_single():
+    say("multi_rhs")
+    p = pb.poisson(32, 2)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, eps=1e-2)
+    S.factor(torch.from_numpy(p.values).cuda())
+    B = pb.rhs(p.n, 4, 9)
+    Z = S.apply(torch.from_numpy(np.ascontiguousarray(B)).cuda()).cpu().numpy()
+    for j in range(4):
+        zj = S.apply(torch.from_numpy(B[:, j].copy()).cuda()).cpu().numpy()
+        assert np.array_equal(zj, Z[:, j])
+    S.close()
+
+
+def test_refactor_and_run_twice_bitwise():
+    say("determinism")
+    p = pb.lognormal(32, 2, 1.0, 77)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8, eps=1e-2)
+    v = torch.from_numpy(p.values).cuda()
+    r = torch.from_numpy(pb.rhs(p.n, 1, 3)[:, 0]).cuda()
+    S.factor(v)
+    z1 = S.apply(r).cpu().numpy()
+    S.factor(v)
+    z2 = S.apply(r).cpu().numpy()
+    assert np.array_equal(z1, z2)
+    S.close()
+
+
+@pytest.mark.parametrize("name,make,leaf,eps", [
+    ("c1_poisson2d_32", lambda: pb.poisson(32, 2), 16, 1e-2),
+    ("lognormal2d_64_s2", lambda: pb.lognormal(64, 2, 2.0, 1002), 16, 1e-2),
+    ("poisson3d_16_leaf64", lambda: pb.poisson(16, 3), 64, 1e-2),
+])
+def test_pcg_matches_oracle(name, make, leaf, eps):
+    say("pcg", name)
+    p = make()
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 1, 2001)[:, 0]
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=eps, variant=O.GC)
+    x_ref, it_ref, rel_ref = O.pcg(A, b, lambda r: O.apply(F, r), tol=TOL)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=eps)
+    S.factor(torch.from_numpy(p.values).cuda())
+    x, st = S.solve(torch.from_numpy(b).cuda())
+    x = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    assert st["converged"] and true_rel <= 2 * TOL, (true_rel, st)
+    assert abs(st["iterations"] - it_ref) <= 1, (st["iterations"], it_ref)
+    assert rel(x, x_ref) < 1e-8
+    S.close()
+
+
+def test_not_spd_is_reported():
+    say("not_spd")
+    p = pb.poisson(8, 2)
+    vals = p.values.copy()
+    diag = np.repeat(np.arange(p.n), np.diff(p.row_ptr)) == p.col_idx
+    vals[diag] -= 8.0
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=4, eps=0.1)
+    with pytest.raises(H.NotSPD):
+        S.factor(torch.from_numpy(vals).cuda())
+    st = S.stats()
+    assert st["fail_level"] >= 0 and st["fail_node"] >= 0
+    S.close()
+
+
+@pytest.mark.slow
+def test_c3_full_size_properties():
+    """64^3 Poisson, leaf 64, eps 1e-2, GC: invariant and PCG at the benchmarked size."""
+    say("c3_full_size")
+    p, w = pb.workload("c3_poisson3d_64")
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=w["leaf"], eps=w["eps"])
+    S.factor(torch.from_numpy(p.values).cuda())
+    A = p.to_scipy()
+    one = np.ones(p.n)
+    z = S.apply(torch.from_numpy(A @ one).cuda()).cpu().numpy()
+    assert np.max(np.abs(z - 1.0)) < 1e-9
+    b = pb.rhs(p.n, 1, 2003)[:, 0]
+    x, st = S.solve(torch.from_numpy(b).cuda())
+    true_rel = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert true_rel <= 2 * TOL and st["iterations"] <= 10, (true_rel, st)
+    S.close()
