@@ -137,6 +137,20 @@ hsolve_status hsolve_destroy(hsolve_plan plan);
 /* Static, human-readable name of a status code. */
 const char* hsolve_status_string(hsolve_status s);
 
+/* Message of the last failed call on this plan ("" if none); valid until the next call. */
+const char* hsolve_last_error(hsolve_plan plan);
+
+/* ---- Kernel timing (HIP events on the plan's stream around every launch) ----
+ * hsolve_profile_begin clears and starts recording for calls on this plan from the calling
+ * thread; hsolve_profile_end stops, waits for the device and aggregates by kernel name
+ * (*nkernels entries); hsolve_profile_entry reads entry i: name, summed milliseconds,
+ * launches, and summed algorithmic work (flops for k_gemm, k_chol_inv, k_compress; bytes
+ * for k_copy, k_fwd, k_bwd, k_spmv). */
+hsolve_status hsolve_profile_begin(hsolve_plan plan);
+hsolve_status hsolve_profile_end(hsolve_plan plan, int32_t* nkernels);
+hsolve_status hsolve_profile_entry(hsolve_plan plan, int i, char* name, int cap, double* ms,
+                                   int64_t* launches, double* work);
+
 /* ---- Introspection of the symbolic schedule (host arrays, caller-allocated) ---- */
 
 /* Tree depth L of the plan. */
@@ -158,6 +172,13 @@ hsolve_status hsolve_level_colours(hsolve_plan plan, int depth, int32_t* colour_
  * written per list; *nn / *nw receive the full lengths. */
 hsolve_status hsolve_node_sets(hsolve_plan plan, int depth, int node, int32_t* nbrs,
                                int32_t* nn, int32_t* ws, int32_t* nw, int cap);
+
+/* Stored factor of super node `node` of level `depth` after the last factorization:
+ * dims[0] = m (super-node size), dims[1] = ntot (rows of all neighbour blocks), dims[2] = k.
+ * If G is not NULL, copies the (m + ntot + k) x m column-major matrix [M_ss; A_Ns M_ss; P_ss]
+ * (Appendix A) to the host array G of `cap` doubles. Empty nodes report m = 0. */
+hsolve_status hsolve_node_factor(hsolve_plan plan, int depth, int node, int32_t* dims,
+                                 double* G, int64_t cap);
 
 /* Red-node sizes (ranks k) of level `depth` after the last factorization
  * (2^depth entries, 0 for empty nodes). */

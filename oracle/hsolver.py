@@ -31,7 +31,11 @@ R4  U1 = orthonormal basis of [phi_s, A_sw phi_w] by modified Gram-Schmidt with 
     norm. U2 lives in the orthogonal complement of U1 (Householder completion).
 R5  A super node with no well-separated block keeps k = 0 (exact elimination, empty
     red node), for both variants. A super node with well-separated blocks keeps at
-    least one column. Nodes of size 0 are dropped from the block pattern.
+    least one column (the first unit vector when A_sw is exactly zero). Nodes of size 0
+    are dropped from the block pattern.
+R7  When k = m (U square and invertible) M_ss is set to exactly zero, the value
+    Appendix A gives for that case; otherwise the fill it creates would be rounding
+    noise, and compressing noise against a relative threshold is not reproducible.
 R6  Neighbour = footprint adjacency in the original graph (§3.1); a red node has the
     footprint of its super node; N(s) / W(s) are the nodes with a block to s that are /
     are not neighbours.
@@ -124,6 +128,8 @@ def compress(A_sw: np.ndarray, eps: float, variant: int,
         k2 = int(np.count_nonzero(sb[:cap] > eps * sigma1))
     if U1.shape[1] + k2 == 0 and cap > 0:
         k2 = 1                                          # R5: keep at least one direction
+        if sigma1 == 0.0:                               # A_sw exactly zero: first unit vector
+            return np.eye(m)[:, :1]
     return np.hstack([U1, Qc @ Ub[:, :k2]])
 
 
@@ -153,7 +159,10 @@ def pivot(A_ss: np.ndarray, U: np.ndarray):
     else:
         Sinv = np.zeros((0, 0))
     P = Sinv @ U.T @ Ainv
-    M = Ainv - P.T @ S @ P
+    if k == m:
+        M = np.zeros((m, m))      # U invertible: M_ss vanishes (Appendix A)
+    else:
+        M = Ainv - P.T @ S @ P
     return M, P, S, Sinv
 
 

@@ -43,13 +43,38 @@ def _compile(src: str) -> str:
     return obj
 
 
+def hip_runtime() -> list[str]:
+    """Link arguments for the HIP runtime.
+
+    Inside a PyTorch-ROCm installation the library links the runtime that PyTorch ships, so
+    that one process holds a single HIP runtime (shared default stream, valid torch stream
+    handles, ordered with torch's work). Without PyTorch (or with HSOLVE_HIP_RUNTIME=rocm)
+    it links /opt/rocm's runtime.
+    """
+    if os.environ.get("HSOLVE_HIP_RUNTIME", "torch") == "torch":
+        try:
+            import importlib.util
+            spec = importlib.util.find_spec("torch")
+            if spec and spec.origin:
+                tlib = os.path.join(os.path.dirname(spec.origin), "lib")
+                rt = os.path.join(tlib, "libamdhip64.so")
+                if os.path.exists(rt):
+                    return [rt, f"-Wl,-rpath,{tlib}"]
+        except Exception:
+            pass
+    return ["-L/opt/rocm/lib", "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"]
+
+
 def build(verbose: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     srcs = sources()
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
         objs = list(ex.map(_compile, srcs))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", "-o", tmp, *objs]
+    clang = os.path.join(os.path.dirname(os.path.realpath(HIPCC)), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = "/opt/rocm/llvm/bin/clang++"
+    cmd = [clang, "-shared", "-fPIC", "-o", tmp, *objs, *hip_runtime()]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")

@@ -33,8 +33,15 @@ hsolve_status guard(hsolve_plan plan, const char* where, void (*fn)(void*), void
     }
 }
 
+struct ProfBind {             // make the plan's profiler visible to the launch wrappers
+    explicit ProfBind(hsolve_plan plan) : prev(hs::t_prof) { hs::t_prof = plan ? &plan->P.prof : nullptr; }
+    ~ProfBind() { hs::t_prof = prev; }
+    hs::Profiler* prev;
+};
+
 template <class F>
 hsolve_status run(hsolve_plan plan, const char* where, F&& f) {
+    ProfBind bind(plan);
     return guard(plan, where, [](void* a) { (*static_cast<F*>(a))(); }, &f);
 }
 
@@ -203,7 +210,42 @@ const char* hsolve_status_string(hsolve_status s) {
     return "HSOLVE_UNKNOWN_STATUS";
 }
 
+hsolve_status hsolve_profile_begin(hsolve_plan plan) {
+    if (!plan) return HSOLVE_ERR_INVALID;
+    plan->P.prof.clear();
+    plan->P.prof_totals.clear();
+    plan->P.prof.on = true;
+    return HSOLVE_OK;
+}
+
+hsolve_status hsolve_profile_end(hsolve_plan plan, int32_t* nkernels) {
+    if (!plan) return HSOLVE_ERR_INVALID;
+    plan->P.prof.on = false;
+    hsolve_status st = run(plan, "profile_end", [&] { plan->P.prof_totals = plan->P.prof.totals(); });
+    plan->P.prof.clear();
+    if (nkernels) *nkernels = int32_t(plan->P.prof_totals.size());
+    return st;
+}
+
+hsolve_status hsolve_profile_entry(hsolve_plan plan, int i, char* name, int cap, double* ms,
+                                   int64_t* launches, double* work) {
+    if (!plan || i < 0 || i >= int(plan->P.prof_totals.size())) return HSOLVE_ERR_INVALID;
+    const hs::ProfTotal& t = plan->P.prof_totals[i];
+    if (name && cap > 0) {
+        std::strncpy(name, t.name.c_str(), size_t(cap) - 1);
+        name[cap - 1] = 0;
+    }
+    if (ms) *ms = t.ms;
+    if (launches) *launches = t.launches;
+    if (work) *work = t.work;
+    return HSOLVE_OK;
+}
+
 int hsolve_depth(hsolve_plan plan) { return plan ? plan->P.L : -1; }
+
+const char* hsolve_last_error(hsolve_plan plan) {
+    return plan ? plan->last_error.c_str() : "";
+}
 
 hsolve_status hsolve_leaf_order(hsolve_plan plan, int32_t* perm, int32_t* leaf_off) {
     if (!plan) return HSOLVE_ERR_INVALID;
@@ -235,6 +277,25 @@ hsolve_status hsolve_node_sets(hsolve_plan plan, int depth, int node, int32_t* n
     for (size_t i = 0; ws && i < S.W[node].size() && int(i) < cap; ++i)
         ws[i] = 2 * S.W[node][i] + S.Wred[node][i];
     return HSOLVE_OK;
+}
+
+hsolve_status hsolve_node_factor(hsolve_plan plan, int depth, int node, int32_t* dims,
+                                 double* G, int64_t cap) {
+    if (!plan || !dims || depth < 0 || depth >= int(plan->P.sym.size())) return HSOLVE_ERR_INVALID;
+    const Plan& P = plan->P;
+    if (!P.factored) return HSOLVE_ERR_STATE;
+    const hs::LevelNum& LN = P.num[depth];
+    if (node < 0 || node >= int(LN.node.size())) return HSOLVE_ERR_INVALID;
+    const hs::NodeNum& nn = LN.node[node];
+    dims[0] = nn.m;
+    dims[1] = nn.ntot;
+    dims[2] = nn.k;
+    const int64_t count = int64_t(nn.ldG) * nn.m;
+    if (!G || !nn.Gm || count == 0) return HSOLVE_OK;
+    if (cap < count) return HSOLVE_ERR_INVALID;
+    return run(plan, "node_factor", [&] {
+        HS_HIP(hipMemcpy(G, nn.Gm, sizeof(double) * count, hipMemcpyDeviceToHost));
+    });
 }
 
 hsolve_status hsolve_ranks(hsolve_plan plan, int depth, int32_t* ranks) {

@@ -66,16 +66,21 @@ struct Batch {
     }
     void flush_copies(Plan& P) {
         if (copies.empty()) return;
+        double bytes = 0.0;
+        for (const CopyTask& c : copies) bytes += 16.0 * c.rows * c.cols;
         CopyTask* d = P.stage.upload_vec(copies, P.spool, P.stream);
-        launch_copy(d, int(copies.size()), P.stream);
+        launch_copy(d, int(copies.size()), bytes, P.stream);
         copies.clear();
     }
     void flush_gemm(Plan& P) {
         if (!tiles.empty()) {
+            double flops = 0.0;
+            for (const GemmTask& t : gt)
+                for (int q = t.t_begin; q < t.t_end; ++q) flops += 2.0 * t.M * t.N * terms[q].K;
             GemmTask* dt = P.stage.upload_vec(gt, P.spool, P.stream);
             GemmTerm* dterm = P.stage.upload_vec(terms, P.spool, P.stream);
             GemmTile* dtile = P.stage.upload_vec(tiles, P.spool, P.stream);
-            launch_gemm(dt, dterm, dtile, int(tiles.size()), P.stream);
+            launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, P.stream);
         }
         gt.clear();
         terms.clear();
@@ -83,8 +88,10 @@ struct Batch {
     }
     void flush_chol(Plan& P, int* d_fail) {
         if (chol.empty()) return;
+        double flops = 0.0;
+        for (const CholTask& c : chol) flops += double(c.m) * c.m * c.m;   // potrf + inverse
         CholTask* d = P.stage.upload_vec(chol, P.spool, P.stream);
-        launch_chol_inv(d, int(chol.size()), d_fail, P.stream);
+        launch_chol_inv(d, int(chol.size()), d_fail, flops, P.stream);
         chol.clear();
     }
 };
@@ -310,9 +317,16 @@ void factor(Plan& P, const double* d_values_in) {
             int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
             B.flush_copies(P);
             B.flush_gemm(P);
-            if (!ctasks.empty())
+            if (!ctasks.empty()) {
+                // tridiagonalisation 4/3 m^3 (twice for GC) + QL with vectors ~6 m^3
+                double cflops = 0.0;
+                for (const CompressTask& ct : ctasks) {
+                    const double m3 = double(ct.m) * ct.m * ct.m;
+                    cflops += (gc ? 8.0 / 3.0 : 4.0 / 3.0) * m3 + 6.0 * m3;
+                }
                 launch_compress(P.stage.upload_vec(ctasks, P.spool, st), int(ctasks.size()),
-                                P.opt.variant, eps, d_rank, st);
+                                P.opt.variant, eps, d_rank, cflops, st);
+            }
             HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
             if (!comp.empty())
                 HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size(),
@@ -328,7 +342,10 @@ void factor(Plan& P, const double* d_values_in) {
             for (const CompNode& cn : comp) {
                 const int k = h_flags[nd + cn.slot];
                 if (k < 0 || k > LN.msz[cn.s])
-                    throw Error{HSOLVE_ERR_DEVICE, "eigen-solver did not converge"};
+                    throw Error{HSOLVE_ERR_DEVICE,
+                                "eigen-solver did not converge (level " + std::to_string(d) + ", node " +
+                                    std::to_string(cn.s) + ", m " + std::to_string(LN.msz[cn.s]) +
+                                    ", |W| " + std::to_string(cn.wt) + ", k " + std::to_string(k) + ")"};
                 LN.ksz[cn.s] = k;
                 max_rank = std::max(max_rank, k);
             }
@@ -407,11 +424,16 @@ void factor(Plan& P, const double* d_values_in) {
                 flops += 2.0 * nn.k * nn.k * nn.m;
             }
             B.flush_gemm(P);
-            // M_ss = A_ss^-1 - Y P_ss
+            // M_ss = A_ss^-1 - Y P_ss; exactly zero when U is square (Appendix A)
             for (size_t q = 0; q < nodes.size(); ++q) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
+                if (nn.k == nn.m) {
+                    B.open(nn.Gm, nn.ldG, nn.m, nn.m, 0.0, 0.0);
+                    B.close();
+                    continue;
+                }
                 B.gemm(nn.Gm, nn.ldG, nn.m, nn.m, -1.0, 1.0, Ysc[q], nn.m, 0, nn.Gm + nn.m + nn.ntot,
                        nn.ldG, 0, nn.k);
                 flops += 2.0 * nn.m * nn.m * nn.k;

@@ -72,6 +72,48 @@ private:
 };
 
 // ---------------------------------------------------------------------------------
+// Optional per-kernel timing: HIP events recorded on the launch stream around every
+// launch while a profile is active on the calling thread
+// ---------------------------------------------------------------------------------
+struct ProfRec {
+    const char* name;
+    double work;             // algorithmic flops (compute kernels) or bytes (memory kernels)
+    hipEvent_t a, b;
+};
+
+struct ProfTotal {
+    std::string name;
+    double ms = 0.0, work = 0.0;
+    int64_t launches = 0;
+};
+
+class Profiler {
+public:
+    ~Profiler();
+    bool on = false;
+    void clear();
+    void record(const char* name, double work, hipEvent_t a, hipEvent_t b);
+    hipEvent_t event();
+    std::vector<ProfTotal> totals();   // synchronises; aggregates by kernel name
+
+private:
+    std::vector<ProfRec> recs_;
+    std::vector<hipEvent_t> pool_;
+    size_t used_ = 0;
+};
+
+extern thread_local Profiler* t_prof;
+
+struct ProfScope {           // brackets one launch
+    ProfScope(const char* name, double work, hipStream_t s);
+    ~ProfScope();
+    const char* name;
+    double work;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+};
+
+// ---------------------------------------------------------------------------------
 // Symbolic schedule of one level (depth d): super nodes are the 2^d clusters of depth d
 // ---------------------------------------------------------------------------------
 struct LevelSym {
@@ -215,6 +257,7 @@ struct Plan {
 
     // apply schedule (device), per level and colour
     struct ColourSched {
+        double fwd_bytes = 0.0, bwd_bytes = 0.0;   // algorithmic bytes per rhs
         FwdTarget* fwd_t = nullptr; int nfwd = 0; int max_len = 0;
         FwdContrib* fwd_c = nullptr;
         BwdNode* bwd_n = nullptr; int nbwd = 0;
@@ -229,6 +272,8 @@ struct Plan {
     int krylov_cols = 0;
 
     hsolve_stats stats{};
+    Profiler prof;
+    std::vector<ProfTotal> prof_totals;
     ~Plan();
 };
 
@@ -245,27 +290,28 @@ int pcg(Plan& P, const double* b, double* x, double tol, int max_iter, double* r
 void spmv(Plan& P, const double* x, double* y);
 
 // kernels.hip: launch wrappers (all asynchronous on stream s)
-void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s);
+void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t s);
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, hipStream_t s);
-void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, hipStream_t s);
+                 int ntiles, double flops, hipStream_t s);
+void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops,
+                     hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, hipStream_t s);
+                     int* d_rank, double flops, hipStream_t s);
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const int32_t* iperm, const int32_t* pos_super,
                          const int32_t* super_first, double* const* blk_ptr,
                          const int32_t* blk_ld, const int32_t* blk_col,
                          const int32_t* blk_begin, int n, hipStream_t s);
 void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, double* V, int64_t ldv,
-                int nrhs, hipStream_t s);
+                int nrhs, double bytes, hipStream_t s);
 void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, double* V, int64_t ldv,
-                int nrhs, int max_rows, hipStream_t s);
+                int nrhs, int max_rows, double bytes, hipStream_t s);
 void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, const int32_t* perm,
                         int n, int nrhs, hipStream_t s);   // dst[p] = src[perm[p]]
 void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
                          const int32_t* perm, int n, int nrhs, hipStream_t s); // dst[perm[p]] = src[p]
 void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
-                 const double* x, double* y, int n, hipStream_t s);
+                 const double* x, double* y, int n, int64_t nnz, hipStream_t s);
 void launch_dot2(const double* a, const double* b, const double* c, const double* d, int n,
                  double* out, hipStream_t s);   // out[0] = a.b, out[1] = c.d
 void launch_axpy2(double* x, const double* p, double* r, const double* q, const double* alpha,

@@ -15,6 +15,12 @@
 namespace hs {
 
 constexpr int NT = 256;          // threads per workgroup (4 waves)
+
+static void check_launch(const char* name) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        throw Error{HSOLVE_ERR_DEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e)};
+}
 constexpr int WAVE = 64;
 
 __device__ inline double wave_sum(double v) {
@@ -63,9 +69,11 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
         }
 }
 
-void launch_copy(const CopyTask* d_tasks, int ntasks, hipStream_t s) {
+void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t s) {
     if (ntasks <= 0) return;
+    ProfScope ps("k_copy", bytes, s);
     hipLaunchKernelGGL(k_copy, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+    check_launch("k_copy");
 }
 
 // ---------------------------------------------------------------------------------
@@ -137,9 +145,11 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
 }
 
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, hipStream_t s) {
+                 int ntiles, double flops, hipStream_t s) {
     if (ntiles <= 0) return;
+    ProfScope ps("k_gemm", flops, s);
     hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles);
+    check_launch("k_gemm");
 }
 
 // ---------------------------------------------------------------------------------
@@ -191,9 +201,12 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     }
 }
 
-void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, hipStream_t s) {
+void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops,
+                     hipStream_t s) {
     if (ntasks <= 0) return;
+    ProfScope ps("k_chol_inv", flops, s);
     hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(NT), 0, s, d_tasks, d_fail);
+    check_launch("k_chol_inv");
 }
 
 // ---------------------------------------------------------------------------------
@@ -341,16 +354,23 @@ __device__ bool ql_implicit(int nn, double* Z, int ldz, EigShared& S) {
     const int tid = threadIdx.x;
     for (int c = 0; c < nn; ++c)
         for (int i = tid; i < nn; i += NT) Z[i + size_t(c) * ldz] = (i == c) ? 1.0 : 0.0;
+    // Deflate against the norm of the whole tridiagonal (eigenvalues are needed to an
+    // absolute accuracy relative to the largest one): clusters of numerically zero
+    // eigenvalues then split at once instead of iterating on rounding noise.
+    if (tid == 0) {
+        double tn = 0.0;
+        for (int i = 0; i < nn; ++i) tn = fmax(tn, fabs(S.d[i]) + fabs(S.e[i]));
+        S.scal[3] = tn;
+    }
     __syncthreads();
+    const double tnorm = S.scal[3];
     for (int l = 0; l < nn; ++l) {
         for (int iter = 0;; ++iter) {
             // S.iscal: [0] = m (deflation point), [1] = lowest rotation index, [2] = status
             if (tid == 0) {
                 int m = l;
-                for (; m < nn - 1; ++m) {
-                    const double dd = fabs(S.d[m]) + fabs(S.d[m + 1]);
-                    if (fabs(S.e[m]) <= DBL_EPSILON * dd) break;
-                }
+                for (; m < nn - 1; ++m)
+                    if (fabs(S.e[m]) <= DBL_EPSILON * tnorm) break;
                 S.iscal[0] = m;
                 S.iscal[2] = 0;
                 if (m != l) {
@@ -449,7 +469,16 @@ __global__ __launch_bounds__(NT) void k_compress(const CompressTask* tasks, int 
     double* gct = gcv + size_t(16) * m;            // their tau
     double* U = T.U;
 
-    for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i];
+    // scale G by its largest entry (eigenvectors unchanged, decisions are relative)
+    double gmax = 0.0;
+    for (size_t i = tid; i < size_t(m) * m; i += NT) gmax = fmax(gmax, fabs(T.G[i]));
+    for (int o = WAVE / 2; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o, WAVE));
+    if (lane == 0) S.red[wv] = gmax;
+    __syncthreads();
+    gmax = fmax(fmax(S.red[0], S.red[1]), fmax(S.red[2], S.red[3]));
+    __syncthreads();
+    const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
+    for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i] * gscale;
     __syncthreads();
 
     int q = 0;
@@ -491,7 +520,7 @@ __global__ __launch_bounds__(NT) void k_compress(const CompressTask* tasks, int 
         }
         // Householder reflectors W = H_{q-1}..H_0 with W U1 = [R; 0]; the complement of U1
         // is W^T [0; I]. Project G there: G' = (W G W^T)(q:, q:)
-        for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i];
+        for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i] * gscale;
         for (int t = 0; t < q; ++t) {
             // x = (H_{t-1}..H_0 u_t)(t..m-1); stored temporarily in Zq column 0
             double* x = Zq;
@@ -533,7 +562,7 @@ __global__ __launch_bounds__(NT) void k_compress(const CompressTask* tasks, int 
     const int nn = m - q;
     // select the leading eigenvalues of the (projected) Gram matrix
     const int cap = min(nn, T.wt);
-    const double thr = eps * eps * lam_max;
+    const double thr = eps * eps * fmax(lam_max, 0.0);   // zero G: nothing passes
     // descending order (NaN last), ties by index: a permutation whatever the values
     for (int j = tid; j < nn; j += NT) {
         int r = 0;
@@ -575,10 +604,12 @@ __global__ __launch_bounds__(NT) void k_compress(const CompressTask* tasks, int 
 }
 
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, hipStream_t s) {
+                     int* d_rank, double flops, hipStream_t s) {
     if (ntasks <= 0) return;
+    ProfScope ps("k_compress", flops, s);
     hipLaunchKernelGGL(k_compress, dim3(ntasks), dim3(NT), sizeof(EigShared), s, d_tasks,
                        variant, eps, d_rank);
+    check_launch("k_compress");
 }
 
 // ---------------------------------------------------------------------------------
@@ -613,6 +644,7 @@ void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const d
     hipLaunchKernelGGL(k_leaf_scatter, dim3((n + NT - 1) / NT), dim3(NT), 0, s, row_ptr,
                        col_idx, vals, iperm, pos_super, super_first, blk_ptr, blk_ld, blk_col,
                        blk_begin, n);
+    check_launch("k_leaf_scatter");
 }
 
 // ---------------------------------------------------------------------------------
@@ -649,9 +681,11 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
 }
 
 void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, double* V, int64_t ldv,
-                int nrhs, hipStream_t s) {
+                int nrhs, double bytes, hipStream_t s) {
     if (nt <= 0) return;
+    ProfScope ps("k_fwd", bytes, s);
     hipLaunchKernelGGL(k_fwd, dim3(nt), dim3(NT), 0, s, t, c, V, ldv, nrhs);
+    check_launch("k_fwd");
 }
 
 constexpr int BWD_MAX_ROWS = 6144;
@@ -682,10 +716,12 @@ __global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* 
 }
 
 void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, double* V, int64_t ldv,
-                int nrhs, int max_rows, hipStream_t s) {
+                int nrhs, int max_rows, double bytes, hipStream_t s) {
     if (nn <= 0) return;
+    ProfScope ps("k_bwd", bytes, s);
     if (max_rows > BWD_MAX_ROWS) throw Error{HSOLVE_ERR_INVALID, "factor block too tall for k_bwd"};
     hipLaunchKernelGGL(k_bwd, dim3(nn), dim3(NT), 0, s, nodes, segs, V, ldv, nrhs);
+    check_launch("k_bwd");
 }
 
 // ---------------------------------------------------------------------------------
@@ -703,6 +739,7 @@ void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, co
                         int n, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(k_gather_perm, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
                        ldd, perm, n, nrhs);
+    check_launch("k_gather_perm");
 }
 
 __global__ void k_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
@@ -717,6 +754,7 @@ void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
                          const int32_t* perm, int n, int nrhs, hipStream_t s) {
     hipLaunchKernelGGL(k_scatter_perm, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
                        ldd, perm, n, nrhs);
+    check_launch("k_scatter_perm");
 }
 
 __global__ void k_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
@@ -729,9 +767,12 @@ __global__ void k_spmv(const int64_t* row_ptr, const int32_t* col_idx, const dou
 }
 
 void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
-                 const double* x, double* y, int n, hipStream_t s) {
+                 const double* x, double* y, int n, int64_t nnz, hipStream_t s) {
+    // values + column indices + row pointers + x once + y once
+    ProfScope ps("k_spmv", 12.0 * nnz + 8.0 * (n + 1) + 16.0 * n, s);
     hipLaunchKernelGGL(k_spmv, dim3((n + NT - 1) / NT), dim3(NT), 0, s, row_ptr, col_idx, vals,
                        x, y, n);
+    check_launch("k_spmv");
 }
 
 constexpr int DOT_BLOCKS = 512;
@@ -774,7 +815,9 @@ void launch_dot2(const double* a, const double* b, const double* c, const double
     int nb = (n + NT - 1) / NT;
     nb = nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
     hipLaunchKernelGGL(k_dot2_part, dim3(nb), dim3(NT), 0, s, a, b, c, d, n, out + 2);
+    check_launch("k_dot2_part");
     hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(NT), 0, s, out + 2, nb, out);
+    check_launch("k_dot2_final");
 }
 
 __global__ void k_axpy2(double* x, const double* p, double* r, const double* q,
@@ -789,6 +832,7 @@ __global__ void k_axpy2(double* x, const double* p, double* r, const double* q,
 void launch_axpy2(double* x, const double* p, double* r, const double* q, const double* alpha,
                   int n, hipStream_t s) {
     hipLaunchKernelGGL(k_axpy2, dim3((n + NT - 1) / NT), dim3(NT), 0, s, x, p, r, q, alpha, n);
+    check_launch("k_axpy2");
 }
 
 __global__ void k_xpby(double* p, const double* z, const double* ratio, int n) {
@@ -799,6 +843,7 @@ __global__ void k_xpby(double* p, const double* z, const double* ratio, int n) {
 
 void launch_xpby(double* p, const double* z, const double* beta, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_xpby, dim3((n + NT - 1) / NT), dim3(NT), 0, s, p, z, beta, n);
+    check_launch("k_xpby");
 }
 
 __global__ void k_fill(double* p, double v, int64_t n) {
@@ -812,6 +857,7 @@ void launch_fill(double* p, double v, int64_t n, hipStream_t s) {
     int64_t nb = (n + NT - 1) / NT;
     if (nb > 4096) nb = 4096;
     hipLaunchKernelGGL(k_fill, dim3(unsigned(nb)), dim3(NT), 0, s, p, v, n);
+    check_launch("k_fill");
 }
 
 }  // namespace hs

@@ -98,6 +98,63 @@ void upload_pattern(Plan& P) {
     HS_HIP(hipMemcpy(P.d_pos_super, pos_super.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice));
 }
 
+thread_local Profiler* t_prof = nullptr;
+
+Profiler::~Profiler() {
+    for (hipEvent_t e : pool_) (void)hipEventDestroy(e);
+}
+
+void Profiler::clear() {
+    recs_.clear();
+    used_ = 0;
+}
+
+hipEvent_t Profiler::event() {
+    if (used_ == pool_.size()) {
+        hipEvent_t e;
+        HS_HIP(hipEventCreate(&e));
+        pool_.push_back(e);
+    }
+    return pool_[used_++];
+}
+
+void Profiler::record(const char* name, double work, hipEvent_t a, hipEvent_t b) {
+    recs_.push_back(ProfRec{name, work, a, b});
+}
+
+std::vector<ProfTotal> Profiler::totals() {
+    HS_HIP(hipDeviceSynchronize());
+    std::vector<ProfTotal> out;
+    for (const ProfRec& r : recs_) {
+        float ms = 0.f;
+        HS_HIP(hipEventElapsedTime(&ms, r.a, r.b));
+        ProfTotal* t = nullptr;
+        for (auto& x : out)
+            if (x.name == r.name) t = &x;
+        if (!t) {
+            out.push_back(ProfTotal{r.name});
+            t = &out.back();
+        }
+        t->ms += ms;
+        t->work += r.work;
+        t->launches += 1;
+    }
+    return out;
+}
+
+ProfScope::ProfScope(const char* n, double w, hipStream_t st) : name(n), work(w), s(st) {
+    if (t_prof && t_prof->on) {
+        a = t_prof->event();
+        HS_HIP(hipEventRecord(a, s));
+    }
+}
+
+ProfScope::~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = t_prof->event();
+    if (hipEventRecord(b, s) == hipSuccess) t_prof->record(name, work, a, b);
+}
+
 Plan::~Plan() {
     if (d_row_ptr) (void)hipFree(d_row_ptr);
     if (d_col_idx) (void)hipFree(d_col_idx);

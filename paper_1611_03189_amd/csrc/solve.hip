@@ -95,6 +95,11 @@ void build_apply_schedule(Plan& P) {
                 max_len = std::max(max_len, t.len);
             }
             Plan::ColourSched& cs = P.sched[d][c];
+            for (int s : S.colours[c]) {
+                const NodeNum& nn = LN.node[s];
+                cs.fwd_bytes += 8.0 * (double(nn.ntot + nn.k) * nn.m + nn.m + 2.0 * (nn.ntot + nn.k));
+                cs.bwd_bytes += 8.0 * (double(nn.ldG) * nn.m + nn.ldG + nn.m);
+            }
             cs.nfwd = int(ft.size());
             cs.max_len = max_len;
             cs.fwd_t = P.stage.upload_vec(ft, P.apool, st);
@@ -131,18 +136,18 @@ void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
     for (int d = nlev - 1; d >= 0; --d)
         for (size_t c = 0; c < P.sched[d].size(); ++c) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_fwd(cs.fwd_t, cs.fwd_c, cs.nfwd, P.d_V, ldv, nrhs, st);
+            launch_fwd(cs.fwd_t, cs.fwd_c, cs.nfwd, P.d_V, ldv, nrhs, cs.fwd_bytes * nrhs, st);
         }
     for (int d = 0; d < nlev; ++d)
         for (size_t c = P.sched[d].size(); c-- > 0;) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_bwd(cs.bwd_n, cs.bwd_s, cs.nbwd, P.d_V, ldv, nrhs, 6144, st);
+            launch_bwd(cs.bwd_n, cs.bwd_s, cs.nbwd, P.d_V, ldv, nrhs, 6144, cs.bwd_bytes * nrhs, st);
         }
     launch_scatter_perm(P.d_V, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
 }
 
 void spmv(Plan& P, const double* x, double* y) {
-    launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, x, y, P.n, P.stream);
+    launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, x, y, P.n, P.nnz, P.stream);
 }
 
 // PCG (Hestenes-Stiefel) with x0 = 0 for one column. Returns the iteration count and the

@@ -73,6 +73,10 @@ def load() -> ctypes.CDLL:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_1611_03189_amd.build`")
+    try:        # the library links the HIP runtime PyTorch ships: load that copy first
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = c_void_p
     sig = {
@@ -86,11 +90,17 @@ def load() -> ctypes.CDLL:
         "hsolve_destroy": (c_int, [P]),
         "hsolve_status_string": (ctypes.c_char_p, [c_int]),
         "hsolve_depth": (c_int, [P]),
+        "hsolve_last_error": (ctypes.c_char_p, [P]),
         "hsolve_leaf_order": (c_int, [P, POINTER(c_int32), POINTER(c_int32)]),
         "hsolve_level_colours": (c_int, [P, c_int, POINTER(c_int32), POINTER(c_int32)]),
         "hsolve_node_sets": (c_int, [P, c_int, c_int, POINTER(c_int32), POINTER(c_int32),
                                      POINTER(c_int32), POINTER(c_int32), c_int]),
         "hsolve_ranks": (c_int, [P, c_int, POINTER(c_int32)]),
+        "hsolve_node_factor": (c_int, [P, c_int, c_int, POINTER(c_int32), POINTER(c_double), c_int64]),
+        "hsolve_profile_begin": (c_int, [P]),
+        "hsolve_profile_end": (c_int, [P, POINTER(c_int32)]),
+        "hsolve_profile_entry": (c_int, [P, c_int, ctypes.c_char_p, c_int, POINTER(c_double),
+                                         POINTER(c_int64), POINTER(c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -100,12 +110,16 @@ def load() -> ctypes.CDLL:
     return lib
 
 
-def _check(status: int, where: str):
+def _check(status: int, where: str, lib=None, handle=None):
+    if status in (0, 1):
+        return status
+    if lib is not None and handle:
+        msg = lib.hsolve_last_error(handle)
+        if msg:
+            where = f"{where} ({msg.decode()})"
     if status == -3:
         raise NotSPD(status, where)
-    if status not in (0, 1):
-        raise HSolveError(status, where)
-    return status
+    raise HSolveError(status, where)
 
 
 def _i32p(a):
@@ -190,7 +204,8 @@ class HSolver:
         import torch
         v = _dev(values, torch)
         self.values = v
-        _check(self._lib.hsolve_factor(self._h, c_void_p(v.data_ptr())), "hsolve_factor")
+        _check(self._lib.hsolve_factor(self._h, c_void_p(v.data_ptr())), "hsolve_factor",
+               self._lib, self._h)
         return self
 
     def apply(self, r, out=None):
@@ -202,7 +217,8 @@ class HSolver:
         Rc = R.t().contiguous()
         Z = torch.empty_like(Rc) if out is None else out
         _check(self._lib.hsolve_apply(self._h, Rc.shape[0], c_void_p(Rc.data_ptr()), self.n,
-                                      c_void_p(Z.data_ptr()), self.n), "hsolve_apply")
+                                      c_void_p(Z.data_ptr()), self.n), "hsolve_apply",
+               self._lib, self._h)
         Z = Z.t()
         return Z.reshape(-1) if vec else Z
 
@@ -216,7 +232,7 @@ class HSolver:
         st = Stats()
         status = _check(self._lib.hsolve_solve(self._h, Bc.shape[0], c_void_p(Bc.data_ptr()), self.n,
                                                c_void_p(X.data_ptr()), self.n, ctypes.byref(st)),
-                        "hsolve_solve")
+                        "hsolve_solve", self._lib, self._h)
         X = X.t()
         d = st.as_dict()
         d["converged"] = status == 0
@@ -229,6 +245,26 @@ class HSolver:
         _check(self._lib.hsolve_spmv(self._h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr())),
                "hsolve_spmv")
         return y
+
+    # -- kernel timing ---------------------------------------------------------------
+    def profile_begin(self):
+        _check(self._lib.hsolve_profile_begin(self._h), "hsolve_profile_begin")
+
+    def profile_end(self) -> list[dict]:
+        """Per-kernel totals since profile_begin: name, ms, launches, work (flops or bytes)."""
+        nk = c_int32()
+        _check(self._lib.hsolve_profile_end(self._h, ctypes.byref(nk)), "hsolve_profile_end",
+               self._lib, self._h)
+        out = []
+        for i in range(nk.value):
+            name = ctypes.create_string_buffer(64)
+            ms, work, launches = c_double(), c_double(), c_int64()
+            _check(self._lib.hsolve_profile_entry(self._h, i, name, 64, ctypes.byref(ms),
+                                                  ctypes.byref(launches), ctypes.byref(work)),
+                   "hsolve_profile_entry")
+            out.append(dict(name=name.value.decode(), ms=ms.value, launches=launches.value,
+                            work=work.value))
+        return out
 
     # -- introspection -------------------------------------------------------------
     def stats(self) -> dict:
@@ -261,6 +297,21 @@ class HSolver:
         _check(self._lib.hsolve_node_sets(self._h, depth, node, _i32p(nb), ctypes.byref(nn),
                                           _i32p(ws), ctypes.byref(nw), cap), "hsolve_node_sets")
         return nb[:nn.value].copy(), ws[:nw.value].copy()
+
+    def node_factor(self, depth: int, node: int):
+        """(M_ss, A_Ns M_ss, P_ss) of one eliminated super node, copied to the host."""
+        dims = np.zeros(3, dtype=np.int32)
+        _check(self._lib.hsolve_node_factor(self._h, depth, node, _i32p(dims), None, 0),
+               "hsolve_node_factor", self._lib, self._h)
+        m, ntot, k = (int(x) for x in dims)
+        if m == 0:
+            return None
+        G = np.zeros((m + ntot + k) * m)
+        _check(self._lib.hsolve_node_factor(self._h, depth, node, _i32p(dims),
+                                            G.ctypes.data_as(POINTER(c_double)), G.size),
+               "hsolve_node_factor", self._lib, self._h)
+        G = G.reshape(m, m + ntot + k).T
+        return G[:m], G[m:m + ntot], G[m + ntot:]
 
     def ranks(self, depth: int):
         out = np.empty(1 << depth, dtype=np.int32)
