@@ -1,0 +1,578 @@
+// Compression of the well-separated block of one super node (§3.2 eq. local_compression /
+// compression_sw; §6 eq. compression_xy / preserve), one workgroup per node.
+//
+// Input: the Gram matrix G = A_sw A_sw^T (m x m). Its eigenvectors are the left singular
+// vectors of A_sw and its eigenvalues their squares, so "sigma_j > eps sigma_1" becomes
+// "lambda_j > eps^2 lambda_max".
+//   LoRaSp: U = eigenvectors of G with lambda > eps^2 lambda_max.
+//   GC:     U1 = orthonormal basis of [phi_s, A_sw phi_w] (modified Gram-Schmidt, twice);
+//           Householder reflectors W with W U1 = [R; 0] give the complement of U1; U2 =
+//           eigenvectors of the projected Gram matrix (W G W^T)(q:, q:) with
+//           lambda > eps^2 lambda_max(G), mapped back by W^T; U = [U1, U2].
+// Eigen-solver, three kernels per batch of nodes:
+//   k_comp_reduce  (one workgroup per node) scale G by its largest entry (decisions are
+//                  relative), Householder tridiagonalisation (in LDS when m <= CMP_LDS_MAX),
+//                  lambda_max by parallel multisection, GC basis and projection, second
+//                  tridiagonalisation, number k2 of kept eigenvalues (Sturm count);
+//   k_comp_bisect  (many workgroups) each kept eigenvalue by bisection to eps ||T||;
+//   k_comp_vectors (many workgroups, one wave per cluster of eigenvalues closer than
+//                  1e-7 ||T||) inverse iteration in LDS, members orthogonalised against
+//                  each other, then back-transformation with the vector held in registers.
+#include <cfloat>
+
+#include "hs_device.h"
+
+namespace hs {
+
+constexpr int CMP_LDS_MAX = 128;
+constexpr int CMP_MAX = 512;            // largest super node the compression accepts
+constexpr int CMP_RMAX = CMP_MAX / WAVE;   // vector entries per lane in the back-transform
+
+// Per-node global work layout (doubles): reflectors H (m x m, ld m) | d, e, tau, lam (4m) |
+// GC reflectors (16 m) + their tau (16) | info (8).
+struct CmpWork {
+    double *H, *d, *e, *tau, *lam, *gcv, *gct, *info;
+    __device__ CmpWork(double* w, int m) {
+        H = w;
+        d = w + size_t(m) * m;
+        e = d + m;
+        tau = e + m;
+        lam = tau + m;
+        gcv = lam + m;
+        gct = gcv + size_t(16) * m;
+        info = gct + 16;
+    }
+};
+enum { INF_Q, INF_K2, INF_NN, INF_TNORM, INF_PIVMIN, INF_LO, INF_HI, INF_DONE };
+
+template <int MAXN>
+struct CmpShared {
+    double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN], lam[MAXN];
+    int clus[MAXN];
+    double red[NT / WAVE];
+    double scal[4];
+    int iscal[4];
+    int pts[NT + 1];
+};
+
+// sum_l A(0, l) x[l] for the row starting at A (column stride ld), eight loads in flight
+__device__ inline double dot_rows(const double* A, int ld, const double* x, int len) {
+    double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    int l = 0;
+    for (; l + 8 <= len; l += 8) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) a[u] += A[size_t(l + u) * ld] * x[l + u];
+    }
+    for (; l < len; ++l) a[0] += A[size_t(l) * ld] * x[l];
+    return ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+}
+
+// A(0, l) -= vi w[l] + wi v[l] along one row (column stride ld)
+__device__ inline void rank2_row(double* A, int ld, double vi, double wi, const double* v,
+                                 const double* w, int len) {
+    int l = 0;
+    for (; l + 8 <= len; l += 8) {
+        double t[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) t[u] = A[size_t(l + u) * ld];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) A[size_t(l + u) * ld] = t[u] - (vi * w[l + u] + wi * v[l + u]);
+    }
+    for (; l < len; ++l) A[size_t(l) * ld] -= vi * w[l] + wi * v[l];
+}
+
+// Householder tridiagonalisation of the symmetric nn x nn matrix H (column-major, ld):
+// reflector j acts on rows j+1.., its vector (first entry 1, implicit) is kept in
+// H(j+2.., j) with tau[j]; diagonal -> d, sub-diagonal -> e (e[nn-1] = 0).
+template <class SH>
+__device__ void tridiagonalize(double* H, int ld, int nn, SH& S) {
+    const int tid = threadIdx.x;
+    for (int j = 0; j + 2 < nn; ++j) {
+        double* col = H + size_t(j) * ld;
+        double part = 0.0;
+        for (int i = j + 2 + tid; i < nn; i += NT) part += col[i] * col[i];
+        const double xn2 = block_sum(part, S.red);
+        const double alpha = col[j + 1];
+        double tau = 0.0, beta = alpha;
+        if (xn2 > 0.0) {
+            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+            tau = (beta - alpha) / beta;
+            const double scal = 1.0 / (alpha - beta);
+            for (int i = j + 2 + tid; i < nn; i += NT) col[i] *= scal;
+        }
+        __syncthreads();
+        const int len = nn - j - 1;
+        for (int i = tid; i < len; i += NT) S.v[i] = (i == 0) ? 1.0 : (xn2 > 0.0 ? col[j + 1 + i] : 0.0);
+        if (tid == 0) {
+            S.tau[j] = tau;
+            S.e[j] = beta;
+        }
+        __syncthreads();
+        if (tau != 0.0) {
+            double* T22 = H + size_t(j + 1) * ld + (j + 1);
+            double pv_part = 0.0;
+            for (int i = tid; i < len; i += NT) {
+                const double acc = tau * dot_rows(T22 + i, ld, S.v, len);
+                S.w[i] = acc;
+                pv_part += acc * S.v[i];
+            }
+            const double K = 0.5 * tau * block_sum(pv_part, S.red);
+            for (int i = tid; i < len; i += NT) S.w[i] -= K * S.v[i];
+            __syncthreads();
+            for (int i = tid; i < len; i += NT) rank2_row(T22 + i, ld, S.v[i], S.w[i], S.v, S.w, len);
+            __syncthreads();
+        }
+    }
+    for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
+    if (tid == 0) {
+        if (nn >= 2) {
+            S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
+            S.tau[nn - 2] = 0.0;
+        }
+        S.e[nn - 1] = 0.0;
+        S.tau[nn - 1] = 0.0;
+    }
+    __syncthreads();
+}
+
+// x <- Q x with the reflectors left in H (one wave)
+__device__ void backtransform_wave(const double* H, int ld, int nn, const double* tau, double* x) {
+    const int lane = threadIdx.x % WAVE;
+    for (int j = nn - 3; j >= 0; --j) {
+        const double tj = tau[j];
+        if (tj == 0.0) continue;
+        const double* col = H + size_t(j) * ld;
+        double part = 0.0;
+        for (int i = j + 1 + lane; i < nn; i += WAVE) part += ((i == j + 1) ? 1.0 : col[i]) * x[i];
+        const double dot = wave_sum(part) * tj;
+        for (int i = j + 1 + lane; i < nn; i += WAVE) x[i] -= dot * ((i == j + 1) ? 1.0 : col[i]);
+    }
+}
+
+// number of eigenvalues of the tridiagonal (d, e) below x
+__device__ int sturm_count(const double* d, const double* e, int nn, double x, double pivmin) {
+    int cnt = 0;
+    double q = d[0] - x;
+    if (fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+    for (int i = 1; i < nn; ++i) {
+        q = d[i] - x - e[i - 1] * e[i - 1] / q;
+        if (fabs(q) < pivmin) q = -pivmin;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// Gershgorin interval, pivmin and norm of (S.d, S.e) into S.scal[0..3]
+template <class SH>
+__device__ void tridiag_bounds(int nn, SH& S) {
+    if (threadIdx.x == 0) {
+        double lo = S.d[0], hi = S.d[0], me = 0.0, tn = 0.0;
+        for (int i = 0; i < nn; ++i) {
+            const double r = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i + 1 < nn ? fabs(S.e[i]) : 0.0);
+            lo = fmin(lo, S.d[i] - r);
+            hi = fmax(hi, S.d[i] + r);
+            if (i + 1 < nn) me = fmax(me, S.e[i] * S.e[i]);
+            tn = fmax(tn, fabs(S.d[i]) + fabs(S.e[i]));
+        }
+        const double pad = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 1e-300;
+        S.scal[0] = lo - pad;
+        S.scal[1] = hi + pad;
+        S.scal[2] = fmax(1e-300, 1e-300 * me);
+        S.scal[3] = tn;
+    }
+    __syncthreads();
+}
+
+// largest eigenvalue by parallel multisection (after tridiag_bounds)
+template <class SH>
+__device__ double largest_eigenvalue(int nn, SH& S) {
+    const int tid = threadIdx.x;
+    double lo = S.scal[0], hi = S.scal[1];
+    const double pivmin = S.scal[2];
+    for (int round = 0; round < 10; ++round) {
+        const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
+        S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
+        __syncthreads();
+        int t = 0;
+        while (t < NT && !S.pts[t]) ++t;
+        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
+        const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
+        lo = xl;
+        hi = xh;
+        __syncthreads();
+    }
+    return 0.5 * (lo + hi);
+}
+
+// a-th smallest eigenvalue (0-based) by bisection to an absolute width of 2 eps ||T||
+__device__ double kth_eigenvalue(const double* d, const double* e, int nn, int a, double lo, double hi,
+                                 double pivmin, double tnorm) {
+    const double tol = 2.0 * DBL_EPSILON * fmax(tnorm, 1e-300);
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (!(hi - lo > tol) || mid == lo || mid == hi) break;
+        if (sturm_count(d, e, nn, mid, pivmin) > a) hi = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Solve (T - lambda I) y = y in place by Gaussian elimination with partial pivoting on the
+// tridiagonal; u0, u1, u2 hold the three diagonals of U. Pivots smaller than `tiny` are
+// raised to +-tiny (the shift may be an exact eigenvalue).
+__device__ void tridiag_shift_solve(const double* d, const double* e, int nn, double lambda,
+                                    double tiny, double* y, double* u0, double* u1, double* u2) {
+    double p0 = d[0] - lambda, p1 = nn > 1 ? e[0] : 0.0, p2 = 0.0;
+    for (int i = 0; i + 1 < nn; ++i) {
+        const double b = e[i];
+        const double a1 = d[i + 1] - lambda;
+        const double c1 = (i + 2 < nn) ? e[i + 1] : 0.0;
+        double np0, np1;
+        if (fabs(b) > fabs(p0) && fabs(b) >= tiny) {
+            const double mult = p0 / b;
+            u0[i] = b; u1[i] = a1; u2[i] = c1;
+            np0 = p1 - mult * a1;
+            np1 = p2 - mult * c1;
+            const double yi = y[i];
+            y[i] = y[i + 1];
+            y[i + 1] = yi - mult * y[i + 1];
+        } else {
+            if (fabs(p0) < tiny) p0 = (p0 < 0.0) ? -tiny : tiny;    // floor tiny pivots
+            const double mult = b / p0;
+            u0[i] = p0; u1[i] = p1; u2[i] = p2;
+            np0 = a1 - mult * p1;
+            np1 = c1 - mult * p2;
+            y[i + 1] -= mult * y[i];
+        }
+        p0 = np0;
+        p1 = np1;
+        p2 = 0.0;
+    }
+    u0[nn - 1] = (fabs(p0) < tiny) ? ((p0 < 0.0) ? -tiny : tiny) : p0;
+    y[nn - 1] /= u0[nn - 1];
+    if (nn >= 2) y[nn - 2] = (y[nn - 2] - u1[nn - 2] * y[nn - 1]) / u0[nn - 2];
+    for (int i = nn - 3; i >= 0; --i) y[i] = (y[i] - u1[i] * y[i + 1] - u2[i] * y[i + 2]) / u0[i];
+}
+
+__device__ inline double start_value(int i, int c) {
+    uint32_t h = uint32_t(i) * 2654435761u ^ (uint32_t(c) * 2246822519u + 374761393u);
+    h ^= h >> 15;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    return 0.5 + double(h & 0xffffu) / 65536.0;       // in [0.5, 1.5): no zero components
+}
+
+// Two-sided application of I - tau v v^T to the symmetric m x m matrix H.
+template <class SH>
+__device__ void reflect_two_sided(double* H, int ld, int m, const double* v, double tau, SH& S) {
+    const int tid = threadIdx.x;
+    double pv_part = 0.0;
+    for (int i = tid; i < m; i += NT) {
+        const double acc = tau * dot_rows(H + i, ld, v, m);
+        S.w[i] = acc;
+        pv_part += acc * v[i];
+    }
+    const double K = 0.5 * tau * block_sum(pv_part, S.red);
+    for (int i = tid; i < m; i += NT) S.w[i] -= K * v[i];
+    __syncthreads();
+    for (int i = tid; i < m; i += NT) rank2_row(H + i, ld, v[i], S.w[i], v, S.w, m);
+    __syncthreads();
+}
+
+
+template <bool LDS, int MAXN>
+__global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
+                                                    int* rank) {
+    extern __shared__ double lds[];
+    __shared__ CmpShared<MAXN> S;
+    const CompressTask T = tasks[blockIdx.x];
+    const int m = T.m, tid = threadIdx.x;
+    CmpWork Wk(T.work, m);
+    const int ld = LDS ? m + 1 : m;
+    double* H = LDS ? lds : Wk.H;
+    double* U = T.U;
+    auto stamp = [&](int k) {
+        if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
+    };
+    stamp(0);
+    double gm = 0.0;
+    for (int e = tid; e < m * m; e += NT) gm = fmax(gm, fabs(T.G[e]));
+    const double gmax = block_max(gm, S.red);
+    const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
+    for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
+    __syncthreads();
+    stamp(1);
+    tridiagonalize(H, ld, m, S);
+    tridiag_bounds(m, S);
+    stamp(2);
+    const double lam_max = (gmax > 0.0) ? largest_eigenvalue(m, S) : 0.0;
+    stamp(3);
+    int q = 0;
+    if (variant == HSOLVE_GC) {
+        for (int c = 0; c < T.nz && q < m; ++c) {
+            const double* z = T.Z + size_t(c) * m;
+            double* u = U + size_t(q) * m;
+            double part = 0.0;
+            for (int i = tid; i < m; i += NT) {
+                u[i] = z[i];
+                part += z[i] * z[i];
+            }
+            const double nz = sqrt(block_sum(part, S.red));
+            if (nz == 0.0) continue;
+            for (int pass = 0; pass < 2; ++pass)
+                for (int b = 0; b < q; ++b) {
+                    const double* ub = U + size_t(b) * m;
+                    double pp = 0.0;
+                    for (int i = tid; i < m; i += NT) pp += ub[i] * u[i];
+                    const double dot = block_sum(pp, S.red);
+                    for (int i = tid; i < m; i += NT) u[i] -= dot * ub[i];
+                    __syncthreads();
+                }
+            part = 0.0;
+            for (int i = tid; i < m; i += NT) part += u[i] * u[i];
+            const double nu = sqrt(block_sum(part, S.red));
+            if (nu > 1e-10 * nz) {
+                for (int i = tid; i < m; i += NT) u[i] /= nu;
+                __syncthreads();
+                ++q;
+            }
+        }
+        // reflectors H_t with (H_{q-1}..H_0) U1 = [R; 0]; project G on the complement of U1
+        for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
+        double* x = S.v;        // free until the next tridiagonalisation
+        for (int t = 0; t < q; ++t) {
+            for (int i = tid; i < m; i += NT) x[i] = U[i + size_t(t) * m];
+            __syncthreads();
+            for (int b = 0; b < t; ++b) {
+                const double* vb = Wk.gcv + size_t(b) * m;
+                double pp = 0.0;
+                for (int i = tid; i < m; i += NT) pp += vb[i] * x[i];
+                const double dot = block_sum(pp, S.red) * Wk.gct[b];
+                for (int i = tid; i < m; i += NT) x[i] -= dot * vb[i];
+                __syncthreads();
+            }
+            double part = 0.0;
+            for (int i = t + 1 + tid; i < m; i += NT) part += x[i] * x[i];
+            const double xn2 = block_sum(part, S.red);
+            const double alpha = x[t];
+            double* vt = Wk.gcv + size_t(t) * m;
+            double tau = 0.0;
+            if (xn2 > 0.0) {
+                const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                const double scal = 1.0 / (alpha - beta);
+                for (int i = tid; i < m; i += NT) vt[i] = (i < t) ? 0.0 : (i == t ? 1.0 : x[i] * scal);
+            } else {
+                for (int i = tid; i < m; i += NT) vt[i] = (i == t) ? 1.0 : 0.0;
+            }
+            if (tid == 0) Wk.gct[t] = tau;
+            __syncthreads();
+            if (tau != 0.0) reflect_two_sided(H, ld, m, vt, tau, S);
+        }
+        if (m - q > 0) {
+            tridiagonalize(H + size_t(q) * ld + q, ld, m - q, S);
+            tridiag_bounds(m - q, S);
+        }
+    }
+    stamp(4);
+    const int nn = m - q;
+    const int cap = min(nn, T.wt);
+    const double thr = eps * eps * fmax(lam_max, 0.0);
+    if (tid == 0) {
+        int k2;
+        if (nn <= 0) k2 = 0;
+        else if (eps == 0.0) k2 = cap;
+        else k2 = min(cap, nn - sturm_count(S.d, S.e, nn, thr, S.scal[2]));
+        if (k2 < 0) k2 = 0;
+        if (q + k2 == 0 && cap > 0) k2 = 1;
+        S.iscal[3] = k2;
+    }
+    __syncthreads();
+    int k2 = S.iscal[3];
+    if (variant == HSOLVE_LORASP && gmax == 0.0 && eps > 0.0) {
+        // A_sw exactly zero: the kept direction is the first unit vector
+        for (int i = tid; i < m; i += NT) U[i] = (i == 0) ? 1.0 : 0.0;
+        k2 = 0;
+        q = 1;
+    }
+    for (int i = tid; i < nn; i += NT) {
+        Wk.d[i] = S.d[i];
+        Wk.e[i] = S.e[i];
+        Wk.tau[i] = S.tau[i];
+    }
+    if (LDS)
+        for (int e = tid; e < m * m; e += NT) Wk.H[e] = H[(e % m) + (e / m) * ld];
+    if (tid == 0) {
+        Wk.info[INF_Q] = q;
+        Wk.info[INF_K2] = k2;
+        Wk.info[INF_NN] = nn;
+        Wk.info[INF_TNORM] = S.scal[3];
+        Wk.info[INF_PIVMIN] = S.scal[2];
+        Wk.info[INF_LO] = S.scal[0];
+        Wk.info[INF_HI] = S.scal[1];
+        rank[T.id] = q + k2;
+    }
+    stamp(5);
+}
+
+// one thread per kept eigenvalue (largest first)
+__global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
+    __shared__ double d[CMP_MAX], e[CMP_MAX];
+    const CompressTask T = tasks[blockIdx.y];
+    CmpWork Wk(T.work, T.m);
+    const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]);
+    if (int(blockIdx.x) * NT >= k2) return;
+    for (int i = threadIdx.x; i < nn; i += NT) {
+        d[i] = Wk.d[i];
+        e[i] = Wk.e[i];
+    }
+    __syncthreads();
+    const int j = blockIdx.x * NT + threadIdx.x;
+    if (j < k2)
+        Wk.lam[j] = kth_eigenvalue(d, e, nn, nn - 1 - j, Wk.info[INF_LO], Wk.info[INF_HI],
+                                   Wk.info[INF_PIVMIN], Wk.info[INF_TNORM]);
+}
+
+// one wave per eigenvalue index; cluster leaders compute their members' eigenvectors by
+// inverse iteration and map them back to the m-dim coordinates
+constexpr int VNT = 128;           // two waves per workgroup in k_comp_vectors
+
+__global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks, int variant) {
+    __shared__ double d[CMP_MAX], e[CMP_MAX];
+    __shared__ double scr[VNT / WAVE][4][CMP_MAX];
+    const CompressTask T = tasks[blockIdx.y];
+    const int m = T.m;
+    CmpWork Wk(T.work, m);
+    const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]), q = int(Wk.info[INF_Q]);
+    if (int(blockIdx.x) * (VNT / WAVE) >= k2) return;
+    for (int i = threadIdx.x; i < nn; i += VNT) {
+        d[i] = Wk.d[i];
+        e[i] = Wk.e[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int c0 = blockIdx.x * (VNT / WAVE) + wv;
+    if (c0 >= k2) return;
+    const double tnorm = Wk.info[INF_TNORM];
+    const double ctol = 1e-7 * tnorm;
+    const double* lam = Wk.lam;
+    if (c0 > 0 && lam[c0 - 1] - lam[c0] <= ctol) return;     // not a cluster leader
+    int c1 = c0 + 1;
+    while (c1 < k2 && lam[c1 - 1] - lam[c1] <= ctol) ++c1;
+    const double tiny = DBL_EPSILON * (tnorm > 0.0 ? tnorm : 1.0);
+    double* y = scr[wv][0];
+    double* u0 = scr[wv][1];
+    double* u1 = scr[wv][2];
+    double* u2 = scr[wv][3];
+    for (int c = c0; c < c1; ++c) {
+        for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
+        for (int it = 0; it < 3; ++it) {
+            if (lane == 0) tridiag_shift_solve(d, e, nn, lam[c], tiny, y, u0, u1, u2);
+            for (int pass = 0; pass < 2; ++pass)
+                for (int b = c0; b < c; ++b) {
+                    const double* yb = T.U + size_t(q + b) * m + q;
+                    double part = 0.0;
+                    for (int i = lane; i < nn; i += WAVE) part += yb[i] * y[i];
+                    const double dot = wave_sum(part);
+                    for (int i = lane; i < nn; i += WAVE) y[i] -= dot * yb[i];
+                }
+            double part = 0.0;
+            for (int i = lane; i < nn; i += WAVE) part += y[i] * y[i];
+            const double nrm = sqrt(wave_sum(part));
+            const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+            for (int i = lane; i < nn; i += WAVE) y[i] *= inv;
+        }
+        double* col = T.U + size_t(q + c) * m + q;
+        for (int i = lane; i < nn; i += WAVE) col[i] = y[i];
+    }
+    // back-transformation of each member, vector in registers: x_full = [0_q; y]
+    for (int c = c0; c < c1; ++c) {
+        double* u = T.U + size_t(q + c) * m;
+        double x[CMP_RMAX];
+#pragma unroll
+        for (int r = 0; r < CMP_RMAX; ++r) {
+            const int i = lane + WAVE * r;
+            x[r] = (i >= q && i < m) ? u[i] : 0.0;
+        }
+        for (int j = nn - 3; j >= 0; --j) {
+            const double tj = Wk.tau[j];
+            if (tj == 0.0) continue;
+            const int col0 = q + j;                 // reflector column in m-dim coordinates
+            const double* hc = Wk.H + size_t(col0) * m;
+            double v[CMP_RMAX];
+            double part = 0.0;
+#pragma unroll
+            for (int r = 0; r < CMP_RMAX; ++r) {
+                const int i = lane + WAVE * r;
+                v[r] = (i > col0 + 1 && i < m) ? hc[i] : (i == col0 + 1 ? 1.0 : 0.0);
+                part += v[r] * x[r];
+            }
+            const double dot = wave_sum(part) * tj;
+#pragma unroll
+            for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * v[r];
+        }
+        for (int t = q - 1; t >= 0; --t) {
+            const double tt = Wk.gct[t];
+            if (variant != HSOLVE_GC || tt == 0.0) continue;
+            const double* vt = Wk.gcv + size_t(t) * m;
+            double part = 0.0;
+            double v[CMP_RMAX];
+#pragma unroll
+            for (int r = 0; r < CMP_RMAX; ++r) {
+                const int i = lane + WAVE * r;
+                v[r] = (i < m) ? vt[i] : 0.0;
+                part += v[r] * x[r];
+            }
+            const double dot = wave_sum(part) * tt;
+#pragma unroll
+            for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * v[r];
+        }
+#pragma unroll
+        for (int r = 0; r < CMP_RMAX; ++r) {
+            const int i = lane + WAVE * r;
+            if (i < m) u[i] = x[r];
+        }
+    }
+}
+
+void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps, int* d_rank,
+                     double flops, bool lds, int max_m, hipStream_t s) {
+    if (ntasks <= 0) return;
+    if (max_m > CMP_MAX)
+        throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
+    {
+        ProfScope ps("k_comp_reduce", flops, s);
+        if (lds) {
+            if (max_m > CMP_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS compression too large"};
+            static bool attr = false;
+            if (!attr) {
+                HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_reduce<true, CMP_LDS_MAX>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           int(size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) * sizeof(double))));
+                attr = true;
+            }
+            const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(double);
+            hipLaunchKernelGGL((k_comp_reduce<true, CMP_LDS_MAX>), dim3(ntasks), dim3(NT), bytes, s,
+                               d_tasks, variant, eps, d_rank);
+            check_launch("k_comp_reduce<lds>");
+        } else {
+            hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(NT), 0, s, d_tasks,
+                               variant, eps, d_rank);
+            check_launch("k_comp_reduce<global>");
+        }
+    }
+    {
+        ProfScope ps("k_comp_bisect", 0.0, s);
+        hipLaunchKernelGGL(k_comp_bisect, dim3((max_m + NT - 1) / NT, ntasks), dim3(NT), 0, s, d_tasks);
+        check_launch("k_comp_bisect");
+    }
+    {
+        ProfScope ps("k_comp_vectors", 0.0, s);
+        hipLaunchKernelGGL(k_comp_vectors, dim3((max_m + VNT / WAVE - 1) / (VNT / WAVE), ntasks), dim3(VNT),
+                           0, s, d_tasks, variant);
+        check_launch("k_comp_vectors");
+    }
+}
+
+}  // namespace hs

@@ -15,6 +15,8 @@
 #include <algorithm>
 #include <array>
 #include <chrono>
+#include <cstdio>
+#include <cstdlib>
 #include <map>
 
 #include "hs_internal.h"
@@ -88,10 +90,26 @@ struct Batch {
     }
     void flush_chol(Plan& P, int* d_fail) {
         if (chol.empty()) return;
-        double flops = 0.0;
-        for (const CholTask& c : chol) flops += double(c.m) * c.m * c.m;   // potrf + inverse
-        CholTask* d = P.stage.upload_vec(chol, P.spool, P.stream);
-        launch_chol_inv(d, int(chol.size()), d_fail, flops, P.stream);
+        for (int big = 0; big < 2; ++big) {       // LDS-resident blocks, then large ones
+            std::vector<CholTask> part;
+            double flops = 0.0;
+            int max_m = 0;
+            for (CholTask c : chol) {
+                if ((c.m > LDS_MAX_M) != bool(big)) continue;
+                if (big) c.work = P.spool.alloc_n<double>(size_t(c.m) * c.m);
+                flops += double(c.m) * c.m * c.m;   // potrf m^3/3 + inverse 2m^3/3
+                max_m = std::max(max_m, c.m);
+                part.push_back(c);
+            }
+            if (part.empty()) continue;
+            CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
+            launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, P.stream);
+            if (big) {      // A^{-1} = X^T X, X = L^{-1} left in the work matrices
+                for (const CholTask& c : part) gemm(c.Ainv, c.ldi, c.m, c.m, 1.0, 0.0, c.work, c.m, 1,
+                                                    c.work, c.m, 0, c.m);
+                flush_gemm(P);
+            }
+        }
         chol.clear();
     }
 };
@@ -137,6 +155,8 @@ void factor(Plan& P, const double* d_values_in) {
                          hipHostMallocDefault));
     struct HostFree { int* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{h_flags};
 
+    const bool trace = std::getenv("HSOLVE_TRACE") != nullptr;
+    auto now_ms = [&] { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); };
     for (int d = nlev - 1; d >= 0; --d) {
         const LevelSym& S = P.sym[d];
         const int nd = 1 << d;
@@ -267,6 +287,7 @@ void factor(Plan& P, const double* d_values_in) {
         for (size_t c = 0; c < S.colours.size(); ++c) {
             const std::vector<int>& nodes = S.colours[c];
             P.spool.reset();    // stream order: the previous colour's kernels run first
+            const double tc0 = trace ? now_ms() : 0.0;
             // --- phase A: compression of the nodes with well-separated blocks
             struct CompNode { int s, slot, wt; double *Asw, *U; };
             std::vector<CompNode> comp;
@@ -274,14 +295,14 @@ void factor(Plan& P, const double* d_values_in) {
             for (int s : nodes) {
                 if (S.W[s].empty()) continue;
                 const int m = LN.msz[s];
-                if (m > 1024)
-                    throw Error{HSOLVE_ERR_INVALID, "super node larger than 1024 unknowns at compression"};
+                if (m > 512)
+                    throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
                 int wt = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) wt += cursize(S.W[s][t], S.Wred[s][t]);
                 double* Asw = P.spool.alloc_n<double>(size_t(m) * wt);
                 double* G = P.spool.alloc_n<double>(size_t(m) * m);
                 double* U = P.spool.alloc_n<double>(size_t(m) * m);
-                double* work = P.spool.alloc_n<double>(size_t(2) * m * m + 32 * size_t(m));
+                double* work = P.spool.alloc_n<double>(size_t(m) * m + 32 * size_t(m) + 64);
                 double* Z = nullptr;
                 int off = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) {
@@ -312,20 +333,32 @@ void factor(Plan& P, const double* d_values_in) {
                 flops += 2.0 * m * m * wt;
                 const int slot = int(comp.size());
                 comp.push_back(CompNode{s, slot, wt, Asw, U});
-                ctasks.push_back(CompressTask{G, Z, work, U, m, gc ? 2 * p : 0, wt, slot});
+                ctasks.push_back(CompressTask{G, Z, work, U, nullptr, m, gc ? 2 * p : 0, wt, slot});
             }
             int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
+            long long* d_stamp = nullptr;
+            if (trace && !ctasks.empty()) {
+                d_stamp = P.spool.alloc_n<long long>(8 * ctasks.size());
+                HS_HIP(hipMemsetAsync(d_stamp, 0, sizeof(long long) * 8 * ctasks.size(), st));
+                for (size_t q2 = 0; q2 < ctasks.size(); ++q2) ctasks[q2].tstamp = d_stamp + 8 * q2;
+            }
             B.flush_copies(P);
             B.flush_gemm(P);
-            if (!ctasks.empty()) {
-                // tridiagonalisation 4/3 m^3 (twice for GC) + QL with vectors ~6 m^3
+            for (int big = 0; big < 2; ++big) {
+                // counted work: tridiagonalisation 4/3 m^3 (twice for GC) + back-transform 2 m^2 k
+                std::vector<CompressTask> part;
                 double cflops = 0.0;
+                int max_m = 0;
                 for (const CompressTask& ct : ctasks) {
+                    if ((ct.m > LDS_MAX_M) != bool(big)) continue;
                     const double m3 = double(ct.m) * ct.m * ct.m;
-                    cflops += (gc ? 8.0 / 3.0 : 4.0 / 3.0) * m3 + 6.0 * m3;
+                    cflops += (gc ? 8.0 / 3.0 : 4.0 / 3.0) * m3 + 2.0 * m3 / 2.0;
+                    max_m = std::max(max_m, ct.m);
+                    part.push_back(ct);
                 }
-                launch_compress(P.stage.upload_vec(ctasks, P.spool, st), int(ctasks.size()),
-                                P.opt.variant, eps, d_rank, cflops, st);
+                if (part.empty()) continue;
+                launch_compress(P.stage.upload_vec(part, P.spool, st), int(part.size()), P.opt.variant,
+                                eps, d_rank, cflops, !big, max_m, st);
             }
             HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
             if (!comp.empty())
@@ -348,6 +381,16 @@ void factor(Plan& P, const double* d_values_in) {
                                     ", |W| " + std::to_string(cn.wt) + ", k " + std::to_string(k) + ")"};
                 LN.ksz[cn.s] = k;
                 max_rank = std::max(max_rank, k);
+            }
+            double tc1 = 0.0;
+            std::vector<long long> stamps;
+            if (trace) {
+                tc1 = now_ms();
+                if (d_stamp) {
+                    stamps.resize(8 * ctasks.size());
+                    HS_HIP(hipMemcpy(stamps.data(), d_stamp, sizeof(long long) * stamps.size(),
+                                     hipMemcpyDeviceToHost));
+                }
             }
             std::vector<const CompNode*> compof(nd, nullptr);
             for (const CompNode& cn : comp) compof[cn.s] = &cn;
@@ -380,7 +423,7 @@ void factor(Plan& P, const double* d_values_in) {
                     else B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
                 }
                 Block* dg = live.find(s, s);
-                B.chol.push_back(CholTask{dg->p, nn.Gm, dg->ld, nn.ldG, m, s});
+                B.chol.push_back(CholTask{dg->p, nn.Gm, nullptr, dg->ld, nn.ldG, m, s});
                 flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
             }
             B.flush_copies(P);
@@ -410,7 +453,7 @@ void factor(Plan& P, const double* d_values_in) {
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
                 Sinv[q] = static_cast<double*>(lp.alloc(blk_bytes(nn.k, nn.k)));
-                B.chol.push_back(CholTask{Ssc[q], Sinv[q], nn.k, nn.k, nn.k, s});
+                B.chol.push_back(CholTask{Ssc[q], Sinv[q], nullptr, nn.k, nn.k, nn.k, s});
                 flops += double(nn.k) * nn.k * nn.k;
             }
             B.flush_chol(P, d_fail);
@@ -529,6 +572,23 @@ void factor(Plan& P, const double* d_values_in) {
                 B.close();
             }
             B.flush_gemm(P);
+            if (trace) {
+                HS_HIP(hipStreamSynchronize(st));
+                int mm = 0, mw = 0, mk = 0;
+                for (int s2 : nodes) {
+                    mm = std::max(mm, LN.msz[s2]);
+                    mk = std::max(mk, LN.ksz[s2]);
+                }
+                for (const CompNode& cn : comp) mw = std::max(mw, cn.wt);
+                std::fprintf(stderr, "trace d=%2d c=%2zu nodes=%5zu comp=%5zu max_m=%4d max_wt=%5d max_k=%4d  A=%8.2f ms  B=%8.2f ms",
+                             d, c, nodes.size(), comp.size(), mm, mw, mk, tc1 - tc0, now_ms() - tc1);
+                long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
+                for (size_t q2 = 0; q2 < stamps.size() / 8; ++q2)
+                    for (int k = 0; k < 7; ++k)
+                        ph[k] = std::max(ph[k], stamps[8 * q2 + k + 1] - stamps[8 * q2 + k]);
+                std::fprintf(stderr, "  kcycles load %lld tri %lld lmax %lld gc %lld count %lld\n",
+                             ph[0] / 1000, ph[1] / 1000, ph[2] / 1000, ph[3] / 1000, ph[4] / 1000);
+            }
         }
         // end of level: surface pivot failures of the last colour
         HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));

@@ -1,0 +1,50 @@
+// Device-side helpers shared by the HIP translation units (wave64, 256-thread blocks).
+#pragma once
+
+#include "hs_internal.h"
+
+namespace hs {
+
+constexpr int NT = 256;          // threads per workgroup (4 waves)
+constexpr int WAVE = 64;
+
+inline void check_launch(const char* name) {
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess)
+        throw Error{HSOLVE_ERR_DEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e)};
+}
+
+__device__ inline double wave_sum(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
+__device__ inline double wave_max(double v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
+    return v;
+}
+
+// block-wide sum; `red` must hold NT/WAVE doubles; result valid in every thread
+__device__ inline double block_sum(double v, double* red) {
+    v = wave_sum(v);
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+    return s;
+}
+
+__device__ inline double block_max(double v, double* red) {
+    v = wave_max(v);
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) red[w] = v;
+    __syncthreads();
+    double s = red[0];
+    for (int i = 1; i < NT / WAVE; ++i) s = fmax(s, red[i]);
+    return s;
+}
+
+}  // namespace hs

@@ -184,14 +184,16 @@ struct GemmTile {            // one 64 x 64 tile of a task
 struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1}
     double* A;
     double* Ainv;
+    double* work;            // m x m scratch for blocks too large for LDS (else null)
     int lda, ldi, m, id;
 };
 
 struct CompressTask {
     const double* G;         // m x m Gram matrix A_sw A_sw^T (ld m), consumed
     const double* Z;         // m x nz vectors to keep [phi_s, A_sw phi_w] (ld m), or null
-    double* work;            // scratch: 2 m^2 + 32 m doubles
+    double* work;            // scratch: m^2 + 32 m + 64 doubles
     double* U;               // out: m x k (ld m)
+    long long* tstamp;       // optional: 8 clock stamps at phase boundaries (trace only)
     int m, nz, wt, id;
 };
 
@@ -293,10 +295,11 @@ void spmv(Plan& P, const double* x, double* y);
 void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t s);
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
                  int ntiles, double flops, hipStream_t s);
-void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops,
-                     hipStream_t s);
+void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
+                     int max_m, hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, double flops, hipStream_t s);
+                     int* d_rank, double flops, bool lds, int max_m, hipStream_t s);
+constexpr int LDS_MAX_M = 128;   // pivot / compression blocks up to this size work in LDS
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const int32_t* iperm, const int32_t* pos_super,
                          const int32_t* super_first, double* const* blk_ptr,

@@ -2,43 +2,14 @@
 //
 //  k_copy        batched 2-D block copies (optional transpose)          block gather / merge
 //  k_gemm        grouped GEMM over tile lists, C = bC + a sum op(A)op(B) Gram, Schur, T_N, L_nr, R
-//  k_chol_inv    per-block Cholesky + explicit inverse                  pivot A_ss^-1, S^-1
-//  k_compress    per-node eigen-decomposition of the Gram matrix of the well-separated block
-//                (Householder tridiagonalisation, implicit QL with shifts, parallel Sturm
-//                bisection), GC basis split, truncation                 compression
+//  (pivot.hip: k_chol_inv; compress.hip: k_compress)
 //  k_fwd / k_bwd level sweeps of the solve phase                        apply
 //  k_spmv, k_dot*, k_axpy2, k_xpby, gathers/scatters                    outer PCG
 #include <cfloat>
 
-#include "hs_internal.h"
+#include "hs_device.h"
 
 namespace hs {
-
-constexpr int NT = 256;          // threads per workgroup (4 waves)
-
-static void check_launch(const char* name) {
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess)
-        throw Error{HSOLVE_ERR_DEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e)};
-}
-constexpr int WAVE = 64;
-
-__device__ inline double wave_sum(double v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
-}
-
-// block-wide sum; `red` must hold NT/WAVE doubles; result valid in every thread
-__device__ inline double block_sum(double v, double* red) {
-    v = wave_sum(v);
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    __syncthreads();
-    if (lane == 0) red[w] = v;
-    __syncthreads();
-    double s = 0.0;
-    for (int i = 0; i < NT / WAVE; ++i) s += red[i];
-    return s;
-}
 
 // ---------------------------------------------------------------------------------
 // Copies
@@ -150,466 +121,6 @@ void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTil
     ProfScope ps("k_gemm", flops, s);
     hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles);
     check_launch("k_gemm");
-}
-
-// ---------------------------------------------------------------------------------
-// Cholesky A = L L^T (lower, in place) and explicit A^{-1} = L^{-T} L^{-1}
-// ---------------------------------------------------------------------------------
-__global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fail) {
-    const CholTask T = tasks[blockIdx.x];
-    const int m = T.m, lda = T.lda, tid = threadIdx.x;
-    double* A = T.A;
-    __shared__ int bad;
-    if (tid == 0) bad = 0;
-    __syncthreads();
-    for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            const double djj = A[j + size_t(j) * lda];
-            if (!(djj > 0.0) || !isfinite(djj)) bad = 1;
-            else A[j + size_t(j) * lda] = sqrt(djj);
-        }
-        __syncthreads();
-        if (bad) break;
-        const double piv = A[j + size_t(j) * lda];
-        for (int i = j + 1 + tid; i < m; i += NT) A[i + size_t(j) * lda] /= piv;
-        __syncthreads();
-        for (int k = j + 1; k < m; ++k) {
-            const double akj = A[k + size_t(j) * lda];
-            for (int i = k + tid; i < m; i += NT)
-                A[i + size_t(k) * lda] -= A[i + size_t(j) * lda] * akj;
-        }
-        __syncthreads();
-    }
-    if (bad) {
-        if (tid == 0) fail[T.id] = 1;
-        return;
-    }
-    // column c of A^{-1}: L y = e_c, then L^T x = y (in place in Ainv[:, c])
-    for (int c = tid; c < m; c += NT) {
-        double* x = T.Ainv + size_t(c) * T.ldi;
-        for (int i = 0; i < c; ++i) x[i] = 0.0;
-        for (int i = c; i < m; ++i) {
-            double s = (i == c) ? 1.0 : 0.0;
-            for (int j = c; j < i; ++j) s -= A[i + size_t(j) * lda] * x[j];
-            x[i] = s / A[i + size_t(i) * lda];
-        }
-        for (int i = m - 1; i >= 0; --i) {
-            double s = x[i];
-            for (int j = i + 1; j < m; ++j) s -= A[j + size_t(i) * lda] * x[j];
-            x[i] = s / A[i + size_t(i) * lda];
-        }
-    }
-}
-
-void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops,
-                     hipStream_t s) {
-    if (ntasks <= 0) return;
-    ProfScope ps("k_chol_inv", flops, s);
-    hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(NT), 0, s, d_tasks, d_fail);
-    check_launch("k_chol_inv");
-}
-
-// ---------------------------------------------------------------------------------
-// Compression: eigen-decomposition of the Gram matrix G = A_sw A_sw^T
-// ---------------------------------------------------------------------------------
-constexpr int MAXN = 1024;       // largest super node handled by k_compress
-
-struct EigShared {
-    double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN], rc[MAXN], rs[MAXN];
-    int idx[MAXN];
-    double red[NT / WAVE];
-    double scal[4];
-    int iscal[4];
-    int pts[NT + 1];
-};
-
-// Householder tridiagonalisation of the symmetric nn x nn matrix H (column-major, ld),
-// Q^T H Q = T. Reflector j acts on rows j+1.., its vector (v[0] = 1 implicit) is kept in
-// H(j+2.., j) and tau[j]; the diagonal goes to d, the sub-diagonal to e.
-__device__ void tridiagonalize(double* H, int ld, int nn, EigShared& S) {
-    const int tid = threadIdx.x;
-    for (int j = 0; j + 2 < nn; ++j) {
-        double* col = H + size_t(j) * ld;
-        double part = 0.0;
-        for (int i = j + 2 + tid; i < nn; i += NT) part += col[i] * col[i];
-        const double xn2 = block_sum(part, S.red);
-        const double alpha = col[j + 1];
-        double tau = 0.0, beta = alpha;
-        if (xn2 > 0.0) {
-            beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-            tau = (beta - alpha) / beta;
-            const double scal = 1.0 / (alpha - beta);
-            for (int i = j + 2 + tid; i < nn; i += NT) col[i] *= scal;
-        }
-        __syncthreads();
-        const int len = nn - j - 1;                       // trailing block rows j+1..nn-1
-        for (int i = tid; i < len; i += NT) S.v[i] = (i == 0) ? 1.0 : (xn2 > 0.0 ? col[j + 1 + i] : 0.0);
-        if (tid == 0) { S.tau[j] = tau; S.e[j] = beta; }
-        __syncthreads();
-        if (tau != 0.0) {
-            double* T22 = H + size_t(j + 1) * ld + (j + 1);
-            double pv_part = 0.0;
-            for (int i = tid; i < len; i += NT) {
-                double acc = 0.0;
-                for (int l = 0; l < len; ++l) acc += T22[i + size_t(l) * ld] * S.v[l];
-                acc *= tau;
-                S.w[i] = acc;
-                pv_part += acc * S.v[i];
-            }
-            const double K = 0.5 * tau * block_sum(pv_part, S.red);
-            for (int i = tid; i < len; i += NT) S.w[i] -= K * S.v[i];
-            __syncthreads();
-            for (int l = 0; l < len; ++l) {
-                const double vl = S.v[l], wl = S.w[l];
-                for (int i = tid; i < len; i += NT)
-                    T22[i + size_t(l) * ld] -= S.v[i] * wl + S.w[i] * vl;
-            }
-            __syncthreads();
-        }
-    }
-    for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
-    if (tid == 0) {
-        if (nn >= 2) S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
-        S.e[nn - 1] = 0.0;
-        if (nn >= 2) S.tau[nn - 2] = 0.0;
-        S.tau[nn - 1] = 0.0;
-    }
-    __syncthreads();
-}
-
-// x <- Q x for a vector stored at x (length nn) using the reflectors left in H; executed by
-// one wave (lane-parallel).
-__device__ void backtransform_wave(const double* H, int ld, int nn, const double* tau, double* x) {
-    const int lane = threadIdx.x % WAVE;
-    for (int j = nn - 3; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj == 0.0) continue;
-        const double* col = H + size_t(j) * ld;
-        double part = 0.0;
-        for (int i = j + 1 + lane; i < nn; i += WAVE) {
-            const double vi = (i == j + 1) ? 1.0 : col[i];
-            part += vi * x[i];
-        }
-        const double dot = wave_sum(part) * tj;
-        for (int i = j + 1 + lane; i < nn; i += WAVE) {
-            const double vi = (i == j + 1) ? 1.0 : col[i];
-            x[i] -= dot * vi;
-        }
-    }
-}
-
-__device__ int sturm_count(const double* d, const double* e, int nn, double x, double pivmin) {
-    int cnt = 0;
-    double q = d[0] - x;
-    if (fabs(q) < pivmin) q = -pivmin;
-    if (q < 0.0) ++cnt;
-    for (int i = 1; i < nn; ++i) {
-        q = d[i] - x - e[i - 1] * e[i - 1] / q;
-        if (fabs(q) < pivmin) q = -pivmin;
-        if (q < 0.0) ++cnt;
-    }
-    return cnt;
-}
-
-// largest eigenvalue of the tridiagonal (S.d, S.e) by parallel multisection
-__device__ double largest_eigenvalue(int nn, EigShared& S) {
-    const int tid = threadIdx.x;
-    if (tid == 0) {
-        double lo = S.d[0], hi = S.d[0], me = 0.0;
-        for (int i = 0; i < nn; ++i) {
-            const double r = (i > 0 ? fabs(S.e[i - 1]) : 0.0) + (i + 1 < nn ? fabs(S.e[i]) : 0.0);
-            lo = fmin(lo, S.d[i] - r);
-            hi = fmax(hi, S.d[i] + r);
-            if (i + 1 < nn) me = fmax(me, S.e[i] * S.e[i]);
-        }
-        const double pad = 2.0 * DBL_EPSILON * fmax(fabs(lo), fabs(hi)) + 1e-300;
-        S.scal[0] = lo - pad;
-        S.scal[1] = hi + pad;
-        S.scal[2] = fmax(1e-300, 1e-300 * me);
-    }
-    __syncthreads();
-    for (int round = 0; round < 10; ++round) {
-        const double lo = S.scal[0], hi = S.scal[1], pivmin = S.scal[2];
-        __syncthreads();
-        const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
-        S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
-        __syncthreads();
-        if (tid == 0) {
-            int t = 0;
-            while (t < NT && !S.pts[t]) ++t;
-            const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
-            const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
-            S.scal[0] = xl;
-            S.scal[1] = xh;
-        }
-        __syncthreads();
-    }
-    return 0.5 * (S.scal[0] + S.scal[1]);
-}
-
-// Implicit QL with shifts on (S.d, S.e) (nn x nn); Z (column-major, ld) starts as the
-// identity and ends with the eigenvectors of the tridiagonal in its columns.
-// Returns false if an eigenvalue fails to converge.
-__device__ bool ql_implicit(int nn, double* Z, int ldz, EigShared& S) {
-    const int tid = threadIdx.x;
-    for (int c = 0; c < nn; ++c)
-        for (int i = tid; i < nn; i += NT) Z[i + size_t(c) * ldz] = (i == c) ? 1.0 : 0.0;
-    // Deflate against the norm of the whole tridiagonal (eigenvalues are needed to an
-    // absolute accuracy relative to the largest one): clusters of numerically zero
-    // eigenvalues then split at once instead of iterating on rounding noise.
-    if (tid == 0) {
-        double tn = 0.0;
-        for (int i = 0; i < nn; ++i) tn = fmax(tn, fabs(S.d[i]) + fabs(S.e[i]));
-        S.scal[3] = tn;
-    }
-    __syncthreads();
-    const double tnorm = S.scal[3];
-    for (int l = 0; l < nn; ++l) {
-        for (int iter = 0;; ++iter) {
-            // S.iscal: [0] = m (deflation point), [1] = lowest rotation index, [2] = status
-            if (tid == 0) {
-                int m = l;
-                for (; m < nn - 1; ++m)
-                    if (fabs(S.e[m]) <= DBL_EPSILON * tnorm) break;
-                S.iscal[0] = m;
-                S.iscal[2] = 0;
-                if (m != l) {
-                    if (iter >= 80) {
-                        S.iscal[2] = 2;
-                    } else {
-                        double g = (S.d[l + 1] - S.d[l]) / (2.0 * S.e[l]);
-                        double r = hypot(g, 1.0);
-                        g = S.d[m] - S.d[l] + S.e[l] / (g + copysign(r, g));
-                        double s = 1.0, c = 1.0, p = 0.0;
-                        int i = m - 1;
-                        bool under = false;
-                        for (; i >= l; --i) {
-                            const double f = s * S.e[i], b = c * S.e[i];
-                            r = hypot(f, g);
-                            S.e[i + 1] = r;
-                            if (r == 0.0) {
-                                S.d[i + 1] -= p;
-                                S.e[m] = 0.0;
-                                under = true;
-                                break;
-                            }
-                            s = f / r;
-                            c = g / r;
-                            g = S.d[i + 1] - p;
-                            r = (S.d[i] - g) * s + 2.0 * c * b;
-                            p = s * r;
-                            S.d[i + 1] = g + p;
-                            g = c * r - b;
-                            S.rc[i] = c;
-                            S.rs[i] = s;
-                        }
-                        S.iscal[1] = under ? i + 1 : l;
-                        if (!under) {
-                            S.d[l] -= p;
-                            S.e[l] = g;
-                            S.e[m] = 0.0;
-                        }
-                        S.iscal[2] = 1;
-                    }
-                }
-            }
-            __syncthreads();
-            const int m = S.iscal[0], status = S.iscal[2], lo = S.iscal[1];
-            if (status == 2) return false;
-            if (status == 0) break;
-            // rotations i = m-1 .. lo act on columns (i, i+1) of Z
-            for (int k = tid; k < nn; k += NT) {
-                double zi1 = Z[k + size_t(m) * ldz];
-                for (int i = m - 1; i >= lo; --i) {
-                    const double zi = Z[k + size_t(i) * ldz];
-                    Z[k + size_t(i + 1) * ldz] = S.rs[i] * zi + S.rc[i] * zi1;
-                    zi1 = S.rc[i] * zi - S.rs[i] * zi1;
-                }
-                Z[k + size_t(lo) * ldz] = zi1;
-            }
-            __syncthreads();
-        }
-    }
-    return true;
-}
-
-// Two-sided application of the reflector I - tau v v^T (v nonzero on rows >= r0) to the
-// symmetric m x m matrix H.
-__device__ void reflect_two_sided(double* H, int ld, int m, const double* v, double tau,
-                                  EigShared& S) {
-    const int tid = threadIdx.x;
-    double pv_part = 0.0;
-    for (int i = tid; i < m; i += NT) {
-        double acc = 0.0;
-        for (int l = 0; l < m; ++l) acc += H[i + size_t(l) * ld] * v[l];
-        acc *= tau;
-        S.w[i] = acc;
-        pv_part += acc * v[i];
-    }
-    const double K = 0.5 * tau * block_sum(pv_part, S.red);
-    for (int i = tid; i < m; i += NT) S.w[i] -= K * v[i];
-    __syncthreads();
-    for (int l = 0; l < m; ++l) {
-        const double vl = v[l], wl = S.w[l];
-        if (vl == 0.0 && wl == 0.0) continue;
-        for (int i = tid; i < m; i += NT) H[i + size_t(l) * ld] -= v[i] * wl + S.w[i] * vl;
-    }
-    __syncthreads();
-}
-
-__global__ __launch_bounds__(NT) void k_compress(const CompressTask* tasks, int variant,
-                                                 double eps, int* rank) {
-    extern __shared__ char smem_raw[];
-    EigShared& S = *reinterpret_cast<EigShared*>(smem_raw);
-    const CompressTask T = tasks[blockIdx.x];
-    const int m = T.m, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    double* H = T.work;                            // m x m
-    double* Zq = T.work + size_t(m) * m;           // m x m eigenvectors
-    double* gcv = T.work + size_t(2) * m * m;      // GC reflectors: up to 16 vectors of m
-    double* gct = gcv + size_t(16) * m;            // their tau
-    double* U = T.U;
-
-    // scale G by its largest entry (eigenvectors unchanged, decisions are relative)
-    double gmax = 0.0;
-    for (size_t i = tid; i < size_t(m) * m; i += NT) gmax = fmax(gmax, fabs(T.G[i]));
-    for (int o = WAVE / 2; o > 0; o >>= 1) gmax = fmax(gmax, __shfl_xor(gmax, o, WAVE));
-    if (lane == 0) S.red[wv] = gmax;
-    __syncthreads();
-    gmax = fmax(fmax(S.red[0], S.red[1]), fmax(S.red[2], S.red[3]));
-    __syncthreads();
-    const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
-    for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i] * gscale;
-    __syncthreads();
-
-    int q = 0;
-    double lam_max;
-    if (variant == HSOLVE_LORASP) {
-        tridiagonalize(H, m, m, S);
-        if (!ql_implicit(m, Zq, m, S)) { if (tid == 0) rank[T.id] = -1; return; }
-        double mx = -DBL_MAX;
-        for (int i = 0; i < m; ++i) mx = fmax(mx, S.d[i]);
-        lam_max = mx;
-    } else {
-        tridiagonalize(H, m, m, S);
-        lam_max = largest_eigenvalue(m, S);
-        // U1 = orthonormal basis of the columns of Z (modified Gram-Schmidt, twice)
-        for (int c = 0; c < T.nz && q < m; ++c) {
-            const double* z = T.Z + size_t(c) * m;
-            double* u = U + size_t(q) * m;
-            double part = 0.0;
-            for (int i = tid; i < m; i += NT) { u[i] = z[i]; part += z[i] * z[i]; }
-            const double nz = sqrt(block_sum(part, S.red));
-            if (nz == 0.0) continue;
-            for (int pass = 0; pass < 2; ++pass)
-                for (int b = 0; b < q; ++b) {
-                    const double* ub = U + size_t(b) * m;
-                    double pp = 0.0;
-                    for (int i = tid; i < m; i += NT) pp += ub[i] * u[i];
-                    const double dot = block_sum(pp, S.red);
-                    for (int i = tid; i < m; i += NT) u[i] -= dot * ub[i];
-                    __syncthreads();
-                }
-            part = 0.0;
-            for (int i = tid; i < m; i += NT) part += u[i] * u[i];
-            const double nu = sqrt(block_sum(part, S.red));
-            if (nu > 1e-10 * nz) {
-                for (int i = tid; i < m; i += NT) u[i] /= nu;
-                __syncthreads();
-                ++q;
-            }
-        }
-        // Householder reflectors W = H_{q-1}..H_0 with W U1 = [R; 0]; the complement of U1
-        // is W^T [0; I]. Project G there: G' = (W G W^T)(q:, q:)
-        for (size_t i = tid; i < size_t(m) * m; i += NT) H[i] = T.G[i] * gscale;
-        for (int t = 0; t < q; ++t) {
-            // x = (H_{t-1}..H_0 u_t)(t..m-1); stored temporarily in Zq column 0
-            double* x = Zq;
-            for (int i = tid; i < m; i += NT) x[i] = U[i + size_t(t) * m];
-            __syncthreads();
-            for (int b = 0; b < t; ++b) {
-                const double* vb = gcv + size_t(b) * m;
-                double pp = 0.0;
-                for (int i = tid; i < m; i += NT) pp += vb[i] * x[i];
-                const double dot = block_sum(pp, S.red) * gct[b];
-                for (int i = tid; i < m; i += NT) x[i] -= dot * vb[i];
-                __syncthreads();
-            }
-            double part = 0.0;
-            for (int i = t + 1 + tid; i < m; i += NT) part += x[i] * x[i];
-            const double xn2 = block_sum(part, S.red);
-            const double alpha = x[t];
-            double* vt = gcv + size_t(t) * m;
-            double tau = 0.0;
-            if (xn2 > 0.0) {
-                const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
-                tau = (beta - alpha) / beta;
-                const double scal = 1.0 / (alpha - beta);
-                for (int i = tid; i < m; i += NT)
-                    vt[i] = (i < t) ? 0.0 : (i == t ? 1.0 : x[i] * scal);
-            } else {
-                for (int i = tid; i < m; i += NT) vt[i] = (i == t) ? 1.0 : 0.0;
-            }
-            if (tid == 0) gct[t] = tau;
-            __syncthreads();
-            if (tau != 0.0) reflect_two_sided(H, m, m, vt, tau, S);
-        }
-        const int nn = m - q;
-        if (nn > 0) {
-            tridiagonalize(H + size_t(q) * m + q, m, nn, S);
-            if (!ql_implicit(nn, Zq, nn, S)) { if (tid == 0) rank[T.id] = -1; return; }
-        }
-    }
-    const int nn = m - q;
-    // select the leading eigenvalues of the (projected) Gram matrix
-    const int cap = min(nn, T.wt);
-    const double thr = eps * eps * fmax(lam_max, 0.0);   // zero G: nothing passes
-    // descending order (NaN last), ties by index: a permutation whatever the values
-    for (int j = tid; j < nn; j += NT) {
-        int r = 0;
-        const double dj = isnan(S.d[j]) ? -DBL_MAX : S.d[j];
-        for (int i = 0; i < nn; ++i) {
-            const double di = isnan(S.d[i]) ? -DBL_MAX : S.d[i];
-            r += (di > dj) || (di == dj && i < j);
-        }
-        S.idx[r] = j;
-    }
-    __syncthreads();
-    if (tid == 0) {
-        int k2 = 0;
-        if (eps == 0.0) k2 = cap;
-        else while (k2 < cap && S.d[S.idx[k2]] > thr) ++k2;
-        if (q + k2 == 0 && cap > 0) k2 = 1;
-        S.iscal[3] = k2;
-    }
-    __syncthreads();
-    const int k2 = S.iscal[3];
-    // eigenvectors of the selected eigenvalues, back in the m-dim coordinates
-    const double* Hs = (variant == HSOLVE_LORASP) ? H : H + size_t(q) * m + q;
-    for (int r = wv; r < k2; r += NT / WAVE) {
-        double* u = U + size_t(q + r) * m;
-        const double* z = Zq + size_t(S.idx[r]) * nn;
-        for (int i = lane; i < m; i += WAVE) u[i] = (i < q) ? 0.0 : z[i - q];
-        backtransform_wave(Hs, m, nn, S.tau, u + q);
-        for (int t = q - 1; t >= 0; --t) {       // u <- H_0 .. H_{q-1} u
-            const double* vt = gcv + size_t(t) * m;
-            const double tt = gct[t];
-            if (tt == 0.0) continue;
-            double part = 0.0;
-            for (int i = lane; i < m; i += WAVE) part += vt[i] * u[i];
-            const double dot = wave_sum(part) * tt;
-            for (int i = lane; i < m; i += WAVE) u[i] -= dot * vt[i];
-        }
-    }
-    if (tid == 0) rank[T.id] = q + k2;
-}
-
-void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, double flops, hipStream_t s) {
-    if (ntasks <= 0) return;
-    ProfScope ps("k_compress", flops, s);
-    hipLaunchKernelGGL(k_compress, dim3(ntasks), dim3(NT), sizeof(EigShared), s, d_tasks,
-                       variant, eps, d_rank);
-    check_launch("k_compress");
 }
 
 // ---------------------------------------------------------------------------------
