@@ -33,7 +33,9 @@ PEAK_FP64_TFLOPS = 78.6
 KERNEL_BOUND = {        # kernel -> (bound, unit of its work counter)
     "k_gemm": ("alu", "flop"),
     "k_chol_inv": ("alu", "flop"),
-    "k_compress": ("alu", "flop"),
+    "k_chol_inv_blk": ("alu", "flop"),
+    "k_comp_reduce<true, 128>": ("alu", "flop"),
+    "k_comp_reduce<false, 512>": ("alu", "flop"),
     "k_fwd": ("hbm", "byte"),
     "k_bwd": ("hbm", "byte"),
     "k_spmv": ("hbm", "byte"),

@@ -144,7 +144,7 @@ const char* hsolve_last_error(hsolve_plan plan);
  * hsolve_profile_begin clears and starts recording for calls on this plan from the calling
  * thread; hsolve_profile_end stops, waits for the device and aggregates by kernel name
  * (*nkernels entries); hsolve_profile_entry reads entry i: name, summed milliseconds,
- * launches, and summed algorithmic work (flops for k_gemm, k_chol_inv, k_compress; bytes
+ * launches, and summed algorithmic work (flops for k_gemm, k_chol_inv*, k_comp_reduce*; bytes
  * for k_copy, k_fwd, k_bwd, k_spmv). */
 hsolve_status hsolve_profile_begin(hsolve_plan plan);
 hsolve_status hsolve_profile_end(hsolve_plan plan, int32_t* nkernels);

@@ -49,7 +49,10 @@ template <int MAXN>
 struct CmpShared {
     double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN], lam[MAXN];
     int clus[MAXN];
+    double bord[4][MAXN];      // GC border rows C (q <= 4) of the bordered tridiagonal
+    double dq[16];             // its leading q x q block D
     double red[NT / WAVE];
+    double red4[4 * (NT / WAVE)];
     double scal[4];
     int iscal[4];
     int pts[NT + 1];
@@ -81,11 +84,28 @@ __device__ inline void rank2_row(double* A, int ld, double vi, double wi, const 
     for (; l < len; ++l) A[size_t(l) * ld] -= vi * w[l] + wi * v[l];
 }
 
+// block-wide sums of v[0..nv), nv <= 4; results valid in every thread
+__device__ inline void block_sum4(double* v, int nv, double* red4) {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    for (int r = 0; r < nv; ++r) v[r] = wave_sum(v[r]);
+    __syncthreads();
+    if (lane == 0)
+        for (int r = 0; r < nv; ++r) red4[r * (NT / WAVE) + w] = v[r];
+    __syncthreads();
+    for (int r = 0; r < nv; ++r) {
+        double s = 0.0;
+        for (int i = 0; i < NT / WAVE; ++i) s += red4[r * (NT / WAVE) + i];
+        v[r] = s;
+    }
+}
+
 // Householder tridiagonalisation of the symmetric nn x nn matrix H (column-major, ld):
 // reflector j acts on rows j+1.., its vector (first entry 1, implicit) is kept in
 // H(j+2.., j) with tau[j]; diagonal -> d, sub-diagonal -> e (e[nn-1] = 0).
+// With nbr > 0, the nbr border rows Bd (Bd[r + l ld] = entry (r, l), l < nn) are multiplied
+// on the right by every reflector, so [D, Bd; Bd^T, H] stays similar to the bordered result.
 template <class SH>
-__device__ void tridiagonalize(double* H, int ld, int nn, SH& S) {
+__device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bd = nullptr, int nbr = 0) {
     const int tid = threadIdx.x;
     for (int j = 0; j + 2 < nn; ++j) {
         double* col = H + size_t(j) * ld;
@@ -120,6 +140,15 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S) {
             for (int i = tid; i < len; i += NT) S.w[i] -= K * S.v[i];
             __syncthreads();
             for (int i = tid; i < len; i += NT) rank2_row(T22 + i, ld, S.v[i], S.w[i], S.v, S.w, len);
+            if (nbr > 0) {
+                double* B1 = Bd + size_t(j + 1) * ld;
+                double dots[4] = {0.0, 0.0, 0.0, 0.0};
+                for (int l = tid; l < len; l += NT)
+                    for (int r = 0; r < nbr; ++r) dots[r] += B1[r + size_t(l) * ld] * S.v[l];
+                block_sum4(dots, nbr, S.red4);
+                for (int l = tid; l < len; l += NT)
+                    for (int r = 0; r < nbr; ++r) B1[r + size_t(l) * ld] -= tau * dots[r] * S.v[l];
+            }
             __syncthreads();
         }
     }
@@ -193,6 +222,77 @@ __device__ double largest_eigenvalue(int nn, SH& S) {
     for (int round = 0; round < 10; ++round) {
         const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
         S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
+        __syncthreads();
+        int t = 0;
+        while (t < NT && !S.pts[t]) ++t;
+        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
+        const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
+        lo = xl;
+        hi = xh;
+        __syncthreads();
+    }
+    return 0.5 * (lo + hi);
+}
+
+// Number of eigenvalues above x of K = [D, C; C^T, T] with T = tridiag(d, e) (nn) and
+// q <= 4 border rows C. Sylvester's law on the block LDL^T that eliminates T first: the
+// positive pivots of T - x I (Sturm recurrence, pivots below pivmin taken as -pivmin) plus
+// the positive eigenvalues of the Schur complement D - x I - C (T - x I)^{-1} C^T, the
+// latter counted by an LDL^T of the q x q matrix. Used only for x at or above the largest
+// eigenvalue of T, where T - x I is negative definite and no cancellation occurs.
+template <int MAXN>
+__device__ int bordered_count_above(const double* d, const double* e, int nn,
+                                    const double (*C)[MAXN], const double* D, int q, double x,
+                                    double pivmin) {
+    double sc[4][4], z[4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        z[a] = 0.0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) sc[a][b] = (a < q && b < q) ? D[a + 4 * b] - (a == b ? x : 0.0) : 0.0;
+    }
+    int cnt = 0;
+    double pp = 1.0, eprev = 0.0;
+    for (int i = 0; i < nn; ++i) {
+        const double l = (i > 0) ? eprev / pp : 0.0;
+        double p = d[i] - x - l * eprev;
+        if (fabs(p) < pivmin) p = -pivmin;
+        if (p > 0.0) ++cnt;
+        const double ip = 1.0 / p;
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            if (a < q) z[a] = C[a][i] - l * z[a];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int b = a; b < 4; ++b)
+                if (b < q) sc[a][b] -= z[a] * z[b] * ip;
+        pp = p;
+        eprev = e[i];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (k >= q) break;
+        double piv = sc[k][k];
+        if (fabs(piv) < pivmin) piv = -pivmin;
+        if (piv > 0.0) ++cnt;
+#pragma unroll
+        for (int a = k + 1; a < 4; ++a)
+#pragma unroll
+            for (int b = a; b < 4; ++b)
+                if (b < q) sc[a][b] -= sc[k][a] * sc[k][b] / piv;
+    }
+    return cnt;
+}
+
+// largest eigenvalue of the bordered matrix by multisection of [lo, hi] (lo below it)
+template <class SH>
+__device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
+    const int tid = threadIdx.x;
+    const double pivmin = S.scal[2];
+    for (int round = 0; round < 10; ++round) {
+        const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
+        S.pts[tid] = bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0 ? 1 : 0;
         __syncthreads();
         int t = 0;
         while (t < NT && !S.pts[t]) ++t;
@@ -300,13 +400,24 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     for (int e = tid; e < m * m; e += NT) gm = fmax(gm, fabs(T.G[e]));
     const double gmax = block_max(gm, S.red);
     const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
-    for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
-    __syncthreads();
+    double fro = 0.0;
+    for (int e = tid; e < m * m; e += NT) {
+        const double g = T.G[e] * gscale;
+        H[(e % m) + (e / m) * ld] = g;
+        fro += g * g;
+    }
+    fro = sqrt(block_sum(fro, S.red));
     stamp(1);
-    tridiagonalize(H, ld, m, S);
-    tridiag_bounds(m, S);
+    // GC with at most 4 kept vectors: lambda_max(G) comes from the bordered tridiagonal form
+    // of the projected matrix (one tridiagonalisation); otherwise G is tridiagonalised first.
+    const bool bordered = variant == HSOLVE_GC && T.nz <= 4;
+    double lam_max = 0.0;
+    if (!bordered) {
+        tridiagonalize(H, ld, m, S);
+        tridiag_bounds(m, S);
+        lam_max = (gmax > 0.0) ? largest_eigenvalue(m, S) : 0.0;
+    }
     stamp(2);
-    const double lam_max = (gmax > 0.0) ? largest_eigenvalue(m, S) : 0.0;
     stamp(3);
     int q = 0;
     if (variant == HSOLVE_GC) {
@@ -339,7 +450,9 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             }
         }
         // reflectors H_t with (H_{q-1}..H_0) U1 = [R; 0]; project G on the complement of U1
-        for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
+        if (!bordered)
+            for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
+        __syncthreads();
         double* x = S.v;        // free until the next tridiagonalisation
         for (int t = 0; t < q; ++t) {
             for (int i = tid; i < m; i += NT) x[i] = U[i + size_t(t) * m];
@@ -370,9 +483,27 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             __syncthreads();
             if (tau != 0.0) reflect_two_sided(H, ld, m, vt, tau, S);
         }
-        if (m - q > 0) {
-            tridiagonalize(H + size_t(q) * ld + q, ld, m - q, S);
-            tridiag_bounds(m - q, S);
+        const int nt = m - q;
+        if (nt > 0) {
+            if (bordered) tridiagonalize(H + size_t(q) * ld + q, ld, nt, S, H + size_t(q) * ld, q);
+            else tridiagonalize(H + size_t(q) * ld + q, ld, nt, S);
+            tridiag_bounds(nt, S);
+        }
+        if (bordered && gmax > 0.0) {
+            // K = [D, C; C^T, T] is similar to G; lambda_max(K) >= lambda_max(T) (interlacing)
+            for (int i = tid; i < nt; i += NT)
+                for (int r = 0; r < q; ++r) S.bord[r][i] = H[r + size_t(q + i) * ld];
+            if (tid < 16) {
+                const int a = tid % 4, b = tid / 4;
+                S.dq[tid] = (a < q && b < q) ? H[a + size_t(b) * ld] : 0.0;
+            }
+            if (nt == 0 && tid == 0) S.scal[2] = 1e-300;
+            __syncthreads();
+            const double lam_t = (nt > 0) ? largest_eigenvalue(nt, S) : 0.0;
+            const double tn = (nt > 0) ? S.scal[3] : 0.0;
+            const double lo = lam_t - 4.0 * DBL_EPSILON * fmax(tn, fro) - 1e-300;
+            const double hi = fro * (1.0 + 1e-12) + 1e-300;
+            lam_max = bordered_largest(nt, q, lo, hi, S);
         }
     }
     stamp(4);
@@ -468,7 +599,9 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
     for (int c = c0; c < c1; ++c) {
         for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
         for (int it = 0; it < 3; ++it) {
+            wave_sync();
             if (lane == 0) tridiag_shift_solve(d, e, nn, lam[c], tiny, y, u0, u1, u2);
+            wave_sync();
             for (int pass = 0; pass < 2; ++pass)
                 for (int b = c0; b < c; ++b) {
                     const double* yb = T.U + size_t(q + b) * m + q;
@@ -486,6 +619,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
         double* col = T.U + size_t(q + c) * m + q;
         for (int i = lane; i < nn; i += WAVE) col[i] = y[i];
     }
+    wave_sync();        // lane l reads entries that lane l - q wrote
     // back-transformation of each member, vector in registers: x_full = [0_q; y]
     for (int c = c0; c < c1; ++c) {
         double* u = T.U + size_t(q + c) * m;
@@ -542,7 +676,7 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     if (max_m > CMP_MAX)
         throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
     {
-        ProfScope ps("k_comp_reduce", flops, s);
+        ProfScope ps(lds ? "k_comp_reduce<true, 128>" : "k_comp_reduce<false, 512>", flops, s);
         if (lds) {
             if (max_m > CMP_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS compression too large"};
             static bool attr = false;

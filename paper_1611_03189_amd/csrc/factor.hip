@@ -97,7 +97,8 @@ struct Batch {
             for (CholTask c : chol) {
                 if ((c.m > LDS_MAX_M) != bool(big)) continue;
                 if (big) c.work = P.spool.alloc_n<double>(size_t(c.m) * c.m);
-                flops += double(c.m) * c.m * c.m;   // potrf m^3/3 + inverse 2m^3/3
+                // potrf m^3/3 + triangular inverse m^3/3 (+ X^T X, m^3/3, in the LDS kernel)
+                flops += (big ? 2.0 / 3.0 : 1.0) * double(c.m) * c.m * c.m;
                 max_m = std::max(max_m, c.m);
                 part.push_back(c);
             }
@@ -345,14 +346,15 @@ void factor(Plan& P, const double* d_values_in) {
             B.flush_copies(P);
             B.flush_gemm(P);
             for (int big = 0; big < 2; ++big) {
-                // counted work: tridiagonalisation 4/3 m^3 (twice for GC) + back-transform 2 m^2 k
+                // counted work of the reduction kernel: one Householder tridiagonalisation,
+                // 4/3 m^3 (two when GC keeps more than four vectors)
                 std::vector<CompressTask> part;
                 double cflops = 0.0;
                 int max_m = 0;
                 for (const CompressTask& ct : ctasks) {
                     if ((ct.m > LDS_MAX_M) != bool(big)) continue;
                     const double m3 = double(ct.m) * ct.m * ct.m;
-                    cflops += (gc ? 8.0 / 3.0 : 4.0 / 3.0) * m3 + 2.0 * m3 / 2.0;
+                    cflops += ((gc && ct.nz > 4) ? 8.0 / 3.0 : 4.0 / 3.0) * m3;
                     max_m = std::max(max_m, ct.m);
                     part.push_back(ct);
                 }

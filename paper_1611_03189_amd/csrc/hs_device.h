@@ -24,6 +24,13 @@ __device__ inline double wave_max(double v) {
     return v;
 }
 
+// Orders the memory accesses of the lanes of one wave around divergent code (a result that
+// one lane wrote to LDS is read by the others afterwards).
+__device__ inline void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
+
 // block-wide sum; `red` must hold NT/WAVE doubles; result valid in every thread
 __device__ inline double block_sum(double v, double* red) {
     v = wave_sum(v);

@@ -96,6 +96,21 @@ def test_gc_eigenvector_phi_on_gpu():
     S.close()
 
 
+def test_gc_three_vectors_on_gpu():
+    # three preserved vectors: up to six kept basis columns per node
+    say("gc_eigenvector_p3")
+    N = 24
+    p = pb.poisson(N, 2)
+    lam, V = np.linalg.eigh(p.dense())
+    phi = np.asfortranarray(V[:, :3])
+    F, S, r, z_ref, z = run_pair(p, 8, 0.1, "gc", phi=phi)
+    assert rel(z, z_ref) <= TOL
+    for j in range(3):
+        zj = S.apply(torch.from_numpy(p.dense() @ phi[:, j]).cuda()).cpu().numpy()
+        assert np.max(np.abs(zj - phi[:, j])) < 1e-10
+    S.close()
+
+
 def test_multiple_rhs_equal_single():
     say("multi_rhs")
     p = pb.poisson(32, 2)
