@@ -11,14 +11,18 @@
 //           lambda > eps^2 lambda_max(G), mapped back by W^T; U = [U1, U2].
 // Eigen-solver, three kernels per batch of nodes:
 //   k_comp_reduce  (one workgroup per node) scale G by its largest entry (decisions are
-//                  relative), Householder tridiagonalisation (in LDS when m <= CMP_LDS_MAX),
-//                  lambda_max by parallel multisection, GC basis and projection, second
-//                  tridiagonalisation, number k2 of kept eigenvalues (Sturm count);
+//                  relative); GC basis and projection; Householder tridiagonalisation of the
+//                  projected matrix (unblocked in LDS when m <= CMP_LDS_MAX, blocked by
+//                  panels of TRI_NB reflectors for larger m). lambda_max(G): for GC with at
+//                  most four kept vectors by multisection on the tridiagonal form bordered
+//                  by the kept directions, which is similar to G; otherwise G itself is
+//                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
 //   k_comp_bisect  (many workgroups) each kept eigenvalue by bisection to eps ||T||;
 //   k_comp_vectors (many workgroups, one wave per cluster of eigenvalues closer than
 //                  1e-7 ||T||) inverse iteration in LDS, members orthogonalised against
 //                  each other, then back-transformation with the vector held in registers.
 #include <cfloat>
+#include <type_traits>
 
 #include "hs_device.h"
 
@@ -31,8 +35,9 @@ constexpr int CMP_RMAX = CMP_MAX / WAVE;   // vector entries per lane in the bac
 // Per-node global work layout (doubles): reflectors H (m x m, ld m) | d, e, tau, lam (4m) |
 // GC reflectors (16 m) + their tau (16) | info (8).
 struct CmpWork {
-    double *H, *d, *e, *tau, *lam, *gcv, *gct, *info;
-    __device__ CmpWork(double* w, int m) {
+    HS_G double *H, *d, *e, *tau, *lam, *gcv, *gct, *info;
+    __device__ CmpWork(double* wg, int m) {
+        HS_G double* w = gp(wg);
         H = w;
         d = w + size_t(m) * m;
         e = d + m;
@@ -47,8 +52,8 @@ enum { INF_Q, INF_K2, INF_NN, INF_TNORM, INF_PIVMIN, INF_LO, INF_HI, INF_DONE };
 
 template <int MAXN>
 struct CmpShared {
-    double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN], lam[MAXN];
-    int clus[MAXN];
+    double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN];
+    double tt[32];
     double bord[4][MAXN];      // GC border rows C (q <= 4) of the bordered tridiagonal
     double dq[16];             // its leading q x q block D
     double red[NT / WAVE];
@@ -59,7 +64,8 @@ struct CmpShared {
 };
 
 // sum_l A(0, l) x[l] for the row starting at A (column stride ld), eight loads in flight
-__device__ inline double dot_rows(const double* A, int ld, const double* x, int len) {
+template <class PA, class PX>
+__device__ inline double dot_rows(PA A, int ld, PX x, int len) {
     double a[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     int l = 0;
     for (; l + 8 <= len; l += 8) {
@@ -71,8 +77,8 @@ __device__ inline double dot_rows(const double* A, int ld, const double* x, int 
 }
 
 // A(0, l) -= vi w[l] + wi v[l] along one row (column stride ld)
-__device__ inline void rank2_row(double* A, int ld, double vi, double wi, const double* v,
-                                 const double* w, int len) {
+template <class PA, class PV, class PW>
+__device__ inline void rank2_row(PA A, int ld, double vi, double wi, PV v, PW w, int len) {
     int l = 0;
     for (; l + 8 <= len; l += 8) {
         double t[8];
@@ -164,18 +170,193 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bd = nu
     __syncthreads();
 }
 
-// x <- Q x with the reflectors left in H (one wave)
-__device__ void backtransform_wave(const double* H, int ld, int nn, const double* tau, double* x) {
-    const int lane = threadIdx.x % WAVE;
-    for (int j = nn - 3; j >= 0; --j) {
-        const double tj = tau[j];
-        if (tj == 0.0) continue;
-        const double* col = H + size_t(j) * ld;
-        double part = 0.0;
-        for (int i = j + 1 + lane; i < nn; i += WAVE) part += ((i == j + 1) ? 1.0 : col[i]) * x[i];
-        const double dot = wave_sum(part) * tj;
-        for (int i = j + 1 + lane; i < nn; i += WAVE) x[i] -= dot * ((i == j + 1) ? 1.0 : col[i]);
+// Blocked form of tridiagonalize for matrices in global memory (same outputs): reflectors
+// are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
+// updated, its product with each new reflector is corrected with the panel's earlier
+// reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
+// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
+// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+constexpr int TRI_NB = 12;
+
+// One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
+// stride ld), rows lane + 64 k for k < KM. Columns are taken SB at a time with all SB x KM
+// loads issued before the products, so that one round trip to memory serves them all.
+template <int KM>
+__device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
+                                 int lane, double* acc) {
+    constexpr int SB = (KM <= 4) ? 16 : 8;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    int rr[KM];
+#pragma unroll
+    for (int k = 0; k < KM; ++k) rr[k] = min(lane + WAVE * k, len - 1);
+    for (int l0 = cb; l0 < ce; l0 += SB) {
+        double a[SB][KM];
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const HS_G double* cl = A + size_t(min(l0 + u, ce - 1)) * ld;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) a[u][k] = cl[rr[k]];
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) {
+            const double vl = (l0 + u < ce) ? v[l0 + u] : 0.0;
+#pragma unroll
+            for (int k = 0; k < KM; ++k) acc[k] += a[u][k] * vl;
+        }
     }
+#pragma unroll
+    for (int k = 0; k < KM; ++k)
+        if (lane + WAVE * k >= len) acc[k] = 0.0;
+}
+
+
+template <class SH>
+__device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, HS_G double* Bd, int nbr,
+                                   double* Vl, double* Wl, double* Pp) {
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int nref = nn - 2;
+    for (int j0 = 0; j0 < nref; j0 += TRI_NB) {
+        const int nb = min(TRI_NB, nref - j0);
+        for (int i = 0; i < nb; ++i) {
+            const int j = j0 + i;
+            HS_G double* col = H + size_t(j) * ld;
+            if (i > 0) {      // column j (rows j..) brought up to date with the panel so far
+                for (int r = j + tid; r < nn; r += NT) {
+                    double a = 0.0;
+                    for (int c = 0; c < i; ++c)
+                        a += Vl[c * nn + r] * Wl[c * nn + j] + Wl[c * nn + r] * Vl[c * nn + j];
+                    col[r] -= a;
+                }
+                __syncthreads();
+            }
+            double part = 0.0;
+            for (int r = j + 2 + tid; r < nn; r += NT) part += col[r] * col[r];
+            const double xn2 = block_sum(part, S.red);
+            const double alpha = col[j + 1];
+            double tau = 0.0, beta = alpha;
+            if (xn2 > 0.0) {
+                beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
+                tau = (beta - alpha) / beta;
+                const double scal = 1.0 / (alpha - beta);
+                for (int r = j + 2 + tid; r < nn; r += NT) col[r] *= scal;
+            }
+            __syncthreads();
+            for (int r = tid; r < nn; r += NT)
+                Vl[i * nn + r] = (r <= j) ? 0.0 : (r == j + 1 ? 1.0 : (xn2 > 0.0 ? col[r] : 0.0));
+            if (tid == 0) {
+                S.tau[j] = tau;
+                S.e[j] = beta;
+            }
+            __syncthreads();
+            const int len = nn - j - 1;
+            const double* v = Vl + i * nn + (j + 1);          // trailing coordinates
+            double* wcol = Wl + i * nn;
+            if (tau != 0.0) {
+                // y = A(j+1:, j+1:) v, columns split over the waves, rows over the lanes
+                {
+                    const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
+                    const int cw = (len + 3) / 4, cb = wv * cw, ce = min(len, cb + cw);
+                    double acc[8];
+                    switch ((len + WAVE - 1) / WAVE) {     // row blocks of 64, uniform
+                        case 1: symv_part<1>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 2: symv_part<2>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 3: symv_part<3>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 4: symv_part<4>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 5: symv_part<5>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 6: symv_part<6>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        case 7: symv_part<7>(A0, ld, v, len, cb, ce, lane, acc); break;
+                        default: symv_part<8>(A0, ld, v, len, cb, ce, lane, acc); break;
+                    }
+#pragma unroll
+                    for (int k = 0; k < 8; ++k) {
+                        const int r = lane + WAVE * k;
+                        if (r < len) Pp[wv * nn + r] = acc[k];
+                    }
+                }
+                // t1 = W(j+1:, :i)^T v, t2 = V(j+1:, :i)^T v: eight lanes per product
+                {
+                    const int g = tid / 8, sub = tid % 8;
+                    double a = 0.0;
+                    if (g < 2 * i) {
+                        const double* P = (g < i) ? Wl + g * nn : Vl + (g - i) * nn;
+                        for (int r = sub; r < len; r += 8) a += P[j + 1 + r] * v[r];
+                    }
+                    a += __shfl_xor(a, 1, WAVE);
+                    a += __shfl_xor(a, 2, WAVE);
+                    a += __shfl_xor(a, 4, WAVE);
+                    if (sub == 0 && g < 2 * i) S.tt[g] = a;
+                }
+                __syncthreads();
+                double pv = 0.0;
+                for (int r = tid; r < len; r += NT) {
+                    double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
+                    for (int c = 0; c < i; ++c)
+                        y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
+                    const double w = tau * y;
+                    S.w[r] = w;
+                    pv += w * v[r];
+                }
+                const double K = 0.5 * tau * block_sum(pv, S.red);
+                for (int r = tid; r < nn; r += NT)
+                    wcol[r] = (r <= j) ? 0.0 : S.w[r - j - 1] - K * v[r - j - 1];
+                if (nbr > 0) {
+                    HS_G double* B1 = Bd + size_t(j + 1) * ld;
+                    double dots[4] = {0.0, 0.0, 0.0, 0.0};
+                    for (int l = tid; l < len; l += NT)
+                        for (int r = 0; r < nbr; ++r) dots[r] += B1[r + size_t(l) * ld] * v[l];
+                    block_sum4(dots, nbr, S.red4);
+                    for (int l = tid; l < len; l += NT)
+                        for (int r = 0; r < nbr; ++r) B1[r + size_t(l) * ld] -= tau * dots[r] * v[l];
+                }
+            } else {
+                for (int r = tid; r < nn; r += NT) wcol[r] = 0.0;
+            }
+            __syncthreads();
+        }
+        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T, 4x4 tiles
+        const int t0 = j0 + nb, tn = nn - t0, Tt = (tn + 3) / 4;
+        for (int idx = tid; idx < Tt * Tt; idx += NT) {
+            const int r0 = t0 + 4 * (idx % Tt), s0 = t0 + 4 * (idx / Tt);
+            double acc[4][4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    acc[u][w] = (r0 + u < nn && s0 + w < nn) ? H[(r0 + u) + size_t(s0 + w) * ld] : 0.0;
+            for (int c = 0; c < nb; ++c) {
+                double vr[4], wr[4], vs[4], ws[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const bool okr = r0 + u < nn, oks = s0 + u < nn;
+                    vr[u] = okr ? Vl[c * nn + r0 + u] : 0.0;
+                    wr[u] = okr ? Wl[c * nn + r0 + u] : 0.0;
+                    vs[u] = oks ? Vl[c * nn + s0 + u] : 0.0;
+                    ws[u] = oks ? Wl[c * nn + s0 + u] : 0.0;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) acc[u][w] -= vr[u] * ws[w] + wr[u] * vs[w];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int w = 0; w < 4; ++w)
+                    if (r0 + u < nn && s0 + w < nn) H[(r0 + u) + size_t(s0 + w) * ld] = acc[u][w];
+        }
+        __syncthreads();
+    }
+    for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
+    if (tid == 0) {
+        if (nn >= 2) {
+            S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
+            S.tau[nn - 2] = 0.0;
+        }
+        S.e[nn - 1] = 0.0;
+        S.tau[nn - 1] = 0.0;
+    }
+    __syncthreads();
 }
 
 // number of eigenvalues of the tridiagonal (d, e) below x
@@ -364,8 +545,8 @@ __device__ inline double start_value(int i, int c) {
 }
 
 // Two-sided application of I - tau v v^T to the symmetric m x m matrix H.
-template <class SH>
-__device__ void reflect_two_sided(double* H, int ld, int m, const double* v, double tau, SH& S) {
+template <class SH, class PH, class PV>
+__device__ void reflect_two_sided(PH H, int ld, int m, PV v, double tau, SH& S) {
     const int tid = threadIdx.x;
     double pv_part = 0.0;
     for (int i = tid; i < m; i += NT) {
@@ -390,19 +571,28 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     const int m = T.m, tid = threadIdx.x;
     CmpWork Wk(T.work, m);
     const int ld = LDS ? m + 1 : m;
-    double* H = LDS ? lds : Wk.H;
-    double* U = T.U;
+    using HPtr = typename std::conditional<LDS, double*, HS_G double*>::type;
+    HPtr H;
+    if constexpr (LDS) H = lds;
+    else H = Wk.H;
+    HS_G double* U = gp(T.U);
+    const HS_G double* G = gp(T.G);
+    // Householder tridiagonalisation: unblocked in LDS, blocked for global matrices
+    auto tri = [&](HPtr A, int n, HPtr Bd, int nbr) {
+        if constexpr (LDS) tridiagonalize(A, ld, n, S, Bd, nbr);
+        else tridiagonalize_blk(A, ld, n, S, Bd, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN);
+    };
     auto stamp = [&](int k) {
         if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
     };
     stamp(0);
     double gm = 0.0;
-    for (int e = tid; e < m * m; e += NT) gm = fmax(gm, fabs(T.G[e]));
+    for (int e = tid; e < m * m; e += NT) gm = fmax(gm, fabs(G[e]));
     const double gmax = block_max(gm, S.red);
     const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
     double fro = 0.0;
     for (int e = tid; e < m * m; e += NT) {
-        const double g = T.G[e] * gscale;
+        const double g = G[e] * gscale;
         H[(e % m) + (e / m) * ld] = g;
         fro += g * g;
     }
@@ -413,7 +603,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     const bool bordered = variant == HSOLVE_GC && T.nz <= 4;
     double lam_max = 0.0;
     if (!bordered) {
-        tridiagonalize(H, ld, m, S);
+        tri(H, m, nullptr, 0);
         tridiag_bounds(m, S);
         lam_max = (gmax > 0.0) ? largest_eigenvalue(m, S) : 0.0;
     }
@@ -422,8 +612,8 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     int q = 0;
     if (variant == HSOLVE_GC) {
         for (int c = 0; c < T.nz && q < m; ++c) {
-            const double* z = T.Z + size_t(c) * m;
-            double* u = U + size_t(q) * m;
+            const HS_G double* z = gp(T.Z) + size_t(c) * m;
+            HS_G double* u = U + size_t(q) * m;
             double part = 0.0;
             for (int i = tid; i < m; i += NT) {
                 u[i] = z[i];
@@ -433,7 +623,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             if (nz == 0.0) continue;
             for (int pass = 0; pass < 2; ++pass)
                 for (int b = 0; b < q; ++b) {
-                    const double* ub = U + size_t(b) * m;
+                    const HS_G double* ub = U + size_t(b) * m;
                     double pp = 0.0;
                     for (int i = tid; i < m; i += NT) pp += ub[i] * u[i];
                     const double dot = block_sum(pp, S.red);
@@ -451,14 +641,14 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         }
         // reflectors H_t with (H_{q-1}..H_0) U1 = [R; 0]; project G on the complement of U1
         if (!bordered)
-            for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = T.G[e] * gscale;
+            for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = G[e] * gscale;
         __syncthreads();
         double* x = S.v;        // free until the next tridiagonalisation
         for (int t = 0; t < q; ++t) {
             for (int i = tid; i < m; i += NT) x[i] = U[i + size_t(t) * m];
             __syncthreads();
             for (int b = 0; b < t; ++b) {
-                const double* vb = Wk.gcv + size_t(b) * m;
+                const HS_G double* vb = Wk.gcv + size_t(b) * m;
                 double pp = 0.0;
                 for (int i = tid; i < m; i += NT) pp += vb[i] * x[i];
                 const double dot = block_sum(pp, S.red) * Wk.gct[b];
@@ -469,7 +659,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             for (int i = t + 1 + tid; i < m; i += NT) part += x[i] * x[i];
             const double xn2 = block_sum(part, S.red);
             const double alpha = x[t];
-            double* vt = Wk.gcv + size_t(t) * m;
+            HS_G double* vt = Wk.gcv + size_t(t) * m;
             double tau = 0.0;
             if (xn2 > 0.0) {
                 const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
@@ -485,8 +675,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         }
         const int nt = m - q;
         if (nt > 0) {
-            if (bordered) tridiagonalize(H + size_t(q) * ld + q, ld, nt, S, H + size_t(q) * ld, q);
-            else tridiagonalize(H + size_t(q) * ld + q, ld, nt, S);
+            tri(H + size_t(q) * ld + q, nt, bordered ? H + size_t(q) * ld : nullptr, bordered ? q : 0);
             tridiag_bounds(nt, S);
         }
         if (bordered && gmax > 0.0) {
@@ -587,7 +776,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
     if (c0 >= k2) return;
     const double tnorm = Wk.info[INF_TNORM];
     const double ctol = 1e-7 * tnorm;
-    const double* lam = Wk.lam;
+    const HS_G double* lam = Wk.lam;
     if (c0 > 0 && lam[c0 - 1] - lam[c0] <= ctol) return;     // not a cluster leader
     int c1 = c0 + 1;
     while (c1 < k2 && lam[c1 - 1] - lam[c1] <= ctol) ++c1;
@@ -604,7 +793,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
             wave_sync();
             for (int pass = 0; pass < 2; ++pass)
                 for (int b = c0; b < c; ++b) {
-                    const double* yb = T.U + size_t(q + b) * m + q;
+                    const HS_G double* yb = gp(T.U) + size_t(q + b) * m + q;
                     double part = 0.0;
                     for (int i = lane; i < nn; i += WAVE) part += yb[i] * y[i];
                     const double dot = wave_sum(part);
@@ -616,13 +805,13 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
             const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
             for (int i = lane; i < nn; i += WAVE) y[i] *= inv;
         }
-        double* col = T.U + size_t(q + c) * m + q;
+        HS_G double* col = gp(T.U) + size_t(q + c) * m + q;
         for (int i = lane; i < nn; i += WAVE) col[i] = y[i];
     }
     wave_sync();        // lane l reads entries that lane l - q wrote
     // back-transformation of each member, vector in registers: x_full = [0_q; y]
     for (int c = c0; c < c1; ++c) {
-        double* u = T.U + size_t(q + c) * m;
+        HS_G double* u = gp(T.U) + size_t(q + c) * m;
         double x[CMP_RMAX];
 #pragma unroll
         for (int r = 0; r < CMP_RMAX; ++r) {
@@ -633,7 +822,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
             const double tj = Wk.tau[j];
             if (tj == 0.0) continue;
             const int col0 = q + j;                 // reflector column in m-dim coordinates
-            const double* hc = Wk.H + size_t(col0) * m;
+            const HS_G double* hc = Wk.H + size_t(col0) * m;
             double v[CMP_RMAX];
             double part = 0.0;
 #pragma unroll
@@ -649,7 +838,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
         for (int t = q - 1; t >= 0; --t) {
             const double tt = Wk.gct[t];
             if (variant != HSOLVE_GC || tt == 0.0) continue;
-            const double* vt = Wk.gcv + size_t(t) * m;
+            const HS_G double* vt = Wk.gcv + size_t(t) * m;
             double part = 0.0;
             double v[CMP_RMAX];
 #pragma unroll
@@ -691,7 +880,14 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
                                d_tasks, variant, eps, d_rank);
             check_launch("k_comp_reduce<lds>");
         } else {
-            hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(NT), 0, s, d_tasks,
+            const size_t bytes = size_t(2 * TRI_NB + 4) * CMP_MAX * sizeof(double);
+            static bool attr = false;
+            if (!attr) {
+                HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+                attr = true;
+            }
+            hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(NT), bytes, s, d_tasks,
                                variant, eps, d_rank);
             check_launch("k_comp_reduce<global>");
         }

@@ -131,6 +131,7 @@ void factor(Plan& P, const double* d_values_in) {
 
     P.factored = false;
     P.d_V = nullptr;
+    P.d_X = nullptr;
     P.V_cols = 0;
     P.d_krylov = nullptr;
     P.krylov_cols = 0;

@@ -8,6 +8,14 @@ namespace hs {
 constexpr int NT = 256;          // threads per workgroup (4 waves)
 constexpr int WAVE = 64;
 
+// Global-memory pointers with an explicit address space. Pointers read from task tables
+// are otherwise generic, and the compiler emits flat accesses for them; a flat load also
+// counts against the LDS wait counter, so every LDS read in a loop would wait for all
+// outstanding global loads. Hot loops access global memory through HS_G pointers.
+#define HS_G __attribute__((address_space(1)))
+template <class T> __device__ inline HS_G T* gp(T* p) { return (HS_G T*)p; }
+template <class T> __device__ inline const HS_G T* gp(const T* p) { return (const HS_G T*)p; }
+
 inline void check_launch(const char* name) {
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess)

@@ -208,15 +208,15 @@ struct FwdContrib {
     int ldG, m;
 };
 
-struct BwdNode {             // x_s = Gm^T [phi_s; -x_N; x_r], written at dst
+struct BwdNode {             // x_s = Gm^T [phi_s; -x_N; x_r], written at dst of X
     const double* G;
     long long dst;
     int ldG, m, rows, seg_begin, seg_end, pad;
 };
 
-struct BwdSeg {
+struct BwdSeg {              // sign * (buf ? X : V)[off .. off + len)
     long long off;
-    int len, sign;
+    int len, sign, buf, pad;
 };
 
 // ---------------------------------------------------------------------------------
@@ -262,11 +262,12 @@ struct Plan {
         double fwd_bytes = 0.0, bwd_bytes = 0.0;   // algorithmic bytes per rhs
         FwdTarget* fwd_t = nullptr; int nfwd = 0; int max_len = 0;
         FwdContrib* fwd_c = nullptr;
-        BwdNode* bwd_n = nullptr; int nbwd = 0;
+        BwdNode* bwd_n = nullptr; int nbwd = 0; int max_m = 0;
         BwdSeg* bwd_s = nullptr;
     };
     std::vector<std::vector<ColourSched>> sched;   // sched[d][c]
-    double* d_V = nullptr;
+    double* d_V = nullptr;                          // forward right-hand sides (phi)
+    double* d_X = nullptr;                          // backward solutions (x)
     int V_cols = 0;
     double* d_scalars = nullptr;                    // dot-product results
     double* h_scalars = nullptr;                    // pinned
@@ -305,10 +306,10 @@ void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const d
                          const int32_t* super_first, double* const* blk_ptr,
                          const int32_t* blk_ld, const int32_t* blk_col,
                          const int32_t* blk_begin, int n, hipStream_t s);
-void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, double* V, int64_t ldv,
-                int nrhs, double bytes, hipStream_t s);
-void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, double* V, int64_t ldv,
-                int nrhs, int max_rows, double bytes, hipStream_t s);
+void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, double* V,
+                int64_t ldv, int nrhs, double bytes, hipStream_t s);
+void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const double* V,
+                double* X, int64_t ldv, int nrhs, double bytes, hipStream_t s);
 void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, const int32_t* perm,
                         int n, int nrhs, hipStream_t s);   // dst[p] = src[perm[p]]
 void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,

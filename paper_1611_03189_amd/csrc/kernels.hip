@@ -2,7 +2,7 @@
 //
 //  k_copy        batched 2-D block copies (optional transpose)          block gather / merge
 //  k_gemm        grouped GEMM over tile lists, C = bC + a sum op(A)op(B) Gram, Schur, T_N, L_nr, R
-//  (pivot.hip: k_chol_inv; compress.hip: k_compress)
+//  (pivot.hip: k_chol_inv*; compress.hip: k_comp_*)
 //  k_fwd / k_bwd level sweeps of the solve phase                        apply
 //  k_spmv, k_dot*, k_axpy2, k_xpby, gathers/scatters                    outer PCG
 #include <cfloat>
@@ -16,11 +16,13 @@ namespace hs {
 // ---------------------------------------------------------------------------------
 __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
     const CopyTask t = tasks[blockIdx.x];
+    const HS_G double* src = gp(t.src);
+    HS_G double* dst = gp(t.dst);
     __shared__ double tile[32][33];
     if (!t.trans) {
         for (int j = 0; j < t.cols; ++j)
             for (int i = threadIdx.x; i < t.rows; i += NT)
-                t.dst[i + size_t(j) * t.ldd] = t.src[i + size_t(j) * t.lds];
+                dst[i + size_t(j) * t.ldd] = src[i + size_t(j) * t.lds];
         return;
     }
     // dst(i,j) = src(j,i), through 32x32 tiles
@@ -29,12 +31,12 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
         for (int j0 = 0; j0 < t.cols; j0 += 32) {
             for (int r = ty; r < 32; r += 8) {           // read src rows j0+r? src is cols x rows
                 int si = j0 + tx, sj = i0 + r;               // src(si, sj)
-                if (si < t.cols && sj < t.rows) tile[r][tx] = t.src[si + size_t(sj) * t.lds];
+                if (si < t.cols && sj < t.rows) tile[r][tx] = src[si + size_t(sj) * t.lds];
             }
             __syncthreads();
             for (int r = ty; r < 32; r += 8) {
                 int di = i0 + tx, dj = j0 + r;               // dst(di, dj) = src(dj, di)
-                if (di < t.rows && dj < t.cols) t.dst[di + size_t(dj) * t.ldd] = tile[tx][r];
+                if (di < t.rows && dj < t.cols) dst[di + size_t(dj) * t.ldd] = tile[tx][r];
             }
             __syncthreads();
         }
@@ -67,6 +69,8 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
     for (int t = T.t_begin; t < T.t_end; ++t) {
         const GemmTerm g = terms[t];
+        const HS_G double* gA = gp(g.A);
+        const HS_G double* gB = gp(g.B);
         for (int k0 = 0; k0 < g.K; k0 += TK) {
             for (int e = tid; e < TM * TK; e += NT) {
                 int ii, kk;
@@ -74,7 +78,7 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
                 const int gi = i0 + ii, gk = k0 + kk;
                 double v = 0.0;
                 if (gi < T.M && gk < g.K)
-                    v = g.transA ? g.A[gk + size_t(gi) * g.lda] : g.A[gi + size_t(gk) * g.lda];
+                    v = g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda];
                 As[kk][ii] = v;
             }
             for (int e = tid; e < TN * TK; e += NT) {
@@ -83,7 +87,7 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
                 const int gj = j0 + jj, gk = k0 + kk;
                 double v = 0.0;
                 if (gj < T.N && gk < g.K)
-                    v = g.transB ? g.B[gj + size_t(gk) * g.ldb] : g.B[gk + size_t(gj) * g.ldb];
+                    v = g.transB ? gB[gj + size_t(gk) * g.ldb] : gB[gk + size_t(gj) * g.ldb];
                 Bs[kk][jj] = v;
             }
             __syncthreads();
@@ -108,7 +112,7 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
         for (int x = 0; x < 4; ++x) {
             const int i = i0 + tx + 16 * x, j = j0 + ty + 16 * y;
             if (i < T.M && j < T.N) {
-                double* c = T.C + i + size_t(j) * T.ldc;
+                HS_G double* c = gp(T.C) + i + size_t(j) * T.ldc;
                 const double old = (T.beta == 0.0) ? 0.0 : T.beta * (*c);
                 *c = old + T.alpha * acc[x][y];
             }
@@ -161,77 +165,105 @@ void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const d
 // ---------------------------------------------------------------------------------
 // Solve phase: forward (gather form) and backward sweeps of one colour
 // ---------------------------------------------------------------------------------
+// Forward, gather form: V[dst + i] += sign * sum_c G_c(i, :) V[src_c + :]. One workgroup per
+// 64 rows of a target; the four waves split the columns of every contribution.
+constexpr int FWD_ROWS = WAVE;
+
 __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdContrib* contrib,
                                             double* V, int64_t ldv, int nrhs) {
-    const FwdTarget t = targets[blockIdx.x];
+    const FwdTarget t = targets[blockIdx.y];
+    const int r0 = blockIdx.x * FWD_ROWS;
+    if (r0 >= t.len) return;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int i = r0 + lane;
     __shared__ double part[NT / WAVE][WAVE];
     for (int c = 0; c < nrhs; ++c) {
         double* Vc = V + size_t(c) * ldv;
-        for (int r0 = 0; r0 < t.len; r0 += WAVE) {
-            const int i = r0 + lane;
-            double acc = 0.0;
-            if (i < t.len) {
-                for (int q = t.c_begin; q < t.c_end; ++q) {
-                    const FwdContrib f = contrib[q];
-                    const double* x = Vc + f.src;
-                    for (int j = wv; j < f.m; j += NT / WAVE)
-                        acc += f.G[i + size_t(j) * f.ldG] * x[j];
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < t.len) {
+            for (int q = t.c_begin; q < t.c_end; ++q) {
+                const FwdContrib f = contrib[q];
+                const double* x = Vc + f.src;
+                const HS_G double* g = gp(f.G) + i;
+                int j = wv;
+                for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int jj = j + u * (NT / WAVE);
+                        acc[u] += g[size_t(jj) * f.ldG] * x[jj];
+                    }
                 }
+                for (; j < f.m; j += NT / WAVE) acc[0] += g[size_t(j) * f.ldG] * x[j];
             }
-            part[wv][lane] = acc;
-            __syncthreads();
-            if (wv == 0 && i < t.len) {
-                double s = 0.0;
-                for (int w = 0; w < NT / WAVE; ++w) s += part[w][lane];
-                Vc[t.dst + i] += t.sign * s;
-            }
-            __syncthreads();
         }
+        part[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+        __syncthreads();
+        if (wv == 0 && i < t.len) {
+            double s = 0.0;
+            for (int w = 0; w < NT / WAVE; ++w) s += part[w][lane];
+            Vc[t.dst + i] += t.sign * s;
+        }
+        __syncthreads();
     }
 }
 
-void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, double* V, int64_t ldv,
+void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, double* V, int64_t ldv,
                 int nrhs, double bytes, hipStream_t s) {
-    if (nt <= 0) return;
+    if (nt <= 0 || max_len <= 0) return;
     ProfScope ps("k_fwd", bytes, s);
-    hipLaunchKernelGGL(k_fwd, dim3(nt), dim3(NT), 0, s, t, c, V, ldv, nrhs);
+    hipLaunchKernelGGL(k_fwd, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt), dim3(NT), 0, s, t, c, V,
+                       ldv, nrhs);
     check_launch("k_fwd");
 }
 
+// Backward: x_s = Gm^T v with v = [phi_s; -x_N; x_r] gathered into LDS (phi from V, the
+// solutions from X), written to X. Each workgroup takes BWD_COLS columns of one node (two
+// per wave); every column is a wave-wide dot product with eight loads in flight per lane.
 constexpr int BWD_MAX_ROWS = 6144;
+constexpr int BWD_COLS = 8;
 
-__global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* segs, double* V,
-                                            int64_t ldv, int nrhs) {
-    const BwdNode nd = nodes[blockIdx.x];
+__global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* segs, const double* V,
+                                            double* X, int64_t ldv, int nrhs) {
+    const BwdNode nd = nodes[blockIdx.y];
+    const int j0 = blockIdx.x * BWD_COLS;
+    if (j0 >= nd.m) return;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     __shared__ double v[BWD_MAX_ROWS];
     for (int c = 0; c < nrhs; ++c) {
-        double* Vc = V + size_t(c) * ldv;
+        const double* Vc = V + size_t(c) * ldv;
+        double* Xc = X + size_t(c) * ldv;
         int pos = 0;
         for (int q = nd.seg_begin; q < nd.seg_end; ++q) {
             const BwdSeg sg = segs[q];
-            for (int i = threadIdx.x; i < sg.len; i += NT) v[pos + i] = sg.sign * Vc[sg.off + i];
+            const double* src = (sg.buf ? Xc : Vc) + sg.off;
+            for (int i = threadIdx.x; i < sg.len; i += NT) v[pos + i] = sg.sign * src[i];
             pos += sg.len;
         }
         __syncthreads();
-        for (int j = wv; j < nd.m; j += NT / WAVE) {
-            const double* g = nd.G + size_t(j) * nd.ldG;
-            double acc = 0.0;
-            for (int i = lane; i < nd.rows; i += WAVE) acc += g[i] * v[i];
-            acc = wave_sum(acc);
-            if (lane == 0) Vc[nd.dst + j] = acc;
+        for (int jj = wv; jj < BWD_COLS; jj += NT / WAVE) {
+            const int j = j0 + jj;
+            if (j >= nd.m) break;
+            const HS_G double* g = gp(nd.G) + size_t(j) * nd.ldG;
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            int i = lane;
+            for (; i + 7 * WAVE < nd.rows; i += 8 * WAVE) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) a[u] += g[i + u * WAVE] * v[i + u * WAVE];
+            }
+            for (; i < nd.rows; i += WAVE) a[0] += g[i] * v[i];
+            const double acc = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+            if (lane == 0) Xc[nd.dst + j] = acc;
         }
         __syncthreads();
     }
 }
 
-void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, double* V, int64_t ldv,
-                int nrhs, int max_rows, double bytes, hipStream_t s) {
-    if (nn <= 0) return;
+void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const double* V, double* X,
+                int64_t ldv, int nrhs, double bytes, hipStream_t s) {
+    if (nn <= 0 || max_m <= 0) return;
     ProfScope ps("k_bwd", bytes, s);
-    if (max_rows > BWD_MAX_ROWS) throw Error{HSOLVE_ERR_INVALID, "factor block too tall for k_bwd"};
-    hipLaunchKernelGGL(k_bwd, dim3(nn), dim3(NT), 0, s, nodes, segs, V, ldv, nrhs);
+    hipLaunchKernelGGL(k_bwd, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn), dim3(NT), 0, s, nodes, segs,
+                       V, X, ldv, nrhs);
     check_launch("k_bwd");
 }
 

@@ -28,9 +28,11 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     const int m = T.m, tid = threadIdx.x;
     double* W = lds;
     const int ldw = m + 1;
+    const HS_G double* A = gp(T.A);
+    HS_G double* Ainv = gp(T.Ainv);
     for (int e = tid; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
-        W[i + j * ldw] = T.A[i + size_t(j) * T.lda];
+        W[i + j * ldw] = A[i + size_t(j) * T.lda];
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -91,8 +93,8 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
         if (i < j) continue;
         double s = 0.0;
         for (int k = i; k < m; ++k) s += W[k + i * ldw] * W[k + j * ldw];
-        T.Ainv[i + size_t(j) * T.ldi] = s;
-        T.Ainv[j + size_t(i) * T.ldi] = s;
+        Ainv[i + size_t(j) * T.ldi] = s;
+        Ainv[j + size_t(i) * T.ldi] = s;
     }
 }
 
@@ -113,11 +115,12 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
-    double* W = T.work;                            // m x m, ld m
+    HS_G double* W = gp(T.work);                   // m x m, ld m
+    const HS_G double* A = gp(T.A);
     const size_t ld = size_t(m);
     for (size_t e = tid; e < ld * m; e += NT) {
         const size_t i = e % ld, j = e / ld;
-        W[e] = T.A[i + j * T.lda];
+        W[e] = A[i + j * T.lda];
     }
     if (tid == 0) bad = 0;
     __syncthreads();
@@ -248,7 +251,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
-                const double* X22 = W + (jb + nb) + (jb + nb) * ld;
+                const HS_G double* X22 = W + (jb + nb) + (jb + nb) * ld;
                 // columns l <= i0: every row of the tile takes part (rows beyond t read 0)
 #pragma unroll 1
                 for (int l = 0; l <= i0 && l < t; ++l) {

@@ -10,6 +10,9 @@
 //             (T_n = A_ns M_ss, so this is phi_n = r_n - A_ns M_ss r_s)
 //   backward  x_s = M_ss phi_s - sum_n T_n^T x_n + P_ss^T x_r(s)
 //             (= M_ss (b_s - A_sn x_n) + P_ss^T psi_r)
+// The forward sweep updates V in place; the backward sweep reads phi from V and writes the
+// solutions to a second vector X of the same layout, so the workgroups that share one node's
+// columns never read a value that another of them has already replaced.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -68,14 +71,14 @@ void build_apply_schedule(Plan& P) {
                     e.second.push_back(FwdContrib{nn.Gm + nn.m + nn.ntot, src, nn.ldG, nn.m});
                 }
                 BwdNode b{nn.Gm, src, nn.ldG, nn.m, nn.m + nn.ntot + nn.k, int(bs.size()), 0, 0};
-                bs.push_back(BwdSeg{src, nn.m, +1});
+                bs.push_back(BwdSeg{src, nn.m, +1, 0, 0});
                 for (size_t t = 0; t < S.N[s].size(); ++t) {
                     const int nb = S.N[s][t];
                     const bool red = S.Nred[s][t];
                     bs.push_back(BwdSeg{red ? LN.red_off[nb] : super_off(d, nb),
-                                        red ? LN.ksz[nb] : LN.msz[nb], -1});
+                                        red ? LN.ksz[nb] : LN.msz[nb], -1, 1, 0});
                 }
-                if (nn.k) bs.push_back(BwdSeg{LN.red_off[s], nn.k, +1});
+                if (nn.k) bs.push_back(BwdSeg{LN.red_off[s], nn.k, +1, 1, 0});
                 b.seg_end = int(bs.size());
                 bn.push_back(b);
                 max_rows = std::max(max_rows, b.rows);
@@ -105,6 +108,7 @@ void build_apply_schedule(Plan& P) {
             cs.fwd_t = P.stage.upload_vec(ft, P.apool, st);
             cs.fwd_c = P.stage.upload_vec(fc, P.apool, st);
             cs.nbwd = int(bn.size());
+            for (const BwdNode& b : bn) cs.max_m = std::max(cs.max_m, b.m);
             cs.bwd_n = P.stage.upload_vec(bn, P.apool, st);
             cs.bwd_s = P.stage.upload_vec(bs, P.apool, st);
             if (max_rows > 6144)
@@ -120,6 +124,7 @@ void build_apply_schedule(Plan& P) {
 static void ensure_V(Plan& P, int nrhs) {
     if (P.d_V && P.V_cols >= nrhs) return;
     P.d_V = P.apool.alloc_n<double>(size_t(P.vlen) * nrhs);
+    P.d_X = P.apool.alloc_n<double>(size_t(P.vlen) * nrhs);
     P.V_cols = nrhs;
 }
 
@@ -136,14 +141,15 @@ void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
     for (int d = nlev - 1; d >= 0; --d)
         for (size_t c = 0; c < P.sched[d].size(); ++c) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_fwd(cs.fwd_t, cs.fwd_c, cs.nfwd, P.d_V, ldv, nrhs, cs.fwd_bytes * nrhs, st);
+            launch_fwd(cs.fwd_t, cs.fwd_c, cs.nfwd, cs.max_len, P.d_V, ldv, nrhs, cs.fwd_bytes * nrhs, st);
         }
     for (int d = 0; d < nlev; ++d)
         for (size_t c = P.sched[d].size(); c-- > 0;) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_bwd(cs.bwd_n, cs.bwd_s, cs.nbwd, P.d_V, ldv, nrhs, 6144, cs.bwd_bytes * nrhs, st);
+            launch_bwd(cs.bwd_n, cs.bwd_s, cs.nbwd, cs.max_m, P.d_V, P.d_X, ldv, nrhs, cs.bwd_bytes * nrhs,
+                       st);
         }
-    launch_scatter_perm(P.d_V, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
+    launch_scatter_perm(P.d_X, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
 }
 
 void spmv(Plan& P, const double* x, double* y) {
