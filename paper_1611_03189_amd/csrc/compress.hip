@@ -17,7 +17,7 @@
 //                  most four kept vectors by multisection on the tridiagonal form bordered
 //                  by the kept directions, which is similar to G; otherwise G itself is
 //                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
-//   k_comp_bisect  (many workgroups) each kept eigenvalue by bisection to eps ||T||;
+//   k_comp_bisect  (many workgroups, one wave per kept eigenvalue) multisection to eps ||T||;
 //   k_comp_vectors (many workgroups, one wave per cluster of eigenvalues closer than
 //                  1e-7 ||T||) inverse iteration in LDS, members orthogonalised against
 //                  each other, then back-transformation with the vector held in registers.
@@ -58,6 +58,7 @@ struct CmpShared {
     double dq[16];             // its leading q x q block D
     double red[NT / WAVE];
     double red4[4 * (NT / WAVE)];
+    double redp[2][5 * (NT / WAVE)];    // double-buffered sums of the blocked reduction
     double scal[4];
     int iscal[4];
     int pts[NT + 1];
@@ -108,10 +109,12 @@ __device__ inline void block_sum4(double* v, int nv, double* red4) {
 // Householder tridiagonalisation of the symmetric nn x nn matrix H (column-major, ld):
 // reflector j acts on rows j+1.., its vector (first entry 1, implicit) is kept in
 // H(j+2.., j) with tau[j]; diagonal -> d, sub-diagonal -> e (e[nn-1] = 0).
-// With nbr > 0, the nbr border rows Bd (Bd[r + l ld] = entry (r, l), l < nn) are multiplied
-// on the right by every reflector, so [D, Bd; Bd^T, H] stays similar to the bordered result.
+// With nbr > 0, the nbr border rows in LDS (Bl[r bst + l] = entry (r, l), l < nn) are
+// multiplied on the right by every reflector, so [D, B; B^T, H] stays similar to the bordered
+// result.
 template <class SH>
-__device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bd = nullptr, int nbr = 0) {
+__device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nullptr, int bst = 0,
+                               int nbr = 0) {
     const int tid = threadIdx.x;
     for (int j = 0; j + 2 < nn; ++j) {
         double* col = H + size_t(j) * ld;
@@ -147,13 +150,13 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bd = nu
             __syncthreads();
             for (int i = tid; i < len; i += NT) rank2_row(T22 + i, ld, S.v[i], S.w[i], S.v, S.w, len);
             if (nbr > 0) {
-                double* B1 = Bd + size_t(j + 1) * ld;
+                double* B1 = Bl + (j + 1);
                 double dots[4] = {0.0, 0.0, 0.0, 0.0};
                 for (int l = tid; l < len; l += NT)
-                    for (int r = 0; r < nbr; ++r) dots[r] += B1[r + size_t(l) * ld] * S.v[l];
+                    for (int r = 0; r < nbr; ++r) dots[r] += B1[r * bst + l] * S.v[l];
                 block_sum4(dots, nbr, S.red4);
                 for (int l = tid; l < len; l += NT)
-                    for (int r = 0; r < nbr; ++r) B1[r + size_t(l) * ld] -= tau * dots[r] * S.v[l];
+                    for (int r = 0; r < nbr; ++r) B1[r * bst + l] -= tau * dots[r] * S.v[l];
             }
             __syncthreads();
         }
@@ -179,174 +182,283 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bd = nu
 constexpr int TRI_NB = 12;
 
 // One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
-// stride ld), rows lane + 64 k for k < KM. Columns are taken SB at a time with all SB x KM
-// loads issued before the products, so that one round trip to memory serves them all.
+// stride ld, len >= 2). Lane l takes the row pairs (2l + 128k, 2l + 128k + 1), k < KM, loaded
+// as one 16-byte access; SB columns are taken at a time with every load issued before the
+// products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
 template <int KM>
 __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
                                  int lane, double* acc) {
-    constexpr int SB = (KM <= 4) ? 16 : 8;
+    constexpr int SB = (KM <= 2) ? 16 : 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     int rr[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) rr[k] = min(lane + WAVE * k, len - 1);
+    for (int k = 0; k < KM; ++k) rr[k] = min(2 * lane + 128 * k, len - 2);
     for (int l0 = cb; l0 < ce; l0 += SB) {
-        double a[SB][KM];
+        double a[SB][KM][2];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const HS_G double* cl = A + size_t(min(l0 + u, ce - 1)) * ld;
 #pragma unroll
-            for (int k = 0; k < KM; ++k) a[u][k] = cl[rr[k]];
+            for (int k = 0; k < KM; ++k) {
+                a[u][k][0] = cl[rr[k]];
+                a[u][k][1] = cl[rr[k] + 1];
+            }
         }
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
             const double vl = (l0 + u < ce) ? v[l0 + u] : 0.0;
 #pragma unroll
-            for (int k = 0; k < KM; ++k) acc[k] += a[u][k] * vl;
+            for (int k = 0; k < KM; ++k) {
+                acc[2 * k] += a[u][k][0] * vl;
+                acc[2 * k + 1] += a[u][k][1] * vl;
+            }
         }
     }
-#pragma unroll
-    for (int k = 0; k < KM; ++k)
-        if (lane + WAVE * k >= len) acc[k] = 0.0;
 }
 
-
+// Block-wide sums of v[0..nv) (nv <= 5) with one barrier: the partial sums alternate between
+// two buffers, and a buffer is written again only after a later barrier.
 template <class SH>
-__device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, HS_G double* Bd, int nbr,
-                                   double* Vl, double* Wl, double* Pp) {
+__device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    double* red = S.redp[parity];
+    parity ^= 1;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        if (r < nv) v[r] = wave_sum(v[r]);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            if (r < nv) red[r * (NT / WAVE) + w] = v[r];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        if (r < nv) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / WAVE; ++i) t += red[r * (NT / WAVE) + i];
+            v[r] = t;
+        }
+    }
+}
+
+// Blocked form of tridiagonalize for matrices in global memory (same outputs): reflectors
+// are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
+// updated, its product with each new reflector is corrected with the panel's earlier
+// reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
+// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
+// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+template <class SH>
+__device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double* Bl, int bst, int nbr,
+                                   double* Vl, double* Wl, double* Pp, long long* prof = nullptr) {
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int nref = nn - 2;
+    int parity = 0;
+    long long pc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tprev = 0;   // trace: cycles per phase
+    auto phase = [&](int k) {
+        if (prof && tid == 0) {
+            const long long t = clock64();
+            if (k >= 0) pc[k] += t - tprev;
+            tprev = t;
+        }
+    };
+    phase(-1);
     for (int j0 = 0; j0 < nref; j0 += TRI_NB) {
         const int nb = min(TRI_NB, nref - j0);
         for (int i = 0; i < nb; ++i) {
             const int j = j0 + i;
             HS_G double* col = H + size_t(j) * ld;
-            if (i > 0) {      // column j (rows j..) brought up to date with the panel so far
-                for (int r = j + tid; r < nn; r += NT) {
-                    double a = 0.0;
-                    for (int c = 0; c < i; ++c)
-                        a += Vl[c * nn + r] * Wl[c * nn + j] + Wl[c * nn + r] * Vl[c * nn + j];
-                    col[r] -= a;
-                }
-                __syncthreads();
+            // column j (rows j..), brought up to date with the panel so far, into LDS (S.w);
+            // the squared norm of rows j+2.. on the way
+            double* cb = S.w;
+            double nrm[1] = {0.0};
+            for (int r = j + tid; r < nn; r += NT) {
+                double a = col[r];
+#pragma unroll
+                for (int c = 0; c < TRI_NB - 1; ++c)
+                    if (c < i) a -= Vl[c * nn + r] * Wl[c * nn + j] + Wl[c * nn + r] * Vl[c * nn + j];
+                cb[r] = a;
+                if (r == j) col[r] = a;             // diagonal entry d_j
+                if (r >= j + 2) nrm[0] += a * a;
             }
-            double part = 0.0;
-            for (int r = j + 2 + tid; r < nn; r += NT) part += col[r] * col[r];
-            const double xn2 = block_sum(part, S.red);
-            const double alpha = col[j + 1];
-            double tau = 0.0, beta = alpha;
+            block_sums_1b(nrm, 1, S, parity);
+            phase(0);
+            const double xn2 = nrm[0];
+            const double alpha = cb[j + 1];
+            double tau = 0.0, beta = alpha, scal = 0.0;
             if (xn2 > 0.0) {
                 beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
                 tau = (beta - alpha) / beta;
-                const double scal = 1.0 / (alpha - beta);
-                for (int r = j + 2 + tid; r < nn; r += NT) col[r] *= scal;
+                scal = 1.0 / (alpha - beta);
             }
-            __syncthreads();
-            for (int r = tid; r < nn; r += NT)
-                Vl[i * nn + r] = (r <= j) ? 0.0 : (r == j + 1 ? 1.0 : (xn2 > 0.0 ? col[r] : 0.0));
+            // reflector: kept in H(j+2.., j) for the back-transformation and in Vl(:, i)
+            for (int r = tid; r < nn; r += NT) {
+                const double vr = (r <= j) ? 0.0 : (r == j + 1 ? 1.0 : cb[r] * scal);
+                Vl[i * nn + r] = vr;
+                if (r >= j + 2) col[r] = vr;
+            }
             if (tid == 0) {
                 S.tau[j] = tau;
                 S.e[j] = beta;
             }
             __syncthreads();
+            phase(1);
             const int len = nn - j - 1;
             const double* v = Vl + i * nn + (j + 1);          // trailing coordinates
             double* wcol = Wl + i * nn;
             if (tau != 0.0) {
-                // y = A(j+1:, j+1:) v, columns split over the waves, rows over the lanes
+                // y = A(j+1:, j+1:) v, columns split over the waves, row pairs over the lanes
                 {
                     const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
-                    const int cw = (len + 3) / 4, cb = wv * cw, ce = min(len, cb + cw);
+                    const int cw = (len + 3) / 4, cbeg = wv * cw, cend = min(len, cbeg + cw);
                     double acc[8];
-                    switch ((len + WAVE - 1) / WAVE) {     // row blocks of 64, uniform
-                        case 1: symv_part<1>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 2: symv_part<2>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 3: symv_part<3>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 4: symv_part<4>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 5: symv_part<5>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 6: symv_part<6>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        case 7: symv_part<7>(A0, ld, v, len, cb, ce, lane, acc); break;
-                        default: symv_part<8>(A0, ld, v, len, cb, ce, lane, acc); break;
+                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
+                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        case 2: symv_part<2>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        case 3: symv_part<3>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        default: symv_part<4>(A0, ld, v, len, cbeg, cend, lane, acc); break;
                     }
 #pragma unroll
-                    for (int k = 0; k < 8; ++k) {
-                        const int r = lane + WAVE * k;
-                        if (r < len) Pp[wv * nn + r] = acc[k];
+                    for (int k = 0; k < 4; ++k) {
+                        const int r0 = 2 * lane + 128 * k;
+                        if (r0 < len) {
+                            if (r0 <= len - 2) {
+                                Pp[wv * nn + r0] = acc[2 * k];
+                                Pp[wv * nn + r0 + 1] = acc[2 * k + 1];
+                            } else {                        // last row of an odd length
+                                Pp[wv * nn + r0] = acc[2 * k + 1];
+                            }
+                        }
                     }
                 }
                 // t1 = W(j+1:, :i)^T v, t2 = V(j+1:, :i)^T v: eight lanes per product
                 {
                     const int g = tid / 8, sub = tid % 8;
-                    double a = 0.0;
+                    double a0 = 0.0, a1 = 0.0;
                     if (g < 2 * i) {
-                        const double* P = (g < i) ? Wl + g * nn : Vl + (g - i) * nn;
-                        for (int r = sub; r < len; r += 8) a += P[j + 1 + r] * v[r];
+                        const double* P = (g < i) ? Wl + g * nn + j + 1 : Vl + (g - i) * nn + j + 1;
+                        int r = sub;
+#pragma unroll 4
+                        for (; r + 8 < len; r += 16) {
+                            a0 += P[r] * v[r];
+                            a1 += P[r + 8] * v[r + 8];
+                        }
+                        for (; r < len; r += 8) a0 += P[r] * v[r];
                     }
+                    double a = a0 + a1;
                     a += __shfl_xor(a, 1, WAVE);
                     a += __shfl_xor(a, 2, WAVE);
                     a += __shfl_xor(a, 4, WAVE);
                     if (sub == 0 && g < 2 * i) S.tt[g] = a;
                 }
                 __syncthreads();
-                double pv = 0.0;
+                phase(2);
+                double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 for (int r = tid; r < len; r += NT) {
                     double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
-                    for (int c = 0; c < i; ++c)
-                        y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
+#pragma unroll
+                    for (int c = 0; c < TRI_NB - 1; ++c)
+                        if (c < i) y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
                     const double w = tau * y;
                     S.w[r] = w;
-                    pv += w * v[r];
+                    pv[0] += w * v[r];
                 }
-                const double K = 0.5 * tau * block_sum(pv, S.red);
+                // v^T w and the border rows' products with v, one reduction
+                double* B1 = nbr ? Bl + (j + 1) : nullptr;
+                for (int l = tid; l < len; l += NT) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < nbr) pv[1 + r] += B1[r * bst + l] * v[l];
+                }
+                block_sums_1b(pv, 1 + nbr, S, parity);
+                phase(3);
+                const double K = 0.5 * tau * pv[0];
                 for (int r = tid; r < nn; r += NT)
                     wcol[r] = (r <= j) ? 0.0 : S.w[r - j - 1] - K * v[r - j - 1];
-                if (nbr > 0) {
-                    HS_G double* B1 = Bd + size_t(j + 1) * ld;
-                    double dots[4] = {0.0, 0.0, 0.0, 0.0};
-                    for (int l = tid; l < len; l += NT)
-                        for (int r = 0; r < nbr; ++r) dots[r] += B1[r + size_t(l) * ld] * v[l];
-                    block_sum4(dots, nbr, S.red4);
-                    for (int l = tid; l < len; l += NT)
-                        for (int r = 0; r < nbr; ++r) B1[r + size_t(l) * ld] -= tau * dots[r] * v[l];
+                for (int l = tid; l < len; l += NT) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < nbr) B1[r * bst + l] -= tau * pv[1 + r] * v[l];
                 }
             } else {
                 for (int r = tid; r < nn; r += NT) wcol[r] = 0.0;
             }
             __syncthreads();
+            phase(4);
         }
-        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T, 4x4 tiles
-        const int t0 = j0 + nb, tn = nn - t0, Tt = (tn + 3) / 4;
-        for (int idx = tid; idx < Tt * Tt; idx += NT) {
-            const int r0 = t0 + 4 * (idx % Tt), s0 = t0 + 4 * (idx / Tt);
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w)
-                    acc[u][w] = (r0 + u < nn && s0 + w < nn) ? H[(r0 + u) + size_t(s0 + w) * ld] : 0.0;
-            for (int c = 0; c < nb; ++c) {
-                double vr[4], wr[4], vs[4], ws[4];
+        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T: 64 x 64 block tiles,
+        // thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w (LDS reads of
+        // consecutive rows by consecutive lanes, no bank conflicts); clamped reads at the edge
+        {
+            const int t0 = j0 + nb, tn = nn - t0, Tb = (tn + 63) / 64;
+            const int tx = tid % 16, ty = tid / 16;
+            // tile bt + 1 is loaded before tile bt is computed
+            auto tile_idx = [&](int bt, int* ri, int* si, bool* okr, bool* oks) {
+                const int rb = t0 + 64 * (bt % Tb), sb = t0 + 64 * (bt / Tb);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    const bool okr = r0 + u < nn, oks = s0 + u < nn;
-                    vr[u] = okr ? Vl[c * nn + r0 + u] : 0.0;
-                    wr[u] = okr ? Wl[c * nn + r0 + u] : 0.0;
-                    vs[u] = oks ? Vl[c * nn + s0 + u] : 0.0;
-                    ws[u] = oks ? Wl[c * nn + s0 + u] : 0.0;
+                    okr[u] = rb + tx + 16 * u < nn;
+                    oks[u] = sb + ty + 16 * u < nn;
+                    ri[u] = min(rb + tx + 16 * u, nn - 1);
+                    si[u] = min(sb + ty + 16 * u, nn - 1);
+                }
+            };
+            int ri[4], si[4], rn[4], sn[4];
+            bool okr[4], oks[4], okrn[4], oksn[4];
+            double nxt[4][4];
+            if (Tb > 0) {
+                tile_idx(0, rn, sn, okrn, oksn);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
+            }
+            for (int bt = 0; bt < Tb * Tb; ++bt) {
+                double acc[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    ri[u] = rn[u];
+                    si[u] = sn[u];
+                    okr[u] = okrn[u];
+                    oks[u] = oksn[u];
+#pragma unroll
+                    for (int w = 0; w < 4; ++w) acc[u][w] = nxt[u][w];
+                }
+                if (bt + 1 < Tb * Tb) {
+                    tile_idx(bt + 1, rn, sn, okrn, oksn);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
+                }
+                for (int c = 0; c < nb; ++c) {
+                    double vr[4], wr[4], vs[4], ws[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        vr[u] = Vl[c * nn + ri[u]];
+                        wr[u] = Wl[c * nn + ri[u]];
+                        vs[u] = Vl[c * nn + si[u]];
+                        ws[u] = Wl[c * nn + si[u]];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int w = 0; w < 4; ++w) acc[u][w] -= vr[u] * ws[w] + wr[u] * vs[w];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) acc[u][w] -= vr[u] * ws[w] + wr[u] * vs[w];
+                    for (int w = 0; w < 4; ++w)
+                        if (okr[u] && oks[w]) H[ri[u] + size_t(si[w]) * ld] = acc[u][w];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int w = 0; w < 4; ++w)
-                    if (r0 + u < nn && s0 + w < nn) H[(r0 + u) + size_t(s0 + w) * ld] = acc[u][w];
         }
         __syncthreads();
+        phase(5);
     }
+    if (prof && tid == 0)
+        for (int k = 0; k < 6; ++k) prof[k] = pc[k];
     for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
     if (tid == 0) {
         if (nn >= 2) {
@@ -433,9 +545,9 @@ __device__ int bordered_count_above(const double* d, const double* e, int nn,
         for (int b = 0; b < 4; ++b) sc[a][b] = (a < q && b < q) ? D[a + 4 * b] - (a == b ? x : 0.0) : 0.0;
     }
     int cnt = 0;
-    double pp = 1.0, eprev = 0.0;
+    double ipp = 0.0, eprev = 0.0;          // 1 / previous pivot, previous off-diagonal
     for (int i = 0; i < nn; ++i) {
-        const double l = (i > 0) ? eprev / pp : 0.0;
+        const double l = eprev * ipp;
         double p = d[i] - x - l * eprev;
         if (fabs(p) < pivmin) p = -pivmin;
         if (p > 0.0) ++cnt;
@@ -448,7 +560,7 @@ __device__ int bordered_count_above(const double* d, const double* e, int nn,
 #pragma unroll
             for (int b = a; b < 4; ++b)
                 if (b < q) sc[a][b] -= z[a] * z[b] * ip;
-        pp = p;
+        ipp = ip;
         eprev = e[i];
     }
 #pragma unroll
@@ -466,44 +578,115 @@ __device__ int bordered_count_above(const double* d, const double* e, int nn,
     return cnt;
 }
 
-// largest eigenvalue of the bordered matrix by multisection of [lo, hi] (lo below it)
+// Counts of eigenvalues above x[0..NX) of the bordered matrix for a border of at most two
+// rows: the same recurrences as bordered_count_above, NX interleaved so that their
+// division chains overlap.
+template <int NX, int MAXN>
+__device__ void bordered_counts2(const double* d, const double* e, int nn, const double (*C)[MAXN],
+                                 const double* D, int q, const double* x, double pivmin, int* cnt) {
+    double s00[NX], s01[NX], s11[NX], z0[NX], z1[NX], ipp[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        s00[k] = (q > 0) ? D[0] - x[k] : 0.0;
+        s01[k] = (q > 1) ? D[4] : 0.0;
+        s11[k] = (q > 1) ? D[5] - x[k] : 0.0;
+        z0[k] = z1[k] = 0.0;
+        ipp[k] = 0.0;
+        cnt[k] = 0;
+    }
+    double eprev = 0.0;
+    for (int i = 0; i < nn; ++i) {
+        const double di = d[i], c0 = C[0][i], c1 = C[1][i];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            const double l = eprev * ipp[k];
+            double p = di - x[k] - l * eprev;
+            if (fabs(p) < pivmin) p = -pivmin;
+            cnt[k] += (p > 0.0);
+            const double ip = 1.0 / p;
+            z0[k] = c0 - l * z0[k];
+            z1[k] = c1 - l * z1[k];
+            s00[k] -= z0[k] * z0[k] * ip;
+            s01[k] -= z0[k] * z1[k] * ip;
+            s11[k] -= z1[k] * z1[k] * ip;
+            ipp[k] = ip;
+        }
+        eprev = e[i];
+    }
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        if (q > 0) {
+            double p0 = s00[k];
+            if (fabs(p0) < pivmin) p0 = -pivmin;
+            cnt[k] += (p0 > 0.0);
+            if (q > 1) {
+                double p1 = s11[k] - s01[k] * s01[k] / p0;
+                if (fabs(p1) < pivmin) p1 = -pivmin;
+                cnt[k] += (p1 > 0.0);
+            }
+        }
+    }
+}
+
+// block-wide minimum of an int
+template <class SH>
+__device__ inline int block_min_int(int v, SH& S) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
+    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
+    __syncthreads();
+    if (lane == 0) S.pts[w] = v;
+    __syncthreads();
+    int r = S.pts[0];
+    for (int i = 1; i < NT / WAVE; ++i) r = min(r, S.pts[i]);
+    return r;
+}
+
+// largest eigenvalue of the bordered matrix by multisection of [lo, hi] (lo below it): each
+// round evaluates NP = 4 NT (two-row border) or NT points and keeps the subinterval where
+// the count above x drops to zero
 template <class SH>
 __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
     const int tid = threadIdx.x;
     const double pivmin = S.scal[2];
-    for (int round = 0; round < 10; ++round) {
+    if (q <= 2) {
+        constexpr int NX = 4, NP = NX * NT;
+        for (int round = 0; round < 5; ++round) {      // (NP + 1)^5 > 2^50
+            double x[NX];
+            int cnt[NX];
+#pragma unroll
+            for (int k = 0; k < NX; ++k) x[k] = lo + (hi - lo) * double(NX * tid + k + 1) / double(NP + 1);
+            bordered_counts2<NX>(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin, cnt);
+            int first = NP;                                   // first point with no eigenvalue above
+#pragma unroll
+            for (int k = NX - 1; k >= 0; --k)
+                if (cnt[k] == 0) first = NX * tid + k;
+            const int t = block_min_int(first, S);
+            const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NP + 1);
+            const double xh = (t == NP) ? hi : lo + (hi - lo) * double(t + 1) / double(NP + 1);
+            lo = xl;
+            hi = xh;
+        }
+        return 0.5 * (lo + hi);
+    }
+    for (int round = 0; round < 7; ++round) {      // (NT + 1)^7 > 2^56
         const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
-        S.pts[tid] = bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0 ? 1 : 0;
-        __syncthreads();
-        int t = 0;
-        while (t < NT && !S.pts[t]) ++t;
+        const int first = (bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0) ? tid : NT;
+        const int t = block_min_int(first, S);
         const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
         const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
         lo = xl;
         hi = xh;
-        __syncthreads();
     }
     return 0.5 * (lo + hi);
 }
 
-// a-th smallest eigenvalue (0-based) by bisection to an absolute width of 2 eps ||T||
-__device__ double kth_eigenvalue(const double* d, const double* e, int nn, int a, double lo, double hi,
-                                 double pivmin, double tnorm) {
-    const double tol = 2.0 * DBL_EPSILON * fmax(tnorm, 1e-300);
-    for (int it = 0; it < 200; ++it) {
-        const double mid = 0.5 * (lo + hi);
-        if (!(hi - lo > tol) || mid == lo || mid == hi) break;
-        if (sturm_count(d, e, nn, mid, pivmin) > a) hi = mid;
-        else lo = mid;
-    }
-    return 0.5 * (lo + hi);
-}
 
-// Solve (T - lambda I) y = y in place by Gaussian elimination with partial pivoting on the
-// tridiagonal; u0, u1, u2 hold the three diagonals of U. Pivots smaller than `tiny` are
-// raised to +-tiny (the shift may be an exact eigenvalue).
-__device__ void tridiag_shift_solve(const double* d, const double* e, int nn, double lambda,
-                                    double tiny, double* y, double* u0, double* u1, double* u2) {
+// LU factorisation with partial pivoting of the tridiagonal T - lambda I, for repeated
+// solves: U has the diagonals u0 (kept as reciprocals r0), u1, u2; row i + 1 is eliminated
+// with multiplier mult[i] after rows i, i + 1 were interchanged when swp[i]. Pivots smaller
+// than `tiny` are raised to +-tiny (the shift may be an exact eigenvalue).
+__device__ void tridiag_shift_factor(const double* d, const double* e, int nn, double lambda, double tiny,
+                                     double* r0, double* u1, double* u2, double* mult, int* swp) {
     double p0 = d[0] - lambda, p1 = nn > 1 ? e[0] : 0.0, p2 = 0.0;
     for (int i = 0; i + 1 < nn; ++i) {
         const double b = e[i];
@@ -511,29 +694,43 @@ __device__ void tridiag_shift_solve(const double* d, const double* e, int nn, do
         const double c1 = (i + 2 < nn) ? e[i + 1] : 0.0;
         double np0, np1;
         if (fabs(b) > fabs(p0) && fabs(b) >= tiny) {
-            const double mult = p0 / b;
-            u0[i] = b; u1[i] = a1; u2[i] = c1;
-            np0 = p1 - mult * a1;
-            np1 = p2 - mult * c1;
-            const double yi = y[i];
-            y[i] = y[i + 1];
-            y[i + 1] = yi - mult * y[i + 1];
+            const double mu = p0 / b;
+            r0[i] = 1.0 / b; u1[i] = a1; u2[i] = c1;
+            mult[i] = mu;
+            swp[i] = 1;
+            np0 = p1 - mu * a1;
+            np1 = p2 - mu * c1;
         } else {
             if (fabs(p0) < tiny) p0 = (p0 < 0.0) ? -tiny : tiny;    // floor tiny pivots
-            const double mult = b / p0;
-            u0[i] = p0; u1[i] = p1; u2[i] = p2;
-            np0 = a1 - mult * p1;
-            np1 = c1 - mult * p2;
-            y[i + 1] -= mult * y[i];
+            const double mu = b / p0;
+            r0[i] = 1.0 / p0; u1[i] = p1; u2[i] = p2;
+            mult[i] = mu;
+            swp[i] = 0;
+            np0 = a1 - mu * p1;
+            np1 = c1 - mu * p2;
         }
         p0 = np0;
         p1 = np1;
         p2 = 0.0;
     }
-    u0[nn - 1] = (fabs(p0) < tiny) ? ((p0 < 0.0) ? -tiny : tiny) : p0;
-    y[nn - 1] /= u0[nn - 1];
-    if (nn >= 2) y[nn - 2] = (y[nn - 2] - u1[nn - 2] * y[nn - 1]) / u0[nn - 2];
-    for (int i = nn - 3; i >= 0; --i) y[i] = (y[i] - u1[i] * y[i + 1] - u2[i] * y[i + 2]) / u0[i];
+    r0[nn - 1] = 1.0 / ((fabs(p0) < tiny) ? ((p0 < 0.0) ? -tiny : tiny) : p0);
+}
+
+// y <- (T - lambda I)^{-1} y with the factors of tridiag_shift_factor
+__device__ void tridiag_shift_apply(int nn, const double* r0, const double* u1, const double* u2,
+                                    const double* mult, const int* swp, double* y) {
+    for (int i = 0; i + 1 < nn; ++i) {
+        if (swp[i]) {
+            const double yi = y[i];
+            y[i] = y[i + 1];
+            y[i + 1] = yi - mult[i] * y[i + 1];
+        } else {
+            y[i + 1] -= mult[i] * y[i];
+        }
+    }
+    y[nn - 1] *= r0[nn - 1];
+    if (nn >= 2) y[nn - 2] = (y[nn - 2] - u1[nn - 2] * y[nn - 1]) * r0[nn - 2];
+    for (int i = nn - 3; i >= 0; --i) y[i] = (y[i] - u1[i] * y[i + 1] - u2[i] * y[i + 2]) * r0[i];
 }
 
 __device__ inline double start_value(int i, int c) {
@@ -578,9 +775,10 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     HS_G double* U = gp(T.U);
     const HS_G double* G = gp(T.G);
     // Householder tridiagonalisation: unblocked in LDS, blocked for global matrices
-    auto tri = [&](HPtr A, int n, HPtr Bd, int nbr) {
-        if constexpr (LDS) tridiagonalize(A, ld, n, S, Bd, nbr);
-        else tridiagonalize_blk(A, ld, n, S, Bd, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN);
+    auto tri = [&](HPtr A, int n, double* Bl, int nbr) {
+        if constexpr (LDS) tridiagonalize(A, ld, n, S, Bl, MAXN, nbr);
+        else tridiagonalize_blk(A, ld, n, S, Bl, MAXN, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN,
+                                T.tstamp ? T.tstamp + 8 : nullptr);
     };
     auto stamp = [&](int k) {
         if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
@@ -608,7 +806,6 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         lam_max = (gmax > 0.0) ? largest_eigenvalue(m, S) : 0.0;
     }
     stamp(2);
-    stamp(3);
     int q = 0;
     if (variant == HSOLVE_GC) {
         for (int c = 0; c < T.nz && q < m; ++c) {
@@ -673,29 +870,38 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             __syncthreads();
             if (tau != 0.0) reflect_two_sided(H, ld, m, vt, tau, S);
         }
+        stamp(3);
         const int nt = m - q;
         if (nt > 0) {
-            tri(H + size_t(q) * ld + q, nt, bordered ? H + size_t(q) * ld : nullptr, bordered ? q : 0);
+            if (bordered) {      // border rows move to LDS for the reduction
+                for (int i = tid; i < nt; i += NT)
+                    for (int r = 0; r < q; ++r) S.bord[r][i] = H[r + size_t(q + i) * ld];
+                __syncthreads();
+            }
+            tri(H + size_t(q) * ld + q, nt, bordered ? &S.bord[0][0] : nullptr, bordered ? q : 0);
             tridiag_bounds(nt, S);
         }
+        stamp(4);
         if (bordered && gmax > 0.0) {
             // K = [D, C; C^T, T] is similar to G; lambda_max(K) >= lambda_max(T) (interlacing)
-            for (int i = tid; i < nt; i += NT)
-                for (int r = 0; r < q; ++r) S.bord[r][i] = H[r + size_t(q + i) * ld];
             if (tid < 16) {
                 const int a = tid % 4, b = tid / 4;
                 S.dq[tid] = (a < q && b < q) ? H[a + size_t(b) * ld] : 0.0;
             }
             if (nt == 0 && tid == 0) S.scal[2] = 1e-300;
             __syncthreads();
-            const double lam_t = (nt > 0) ? largest_eigenvalue(nt, S) : 0.0;
-            const double tn = (nt > 0) ? S.scal[3] : 0.0;
-            const double lo = lam_t - 4.0 * DBL_EPSILON * fmax(tn, fro) - 1e-300;
+            // lower end: the largest diagonal entry of K (at most lambda_max); below the
+            // largest eigenvalue of T the Sturm part of the count alone is already positive
+            double dmax = -DBL_MAX;
+            for (int i = tid; i < nt; i += NT) dmax = fmax(dmax, S.d[i]);
+            if (tid < q) dmax = fmax(dmax, S.dq[tid + 4 * tid]);
+            dmax = block_max(dmax, S.red);
+            const double lo = dmax - 4.0 * DBL_EPSILON * fro - 1e-300;
             const double hi = fro * (1.0 + 1e-12) + 1e-300;
             lam_max = bordered_largest(nt, q, lo, hi, S);
         }
     }
-    stamp(4);
+    stamp(5);
     const int nn = m - q;
     const int cap = min(nn, T.wt);
     const double thr = eps * eps * fmax(lam_max, 0.0);
@@ -733,25 +939,75 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         Wk.info[INF_HI] = S.scal[1];
         rank[T.id] = q + k2;
     }
-    stamp(5);
+    stamp(6);
 }
 
 // one thread per kept eigenvalue (largest first)
+// numbers of eigenvalues of the tridiagonal (d, e) below x[0..NX), NX recurrences interleaved
+template <int NX>
+__device__ __forceinline__ void sturm_counts(const double* d, const double* e, int nn, const double* x,
+                                             double pivmin, int* cnt) {
+    double q[NX];
+#pragma unroll
+    for (int k = 0; k < NX; ++k) {
+        cnt[k] = 0;
+        q[k] = 1.0;
+    }
+    double e2 = 0.0;
+    for (int i = 0; i < nn; ++i) {
+        const double di = d[i];
+#pragma unroll
+        for (int k = 0; k < NX; ++k) {
+            double t = di - x[k] - e2 / q[k];
+            if (fabs(t) < pivmin) t = -pivmin;
+            cnt[k] += (t < 0.0);
+            q[k] = t;
+        }
+        e2 = e[i] * e[i];
+    }
+}
+
+// One wave per kept eigenvalue (largest first): multisection of the Gershgorin interval, each
+// lane evaluating BIS_NX points per round (64 BIS_NX points in all), until the bracket is
+// narrower than 2 eps ||T|| (the accuracy of the counts).
+constexpr int BIS_NX = 4;
+
 __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
     __shared__ double d[CMP_MAX], e[CMP_MAX];
     const CompressTask T = tasks[blockIdx.y];
     CmpWork Wk(T.work, T.m);
     const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]);
-    if (int(blockIdx.x) * NT >= k2) return;
+    constexpr int WPB = NT / WAVE;
+    if (int(blockIdx.x) * WPB >= k2) return;
     for (int i = threadIdx.x; i < nn; i += NT) {
         d[i] = Wk.d[i];
         e[i] = Wk.e[i];
     }
     __syncthreads();
-    const int j = blockIdx.x * NT + threadIdx.x;
-    if (j < k2)
-        Wk.lam[j] = kth_eigenvalue(d, e, nn, nn - 1 - j, Wk.info[INF_LO], Wk.info[INF_HI],
-                                   Wk.info[INF_PIVMIN], Wk.info[INF_TNORM]);
+    const int lane = threadIdx.x % WAVE, j = blockIdx.x * WPB + threadIdx.x / WAVE;
+    if (j >= k2) return;
+    const int a = nn - 1 - j;                      // a-th smallest
+    const double pivmin = Wk.info[INF_PIVMIN];
+    const double tol = 2.0 * DBL_EPSILON * fmax(Wk.info[INF_TNORM], 1e-300);
+    constexpr int NP = BIS_NX * WAVE;
+    double lo = Wk.info[INF_LO], hi = Wk.info[INF_HI];
+    for (int round = 0; round < 12 && hi - lo > tol; ++round) {
+        double x[BIS_NX];
+        int cnt[BIS_NX];
+#pragma unroll
+        for (int k = 0; k < BIS_NX; ++k) x[k] = lo + (hi - lo) * double(BIS_NX * lane + k + 1) / double(NP + 1);
+        sturm_counts<BIS_NX>(d, e, nn, x, pivmin, cnt);
+        int first = NP;                            // first point with more than a eigenvalues below
+#pragma unroll
+        for (int k = BIS_NX - 1; k >= 0; --k)
+            if (cnt[k] > a) first = BIS_NX * lane + k;
+        for (int o = WAVE / 2; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, WAVE));
+        const double xl = (first == 0) ? lo : lo + (hi - lo) * double(first) / double(NP + 1);
+        const double xh = (first == NP) ? hi : lo + (hi - lo) * double(first + 1) / double(NP + 1);
+        lo = xl;
+        hi = xh;
+    }
+    if (lane == 0) Wk.lam[j] = 0.5 * (lo + hi);
 }
 
 // one wave per eigenvalue index; cluster leaders compute their members' eigenvectors by
@@ -760,7 +1016,8 @@ constexpr int VNT = 128;           // two waves per workgroup in k_comp_vectors
 
 __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks, int variant) {
     __shared__ double d[CMP_MAX], e[CMP_MAX];
-    __shared__ double scr[VNT / WAVE][4][CMP_MAX];
+    __shared__ double scr[VNT / WAVE][5][CMP_MAX];
+    __shared__ int swp_all[VNT / WAVE][CMP_MAX];
     const CompressTask T = tasks[blockIdx.y];
     const int m = T.m;
     CmpWork Wk(T.work, m);
@@ -785,11 +1042,15 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
     double* u0 = scr[wv][1];
     double* u1 = scr[wv][2];
     double* u2 = scr[wv][3];
+    double* mult = scr[wv][4];
+    int* swp = swp_all[wv];
     for (int c = c0; c < c1; ++c) {
         for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
+        wave_sync();
+        if (lane == 0) tridiag_shift_factor(d, e, nn, lam[c], tiny, u0, u1, u2, mult, swp);
         for (int it = 0; it < 3; ++it) {
             wave_sync();
-            if (lane == 0) tridiag_shift_solve(d, e, nn, lam[c], tiny, y, u0, u1, u2);
+            if (lane == 0) tridiag_shift_apply(nn, u0, u1, u2, mult, swp, y);
             wave_sync();
             for (int pass = 0; pass < 2; ++pass)
                 for (int b = c0; b < c; ++b) {
@@ -818,22 +1079,41 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
             const int i = lane + WAVE * r;
             x[r] = (i >= q && i < m) ? u[i] : 0.0;
         }
-        for (int j = nn - 3; j >= 0; --j) {
-            const double tj = Wk.tau[j];
-            if (tj == 0.0) continue;
+        // reflectors j = nn-3 .. 0, the next one's column loaded before the current dot product
+        const int rmax = (m + WAVE - 1) / WAVE;
+        auto load_refl = [&](int j, double* v) {
             const int col0 = q + j;                 // reflector column in m-dim coordinates
             const HS_G double* hc = Wk.H + size_t(col0) * m;
-            double v[CMP_RMAX];
-            double part = 0.0;
 #pragma unroll
             for (int r = 0; r < CMP_RMAX; ++r) {
                 const int i = lane + WAVE * r;
-                v[r] = (i > col0 + 1 && i < m) ? hc[i] : (i == col0 + 1 ? 1.0 : 0.0);
-                part += v[r] * x[r];
+                const double h = (r < rmax) ? hc[min(i, m - 1)] : 0.0;
+                v[r] = (i > col0 + 1 && i < m) ? h : (i == col0 + 1 ? 1.0 : 0.0);
             }
-            const double dot = wave_sum(part) * tj;
+        };
+        double va[CMP_RMAX], vb[CMP_RMAX];
+        double ta = 0.0;
+        if (nn - 3 >= 0) {
+            load_refl(nn - 3, va);
+            ta = Wk.tau[nn - 3];
+        }
+        for (int j = nn - 3; j >= 0; --j) {
+            double tb = 0.0;
+            if (j >= 1) {
+                load_refl(j - 1, vb);
+                tb = Wk.tau[j - 1];
+            }
+            if (ta != 0.0) {
+                double part = 0.0;
 #pragma unroll
-            for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * v[r];
+                for (int r = 0; r < CMP_RMAX; ++r) part += va[r] * x[r];
+                const double dot = wave_sum(part) * ta;
+#pragma unroll
+                for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * va[r];
+            }
+#pragma unroll
+            for (int r = 0; r < CMP_RMAX; ++r) va[r] = vb[r];
+            ta = tb;
         }
         for (int t = q - 1; t >= 0; --t) {
             const double tt = Wk.gct[t];
@@ -894,7 +1174,8 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     }
     {
         ProfScope ps("k_comp_bisect", 0.0, s);
-        hipLaunchKernelGGL(k_comp_bisect, dim3((max_m + NT - 1) / NT, ntasks), dim3(NT), 0, s, d_tasks);
+        hipLaunchKernelGGL(k_comp_bisect, dim3((max_m + NT / WAVE - 1) / (NT / WAVE), ntasks), dim3(NT), 0, s,
+                           d_tasks);
         check_launch("k_comp_bisect");
     }
     {

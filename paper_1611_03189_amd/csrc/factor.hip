@@ -36,6 +36,7 @@ struct Live {
 };
 
 struct Batch {
+    bool trace_pivots = false;
     std::vector<CopyTask> copies;
     std::vector<GemmTask> gt;
     std::vector<GemmTerm> terms;
@@ -95,7 +96,7 @@ struct Batch {
             double flops = 0.0;
             int max_m = 0;
             for (CholTask c : chol) {
-                if ((c.m > LDS_MAX_M) != bool(big)) continue;
+                if ((c.m > PIV_LDS_MAX_M) != bool(big)) continue;
                 if (big) c.work = P.spool.alloc_n<double>(size_t(c.m) * c.m);
                 // potrf m^3/3 + triangular inverse m^3/3 (+ X^T X, m^3/3, in the LDS kernel)
                 flops += (big ? 2.0 / 3.0 : 1.0) * double(c.m) * c.m * c.m;
@@ -103,8 +104,22 @@ struct Batch {
                 part.push_back(c);
             }
             if (part.empty()) continue;
+            long long* d_stamp = nullptr;
+            if (big && trace_pivots) {
+                d_stamp = P.spool.alloc_n<long long>(4 * part.size());
+                for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 4 * q;
+            }
             CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
             launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, P.stream);
+            if (d_stamp) {
+                std::vector<long long> h(4 * part.size());
+                HS_HIP(hipMemcpy(h.data(), d_stamp, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
+                long long ph[3] = {0, 0, 0};
+                for (size_t q = 0; q < part.size(); ++q)
+                    for (int k = 0; k < 3; ++k) ph[k] = std::max(ph[k], h[4 * q + k + 1] - h[4 * q + k]);
+                std::fprintf(stderr, "    pivot batch n=%zu max_m=%d kcycles copy %lld chol %lld trinv %lld\n",
+                             part.size(), max_m, ph[0] / 1000, ph[1] / 1000, ph[2] / 1000);
+            }
             if (big) {      // A^{-1} = X^T X, X = L^{-1} left in the work matrices
                 for (const CholTask& c : part) gemm(c.Ainv, c.ldi, c.m, c.m, 1.0, 0.0, c.work, c.m, 1,
                                                     c.work, c.m, 0, c.m);
@@ -183,6 +198,7 @@ void factor(Plan& P, const double* d_values_in) {
         int* d_fail = lp.alloc_n<int>(nd);
         HS_HIP(hipMemsetAsync(d_fail, 0, sizeof(int) * nd, st));
         Batch B;
+        B.trace_pivots = trace;
 
         // ---- blocks of the level at its start: diagonal + upper partners, one zeroed region
         size_t region = 0;
@@ -340,9 +356,9 @@ void factor(Plan& P, const double* d_values_in) {
             int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
             long long* d_stamp = nullptr;
             if (trace && !ctasks.empty()) {
-                d_stamp = P.spool.alloc_n<long long>(8 * ctasks.size());
-                HS_HIP(hipMemsetAsync(d_stamp, 0, sizeof(long long) * 8 * ctasks.size(), st));
-                for (size_t q2 = 0; q2 < ctasks.size(); ++q2) ctasks[q2].tstamp = d_stamp + 8 * q2;
+                d_stamp = P.spool.alloc_n<long long>(16 * ctasks.size());
+                HS_HIP(hipMemsetAsync(d_stamp, 0, sizeof(long long) * 16 * ctasks.size(), st));
+                for (size_t q2 = 0; q2 < ctasks.size(); ++q2) ctasks[q2].tstamp = d_stamp + 16 * q2;
             }
             B.flush_copies(P);
             B.flush_gemm(P);
@@ -390,7 +406,7 @@ void factor(Plan& P, const double* d_values_in) {
             if (trace) {
                 tc1 = now_ms();
                 if (d_stamp) {
-                    stamps.resize(8 * ctasks.size());
+                    stamps.resize(16 * ctasks.size());
                     HS_HIP(hipMemcpy(stamps.data(), d_stamp, sizeof(long long) * stamps.size(),
                                      hipMemcpyDeviceToHost));
                 }
@@ -426,7 +442,7 @@ void factor(Plan& P, const double* d_values_in) {
                     else B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
                 }
                 Block* dg = live.find(s, s);
-                B.chol.push_back(CholTask{dg->p, nn.Gm, nullptr, dg->ld, nn.ldG, m, s});
+                B.chol.push_back(CholTask{dg->p, nn.Gm, nullptr, nullptr, dg->ld, nn.ldG, m, s});
                 flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
             }
             B.flush_copies(P);
@@ -456,7 +472,7 @@ void factor(Plan& P, const double* d_values_in) {
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
                 Sinv[q] = static_cast<double*>(lp.alloc(blk_bytes(nn.k, nn.k)));
-                B.chol.push_back(CholTask{Ssc[q], Sinv[q], nullptr, nn.k, nn.k, nn.k, s});
+                B.chol.push_back(CholTask{Ssc[q], Sinv[q], nullptr, nullptr, nn.k, nn.k, nn.k, s});
                 flops += double(nn.k) * nn.k * nn.k;
             }
             B.flush_chol(P, d_fail);
@@ -586,11 +602,16 @@ void factor(Plan& P, const double* d_values_in) {
                 std::fprintf(stderr, "trace d=%2d c=%2zu nodes=%5zu comp=%5zu max_m=%4d max_wt=%5d max_k=%4d  A=%8.2f ms  B=%8.2f ms",
                              d, c, nodes.size(), comp.size(), mm, mw, mk, tc1 - tc0, now_ms() - tc1);
                 long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
-                for (size_t q2 = 0; q2 < stamps.size() / 8; ++q2)
+                long long tp[6] = {0, 0, 0, 0, 0, 0};
+                for (size_t q2 = 0; q2 < stamps.size() / 16; ++q2) {
                     for (int k = 0; k < 7; ++k)
-                        ph[k] = std::max(ph[k], stamps[8 * q2 + k + 1] - stamps[8 * q2 + k]);
-                std::fprintf(stderr, "  kcycles load %lld tri %lld lmax %lld gc %lld count %lld\n",
-                             ph[0] / 1000, ph[1] / 1000, ph[2] / 1000, ph[3] / 1000, ph[4] / 1000);
+                        ph[k] = std::max(ph[k], stamps[16 * q2 + k + 1] - stamps[16 * q2 + k]);
+                    for (int k = 0; k < 6; ++k) tp[k] = std::max(tp[k], stamps[16 * q2 + 8 + k]);
+                }
+                std::fprintf(stderr, "  kcycles load %lld tri0 %lld gcref %lld tri %lld lmax %lld count %lld"
+                             " | tri: col %lld refl %lld symv %lld pv %lld wb %lld trail %lld\n",
+                             ph[0] / 1000, ph[1] / 1000, ph[2] / 1000, ph[3] / 1000, ph[4] / 1000, ph[5] / 1000,
+                             tp[0] / 1000, tp[1] / 1000, tp[2] / 1000, tp[3] / 1000, tp[4] / 1000, tp[5] / 1000);
             }
         }
         // end of level: surface pivot failures of the last colour

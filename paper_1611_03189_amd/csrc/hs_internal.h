@@ -185,6 +185,7 @@ struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1}
     double* A;
     double* Ainv;
     double* work;            // m x m scratch for blocks too large for LDS (else null)
+    long long* tstamp;       // optional: 4 clock stamps at phase boundaries (trace only)
     int lda, ldi, m, id;
 };
 
@@ -300,7 +301,9 @@ void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double fl
                      int max_m, hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
                      int* d_rank, double flops, bool lds, int max_m, hipStream_t s);
-constexpr int LDS_MAX_M = 128;   // pivot / compression blocks up to this size work in LDS
+constexpr int LDS_MAX_M = 128;   // compression blocks up to this size work in LDS
+constexpr int PIV_LDS_MAX_M = 64; // pivot blocks up to this size are factored in LDS; larger
+                                  // ones by the blocked kernel (panels of 32 columns)
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const int32_t* iperm, const int32_t* pos_super,
                          const int32_t* super_first, double* const* blk_ptr,

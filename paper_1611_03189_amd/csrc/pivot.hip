@@ -108,15 +108,60 @@ __device__ inline void next_lower_tile(int& I, int& J, int step, int T) {
     }
 }
 
+// Inverse of the lower-triangular nb x nb block in X11 (ld PIV_NB + 1), in place, by the
+// calling wave (lane = row), columns right to left; entries above the diagonal and outside
+// nb are set to zero so that X11 can be used as a full PIV_NB x PIV_NB matrix.
+__device__ inline void wave_trinv32(double* X11, int nb, int lane) {
+    constexpr int l11 = PIV_NB + 1;
+    for (int c = 0; c < PIV_NB; ++c)
+        if (lane < PIV_NB && (lane < c || lane >= nb || c >= nb)) X11[lane + c * l11] = 0.0;
+    wave_sync();
+    for (int j = nb - 1; j >= 0; --j) {
+        if (lane == j) X11[j + j * l11] = 1.0 / X11[j + j * l11];
+        wave_sync();
+        double y = 0.0;
+        if (lane > j && lane < nb) {
+            for (int l = j + 1; l <= lane; ++l) y += X11[lane + l * l11] * X11[l + j * l11];
+            y *= -X11[j + j * l11];
+        }
+        wave_sync();
+        if (lane > j && lane < nb) X11[lane + j * l11] = y;
+        wave_sync();
+    }
+}
+
+// rows [i_begin, i_end) of P (column-major, ld ldp): P(i, :) <- P(i, :) X11^T (trans) or
+// P(i, :) X11, X11 a full PIV_NB x PIV_NB matrix in LDS; the row is held in registers
+template <bool TRANS>
+__device__ inline void rows_times_x11(double* P, int ldp, int i_begin, int i_end, int nb, const double* X11) {
+    constexpr int l11 = PIV_NB + 1;
+    for (int i = i_begin + threadIdx.x; i < i_end; i += NT) {
+        double a[PIV_NB];
+#pragma unroll
+        for (int l = 0; l < PIV_NB; ++l) a[l] = (l < nb) ? P[i + l * ldp] : 0.0;
+#pragma unroll 1
+        for (int c = 0; c < nb; ++c) {
+            double s = 0.0;
+#pragma unroll
+            for (int l = 0; l < PIV_NB; ++l) s += a[l] * (TRANS ? X11[c + l * l11] : X11[l + c * l11]);
+            P[i + c * ldp] = s;
+        }
+    }
+}
+
 __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int* fail) {
     extern __shared__ double Pn[];                  // panel / Y buffer, PIV_PANEL doubles
     __shared__ double X11[PIV_NB * (PIV_NB + 1)];
-    __shared__ double yv[PIV_NB];
     __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
-    const int m = T.m, tid = threadIdx.x;
+    const int m = T.m, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    constexpr int l11 = PIV_NB + 1;
     HS_G double* W = gp(T.work);                   // m x m, ld m
     const HS_G double* A = gp(T.A);
+    auto stamp = [&](int k) {
+        if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
+    };
+    stamp(0);
     const size_t ld = size_t(m);
     for (size_t e = tid; e < ld * m; e += NT) {
         const size_t i = e % ld, j = e / ld;
@@ -124,8 +169,9 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     }
     if (tid == 0) bad = 0;
     __syncthreads();
+    stamp(1);
 
-    // ---- blocked right-looking Cholesky ----
+    // ---- blocked right-looking Cholesky; the diagonal blocks of W receive L11^{-1} ----
     for (int jb = 0; jb < m; jb += PIV_NB) {
         const int nb = min(PIV_NB, m - jb);
         const int r = m - jb;                        // panel rows (diagonal block first)
@@ -134,28 +180,39 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             Pn[i + c * r] = W[(jb + i) + (jb + c) * ld];
         }
         __syncthreads();
-        for (int j = 0; j < nb; ++j) {
-            if (tid == 0) {
-                const double d = Pn[j + j * r];
-                if (!(d > 0.0) || !isfinite(d)) bad = 1;
-                else Pn[j + j * r] = sqrt(d);
+        // L11 and its inverse by the first wave alone (lane = row, no workgroup barriers)
+        if (wv == 0) {
+            for (int j = 0; j < nb; ++j) {
+                if (lane == j) {
+                    const double d = Pn[j + j * r];
+                    if (!(d > 0.0) || !isfinite(d)) bad = 1;
+                    else Pn[j + j * r] = sqrt(d);
+                }
+                wave_sync();
+                if (bad) break;
+                const double piv = Pn[j + j * r];
+                if (lane > j && lane < nb) Pn[lane + j * r] /= piv;
+                wave_sync();
+                if (lane > j && lane < nb) {
+                    const double lij = Pn[lane + j * r];
+                    for (int c = j + 1; c <= lane; ++c) Pn[lane + c * r] -= lij * Pn[c + j * r];
+                }
+                wave_sync();
             }
-            __syncthreads();
-            if (bad) break;
-            const double piv = Pn[j + j * r];
-            for (int i = j + 1 + tid; i < r; i += NT) Pn[i + j * r] /= piv;
-            __syncthreads();
-            for (int i = j + 1 + tid; i < r; i += NT) {
-                const double lij = Pn[i + j * r];
-                const int cend = min(i, nb - 1);
-                for (int c = j + 1; c <= cend; ++c) Pn[i + c * r] -= lij * Pn[c + j * r];
+            if (!bad) {
+                for (int c = 0; c < nb; ++c)
+                    if (lane < nb) X11[lane + c * l11] = Pn[lane + c * r];
+                wave_trinv32(X11, nb, lane);
             }
-            __syncthreads();
         }
+        __syncthreads();
         if (bad) break;
+        // L21 = A21 L11^{-T}, rows in registers
+        rows_times_x11<true>(Pn, r, nb, r, nb, X11);
+        __syncthreads();
         for (int e = tid; e < r * nb; e += NT) {
             const int i = e % r, c = e / r;
-            W[(jb + i) + (jb + c) * ld] = Pn[i + c * r];
+            W[(jb + i) + (jb + c) * ld] = (i < nb) ? X11[i + c * l11] : Pn[i + c * r];
         }
         // trailing update W22 -= L21 L21^T on the lower 4x4 tiles, L21 = Pn(nb.., :)
         const int t = r - nb;
@@ -196,94 +253,89 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
         return;
     }
 
-    // ---- blocked inverse X = L^{-1}, panels right to left ----
+    stamp(2);
+    // ---- blocked inverse X = L^{-1}, panels right to left: X21 = -X22 L21 X11 ----
     const int last = ((m - 1) / PIV_NB) * PIV_NB;
     for (int jb = last; jb >= 0; jb -= PIV_NB) {
         const int nb = min(PIV_NB, m - jb);
         const int t = m - jb - nb;
-        const int l11 = PIV_NB + 1;
-        for (int e = tid; e < nb * nb; e += NT) {
-            const int i = e % nb, c = e / nb;
-            X11[i + c * l11] = W[(jb + i) + (jb + c) * ld];
+        if (t == 0) continue;                      // the last diagonal block holds X11 already
+        for (int e = tid; e < PIV_NB * PIV_NB; e += NT) {
+            const int i = e % PIV_NB, c = e / PIV_NB;
+            X11[i + c * l11] = (i < nb && c < nb && i >= c) ? W[(jb + i) + (jb + c) * ld] : 0.0;
+        }
+        for (int e = tid; e < t * nb; e += NT) {
+            const int i = e % t, c = e / t;
+            Pn[i + c * t] = W[(jb + nb + i) + (jb + c) * ld];
         }
         __syncthreads();
-        // X11 = L11^{-1} in place, columns right to left
-        for (int j = nb - 1; j >= 0; --j) {
-            if (tid == 0) X11[j + j * l11] = 1.0 / X11[j + j * l11];
-            __syncthreads();
-            const int i = j + 1 + tid;
-            if (i < nb) {
-                double s = 0.0;
-                for (int l = j + 1; l <= i; ++l) s += X11[i + l * l11] * X11[l + j * l11];
-                yv[i] = -X11[j + j * l11] * s;
-            }
-            __syncthreads();
-            if (i < nb) X11[i + j * l11] = yv[i];
-            __syncthreads();
-        }
-        for (int e = tid; e < nb * nb; e += NT) {
-            const int i = e % nb, c = e / nb;
-            if (i >= c) W[(jb + i) + (jb + c) * ld] = X11[i + c * l11];
-        }
-        if (t > 0) {
-            // Y = L21 X11 (t x nb) into LDS; items of one row and 4 columns
-            for (int idx = tid; idx < t * (PIV_NB / 4); idx += NT) {
-                const int i = idx % t, c0 = 4 * (idx / t);
-                if (c0 >= nb) continue;
-                double acc[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int l = c0; l < nb; ++l) {
-                    const double rl = W[(jb + nb + i) + (jb + l) * ld];
+        rows_times_x11<false>(Pn, t, 0, t, nb, X11);     // Y = L21 X11
+        __syncthreads();
+        // X21 = -X22 Y, X22 = the lower-triangular inverse already in W; tiles of 4 rows x 8 cols
+        const int Tr = (t + 3) / 4, Tc = (nb + 7) / 8;
+        for (int idx = tid; idx < Tr * Tc; idx += NT) {
+            const int i0 = 4 * (idx % Tr), c0 = 8 * (idx / Tr);
+            double acc[4][8];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (c0 + v <= l) acc[v] += rl * X11[l + (c0 + v) * l11];
-                }
+            for (int u = 0; u < 4; ++u)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (c0 + v < nb) Pn[i + (c0 + v) * t] = acc[v];
-            }
-            __syncthreads();
-            // X21 = -X22 Y, X22 = the lower-triangular inverse already in W; tiles of 4 rows x 8 cols
-            const int Tr = (t + 3) / 4, Tc = (nb + 7) / 8;
-            for (int idx = tid; idx < Tr * Tc; idx += NT) {
-                const int i0 = 4 * (idx % Tr), c0 = 8 * (idx / Tr);
-                double acc[4][8];
+                for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+            const HS_G double* X22 = W + (jb + nb) + (jb + nb) * ld;
+            // columns l <= i0: every row of the tile takes part. Rows past t and columns
+            // past nb read clamped (in-bounds) entries; their sums are never stored.
+            int xr[4], yc[8];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+            for (int u = 0; u < 4; ++u) xr[u] = min(i0 + u, t - 1);
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
-                const HS_G double* X22 = W + (jb + nb) + (jb + nb) * ld;
-                // columns l <= i0: every row of the tile takes part (rows beyond t read 0)
-#pragma unroll 1
-                for (int l = 0; l <= i0 && l < t; ++l) {
-                    double x[4], y[8];
+            for (int v = 0; v < 8; ++v) yc[v] = min(c0 + v, nb - 1) * t;
+            const int lend = min(i0, t - 1);
+            int l = 0;
+            for (; l + 3 <= lend; l += 4) {
+                double x[4][4], y[4][8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) x[u] = (i0 + u < t) ? X22[(i0 + u) + l * ld] : 0.0;
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) y[v] = (c0 + v < nb) ? Pn[l + (c0 + v) * t] : 0.0;
+                    for (int u = 0; u < 4; ++u) x[q][u] = X22[xr[u] + size_t(l + q) * ld];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) y[q][v] = Pn[l + q + yc[v]];
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
-                        for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
-                }
-                // columns i0 < l <= i0 + 3: only rows u with l <= i0 + u
-#pragma unroll 1
-                for (int l = i0 + 1; l <= i0 + 3 && l < t; ++l) {
-                    double x[4], y[8];
+                        for (int v = 0; v < 8; ++v) acc[u][v] += x[q][u] * y[q][v];
+            }
+            for (; l <= lend; ++l) {
+                double x[4], y[8];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) x[u] = (i0 + u < t && l <= i0 + u) ? X22[(i0 + u) + l * ld] : 0.0;
+                for (int u = 0; u < 4; ++u) x[u] = X22[xr[u] + size_t(l) * ld];
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) y[v] = (c0 + v < nb) ? Pn[l + (c0 + v) * t] : 0.0;
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
-                }
+                for (int v = 0; v < 8; ++v) y[v] = Pn[l + yc[v]];
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int v = 0; v < 8; ++v)
-                        if (i0 + u < t && c0 + v < nb) W[(jb + nb + i0 + u) + (jb + c0 + v) * ld] = -acc[u][v];
+                    for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
             }
+            // columns i0 < l <= i0 + 3: only rows u with l <= i0 + u
+            for (int l2 = i0 + 1; l2 <= i0 + 3 && l2 < t; ++l2) {
+                double x[4], y[8];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    x[u] = (i0 + u < t && l2 <= i0 + u) ? X22[(i0 + u) + size_t(l2) * ld] : 0.0;
+#pragma unroll
+                for (int v = 0; v < 8; ++v) y[v] = (c0 + v < nb) ? Pn[l2 + (c0 + v) * t] : 0.0;
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int v = 0; v < 8; ++v)
+                    if (i0 + u < t && c0 + v < nb) W[(jb + nb + i0 + u) + (jb + c0 + v) * ld] = -acc[u][v];
         }
         __syncthreads();
     }
@@ -292,6 +344,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
         const size_t i = e % ld, j = e / ld;
         if (i < j) W[e] = 0.0;
     }
+    stamp(3);
 }
 
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
