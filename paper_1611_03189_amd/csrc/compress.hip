@@ -967,47 +967,60 @@ __device__ __forceinline__ void sturm_counts(const double* d, const double* e, i
     }
 }
 
-// One wave per kept eigenvalue (largest first): multisection of the Gershgorin interval, each
-// lane evaluating BIS_NX points per round (64 BIS_NX points in all), until the bracket is
-// narrower than 2 eps ||T|| (the accuracy of the counts).
+// Kept eigenvalues (largest first) by multisection of the Gershgorin interval: a group of LPE
+// lanes per eigenvalue, each lane evaluating BIS_NX points per round (BIS_NX LPE points in
+// all), until the bracket is narrower than 2 eps ||T|| (the accuracy of the counts). Wide
+// groups finish in few rounds (latency) for few nodes; narrow groups do less total work
+// (throughput) when a launch holds many nodes.
 constexpr int BIS_NX = 4;
 
+template <int LPE>
 __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
     __shared__ double d[CMP_MAX], e[CMP_MAX];
     const CompressTask T = tasks[blockIdx.y];
     CmpWork Wk(T.work, T.m);
     const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]);
-    constexpr int WPB = NT / WAVE;
-    if (int(blockIdx.x) * WPB >= k2) return;
+    constexpr int GPB = NT / LPE;                  // eigenvalues per workgroup
+    if (int(blockIdx.x) * GPB >= k2) return;
     for (int i = threadIdx.x; i < nn; i += NT) {
         d[i] = Wk.d[i];
         e[i] = Wk.e[i];
     }
     __syncthreads();
-    const int lane = threadIdx.x % WAVE, j = blockIdx.x * WPB + threadIdx.x / WAVE;
-    if (j >= k2) return;
-    const int a = nn - 1 - j;                      // a-th smallest
+    const int g = threadIdx.x % LPE, j = blockIdx.x * GPB + threadIdx.x / LPE;
+    if ((j - int(threadIdx.x % WAVE) / LPE) >= k2) return;      // whole wave past the last one
+    const bool active = j < k2;
+    const int a = nn - 1 - (active ? j : k2 - 1);                // a-th smallest
     const double pivmin = Wk.info[INF_PIVMIN];
     const double tol = 2.0 * DBL_EPSILON * fmax(Wk.info[INF_TNORM], 1e-300);
-    constexpr int NP = BIS_NX * WAVE;
+    constexpr int NP = BIS_NX * LPE;
     double lo = Wk.info[INF_LO], hi = Wk.info[INF_HI];
-    for (int round = 0; round < 12 && hi - lo > tol; ++round) {
+    bool need = hi - lo > tol;
+    for (int round = 0; round < 64; ++round) {
+        // every lane of the wave stays in the loop until all groups have converged
+        int any = need ? 1 : 0;
+        for (int o = WAVE / 2; o > 0; o >>= 1) any = max(any, __shfl_xor(any, o, WAVE));
+        if (!any) break;
         double x[BIS_NX];
         int cnt[BIS_NX];
 #pragma unroll
-        for (int k = 0; k < BIS_NX; ++k) x[k] = lo + (hi - lo) * double(BIS_NX * lane + k + 1) / double(NP + 1);
+        for (int k = 0; k < BIS_NX; ++k) x[k] = lo + (hi - lo) * double(BIS_NX * g + k + 1) / double(NP + 1);
         sturm_counts<BIS_NX>(d, e, nn, x, pivmin, cnt);
         int first = NP;                            // first point with more than a eigenvalues below
 #pragma unroll
         for (int k = BIS_NX - 1; k >= 0; --k)
-            if (cnt[k] > a) first = BIS_NX * lane + k;
-        for (int o = WAVE / 2; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, WAVE));
+            if (cnt[k] > a) first = BIS_NX * g + k;
+        for (int o = LPE / 2; o > 0; o >>= 1) first = min(first, __shfl_xor(first, o, WAVE));
         const double xl = (first == 0) ? lo : lo + (hi - lo) * double(first) / double(NP + 1);
         const double xh = (first == NP) ? hi : lo + (hi - lo) * double(first + 1) / double(NP + 1);
-        lo = xl;
-        hi = xh;
+        if (need) {
+            if (xl == lo && xh == hi) need = false;       // no progress in floating point
+            lo = xl;
+            hi = xh;
+            if (!(hi - lo > tol)) need = false;
+        }
     }
-    if (lane == 0) Wk.lam[j] = 0.5 * (lo + hi);
+    if (active && g == 0) Wk.lam[j] = 0.5 * (lo + hi);
 }
 
 // one wave per eigenvalue index; cluster leaders compute their members' eigenvectors by
@@ -1174,8 +1187,17 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     }
     {
         ProfScope ps("k_comp_bisect", 0.0, s);
-        hipLaunchKernelGGL(k_comp_bisect, dim3((max_m + NT / WAVE - 1) / (NT / WAVE), ntasks), dim3(NT), 0, s,
-                           d_tasks);
+        // lanes per eigenvalue from the number of eigenvalues the launch can hold
+        const double total = double(max_m) * ntasks;
+        if (total <= 1024.0) {
+            hipLaunchKernelGGL(k_comp_bisect<64>, dim3((max_m + NT / 64 - 1) / (NT / 64), ntasks), dim3(NT), 0,
+                               s, d_tasks);
+        } else if (total <= 8192.0) {
+            hipLaunchKernelGGL(k_comp_bisect<8>, dim3((max_m + NT / 8 - 1) / (NT / 8), ntasks), dim3(NT), 0,
+                               s, d_tasks);
+        } else {
+            hipLaunchKernelGGL(k_comp_bisect<1>, dim3((max_m + NT - 1) / NT, ntasks), dim3(NT), 0, s, d_tasks);
+        }
         check_launch("k_comp_bisect");
     }
     {

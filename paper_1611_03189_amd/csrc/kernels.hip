@@ -50,73 +50,116 @@ void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------------
-// Grouped GEMM: 64 x 64 output tiles, 256 threads, 4 x 4 outputs per thread
+// Grouped GEMM on the FP64 matrix cores: 64 x 64 output tiles, 256 threads (4 waves, each
+// 32 x 32 = 2 x 2 blocks of v_mfma_f64_16x16x4f64), K in steps of 16 through two LDS
+// buffers, the next K step loaded into registers while the current one is multiplied.
+// Operand layout of the instruction (per lane l of the wave): A(l % 16, l / 16),
+// B(l / 16, l % 16); result register r holds C(l / 16 + 4 r, l % 16).
 // ---------------------------------------------------------------------------------
 constexpr int TM = 64, TN = 64, TK = 16;
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+struct GemmStep {            // position in the concatenated K loop of a task's terms
+    int term, k0;
+};
 
 __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
                                              const GemmTile* tiles) {
     const GemmTile tl = tiles[blockIdx.x];
     const GemmTask T = tasks[tl.task];
-    const int tid = threadIdx.x, tx = tid % 16, ty = tid / 16;
-    __shared__ double As[TK][TM + 1];
-    __shared__ double Bs[TK][TN + 1];
-    double acc[4][4];
-#pragma unroll
-    for (int x = 0; x < 4; ++x)
-#pragma unroll
-        for (int y = 0; y < 4; ++y) acc[x][y] = 0.0;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    __shared__ double As[2][TK][TM + 1];
+    __shared__ double Bs[2][TK][TN + 1];
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
-    for (int t = T.t_begin; t < T.t_end; ++t) {
-        const GemmTerm g = terms[t];
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+
+    // registers of one K step: 4 A and 4 B elements per thread
+    double ra[4], rb[4];
+    auto load_step = [&](GemmStep st) {
+        const GemmTerm g = terms[st.term];
         const HS_G double* gA = gp(g.A);
         const HS_G double* gB = gp(g.B);
-        for (int k0 = 0; k0 < g.K; k0 += TK) {
-            for (int e = tid; e < TM * TK; e += NT) {
-                int ii, kk;
-                if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
-                const int gi = i0 + ii, gk = k0 + kk;
-                double v = 0.0;
-                if (gi < T.M && gk < g.K)
-                    v = g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda];
-                As[kk][ii] = v;
-            }
-            for (int e = tid; e < TN * TK; e += NT) {
-                int jj, kk;
-                if (g.transB) { jj = e % TN; kk = e / TN; } else { kk = e % TK; jj = e / TK; }
-                const int gj = j0 + jj, gk = k0 + kk;
-                double v = 0.0;
-                if (gj < T.N && gk < g.K)
-                    v = g.transB ? gB[gj + size_t(gk) * g.ldb] : gB[gk + size_t(gj) * g.ldb];
-                Bs[kk][jj] = v;
-            }
-            __syncthreads();
 #pragma unroll
-            for (int kk = 0; kk < TK; ++kk) {
-                double a[4], b[4];
-#pragma unroll
-                for (int x = 0; x < 4; ++x) a[x] = As[kk][tx + 16 * x];
-#pragma unroll
-                for (int y = 0; y < 4; ++y) b[y] = Bs[kk][ty + 16 * y];
-#pragma unroll
-                for (int x = 0; x < 4; ++x)
-#pragma unroll
-                    for (int y = 0; y < 4; ++y) acc[x][y] = fma(a[x], b[y], acc[x][y]);
-            }
-            __syncthreads();
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + NT * q;
+            int ii, kk;
+            if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
+            const int gi = i0 + ii, gk = st.k0 + kk;
+            ra[q] = (gi < T.M && gk < g.K) ? (g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda])
+                                           : 0.0;
+            int jj, kb;
+            if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
+            const int gj = j0 + jj, gkb = st.k0 + kb;
+            rb[q] = (gj < T.N && gkb < g.K) ? (g.transB ? gB[gj + size_t(gkb) * g.ldb] : gB[gkb + size_t(gj) * g.ldb])
+                                            : 0.0;
         }
+    };
+    auto store_step = [&](GemmStep st, int buf) {
+        const GemmTerm g = terms[st.term];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int e = tid + NT * q;
+            int ii, kk;
+            if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
+            As[buf][kk][ii] = ra[q];
+            int jj, kb;
+            if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
+            Bs[buf][kb][jj] = rb[q];
+        }
+    };
+    auto next_step = [&](GemmStep st) {
+        st.k0 += TK;
+        while (st.term < T.t_end && st.k0 >= terms[st.term].K) {
+            ++st.term;
+            st.k0 = 0;
+        }
+        return st;
+    };
+    GemmStep cur{T.t_begin, 0};
+    while (cur.term < T.t_end && terms[cur.term].K <= 0) ++cur.term;
+    const int wr = (wv / 2) * 32, wc = (wv % 2) * 32;    // this wave's 32 x 32 sub-tile
+    const int fr = lane % 16, fk = lane / 16;
+    int buf = 0;
+    if (cur.term < T.t_end) load_step(cur);
+    while (cur.term < T.t_end) {
+        store_step(cur, buf);
+        __syncthreads();
+        const GemmStep nxt = next_step(cur);
+        if (nxt.term < T.t_end) load_step(nxt);
+#pragma unroll
+        for (int kk = 0; kk < TK; kk += 4) {
+            double af[2], bf[2];
+#pragma unroll
+            for (int x = 0; x < 2; ++x) af[x] = As[buf][kk + fk][wr + 16 * x + fr];
+#pragma unroll
+            for (int y = 0; y < 2; ++y) bf[y] = Bs[buf][kk + fk][wc + 16 * y + fr];
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+        }
+        cur = nxt;
+        buf ^= 1;
     }
+    HS_G double* C = gp(T.C);
 #pragma unroll
-    for (int y = 0; y < 4; ++y)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int x = 0; x < 4; ++x) {
-            const int i = i0 + tx + 16 * x, j = j0 + ty + 16 * y;
-            if (i < T.M && j < T.N) {
-                HS_G double* c = gp(T.C) + i + size_t(j) * T.ldc;
-                const double old = (T.beta == 0.0) ? 0.0 : T.beta * (*c);
-                *c = old + T.alpha * acc[x][y];
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = i0 + wr + 16 * x + fk + 4 * r, j = j0 + wc + 16 * y + fr;
+                if (i < T.M && j < T.N) {
+                    HS_G double* c = C + i + size_t(j) * T.ldc;
+                    const double old = (T.beta == 0.0) ? 0.0 : T.beta * (*c);
+                    *c = old + T.alpha * acc[x][y][r];
+                }
             }
-        }
 }
 
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,

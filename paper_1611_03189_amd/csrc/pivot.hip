@@ -98,36 +98,64 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     }
 }
 
-// advance (I, J) by `step` positions in the column-major order of the lower tiles of a
-// T x T tile grid (column J holds rows J..T-1); J == T marks the end
-__device__ inline void next_lower_tile(int& I, int& J, int step, int T) {
-    I += step;
-    while (J < T && I >= T) {
-        I -= T - (J + 1);
-        ++J;
-    }
-}
 
-// Inverse of the lower-triangular nb x nb block in X11 (ld PIV_NB + 1), in place, by the
-// calling wave (lane = row), columns right to left; entries above the diagonal and outside
-// nb are set to zero so that X11 can be used as a full PIV_NB x PIV_NB matrix.
-__device__ inline void wave_trinv32(double* X11, int nb, int lane) {
+// Cholesky of the nb x nb diagonal block at P (column-major, ld ldp, nb <= PIV_NB) in place
+// and its inverse in X11 (full PIV_NB x PIV_NB, zeros above the diagonal and outside nb), by
+// the whole workgroup: thread t owns the entries (t % 32, t / 32 + 8k), k < 4. The
+// factorisation keeps each column unscaled until the end (updates use a_rj a_cj / d_j),
+// and the inverse solves L X = I by columns, one barrier per step. Sets *bad on a
+// non-positive pivot (every thread sees the same pivot, so all leave together).
+__device__ void block_potrf_trinv32(double* P, int ldp, int nb, double* X11, int* bad) {
     constexpr int l11 = PIV_NB + 1;
-    for (int c = 0; c < PIV_NB; ++c)
-        if (lane < PIV_NB && (lane < c || lane >= nb || c >= nb)) X11[lane + c * l11] = 0.0;
-    wave_sync();
-    for (int j = nb - 1; j >= 0; --j) {
-        if (lane == j) X11[j + j * l11] = 1.0 / X11[j + j * l11];
-        wave_sync();
-        double y = 0.0;
-        if (lane > j && lane < nb) {
-            for (int l = j + 1; l <= lane; ++l) y += X11[lane + l * l11] * X11[l + j * l11];
-            y *= -X11[j + j * l11];
+    const int r = threadIdx.x % PIV_NB, cb = threadIdx.x / PIV_NB;
+    for (int j = 0; j < nb; ++j) {
+        const double dj = P[j + j * ldp];
+        if (!(dj > 0.0) || !isfinite(dj)) {
+            if (threadIdx.x == 0) *bad = 1;
+            return;                                 // uniform: every thread read the same dj
         }
-        wave_sync();
-        if (lane > j && lane < nb) X11[lane + j * l11] = y;
-        wave_sync();
+        const double idj = 1.0 / dj;
+        const double arj = (r < nb) ? P[r + j * ldp] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = cb + 8 * k;
+            if (c > j && c <= r && r < nb) P[r + c * ldp] -= arj * P[c + j * ldp] * idj;
+        }
+        __syncthreads();
     }
+    // scale: L(r, c) = a_rc / sqrt(d_c), L(c, c) = sqrt(d_c); X11 = I
+    double l[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cb + 8 * k;
+        l[k] = 0.0;
+        if (r < nb && c < nb && c <= r) l[k] = (r == c) ? sqrt(P[c + c * ldp]) : P[r + c * ldp] / sqrt(P[c + c * ldp]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cb + 8 * k;
+        if (r < nb && c < nb && c <= r) P[r + c * ldp] = l[k];
+        X11[r + c * l11] = (r == c && r < nb) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // forward substitution L X = I, columns in parallel; row j of X is scaled at the end
+    for (int j = 0; j < nb; ++j) {
+        const double ilj = 1.0 / P[j + j * ldp];
+        const double lrj = (r > j && r < nb) ? P[r + j * ldp] : 0.0;
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int c = cb + 8 * k;
+            if (r > j && r < nb && c <= j) X11[r + c * l11] -= lrj * X11[j + c * l11] * ilj;
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cb + 8 * k;
+        if (r < nb) X11[r + c * l11] /= P[r + r * ldp];
+    }
+    __syncthreads();
 }
 
 // rows [i_begin, i_end) of P (column-major, ld ldp): P(i, :) <- P(i, :) X11^T (trans) or
@@ -154,7 +182,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     __shared__ double X11[PIV_NB * (PIV_NB + 1)];
     __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
-    const int m = T.m, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    const int m = T.m, tid = threadIdx.x;
     constexpr int l11 = PIV_NB + 1;
     HS_G double* W = gp(T.work);                   // m x m, ld m
     const HS_G double* A = gp(T.A);
@@ -180,31 +208,8 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             Pn[i + c * r] = W[(jb + i) + (jb + c) * ld];
         }
         __syncthreads();
-        // L11 and its inverse by the first wave alone (lane = row, no workgroup barriers)
-        if (wv == 0) {
-            for (int j = 0; j < nb; ++j) {
-                if (lane == j) {
-                    const double d = Pn[j + j * r];
-                    if (!(d > 0.0) || !isfinite(d)) bad = 1;
-                    else Pn[j + j * r] = sqrt(d);
-                }
-                wave_sync();
-                if (bad) break;
-                const double piv = Pn[j + j * r];
-                if (lane > j && lane < nb) Pn[lane + j * r] /= piv;
-                wave_sync();
-                if (lane > j && lane < nb) {
-                    const double lij = Pn[lane + j * r];
-                    for (int c = j + 1; c <= lane; ++c) Pn[lane + c * r] -= lij * Pn[c + j * r];
-                }
-                wave_sync();
-            }
-            if (!bad) {
-                for (int c = 0; c < nb; ++c)
-                    if (lane < nb) X11[lane + c * l11] = Pn[lane + c * r];
-                wave_trinv32(X11, nb, lane);
-            }
-        }
+        // L11 and its inverse by the whole workgroup
+        block_potrf_trinv32(Pn, r, nb, X11, &bad);
         __syncthreads();
         if (bad) break;
         // L21 = A21 L11^{-T}, rows in registers
@@ -214,37 +219,76 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             const int i = e % r, c = e / r;
             W[(jb + i) + (jb + c) * ld] = (i < nb) ? X11[i + c * l11] : Pn[i + c * r];
         }
-        // trailing update W22 -= L21 L21^T on the lower 4x4 tiles, L21 = Pn(nb.., :)
-        const int t = r - nb;
-        const int Tt = (t + 3) / 4;
-        int I = tid, J = 0;
-        next_lower_tile(I, J, 0, Tt);
-        for (; J < Tt; next_lower_tile(I, J, NT, Tt)) {
-            const int pi = nb + 4 * I, pj = nb + 4 * J;      // panel rows of the tile
-            double acc[4][4];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    acc[u][v] = (pi + u < r && pj + v < r) ? W[(jb + pi + u) + (jb + pj + v) * ld] : 0.0;
-#pragma unroll 2
-            for (int k = 0; k < nb; ++k) {
-                double a[4], b[4];
+        // trailing update W22 -= L21 L21^T, L21 = Pn(nb.., :): 64 x 64 block tiles on and below
+        // the diagonal, thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w;
+        // the next tile is loaded before the current one is computed
+        {
+            const int t = r - nb;
+            const int Tb = (t + 63) / 64, ntile = Tb * (Tb + 1) / 2;
+            const int tx = tid % 16, ty = tid / 16;
+            auto tile_rc = [&](int bt, int* pr, int* pc, bool* okr, bool* okc) {
+                int bj = 0, rem = bt;                 // column-major order of the lower tiles
+                while (rem >= Tb - bj) {
+                    rem -= Tb - bj;
+                    ++bj;
+                }
+                const int bi = bj + rem;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
-                    a[u] = (pi + u < r) ? Pn[pi + u + k * r] : 0.0;
-                    b[u] = (pj + u < r) ? Pn[pj + u + k * r] : 0.0;
+                    const int ii = 64 * bi + tx + 16 * u, jj = 64 * bj + ty + 16 * u;
+                    okr[u] = ii < t;
+                    okc[u] = jj < t;
+                    pr[u] = nb + min(ii, t - 1);      // panel rows (clamped)
+                    pc[u] = nb + min(jj, t - 1);
+                }
+            };
+            int pr[4], pc[4], prn[4], pcn[4];
+            bool okr[4], okc[4], okrn[4], okcn[4];
+            double nxt[4][4];
+            if (ntile > 0) {
+                tile_rc(0, prn, pcn, okrn, okcn);
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) nxt[u][v] = W[(jb + prn[u]) + (jb + pcn[v]) * ld];
+            }
+            for (int bt = 0; bt < ntile; ++bt) {
+                double acc[4][4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    pr[u] = prn[u];
+                    pc[u] = pcn[u];
+                    okr[u] = okrn[u];
+                    okc[u] = okcn[u];
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) acc[u][v] = nxt[u][v];
+                }
+                if (bt + 1 < ntile) {
+                    tile_rc(bt + 1, prn, pcn, okrn, okcn);
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) nxt[u][v] = W[(jb + prn[u]) + (jb + pcn[v]) * ld];
+                }
+#pragma unroll 2
+                for (int k = 0; k < nb; ++k) {
+                    double a[4], b[4];
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        a[u] = Pn[pr[u] + k * r];
+                        b[u] = Pn[pc[u] + k * r];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; ++u)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) acc[u][v] -= a[u] * b[v];
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] -= a[u] * b[v];
+                    for (int v = 0; v < 4; ++v)
+                        if (okr[u] && okc[v]) W[(jb + pr[u]) + (jb + pc[v]) * ld] = acc[u][v];
             }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    if (pi + u < r && pj + v < r) W[(jb + pi + u) + (jb + pj + v) * ld] = acc[u][v];
         }
         __syncthreads();
     }
@@ -290,22 +334,35 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             for (int v = 0; v < 8; ++v) yc[v] = min(c0 + v, nb - 1) * t;
             const int lend = min(i0, t - 1);
             int l = 0;
-            for (; l + 3 <= lend; l += 4) {
-                double x[4][4], y[4][8];
+            if (l + 3 <= lend) {
+                double xn[4][4];                    // next batch of columns, loaded ahead
 #pragma unroll
                 for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) x[q][u] = X22[xr[u] + size_t(l + q) * ld];
+                    for (int u = 0; u < 4; ++u) xn[q][u] = X22[xr[u] + size_t(l + q) * ld];
+                for (; l + 3 <= lend; l += 4) {
+                    double x[4][4], y[4][8];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int v = 0; v < 8; ++v) y[q][v] = Pn[l + q + yc[v]];
+                        for (int u = 0; u < 4; ++u) x[q][u] = xn[q][u];
+                    if (l + 7 <= lend) {
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                        for (int q = 0; q < 4; ++q)
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                            for (int u = 0; u < 4; ++u) xn[q][u] = X22[xr[u] + size_t(l + 4 + q) * ld];
+                    }
 #pragma unroll
-                        for (int v = 0; v < 8; ++v) acc[u][v] += x[q][u] * y[q][v];
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int v = 0; v < 8; ++v) y[q][v] = Pn[l + q + yc[v]];
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+#pragma unroll
+                            for (int v = 0; v < 8; ++v) acc[u][v] += x[q][u] * y[q][v];
+                }
             }
             for (; l <= lend; ++l) {
                 double x[4], y[8];
