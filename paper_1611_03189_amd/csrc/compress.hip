@@ -18,9 +18,12 @@
 //                  by the kept directions, which is similar to G; otherwise G itself is
 //                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
 //   k_comp_bisect  (many workgroups, one wave per kept eigenvalue) multisection to eps ||T||;
-//   k_comp_vectors (many workgroups, one wave per cluster of eigenvalues closer than
-//                  1e-7 ||T||) inverse iteration in LDS, members orthogonalised against
-//                  each other, then back-transformation with the vector held in registers.
+//   k_comp_vectors (many workgroups, one wave per kept eigenvalue) inverse iteration in LDS;
+//   k_comp_orth    the vectors of each cluster of eigenvalues closer than 1e-7 ||T|| made
+//                  orthonormal (they span the cluster's invariant subspace);
+//   k_comp_wy      block reflector factors T of the tridiagonalisation (compact WY form);
+//   k_comp_bt      back-transformation of BT_COLS eigenvectors per workgroup, in LDS, by
+//                  blocks of reflectors, then the GC reflectors.
 #include <cfloat>
 #include <type_traits>
 
@@ -30,12 +33,13 @@ namespace hs {
 
 constexpr int CMP_LDS_MAX = 128;
 constexpr int CMP_MAX = 512;            // largest super node the compression accepts
-constexpr int CMP_RMAX = CMP_MAX / WAVE;   // vector entries per lane in the back-transform
 
 // Per-node global work layout (doubles): reflectors H (m x m, ld m) | d, e, tau, lam (4m) |
-// GC reflectors (16 m) + their tau (16) | info (8).
+// GC reflectors (16 m) + their tau (16) | info (8) | block reflector factors T (WY_NB x WY_NB
+// per block of WY_NB tridiagonalisation reflectors). Size: cmp_work_doubles(m).
+constexpr int WY_NB = CMP_WY_NB;
 struct CmpWork {
-    HS_G double *H, *d, *e, *tau, *lam, *gcv, *gct, *info;
+    HS_G double *H, *d, *e, *tau, *lam, *gcv, *gct, *info, *wyT;
     __device__ CmpWork(double* wg, int m) {
         HS_G double* w = gp(wg);
         H = w;
@@ -46,6 +50,7 @@ struct CmpWork {
         gcv = lam + m;
         gct = gcv + size_t(16) * m;
         info = gct + 16;
+        wyT = info + 8;
     }
 };
 enum { INF_Q, INF_K2, INF_NN, INF_TNORM, INF_PIVMIN, INF_LO, INF_HI, INF_DONE };
@@ -1023,14 +1028,15 @@ __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
     if (active && g == 0) Wk.lam[j] = 0.5 * (lo + hi);
 }
 
-// one wave per eigenvalue index; cluster leaders compute their members' eigenvectors by
-// inverse iteration and map them back to the m-dim coordinates
+// one wave per kept eigenvalue: inverse iteration with the tridiagonal, in trailing coordinates
 constexpr int VNT = 128;           // two waves per workgroup in k_comp_vectors
 
-__global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks, int variant) {
-    __shared__ double d[CMP_MAX], e[CMP_MAX];
-    __shared__ double scr[VNT / WAVE][5][CMP_MAX];
-    __shared__ int swp_all[VNT / WAVE][CMP_MAX];
+__global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks, int variant, int ldn) {
+    // LDS (ldn >= every node's order): d, e, then per wave y, u0, u1, u2, mult and the
+    // interchange flags
+    extern __shared__ double lds[];
+    double* d = lds;
+    double* e = d + ldn;
     const CompressTask T = tasks[blockIdx.y];
     const int m = T.m;
     CmpWork Wk(T.work, m);
@@ -1045,110 +1051,240 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks,
     const int c0 = blockIdx.x * (VNT / WAVE) + wv;
     if (c0 >= k2) return;
     const double tnorm = Wk.info[INF_TNORM];
-    const double ctol = 1e-7 * tnorm;
+    const HS_G double* lam = Wk.lam;
+    const double tiny = DBL_EPSILON * (tnorm > 0.0 ? tnorm : 1.0);
+    double* y = e + ldn + size_t(wv) * 5 * ldn;
+    double* u0 = y + ldn;
+    double* u1 = u0 + ldn;
+    double* u2 = u1 + ldn;
+    double* mult = u2 + ldn;
+    int* swp = reinterpret_cast<int*>(e + ldn + size_t(VNT / WAVE) * 5 * ldn) + wv * ldn;
+    const int c = c0;
+    for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
+    wave_sync();
+    if (lane == 0) tridiag_shift_factor(d, e, nn, lam[c], tiny, u0, u1, u2, mult, swp);
+    for (int it = 0; it < 3; ++it) {
+        wave_sync();
+        if (lane == 0) tridiag_shift_apply(nn, u0, u1, u2, mult, swp, y);
+        wave_sync();
+        double part = 0.0;
+        for (int i = lane; i < nn; i += WAVE) part += y[i] * y[i];
+        const double nrm = sqrt(wave_sum(part));
+        const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+        for (int i = lane; i < nn; i += WAVE) y[i] *= inv;
+    }
+    HS_G double* col = gp(T.U) + size_t(q + c) * m + q;
+    for (int i = lane; i < nn; i += WAVE) col[i] = y[i];
+}
+
+// Eigenvectors of a cluster (consecutive eigenvalues closer than 1e-7 ||T||) are computed
+// independently from different start vectors; they span the cluster's invariant subspace
+// and are made orthonormal here by modified Gram-Schmidt, twice. One wave per cluster
+// leader.
+__global__ __launch_bounds__(NT) void k_comp_orth(const CompressTask* tasks) {
+    const CompressTask T = tasks[blockIdx.y];
+    const int m = T.m;
+    CmpWork Wk(T.work, m);
+    const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]), q = int(Wk.info[INF_Q]);
+    const int lane = threadIdx.x % WAVE, c0 = blockIdx.x * (NT / WAVE) + threadIdx.x / WAVE;
+    if (c0 >= k2) return;
+    const double ctol = 1e-7 * Wk.info[INF_TNORM];
     const HS_G double* lam = Wk.lam;
     if (c0 > 0 && lam[c0 - 1] - lam[c0] <= ctol) return;     // not a cluster leader
     int c1 = c0 + 1;
     while (c1 < k2 && lam[c1 - 1] - lam[c1] <= ctol) ++c1;
-    const double tiny = DBL_EPSILON * (tnorm > 0.0 ? tnorm : 1.0);
-    double* y = scr[wv][0];
-    double* u0 = scr[wv][1];
-    double* u1 = scr[wv][2];
-    double* u2 = scr[wv][3];
-    double* mult = scr[wv][4];
-    int* swp = swp_all[wv];
+    if (c1 - c0 < 2) return;
+    HS_G double* U = gp(T.U);
     for (int c = c0; c < c1; ++c) {
-        for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
-        wave_sync();
-        if (lane == 0) tridiag_shift_factor(d, e, nn, lam[c], tiny, u0, u1, u2, mult, swp);
-        for (int it = 0; it < 3; ++it) {
-            wave_sync();
-            if (lane == 0) tridiag_shift_apply(nn, u0, u1, u2, mult, swp, y);
-            wave_sync();
-            for (int pass = 0; pass < 2; ++pass)
-                for (int b = c0; b < c; ++b) {
-                    const HS_G double* yb = gp(T.U) + size_t(q + b) * m + q;
-                    double part = 0.0;
-                    for (int i = lane; i < nn; i += WAVE) part += yb[i] * y[i];
-                    const double dot = wave_sum(part);
-                    for (int i = lane; i < nn; i += WAVE) y[i] -= dot * yb[i];
-                }
-            double part = 0.0;
-            for (int i = lane; i < nn; i += WAVE) part += y[i] * y[i];
-            const double nrm = sqrt(wave_sum(part));
-            const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
-            for (int i = lane; i < nn; i += WAVE) y[i] *= inv;
-        }
-        HS_G double* col = gp(T.U) + size_t(q + c) * m + q;
-        for (int i = lane; i < nn; i += WAVE) col[i] = y[i];
-    }
-    wave_sync();        // lane l reads entries that lane l - q wrote
-    // back-transformation of each member, vector in registers: x_full = [0_q; y]
-    for (int c = c0; c < c1; ++c) {
-        HS_G double* u = gp(T.U) + size_t(q + c) * m;
-        double x[CMP_RMAX];
-#pragma unroll
-        for (int r = 0; r < CMP_RMAX; ++r) {
-            const int i = lane + WAVE * r;
-            x[r] = (i >= q && i < m) ? u[i] : 0.0;
-        }
-        // reflectors j = nn-3 .. 0, the next one's column loaded before the current dot product
-        const int rmax = (m + WAVE - 1) / WAVE;
-        auto load_refl = [&](int j, double* v) {
-            const int col0 = q + j;                 // reflector column in m-dim coordinates
-            const HS_G double* hc = Wk.H + size_t(col0) * m;
-#pragma unroll
-            for (int r = 0; r < CMP_RMAX; ++r) {
-                const int i = lane + WAVE * r;
-                const double h = (r < rmax) ? hc[min(i, m - 1)] : 0.0;
-                v[r] = (i > col0 + 1 && i < m) ? h : (i == col0 + 1 ? 1.0 : 0.0);
-            }
-        };
-        double va[CMP_RMAX], vb[CMP_RMAX];
-        double ta = 0.0;
-        if (nn - 3 >= 0) {
-            load_refl(nn - 3, va);
-            ta = Wk.tau[nn - 3];
-        }
-        for (int j = nn - 3; j >= 0; --j) {
-            double tb = 0.0;
-            if (j >= 1) {
-                load_refl(j - 1, vb);
-                tb = Wk.tau[j - 1];
-            }
-            if (ta != 0.0) {
+        HS_G double* yc = U + size_t(q + c) * m + q;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int b = c0; b < c; ++b) {
+                const HS_G double* yb = U + size_t(q + b) * m + q;
                 double part = 0.0;
-#pragma unroll
-                for (int r = 0; r < CMP_RMAX; ++r) part += va[r] * x[r];
-                const double dot = wave_sum(part) * ta;
-#pragma unroll
-                for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * va[r];
+                for (int i = lane; i < nn; i += WAVE) part += yb[i] * yc[i];
+                const double dot = wave_sum(part);
+                for (int i = lane; i < nn; i += WAVE) yc[i] -= dot * yb[i];
             }
-#pragma unroll
-            for (int r = 0; r < CMP_RMAX; ++r) va[r] = vb[r];
-            ta = tb;
+        double part = 0.0;
+        for (int i = lane; i < nn; i += WAVE) part += yc[i] * yc[i];
+        const double nrm = sqrt(wave_sum(part));
+        const double inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+        for (int i = lane; i < nn; i += WAVE) yc[i] *= inv;
+    }
+}
+
+// Block reflector factors (compact WY form): for block b of WY_NB consecutive
+// tridiagonalisation reflectors, H_j0 ... H_j0+nb-1 = I - V T V^T with T upper triangular
+// (T_ii = tau_i, T(0:i, i) = -tau_i T(0:i, 0:i) V(:, 0:i)^T v_i). One workgroup per block.
+// Reflector j acts on the trailing coordinates: v_j(j + 1) = 1, v_j(r) = H(q + r, q + j) for
+// r >= j + 2 (m-dim row q + r), zero elsewhere.
+__global__ __launch_bounds__(NT) void k_comp_wy(const CompressTask* tasks) {
+    __shared__ double Vs[WY_NB][CMP_MAX + 1];
+    __shared__ double Gs[WY_NB][WY_NB + 1];
+    __shared__ double Ts[WY_NB][WY_NB + 1];
+    const CompressTask T = tasks[blockIdx.y];
+    const int m = T.m;
+    CmpWork Wk(T.work, m);
+    const int nn = int(Wk.info[INF_NN]), q = int(Wk.info[INF_Q]), k2 = int(Wk.info[INF_K2]);
+    const int nref = nn - 2;
+    const int j0 = blockIdx.x * WY_NB;
+    if (k2 <= 0 || j0 >= nref) return;
+    const int nb = min(WY_NB, nref - j0);
+    const int tid = threadIdx.x;
+    for (int e = tid; e < WY_NB * nn; e += NT) {
+        const int i = e / nn, r = e % nn, j = j0 + i;
+        double v = 0.0;
+        if (i < nb) v = (r == j + 1) ? 1.0 : (r >= j + 2 ? Wk.H[(q + r) + size_t(q + j) * m] : 0.0);
+        Vs[i][r] = v;
+    }
+    __syncthreads();
+    // Gram matrix G = V^T V (upper part), 8 lanes per entry
+    for (int p = tid / 8; p < WY_NB * WY_NB; p += NT / 8) {
+        const int a = p % WY_NB, c = p / WY_NB;
+        double sum = 0.0;
+        if (a < c && c < nb)
+            for (int r = tid % 8; r < nn; r += 8) sum += Vs[a][r] * Vs[c][r];
+        sum += __shfl_xor(sum, 1, WAVE);
+        sum += __shfl_xor(sum, 2, WAVE);
+        sum += __shfl_xor(sum, 4, WAVE);
+        if (tid % 8 == 0) Gs[a][c] = sum;
+    }
+    __syncthreads();
+    // T column by column (first wave, lane = row)
+    if (tid < WAVE) {
+        const int lane = tid;
+        for (int i = 0; i < WY_NB; ++i)
+            if (lane < WY_NB) Ts[lane][i] = 0.0;
+        wave_sync();
+        for (int i = 0; i < nb; ++i) {
+            const double ti = Wk.tau[j0 + i];
+            double t = 0.0;
+            if (lane < i) {
+                for (int l = lane; l < i; ++l) t += Ts[lane][l] * Gs[l][i];
+                t *= -ti;
+            }
+            wave_sync();
+            if (lane < i) Ts[lane][i] = t;
+            if (lane == i) Ts[i][i] = ti;
+            wave_sync();
         }
+    }
+    __syncthreads();
+    HS_G double* Tg = Wk.wyT + size_t(blockIdx.x) * WY_NB * WY_NB;
+    for (int e = tid; e < WY_NB * WY_NB; e += NT) Tg[e] = Ts[e % WY_NB][e / WY_NB];
+}
+
+// Back-transformation of the eigenvectors y (trailing coordinates, columns q.. of U) to the
+// m-dim coordinates: U(:, q + c) = W_gc^T [0_q; Q y_c] with Q = B_0 ... B_{nb-1} the
+// tridiagonalisation blocks (B_b = I - V_b T_b V_b^T, applied last first) and W_gc the GC
+// reflectors. One workgroup per BT_COLS eigenvectors, held in LDS.
+constexpr int BT_COLS = 16;
+
+__global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int variant) {
+    extern __shared__ double lds[];
+    const CompressTask T = tasks[blockIdx.y];
+    const int m = T.m;
+    CmpWork Wk(T.work, m);
+    const int nn = int(Wk.info[INF_NN]), q = int(Wk.info[INF_Q]), k2 = int(Wk.info[INF_K2]);
+    const int c0 = blockIdx.x * BT_COLS;
+    if (c0 >= k2) return;
+    const int nc = min(BT_COLS, k2 - c0);
+    const int tid = threadIdx.x;
+    const int ldy = m + 1;                          // Y: m x BT_COLS, column-major
+    double* Y = lds;
+    double* Vs = Y + size_t(BT_COLS) * ldy;        // V block: WY_NB columns of nn (ld nn + 1)
+    const int ldv = nn + 1;
+    double* Wm = Vs + size_t(WY_NB) * ldv;         // W = V^T Y then T W: WY_NB x BT_COLS
+    double* Ts = Wm + WY_NB * BT_COLS;             // T: WY_NB x WY_NB (ld WY_NB + 1)
+    HS_G double* U = gp(T.U);
+    for (int e = tid; e < BT_COLS * m; e += NT) {
+        const int c = e / m, r = e % m;
+        Y[r + c * ldy] = (c < nc && r >= q) ? U[r + size_t(q + c0 + c) * m] : 0.0;
+    }
+    const int nref = nn - 2;
+    const int nblk = nref > 0 ? (nref + WY_NB - 1) / WY_NB : 0;
+    double* Yt = Y + q;                              // trailing coordinates
+    for (int b = nblk - 1; b >= 0; --b) {
+        const int j0 = b * WY_NB, nb = min(WY_NB, nref - j0);
+        __syncthreads();
+        for (int e = tid; e < WY_NB * nn; e += NT) {
+            const int i = e / nn, r = e % nn, j = j0 + i;
+            double v = 0.0;
+            if (i < nb) v = (r == j + 1) ? 1.0 : (r >= j + 2 ? Wk.H[(q + r) + size_t(q + j) * m] : 0.0);
+            Vs[r + i * ldv] = v;
+        }
+        const HS_G double* Tg = Wk.wyT + size_t(b) * WY_NB * WY_NB;
+        for (int e = tid; e < WY_NB * WY_NB; e += NT) Ts[(e % WY_NB) + (e / WY_NB) * (WY_NB + 1)] = Tg[e];
+        __syncthreads();
+        // W = V^T Y: WY_NB x BT_COLS dot products of length nn, two per thread
+        for (int p = tid; p < WY_NB * BT_COLS; p += NT) {
+            const int i = p % WY_NB, c = p / WY_NB;
+            double s0 = 0.0, s1 = 0.0;
+            const double* vi = Vs + i * ldv;
+            const double* yc = Yt + c * ldy;
+            int r = j0 + i + 1;                      // v_i is zero above its unit entry
+            for (; r + 1 < nn; r += 2) {
+                s0 += vi[r] * yc[r];
+                s1 += vi[r + 1] * yc[r + 1];
+            }
+            if (r < nn) s0 += vi[r] * yc[r];
+            Wm[i + c * WY_NB] = s0 + s1;
+        }
+        __syncthreads();
+        // W <- T W (T upper triangular)
+        double tw[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = tid + h * NT;
+            tw[h] = 0.0;
+            if (p < WY_NB * BT_COLS) {
+                const int i = p % WY_NB, c = p / WY_NB;
+                for (int l = i; l < WY_NB; ++l) tw[h] += Ts[i + l * (WY_NB + 1)] * Wm[l + c * WY_NB];
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int p = tid + h * NT;
+            if (p < WY_NB * BT_COLS) Wm[p] = tw[h];
+        }
+        __syncthreads();
+        // Y -= V W
+        for (int e = tid; e < nn * BT_COLS; e += NT) {
+            const int r = e % nn, c = e / nn;
+            double acc = 0.0;
+#pragma unroll 8
+            for (int i = 0; i < WY_NB; ++i) acc += Vs[r + i * ldv] * Wm[i + c * WY_NB];
+            Yt[r + c * ldy] -= acc;
+        }
+    }
+    __syncthreads();
+    // GC reflectors, last first: y <- (I - tau v v^T) y in m-dim coordinates
+    if (variant == HSOLVE_GC) {
+        double* dots = Wm;                           // BT_COLS partial sums
         for (int t = q - 1; t >= 0; --t) {
             const double tt = Wk.gct[t];
-            if (variant != HSOLVE_GC || tt == 0.0) continue;
+            if (tt == 0.0) continue;
             const HS_G double* vt = Wk.gcv + size_t(t) * m;
-            double part = 0.0;
-            double v[CMP_RMAX];
-#pragma unroll
-            for (int r = 0; r < CMP_RMAX; ++r) {
-                const int i = lane + WAVE * r;
-                v[r] = (i < m) ? vt[i] : 0.0;
-                part += v[r] * x[r];
+            // one wave per column: dot of v with column c
+            for (int c = tid / WAVE; c < BT_COLS; c += NT / WAVE) {
+                double part = 0.0;
+                for (int r = tid % WAVE; r < m; r += WAVE) part += vt[r] * Y[r + c * ldy];
+                part = wave_sum(part);
+                if (tid % WAVE == 0) dots[c] = part * tt;
             }
-            const double dot = wave_sum(part) * tt;
-#pragma unroll
-            for (int r = 0; r < CMP_RMAX; ++r) x[r] -= dot * v[r];
+            __syncthreads();
+            for (int e = tid; e < m * BT_COLS; e += NT) {
+                const int r = e % m, c = e / m;
+                Y[r + c * ldy] -= dots[c] * vt[r];
+            }
+            __syncthreads();
         }
-#pragma unroll
-        for (int r = 0; r < CMP_RMAX; ++r) {
-            const int i = lane + WAVE * r;
-            if (i < m) u[i] = x[r];
-        }
+    }
+    __syncthreads();
+    for (int e = tid; e < nc * m; e += NT) {
+        const int c = e / m, r = e % m;
+        U[r + size_t(q + c0 + c) * m] = Y[r + c * ldy];
     }
 }
 
@@ -1202,9 +1338,38 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     }
     {
         ProfScope ps("k_comp_vectors", 0.0, s);
+        const int ldn = max_m;
+        const size_t bytes = sizeof(double) * (2 + 5 * (VNT / WAVE)) * size_t(ldn) + sizeof(int) * (VNT / WAVE) * size_t(ldn);
         hipLaunchKernelGGL(k_comp_vectors, dim3((max_m + VNT / WAVE - 1) / (VNT / WAVE), ntasks), dim3(VNT),
-                           0, s, d_tasks, variant);
+                           bytes, s, d_tasks, variant, ldn);
         check_launch("k_comp_vectors");
+    }
+    {
+        ProfScope ps("k_comp_orth", 0.0, s);
+        hipLaunchKernelGGL(k_comp_orth, dim3((max_m + NT / WAVE - 1) / (NT / WAVE), ntasks), dim3(NT), 0, s,
+                           d_tasks);
+        check_launch("k_comp_orth");
+    }
+    {
+        ProfScope ps("k_comp_wy", 0.0, s);
+        hipLaunchKernelGGL(k_comp_wy, dim3((max_m + WY_NB - 1) / WY_NB, ntasks), dim3(NT), 0, s, d_tasks);
+        check_launch("k_comp_wy");
+    }
+    {
+        ProfScope ps("k_comp_bt", 0.0, s);
+        const size_t bytes = sizeof(double) * (size_t(BT_COLS) * (max_m + 1) + size_t(WY_NB) * (max_m + 1) +
+                                               WY_NB * BT_COLS + WY_NB * (WY_NB + 1));
+        static bool attr = false;
+        if (!attr) {
+            const size_t most = sizeof(double) * (size_t(BT_COLS) * (CMP_MAX + 1) + size_t(WY_NB) * (CMP_MAX + 1) +
+                                                  WY_NB * BT_COLS + WY_NB * (WY_NB + 1));
+            HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_bt),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(most)));
+            attr = true;
+        }
+        hipLaunchKernelGGL(k_comp_bt, dim3((max_m + BT_COLS - 1) / BT_COLS, ntasks), dim3(NT), bytes, s, d_tasks,
+                           variant);
+        check_launch("k_comp_bt");
     }
 }
 

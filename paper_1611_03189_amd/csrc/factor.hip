@@ -320,7 +320,7 @@ void factor(Plan& P, const double* d_values_in) {
                 double* Asw = P.spool.alloc_n<double>(size_t(m) * wt);
                 double* G = P.spool.alloc_n<double>(size_t(m) * m);
                 double* U = P.spool.alloc_n<double>(size_t(m) * m);
-                double* work = P.spool.alloc_n<double>(size_t(m) * m + 32 * size_t(m) + 64);
+                double* work = P.spool.alloc_n<double>(cmp_work_doubles(m));
                 double* Z = nullptr;
                 int off = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) {

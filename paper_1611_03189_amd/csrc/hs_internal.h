@@ -302,6 +302,11 @@ void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double fl
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
                      int* d_rank, double flops, bool lds, int max_m, hipStream_t s);
 constexpr int LDS_MAX_M = 128;   // compression blocks up to this size work in LDS
+constexpr int CMP_WY_NB = 16;     // reflectors per block in the compression back-transformation
+// doubles of the per-node compression work buffer for a super node of m unknowns
+inline size_t cmp_work_doubles(int m) {
+    return size_t(m) * m + 32 * size_t(m) + 64 + size_t(CMP_WY_NB) * CMP_WY_NB * ((m + CMP_WY_NB - 1) / CMP_WY_NB);
+}
 constexpr int PIV_LDS_MAX_M = 64; // pivot blocks up to this size are factored in LDS; larger
                                   // ones by the blocked kernel (panels of 32 columns)
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
