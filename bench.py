@@ -127,6 +127,17 @@ def main() -> int:
     prof = S.profile_end()
     ms_per_step = elapsed / args.steps * 1e3
 
+    # the same workload with 32 right-hand sides in one batched solve (reported beside)
+    B32 = torch.from_numpy(np.ascontiguousarray(pb.rhs(p.n, 32, 2103))).cuda()
+    S.factor(vals)
+    S.solve(B32)
+    torch.cuda.synchronize()
+    t32 = time.perf_counter()
+    S.factor(vals)
+    X32, st32 = S.solve(B32)
+    torch.cuda.synchronize()
+    ms32 = (time.perf_counter() - t32) * 1e3
+
     xs = x.cpu().numpy()
     A = p.to_scipy()
     true_rel = float(np.linalg.norm(b_host - A @ xs) / np.linalg.norm(b_host))
@@ -168,6 +179,8 @@ def main() -> int:
         "factor_bytes": stats["factor_bytes"],
         "apply_bytes": stats["apply_bytes"],
         "max_rank": stats["max_rank"],
+        "nrhs32": {"ms": round(ms32, 3), "ms_per_rhs": round(ms32 / 32, 3),
+                   "pcg_iterations_max": st32["iterations"], "converged": st32["converged"]},
         "roofline": roofline,
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
                     for e in sorted(prof, key=lambda e: -e["ms"])],

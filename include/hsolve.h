@@ -119,9 +119,12 @@ hsolve_status hsolve_factor(hsolve_plan plan, const double* values);
 hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
                            int ldz);
 
-/* Solve A x = b by PCG preconditioned with A_H^{-1} (x0 = 0), per column, to the
- * relative residual opt.tol. b, x: device, n x nrhs column-major. stats may be NULL.
- * HSOLVE_NOT_CONVERGED if max_iter is reached first (x = last iterate). */
+/* Solve A x = b by PCG preconditioned with A_H^{-1} (x0 = 0) to the relative residual
+ * opt.tol. b, x: device, n x nrhs column-major. The columns advance together (one batched
+ * SpMV and apply per iteration), each with its own scalars, and a column stops changing
+ * once it has converged, so every column equals its own single-column solve. stats may be
+ * NULL; stats.iterations is the largest count over the columns. HSOLVE_NOT_CONVERGED if
+ * max_iter is reached first (x = last iterate). */
 hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb, double* x,
                            int ldx, hsolve_stats* stats);
 

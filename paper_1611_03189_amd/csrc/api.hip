@@ -154,18 +154,18 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
     bool converged = true;
     auto t0 = std::chrono::steady_clock::now();
     hsolve_status st = run(plan, "solve", [&] {
-        int its = 0;
+        std::vector<int> its(nrhs);
+        std::vector<double> rel(nrhs);
+        hs::pcg(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, its.data(), rel.data());
+        HS_HIP(hipStreamSynchronize(P.stream));
+        int most = 0;
         double worst = 0.0;
         for (int c = 0; c < nrhs; ++c) {
-            double rel = 0.0;
-            int it = hs::pcg(P, b + size_t(c) * ldb, x + size_t(c) * ldx, P.opt.tol,
-                             P.opt.max_iter, &rel);
-            if (!(rel <= P.opt.tol)) converged = false;
-            its = std::max(its, it);
-            worst = std::max(worst, rel);
+            if (!(rel[c] <= P.opt.tol)) converged = false;
+            most = std::max(most, its[c]);
+            worst = std::max(worst, rel[c]);
         }
-        HS_HIP(hipStreamSynchronize(P.stream));
-        P.stats.iterations = its;
+        P.stats.iterations = most;
         P.stats.rel_residual = worst;
     });
     P.stats.t_solve = seconds_since(t0);

@@ -272,8 +272,11 @@ struct Plan {
     int V_cols = 0;
     double* d_scalars = nullptr;                    // dot-product results
     double* h_scalars = nullptr;                    // pinned
-    double* d_krylov = nullptr;                     // PCG vectors
+    double* d_krylov = nullptr;                     // PCG vectors (R, Z, P, Q, X blocks)
+    double* d_kscal = nullptr;                      // PCG scalars per column + dot partials
+    int* d_kflag = nullptr;                         // PCG: column still iterating
     int krylov_cols = 0;
+    int h_scalar_cols = 0;
 
     hsolve_stats stats{};
     Profiler prof;
@@ -290,7 +293,8 @@ void factor(Plan& P, const double* d_values);
 // solve.hip
 void build_apply_schedule(Plan& P);
 void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
-int pcg(Plan& P, const double* b, double* x, double tol, int max_iter, double* rel_out);
+void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+         int* its, double* rel);
 void spmv(Plan& P, const double* x, double* y);
 
 // kernels.hip: launch wrappers (all asynchronous on stream s)
@@ -324,11 +328,19 @@ void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
                          const int32_t* perm, int n, int nrhs, hipStream_t s); // dst[perm[p]] = src[p]
 void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y, int n, int64_t nnz, hipStream_t s);
-void launch_dot2(const double* a, const double* b, const double* c, const double* d, int n,
-                 double* out, hipStream_t s);   // out[0] = a.b, out[1] = c.d
-void launch_axpy2(double* x, const double* p, double* r, const double* q, const double* alpha,
-                  int n, hipStream_t s);        // x += a p, r -= a q (a = alpha[0]/alpha[1])
-void launch_xpby(double* p, const double* z, const double* beta, int n, hipStream_t s);
+constexpr int DOTM_BLOCKS = 512;   // partial sums per column of a batched dot product
+void launch_spmv_multi(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
+                       const double* X, int64_t ldx, double* Y, int64_t ldy, int n, int nrhs,
+                       int64_t nnz, hipStream_t s);
+void launch_dots(const double* A, const double* B, int64_t ld, int n, int nrhs, double* part, double* out,
+                 hipStream_t s);    // out[c] = A(:, c) . B(:, c); part: DOTM_BLOCKS * nrhs scratch
+void launch_axpy2_multi(double* X, const double* P, double* R, const double* Q, int64_t ld, int n, int nrhs,
+                        const double* num, const double* den, const int* active, hipStream_t s);
+void launch_xpby_multi(double* P, const double* Z, int64_t ld, int n, int nrhs, const double* num,
+                       const double* den, const int* active, hipStream_t s);
+void launch_pcg_flags(const double* rr, const double* nb, double tol, int* active, double* dst,
+                      const double* src, int nrhs, hipStream_t s);
+void launch_copy_scalars(double* dst, const double* src, int n, hipStream_t s);
 void launch_fill(double* p, double v, int64_t n, hipStream_t s);
 
 }  // namespace hs

@@ -4,7 +4,7 @@
 //  k_gemm        grouped GEMM over tile lists, C = bC + a sum op(A)op(B) Gram, Schur, T_N, L_nr, R
 //  (pivot.hip: k_chol_inv*; compress.hip: k_comp_*)
 //  k_fwd / k_bwd level sweeps of the solve phase                        apply
-//  k_spmv, k_dot*, k_axpy2, k_xpby, gathers/scatters                    outer PCG
+//  k_spmv, gathers/scatters (batched PCG kernels: krylov.hip)             outer PCG
 #include <cfloat>
 
 #include "hs_device.h"
@@ -250,13 +250,74 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
     }
 }
 
+// Several right-hand sides (APPLY_RC per workgroup, blockIdx.z): every factor entry is loaded
+// once for all of them; each column is accumulated in exactly the order of k_fwd, so a
+// column's result does not depend on the others.
+constexpr int APPLY_RC = 8;
+
+__global__ __launch_bounds__(NT) void k_fwd_m(const FwdTarget* targets, const FwdContrib* contrib,
+                                              double* V, int64_t ldv, int nrhs) {
+    const FwdTarget t = targets[blockIdx.y];
+    const int r0 = blockIdx.x * FWD_ROWS, c0 = blockIdx.z * APPLY_RC;
+    if (r0 >= t.len) return;
+    const int nc = min(APPLY_RC, nrhs - c0);
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int i = r0 + lane;
+    __shared__ double part[APPLY_RC][NT / WAVE][WAVE];
+    double acc[APPLY_RC][4];
+#pragma unroll
+    for (int c = 0; c < APPLY_RC; ++c)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[c][u] = 0.0;
+    if (i < t.len) {
+        for (int q = t.c_begin; q < t.c_end; ++q) {
+            const FwdContrib f = contrib[q];
+            const double* x = V + size_t(c0) * ldv + f.src;
+            const HS_G double* g = gp(f.G) + i;
+            int j = wv;
+            for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int jj = j + u * (NT / WAVE);
+                    const double gv = g[size_t(jj) * f.ldG];
+#pragma unroll
+                    for (int c = 0; c < APPLY_RC; ++c)
+                        if (c < nc) acc[c][u] += gv * x[size_t(c) * ldv + jj];
+                }
+            }
+            for (; j < f.m; j += NT / WAVE) {
+                const double gv = g[size_t(j) * f.ldG];
+#pragma unroll
+                for (int c = 0; c < APPLY_RC; ++c)
+                    if (c < nc) acc[c][0] += gv * x[size_t(c) * ldv + j];
+            }
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < APPLY_RC; ++c) part[c][wv][lane] = (acc[c][0] + acc[c][1]) + (acc[c][2] + acc[c][3]);
+    __syncthreads();
+    if (wv == 0 && i < t.len) {
+        for (int c = 0; c < nc; ++c) {
+            double s = 0.0;
+            for (int w = 0; w < NT / WAVE; ++w) s += part[c][w][lane];
+            V[size_t(c0 + c) * ldv + t.dst + i] += t.sign * s;
+        }
+    }
+}
+
 void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, double* V, int64_t ldv,
                 int nrhs, double bytes, hipStream_t s) {
     if (nt <= 0 || max_len <= 0) return;
     ProfScope ps("k_fwd", bytes, s);
-    hipLaunchKernelGGL(k_fwd, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt), dim3(NT), 0, s, t, c, V,
-                       ldv, nrhs);
-    check_launch("k_fwd");
+    if (nrhs == 1) {
+        hipLaunchKernelGGL(k_fwd, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt), dim3(NT), 0, s, t, c, V,
+                           ldv, nrhs);
+        check_launch("k_fwd");
+    } else {
+        hipLaunchKernelGGL(k_fwd_m, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt, (nrhs + APPLY_RC - 1) / APPLY_RC),
+                           dim3(NT), 0, s, t, c, V, ldv, nrhs);
+        check_launch("k_fwd_m");
+    }
 }
 
 // Backward: x_s = Gm^T v with v = [phi_s; -x_N; x_r] gathered into LDS (phi from V, the
@@ -301,13 +362,94 @@ __global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* 
     }
 }
 
+// Several right-hand sides (APPLY_RC per workgroup, blockIdx.z): v is gathered BWD_CHUNK rows
+// at a time for all of them, each factor entry is loaded once; a column's sums follow the
+// order of k_bwd exactly (rows lane + 64 u + 512 t in a[u] while all eight exist, the
+// lane's remaining rows in a[0]).
+constexpr int BWD_CHUNK = 512;
+
+__global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg* segs, const double* V,
+                                              double* X, int64_t ldv, int nrhs) {
+    const BwdNode nd = nodes[blockIdx.y];
+    const int j0 = blockIdx.x * BWD_COLS, c0 = blockIdx.z * APPLY_RC;
+    if (j0 >= nd.m) return;
+    const int nc = min(APPLY_RC, nrhs - c0);
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    __shared__ double v[APPLY_RC][BWD_CHUNK];
+    constexpr int JW = BWD_COLS / (NT / WAVE);           // output columns per wave
+    double a[JW][APPLY_RC][8];
+#pragma unroll
+    for (int q = 0; q < JW; ++q)
+#pragma unroll
+        for (int c = 0; c < APPLY_RC; ++c)
+#pragma unroll
+            for (int u = 0; u < 8; ++u) a[q][c][u] = 0.0;
+    for (int r0 = 0; r0 < nd.rows; r0 += BWD_CHUNK) {
+        const int r1 = min(nd.rows, r0 + BWD_CHUNK);
+        __syncthreads();
+        int pos = 0;
+        for (int q = nd.seg_begin; q < nd.seg_end; ++q) {
+            const BwdSeg sg = segs[q];
+            const int lo = max(pos, r0), hi = min(pos + sg.len, r1);
+            for (int e = threadIdx.x; e < APPLY_RC * (hi - lo); e += NT) {
+                const int c = e / (hi - lo), r = lo + e % (hi - lo);
+                if (c < nc) {
+                    const double* src = (sg.buf ? X : V) + size_t(c0 + c) * ldv + sg.off;
+                    v[c][r - r0] = sg.sign * src[r - pos];
+                }
+            }
+            pos += sg.len;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < JW; ++q) {
+            const int j = j0 + wv + q * (NT / WAVE);
+            if (j >= nd.m) break;
+            const HS_G double* g = gp(nd.G) + size_t(j) * nd.ldG;
+            if (r0 + lane + 7 * WAVE < nd.rows) {           // this lane's rows of the block all exist
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = r0 + lane + u * WAVE;
+                    const double gv = g[i];
+#pragma unroll
+                    for (int c = 0; c < APPLY_RC; ++c)
+                        if (c < nc) a[q][c][u] += gv * v[c][i - r0];
+                }
+            } else {                                        // the rest, in a[0] (as k_bwd)
+                for (int i = r0 + lane; i < r1; i += WAVE) {
+                    const double gv = g[i];
+#pragma unroll
+                    for (int c = 0; c < APPLY_RC; ++c)
+                        if (c < nc) a[q][c][0] += gv * v[c][i - r0];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < JW; ++q) {
+        const int j = j0 + wv + q * (NT / WAVE);
+#pragma unroll
+        for (int c = 0; c < APPLY_RC; ++c) {
+            const double acc = wave_sum(((a[q][c][0] + a[q][c][1]) + (a[q][c][2] + a[q][c][3])) +
+                                        ((a[q][c][4] + a[q][c][5]) + (a[q][c][6] + a[q][c][7])));
+            if (lane == 0 && j < nd.m && c < nc) X[size_t(c0 + c) * ldv + nd.dst + j] = acc;
+        }
+    }
+}
+
 void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const double* V, double* X,
                 int64_t ldv, int nrhs, double bytes, hipStream_t s) {
     if (nn <= 0 || max_m <= 0) return;
     ProfScope ps("k_bwd", bytes, s);
-    hipLaunchKernelGGL(k_bwd, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn), dim3(NT), 0, s, nodes, segs,
-                       V, X, ldv, nrhs);
-    check_launch("k_bwd");
+    if (nrhs == 1) {
+        hipLaunchKernelGGL(k_bwd, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn), dim3(NT), 0, s, nodes, segs,
+                           V, X, ldv, nrhs);
+        check_launch("k_bwd");
+    } else {
+        hipLaunchKernelGGL(k_bwd_m, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn, (nrhs + APPLY_RC - 1) / APPLY_RC),
+                           dim3(NT), 0, s, nodes, segs, V, X, ldv, nrhs);
+        check_launch("k_bwd_m");
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -359,77 +501,6 @@ void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* v
     hipLaunchKernelGGL(k_spmv, dim3((n + NT - 1) / NT), dim3(NT), 0, s, row_ptr, col_idx, vals,
                        x, y, n);
     check_launch("k_spmv");
-}
-
-constexpr int DOT_BLOCKS = 512;
-
-__global__ __launch_bounds__(NT) void k_dot2_part(const double* a, const double* b,
-                                                  const double* c, const double* d, int n,
-                                                  double* part) {
-    __shared__ double red[NT / WAVE];
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = blockIdx.x * NT + threadIdx.x; i < n; i += gridDim.x * NT) {
-        s0 += a[i] * b[i];
-        if (c) s1 += c[i] * d[i];
-    }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
-    if (threadIdx.x == 0) {
-        part[2 * blockIdx.x] = s0;
-        part[2 * blockIdx.x + 1] = s1;
-    }
-}
-
-__global__ __launch_bounds__(NT) void k_dot2_final(const double* part, int nb, double* out) {
-    __shared__ double red[NT / WAVE];
-    double s0 = 0.0, s1 = 0.0;
-    for (int i = threadIdx.x; i < nb; i += NT) {
-        s0 += part[2 * i];
-        s1 += part[2 * i + 1];
-    }
-    s0 = block_sum(s0, red);
-    s1 = block_sum(s1, red);
-    if (threadIdx.x == 0) {
-        out[0] = s0;
-        out[1] = s1;
-    }
-}
-
-void launch_dot2(const double* a, const double* b, const double* c, const double* d, int n,
-                 double* out, hipStream_t s) {
-    // out[2 .. 2 + 2*DOT_BLOCKS) is used as partial-sum scratch
-    int nb = (n + NT - 1) / NT;
-    nb = nb < 1 ? 1 : (nb > DOT_BLOCKS ? DOT_BLOCKS : nb);
-    hipLaunchKernelGGL(k_dot2_part, dim3(nb), dim3(NT), 0, s, a, b, c, d, n, out + 2);
-    check_launch("k_dot2_part");
-    hipLaunchKernelGGL(k_dot2_final, dim3(1), dim3(NT), 0, s, out + 2, nb, out);
-    check_launch("k_dot2_final");
-}
-
-__global__ void k_axpy2(double* x, const double* p, double* r, const double* q,
-                        const double* ratio, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double a = ratio[0] / ratio[1];
-    x[i] += a * p[i];
-    r[i] -= a * q[i];
-}
-
-void launch_axpy2(double* x, const double* p, double* r, const double* q, const double* alpha,
-                  int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_axpy2, dim3((n + NT - 1) / NT), dim3(NT), 0, s, x, p, r, q, alpha, n);
-    check_launch("k_axpy2");
-}
-
-__global__ void k_xpby(double* p, const double* z, const double* ratio, int n) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    p[i] = z[i] + (ratio[0] / ratio[1]) * p[i];
-}
-
-void launch_xpby(double* p, const double* z, const double* beta, int n, hipStream_t s) {
-    hipLaunchKernelGGL(k_xpby, dim3((n + NT - 1) / NT), dim3(NT), 0, s, p, z, beta, n);
-    check_launch("k_xpby");
 }
 
 __global__ void k_fill(double* p, double v, int64_t n) {

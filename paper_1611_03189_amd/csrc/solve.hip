@@ -156,65 +156,97 @@ void spmv(Plan& P, const double* x, double* y) {
     launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, x, y, P.n, P.nnz, P.stream);
 }
 
-// PCG (Hestenes-Stiefel) with x0 = 0 for one column. Returns the iteration count and the
-// relative residual ||r_k|| / ||b|| of the recursion at exit in *rel_out; the loop stops
-// when that value is <= tol.
-int pcg(Plan& P, const double* b, double* x, double tol, int max_iter, double* rel_out) {
+// PCG (Hestenes-Stiefel) with x0 = 0 on nrhs columns at once, each with its own scalars: a
+// column stops changing once ||r_k|| <= tol ||b|| (by the recursion). One SpMV, one apply and
+// one scalar read-back per iteration for the whole block. its[c] and rel[c] receive the
+// iteration count and the final recursive relative residual of column c.
+void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+         int* its, double* rel) {
     hipStream_t st = P.stream;
     const int n = P.n;
-    if (!P.d_krylov || P.krylov_cols < 4) {
-        P.d_krylov = P.apool.alloc_n<double>(size_t(n) * 4);
-        P.krylov_cols = 4;
+    const int64_t ld = n;
+    if (!P.d_krylov || P.krylov_cols < nrhs) {
+        P.d_krylov = P.apool.alloc_n<double>(size_t(n) * 5 * nrhs);
+        P.d_kscal = P.apool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
+        P.d_kflag = P.apool.alloc_n<int>(size_t(nrhs));
+        P.krylov_cols = nrhs;
     }
-    if (!P.h_scalars)
-        HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_scalars), 64 * sizeof(double),
+    if (!P.h_scalars || P.h_scalar_cols < nrhs) {
+        if (P.h_scalars) HS_HIP(hipHostFree(P.h_scalars));
+        HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_scalars), sizeof(double) * 3 * size_t(nrhs) + 64,
                              hipHostMallocDefault));
-    double* r = P.d_krylov;
-    double* z = r + n;
-    double* pv = z + n;
-    double* q = pv + n;
-    double* sc = P.d_scalars;                    // [0..1] dot results, [2..] partial sums
-    double* keep = P.d_scalars + 2 + 2 * 512;    // [rz, pq, rz_new, rz_old]
-    double* h = P.h_scalars;
-    auto dcopy1 = [&](double* dst, const double* src) {
-        HS_HIP(hipMemcpyAsync(dst, src, sizeof(double), hipMemcpyDeviceToDevice, st));
+        P.h_scalar_cols = nrhs;
+    }
+    double* R = P.d_krylov;
+    double* Z = R + size_t(n) * nrhs;
+    double* Pv = Z + size_t(n) * nrhs;
+    double* Q = Pv + size_t(n) * nrhs;
+    double* X = Q + size_t(n) * nrhs;
+    double* bb = P.d_kscal;                     // ||b||^2, then ||b||
+    double* rz = bb + nrhs;
+    double* pq = rz + nrhs;
+    double* rr = pq + nrhs;
+    double* rzn = rr + nrhs;
+    double* part = rzn + 2 * nrhs;              // DOTM_BLOCKS partial sums per column
+    int* active = P.d_kflag;
+    double* h = P.h_scalars;                    // host: ||b||, rr, active (as doubles)
+    int* hact = reinterpret_cast<int*>(h + 2 * size_t(nrhs));
+    HS_HIP(hipMemcpy2DAsync(R, sizeof(double) * ld, b, sizeof(double) * size_t(ldb), sizeof(double) * n, nrhs,
+                            hipMemcpyDeviceToDevice, st));
+    launch_fill(X, 0.0, int64_t(n) * nrhs, st);
+    auto copy_out = [&] {
+        HS_HIP(hipMemcpy2DAsync(x, sizeof(double) * size_t(ldx), X, sizeof(double) * ld, sizeof(double) * n, nrhs,
+                                hipMemcpyDeviceToDevice, st));
     };
-    HS_HIP(hipMemcpyAsync(r, b, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    launch_fill(x, 0.0, n, st);
-    launch_dot2(b, b, nullptr, nullptr, n, sc, st);
-    HS_HIP(hipMemcpyAsync(h, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+    launch_dots(R, R, ld, n, nrhs, part, bb, st);
+    HS_HIP(hipMemcpyAsync(h, bb, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     HS_HIP(hipStreamSynchronize(st));
-    const double nb = std::sqrt(h[0]);
-    if (nb == 0.0) {
-        *rel_out = 0.0;
-        return 0;
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) {
+        h[c] = std::sqrt(h[c]);
+        hact[c] = h[c] > 0.0 ? 1 : 0;
+        any = any || hact[c];
+        its[c] = 0;
+        rel[c] = 0.0;
     }
-    apply(P, 1, r, n, z, n);
-    HS_HIP(hipMemcpyAsync(pv, z, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-    launch_dot2(r, z, nullptr, nullptr, n, sc, st);
-    dcopy1(keep, sc);                                       // rz
+    HS_HIP(hipMemcpyAsync(bb, h, sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+    HS_HIP(hipMemcpyAsync(active, hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    HS_HIP(hipStreamSynchronize(st));            // the host buffer is reused below
+    if (!any) {
+        copy_out();
+        return;
+    }
+    std::vector<double> nbh(h, h + nrhs);
+    std::vector<int> live(hact, hact + nrhs);
+    apply(P, nrhs, R, n, Z, n);
+    HS_HIP(hipMemcpyAsync(Pv, Z, sizeof(double) * size_t(n) * nrhs, hipMemcpyDeviceToDevice, st));
+    launch_dots(R, Z, ld, n, nrhs, part, rz, st);
     int it = 0;
-    double rel = 1.0;
     while (it < max_iter) {
-        spmv(P, pv, q);
-        launch_dot2(pv, q, nullptr, nullptr, n, sc, st);
-        dcopy1(keep + 1, sc);                               // pq
-        launch_axpy2(x, pv, r, q, keep, n, st);             // alpha = rz / pq
+        launch_spmv_multi(P.d_row_ptr, P.d_col_idx, P.d_values, Pv, ld, Q, ld, n, nrhs, P.nnz, st);
+        launch_dots(Pv, Q, ld, n, nrhs, part, pq, st);
+        launch_axpy2_multi(X, Pv, R, Q, ld, n, nrhs, rz, pq, active, st);
         ++it;
-        launch_dot2(r, r, nullptr, nullptr, n, sc, st);
-        HS_HIP(hipMemcpyAsync(h, sc, sizeof(double), hipMemcpyDeviceToHost, st));
+        launch_dots(R, R, ld, n, nrhs, part, rr, st);
+        launch_pcg_flags(rr, bb, tol, active, nullptr, nullptr, nrhs, st);
+        HS_HIP(hipMemcpyAsync(h + nrhs, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+        HS_HIP(hipMemcpyAsync(hact, active, sizeof(int) * nrhs, hipMemcpyDeviceToHost, st));
         HS_HIP(hipStreamSynchronize(st));
-        rel = std::sqrt(h[0]) / nb;
-        if (!(rel > tol)) break;
-        apply(P, 1, r, n, z, n);
-        launch_dot2(r, z, nullptr, nullptr, n, sc, st);
-        dcopy1(keep + 2, sc);                               // rz_new
-        dcopy1(keep + 3, keep);                             // rz
-        launch_xpby(pv, z, keep + 2, n, st);                // p = z + (rz_new / rz) p
-        dcopy1(keep, keep + 2);
+        any = false;
+        for (int c = 0; c < nrhs; ++c) {
+            if (!live[c]) continue;
+            its[c] = it;
+            rel[c] = std::sqrt(h[nrhs + c]) / nbh[c];
+            if (!hact[c]) live[c] = 0;
+            any = any || live[c];
+        }
+        if (!any) break;
+        apply(P, nrhs, R, n, Z, n);
+        launch_dots(R, Z, ld, n, nrhs, part, rzn, st);
+        launch_xpby_multi(Pv, Z, ld, n, nrhs, rzn, rz, active, st);
+        launch_copy_scalars(rz, rzn, nrhs, st);
     }
-    *rel_out = rel;
-    return it;
+    copy_out();
 }
 
 }  // namespace hs

@@ -124,6 +124,30 @@ def test_multiple_rhs_equal_single():
     S.close()
 
 
+def test_batched_pcg_equals_single_columns():
+    # all columns advance together with their own scalars; each must equal its own solve
+    say("batched_pcg")
+    p = pb.lognormal(40, 2, 1.0, 5)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, eps=1e-2, tol=1e-10)
+    S.factor(torch.from_numpy(p.values).cuda())
+    B = pb.rhs(p.n, 5, 11)
+    B[:, 3] = 0.0
+    X, st = S.solve(torch.from_numpy(np.ascontiguousarray(B)).cuda())
+    X = X.cpu().numpy()
+    A = p.to_scipy()
+    most = 0
+    for j in range(5):
+        xj, stj = S.solve(torch.from_numpy(B[:, j].copy()).cuda())
+        assert np.array_equal(xj.cpu().numpy(), X[:, j])
+        most = max(most, stj["iterations"])
+        if j == 3:
+            assert np.all(X[:, 3] == 0.0) and stj["iterations"] == 0
+        else:
+            assert np.linalg.norm(B[:, j] - A @ X[:, j]) <= 2e-10 * np.linalg.norm(B[:, j])
+    assert st["iterations"] == most and st["converged"]
+    S.close()
+
+
 def test_refactor_and_run_twice_bitwise():
     say("determinism")
     p = pb.lognormal(32, 2, 1.0, 77)
