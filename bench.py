@@ -78,12 +78,38 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     }
 
 
+def serving(count: int, slots: int) -> dict:
+    """The serving stream (mixed 2-D / 3-D lognormal systems, 1..8 right-hand sides each):
+    first closed loop (every request waiting at t = 0, saturation), then open loop with
+    Poisson arrivals at 0.7 x the closed-loop request rate. Latency runs from arrival to the
+    last right-hand side solved; the systems are generated before the timed runs."""
+    from paper_1611_03189_amd import problems as pb
+    from paper_1611_03189_amd.serve import RequestLoop, requests_from_stream
+    specs = pb.serving_stream(count, seed=4)
+    reqs = requests_from_stream(specs)
+    loop = RequestLoop(slots=slots)
+    loop.run(reqs[:min(4, len(reqs))], realtime=False)          # warm-up
+    closed = loop.run(reqs, realtime=False).stats()
+    rate = 0.7 * closed["requests_per_s"]
+    arrivals = pb.serving_stream(count, seed=4, rate=rate)
+    for r, sp in zip(reqs, arrivals):
+        r.arrival = sp["arrival"]
+    opened = loop.run(reqs, realtime=True).stats()
+    opened["arrival_rate_per_s"] = round(rate, 3)
+    return {"workload": f"{count} systems: 2-D N~U{{64..256}} / 3-D N~U{{16..48}}, lognormal sigma 1, "
+                        f"1-8 rhs, GC eps 1e-2, PCG 1e-10", "slots": slots,
+            "closed_loop": closed, "open_loop": opened}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=64,
+                    help="requests of the serving stream (0: skip the serving measurement)")
+    ap.add_argument("--serve-slots", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -185,6 +211,8 @@ def main() -> int:
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
                     for e in sorted(prof, key=lambda e: -e["ms"])],
     }
+    if args.serve_requests > 0:
+        out["serving"] = serving(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
     S.close()

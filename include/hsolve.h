@@ -87,6 +87,8 @@ typedef struct {
     double apply_bytes;         /* algorithmic bytes read+written by one apply (1 rhs) */
     int fail_level;             /* for HSOLVE_ERR_NOT_SPD: depth and node of the failure */
     int fail_node;
+    int64_t device_bytes;       /* device memory held by the plan now (pattern, values, factors,
+                                   work pools); released by hsolve_destroy */
 } hsolve_stats;
 
 /* Fill *opt with the defaults listed above. */

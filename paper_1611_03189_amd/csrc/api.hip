@@ -169,6 +169,7 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
         P.stats.rel_residual = worst;
     });
     P.stats.t_solve = seconds_since(t0);
+    P.stats.device_bytes = int64_t(P.device_bytes());
     if (stats) *stats = P.stats;
     if (st != HSOLVE_OK) return st;
     return converged ? HSOLVE_OK : HSOLVE_NOT_CONVERGED;
@@ -185,7 +186,9 @@ hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y) {
 
 hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats) {
     if (!plan || !stats) return HSOLVE_ERR_INVALID;
-    *stats = plan->P.stats;
+    hs::Plan& P = plan->P;
+    P.stats.device_bytes = int64_t(P.device_bytes());
+    *stats = P.stats;
     return HSOLVE_OK;
 }
 

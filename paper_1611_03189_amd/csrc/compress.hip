@@ -1297,25 +1297,17 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
         ProfScope ps(lds ? "k_comp_reduce<true, 128>" : "k_comp_reduce<false, 512>", flops, s);
         if (lds) {
             if (max_m > CMP_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS compression too large"};
-            static bool attr = false;
-            if (!attr) {
-                HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_reduce<true, CMP_LDS_MAX>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           int(size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) * sizeof(double))));
-                attr = true;
-            }
+            static std::once_flag once;
+            set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<true, CMP_LDS_MAX>),
+                          size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) * sizeof(double));
             const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(double);
             hipLaunchKernelGGL((k_comp_reduce<true, CMP_LDS_MAX>), dim3(ntasks), dim3(NT), bytes, s,
                                d_tasks, variant, eps, d_rank);
             check_launch("k_comp_reduce<lds>");
         } else {
             const size_t bytes = size_t(2 * TRI_NB + 4) * CMP_MAX * sizeof(double);
-            static bool attr = false;
-            if (!attr) {
-                HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>),
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
-                attr = true;
-            }
+            static std::once_flag once;
+            set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>), bytes);
             hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(NT), bytes, s, d_tasks,
                                variant, eps, d_rank);
             check_launch("k_comp_reduce<global>");
@@ -1359,14 +1351,10 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
         ProfScope ps("k_comp_bt", 0.0, s);
         const size_t bytes = sizeof(double) * (size_t(BT_COLS) * (max_m + 1) + size_t(WY_NB) * (max_m + 1) +
                                                WY_NB * BT_COLS + WY_NB * (WY_NB + 1));
-        static bool attr = false;
-        if (!attr) {
-            const size_t most = sizeof(double) * (size_t(BT_COLS) * (CMP_MAX + 1) + size_t(WY_NB) * (CMP_MAX + 1) +
-                                                  WY_NB * BT_COLS + WY_NB * (WY_NB + 1));
-            HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_comp_bt),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(most)));
-            attr = true;
-        }
+        static std::once_flag once;
+        set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_bt),
+                      sizeof(double) * (size_t(BT_COLS) * (CMP_MAX + 1) + size_t(WY_NB) * (CMP_MAX + 1) +
+                                        WY_NB * BT_COLS + WY_NB * (WY_NB + 1)));
         hipLaunchKernelGGL(k_comp_bt, dim3((max_m + BT_COLS - 1) / BT_COLS, ntasks), dim3(NT), bytes, s, d_tasks,
                            variant);
         check_launch("k_comp_bt");

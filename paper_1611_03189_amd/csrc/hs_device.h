@@ -1,6 +1,8 @@
 // Device-side helpers shared by the HIP translation units (wave64, 256-thread blocks).
 #pragma once
 
+#include <mutex>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -15,6 +17,13 @@ constexpr int WAVE = 64;
 #define HS_G __attribute__((address_space(1)))
 template <class T> __device__ inline HS_G T* gp(T* p) { return (HS_G T*)p; }
 template <class T> __device__ inline const HS_G T* gp(const T* p) { return (const HS_G T*)p; }
+
+// Raise the dynamic LDS limit of a kernel once per process (safe from several host threads)
+inline void set_lds_limit(std::once_flag& flag, const void* kernel, size_t bytes) {
+    std::call_once(flag, [&] {
+        HS_HIP(hipFuncSetAttribute(kernel, hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
+    });
+}
 
 inline void check_launch(const char* name) {
     const hipError_t e = hipGetLastError();

@@ -46,6 +46,7 @@ public:
     void release();    // free every chunk
     size_t high_water() const { return high_; }
     size_t in_use() const;
+    size_t reserved() const;   // device bytes held by the chunks
 
 private:
     struct Chunk { char* p; size_t size; };
@@ -278,6 +279,14 @@ struct Plan {
     int krylov_cols = 0;
     int h_scalar_cols = 0;
 
+    // device memory held by the plan (pattern arrays, values, pools)
+    size_t device_bytes() const {
+        size_t s = fpool.reserved() + lpool[0].reserved() + lpool[1].reserved() + spool.reserved() +
+                   apool.reserved();
+        if (d_row_ptr) s += sizeof(int64_t) * (size_t(n) + 1) + (sizeof(int32_t) + sizeof(double)) * size_t(nnz) +
+                            sizeof(int32_t) * 3 * size_t(n);
+        return s;
+    }
     hsolve_stats stats{};
     Profiler prof;
     std::vector<ProfTotal> prof_totals;

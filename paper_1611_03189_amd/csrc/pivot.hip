@@ -412,23 +412,15 @@ void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double fl
     if (lds) {
         if (max_m > PIV_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS pivot too large"};
         const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(double);
-        static bool attr = false;
-        if (!attr) {
-            HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_inv),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       int(size_t(PIV_LDS_MAX) * (PIV_LDS_MAX + 1) * sizeof(double))));
-            attr = true;
-        }
+        static std::once_flag once;
+        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv),
+                      size_t(PIV_LDS_MAX) * (PIV_LDS_MAX + 1) * sizeof(double));
         hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
         check_launch("k_chol_inv");
     } else {
         const size_t bytes = size_t(PIV_PANEL) * sizeof(double);
-        static bool attr = false;
-        if (!attr) {
-            HS_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(&k_chol_inv_blk),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, int(bytes)));
-            attr = true;
-        }
+        static std::once_flag once;
+        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv_blk), bytes);
         hipLaunchKernelGGL(k_chol_inv_blk, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
         check_launch("k_chol_inv_blk");
     }

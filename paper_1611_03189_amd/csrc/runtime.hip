@@ -36,6 +36,12 @@ void* Pool::alloc(size_t bytes) {
 
 size_t Pool::in_use() const { return used_before_ + off_; }
 
+size_t Pool::reserved() const {
+    size_t s = 0;
+    for (const auto& c : chunks_) s += c.size;
+    return s;
+}
+
 void Pool::reset() {
     cur_ = 0;
     off_ = 0;

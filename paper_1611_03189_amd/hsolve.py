@@ -52,6 +52,7 @@ class Stats(ctypes.Structure):
         ("t_factor", c_double), ("t_solve", c_double), ("levels", c_int), ("colours", c_int),
         ("max_rank", c_int), ("factor_bytes", c_int64), ("factor_flops", c_double),
         ("apply_bytes", c_double), ("fail_level", c_int), ("fail_node", c_int),
+        ("device_bytes", c_int64),
     ]
 
     def as_dict(self) -> dict:

@@ -198,3 +198,35 @@ def workload(name: str) -> tuple[Problem, dict]:
         p = lognormal(w["N"], w["dim"], w["sigma"], 1000 + w["seed"],
                       axis_scale=w.get("axis_scale", (1.0, 1.0, 1.0)))
     return p, w
+
+
+# ---------------------------------------------------------------------------------------
+# Serving stream: a sequence of independent SPD systems of mixed sizes
+# ---------------------------------------------------------------------------------------
+def serving_stream(count: int, seed: int = 4, rate: float | None = None) -> list[dict]:
+    """Request specifications for a stream of `count` systems (generated lazily by
+    `serving_problem`): half 2-D 5-point on N^2 with N ~ U{64..256}, half 3-D 7-point on N^3
+    with N ~ U{16..48}, lognormal cell coefficients (sigma = 1), leaf 16 (2-D) / 64 (3-D),
+    eps 1e-2, 1..8 right-hand sides. Arrival times follow a Poisson process of `rate`
+    requests per second (all at t = 0 when rate is None). Seeds come from one SeedSequence."""
+    ss = np.random.SeedSequence(seed)
+    kids = ss.spawn(count + 1)
+    top = np.random.default_rng(kids[0])
+    t = 0.0
+    out = []
+    for i in range(count):
+        if rate is not None and i > 0:
+            t += top.exponential(1.0 / rate)
+        dim = 2 if top.random() < 0.5 else 3
+        N = int(top.integers(64, 257)) if dim == 2 else int(top.integers(16, 49))
+        out.append(dict(rid=i, dim=dim, N=N, sigma=1.0, leaf=16 if dim == 2 else 64, eps=1e-2,
+                        nrhs=int(top.integers(1, 9)), seed=int(kids[i + 1].generate_state(1)[0]),
+                        arrival=t))
+    return out
+
+
+def serving_problem(spec: dict) -> tuple[Problem, np.ndarray]:
+    """Matrix and right-hand sides (n x nrhs, Fortran order, U(-1, 1)) of one request."""
+    p = lognormal(spec["N"], spec["dim"], spec["sigma"], spec["seed"] % (2 ** 31))
+    b = rhs(p.n, spec["nrhs"], (spec["seed"] + 1) % (2 ** 31))
+    return p, b

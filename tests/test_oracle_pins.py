@@ -458,3 +458,20 @@ def test_convergence_trend_gc_flat_lorasp_grows():
     assert (lo[-1] - lo[0]) >= 2 * (gc[-1] - gc[0]), its
     assert all(abs(a - b) <= 1 for a, b in zip(gc, eig)), its
     assert its["st_lo"][-1] > its["st_gc"][-1], its
+
+
+def test_serving_stream_is_seeded_and_mixed():
+    # the serving workload: deterministic, half 2-D / half 3-D in expectation, sizes and
+    # right-hand-side counts in their ranges, arrivals increasing
+    a = pb.serving_stream(200, seed=4, rate=10.0)
+    b = pb.serving_stream(200, seed=4, rate=10.0)
+    assert a == b
+    dims = [s["dim"] for s in a]
+    assert 60 <= dims.count(2) <= 140
+    for s in a:
+        assert (64 <= s["N"] <= 256) if s["dim"] == 2 else (16 <= s["N"] <= 48)
+        assert 1 <= s["nrhs"] <= 8
+    arr = [s["arrival"] for s in a]
+    assert arr[0] == 0.0 and all(x <= y for x, y in zip(arr, arr[1:]))
+    p, bb = pb.serving_problem(a[0])
+    assert bb.shape == (p.n, a[0]["nrhs"])
