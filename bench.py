@@ -43,6 +43,24 @@ KERNEL_BOUND = {        # kernel -> (bound, unit of its work counter)
 }
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "c3_poisson3d_64_fp64_hbm_traffic.txt")
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE runs, scaled by a copy of known size); None when the summary is missing or the
+    library sources have changed since the counters were taken."""
+    try:
+        d = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    from paper_1611_03189_amd.profile_summary import source_hashes
+    if d.get("sources") != source_hashes():
+        return None
+    v = d.get("kernels", {}).get(kernel)
+    return None if v is None else round(float(v["hbm_bytes"]), 1)
+
+
 def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     """The FP64 oracle (factor + PCG) on 32^3 Poisson, leaf 64, eps 1e-2, one BLAS thread,
     scaled by 8 to the 64^3 size (the method's cost is linear in n, §3.2)."""
@@ -110,6 +128,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one elementwise copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -122,6 +142,13 @@ def main() -> int:
     from paper_1611_03189_amd import problems as pb
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        # reads 256 MiB and writes 256 MiB: the reference for the memory counters
+        xs_ = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        ys_ = torch.empty_like(xs_)
+        torch.mul(xs_, 1.0, out=ys_)
+        torch.cuda.synchronize()
+        del xs_, ys_
     p, w = pb.workload("c3_poisson3d_64")
     b_host = pb.rhs(p.n, 1, 2003)[:, 0]
     t0 = time.perf_counter()
@@ -178,7 +205,9 @@ def main() -> int:
     else:
         achieved, peak, u = per_launch_work / avg_s / 1e12, PEAK_FP64_TFLOPS, "TFLOP/s"
     roofline = {"bound": bound, "kernel": dom["name"], "achieved": round(achieved, 3),
-                "peak": peak, "unit": u, "frac": round(achieved / peak, 5), "traffic": None}
+                "peak": peak, "unit": u, "frac": round(achieved / peak, 5),
+                "traffic": measured_traffic(dom["name"]), "avg_launch_ms": round(avg_s * 1e3, 4),
+                "work_per_launch": round(per_launch_work, 1)}
 
     out = {
         "metric": METRIC,

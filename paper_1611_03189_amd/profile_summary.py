@@ -1,7 +1,10 @@
-"""Condense a rocprofv3 ``--stats`` kernel table (``*_kernel_stats.csv``) into the short text
-summary kept beside the measurements: one line per kernel with calls, total and mean time.
+"""Condense rocprofv3 output into the short text summaries kept beside the measurements.
 
     python -m paper_1611_03189_amd.profile_summary STATS_CSV "COMMAND" [TITLE] > summary.txt
+        one line per kernel with calls, total and mean time (``*_kernel_stats.csv``)
+    python -m paper_1611_03189_amd.profile_summary --pmc FETCH_CSV WRITE_CSV CALIB_KERNEL BYTES "COMMANDS"
+        per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE counter runs, scaled by
+        a copy of known size; prints JSON with the source hashes of the kernels
 """
 import csv
 import sys
@@ -24,5 +27,57 @@ def summarize(path: str, command: str, title: str = "") -> str:
     return "\n".join(out) + "\n"
 
 
+def pmc_summary(fetch_csv: str, write_csv: str, calib_kernel: str, calib_bytes: float) -> dict:
+    """Per-kernel mean FETCH_SIZE and WRITE_SIZE per dispatch (KiB, as the counters report
+    them) from two rocprofv3 --pmc runs, and HBM bytes per dispatch after scaling each
+    counter by what it reads for a plain copy of known size (calib_bytes read and written)."""
+    def per_kernel(path, counter):
+        acc = {}
+        for r in csv.DictReader(open(path)):
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            if "(" in name:
+                name = name[:name.index("(")]
+            name = name.replace("void ", "").replace("hs::", "")
+            v = acc.setdefault(name, [0.0, 0])
+            v[0] += float(r["Counter_Value"])
+            v[1] += 1
+        return {k: v[0] / v[1] for k, v in acc.items()}
+
+    f = per_kernel(fetch_csv, "FETCH_SIZE")
+    w = per_kernel(write_csv, "WRITE_SIZE")
+    cal = [k for k in f if calib_kernel in k]
+    if not cal:
+        raise SystemExit(f"calibration kernel '{calib_kernel}' not found")
+    # the copy runs once: its counters over its known traffic give the scale
+    f_scale = calib_bytes / (f[cal[0]] * 1024.0)
+    w_scale = calib_bytes / (w[cal[0]] * 1024.0)
+    out = {"calibration": {"kernel": cal[0], "bytes": calib_bytes, "fetch_kib": f[cal[0]],
+                           "write_kib": w[cal[0]], "fetch_scale": f_scale, "write_scale": w_scale},
+           "kernels": {}}
+    for k in sorted(set(f) | set(w)):
+        fb = f.get(k, 0.0) * 1024.0 * f_scale
+        wb = w.get(k, 0.0) * 1024.0 * w_scale
+        out["kernels"][k] = {"fetch_kib": f.get(k), "write_kib": w.get(k), "hbm_bytes": fb + wb}
+    return out
+
+
+def source_hashes() -> dict:
+    """sha256 of every HIP source of the library: counters are valid for this code only."""
+    import hashlib
+    import os
+    here = os.path.join(os.path.dirname(os.path.abspath(__file__)), "csrc")
+    return {f: hashlib.sha256(open(os.path.join(here, f), "rb").read()).hexdigest()[:16]
+            for f in sorted(os.listdir(here)) if f.endswith((".hip", ".h"))}
+
+
 if __name__ == "__main__":
-    print(summarize(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""), end="")
+    if sys.argv[1] == "--pmc":
+        import json
+        res = pmc_summary(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]))
+        res["command"] = sys.argv[6]
+        res["sources"] = source_hashes()
+        print(json.dumps(res, indent=1))
+    else:
+        print(summarize(sys.argv[1], sys.argv[2], sys.argv[3] if len(sys.argv) > 3 else ""), end="")
