@@ -53,7 +53,9 @@ typedef enum {
 } hsolve_status;
 
 enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
-enum { HSOLVE_PCG = 0 };
+/* outer iteration of hsolve_solve (§7): conjugate gradients with the standard or the
+   flexible beta, or right-preconditioned restarted GMRES */
+enum { HSOLVE_PCG = 0, HSOLVE_FPCG = 1, HSOLVE_GMRES = 2 };
 
 typedef struct {
     int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
@@ -69,8 +71,13 @@ typedef struct {
                                the unknown index as a 1-D coordinate */
     double tol;             /* hsolve_solve: stop at ||b - A x||_2 <= tol ||b||_2 (1e-10) */
     int max_iter;           /* hsolve_solve: iteration cap (1000) */
-    int krylov;             /* HSOLVE_PCG */
+    int krylov;             /* HSOLVE_PCG (default), HSOLVE_FPCG or HSOLVE_GMRES */
     void* stream;           /* hipStream_t or NULL */
+    int apply_prec;         /* 64 (default) or 32: precision of the solve phase. With 32 the
+                               factor is computed in FP64 and its solve-phase blocks are rounded
+                               once to FP32; the sweeps read and accumulate in FP32 (vectors
+                               enter and leave in FP64). Pair it with HSOLVE_FPCG or GMRES. */
+    int restart;            /* HSOLVE_GMRES: Krylov vectors per cycle (200) */
 } hsolve_options;
 
 typedef struct {
@@ -121,12 +128,17 @@ hsolve_status hsolve_factor(hsolve_plan plan, const double* values);
 hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
                            int ldz);
 
-/* Solve A x = b by PCG preconditioned with A_H^{-1} (x0 = 0) to the relative residual
- * opt.tol. b, x: device, n x nrhs column-major. The columns advance together (one batched
- * SpMV and apply per iteration), each with its own scalars, and a column stops changing
- * once it has converged, so every column equals its own single-column solve. stats may be
- * NULL; stats.iterations is the largest count over the columns. HSOLVE_NOT_CONVERGED if
- * max_iter is reached first (x = last iterate). */
+/* Solve A x = b preconditioned with A_H^{-1} (x0 = 0) to the relative residual opt.tol, with
+ * the outer iteration opt.krylov. b, x: device, n x nrhs column-major.
+ * PCG / FPCG: the columns advance together (one batched SpMV and apply per iteration), each
+ * with its own scalars, and a column stops changing once it has converged, so every column
+ * equals its own single-column solve. FPCG takes beta = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k.
+ * GMRES: right-preconditioned, restarted every opt.restart steps, modified Gram-Schmidt; the
+ * columns are solved one after the other. Needs (2 restart + 4) n doubles of device memory.
+ * stats may be NULL; stats.iterations is the largest count over the columns and
+ * stats.rel_residual the largest final relative residual (PCG: of the recursion; GMRES:
+ * recomputed as ||b - A x|| / ||b||). HSOLVE_NOT_CONVERGED if max_iter is reached first
+ * (x = last iterate). */
 hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb, double* x,
                            int ldx, hsolve_stats* stats);
 

@@ -26,7 +26,7 @@ the code that takes them.
 from .tree import tree_depth, cluster_leaves, footprint_adjacency
 from .hsolver import (Factorization, NotSPDError, compress, pivot, eliminate_node,
                       factor, apply, apply_matrix, LORASP, GC)
-from .krylov import pcg, gmres, stationary
+from .krylov import pcg, fpcg, gmres, stationary
 
 __all__ = [
     "tree_depth", "cluster_leaves", "footprint_adjacency",

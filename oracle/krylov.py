@@ -8,6 +8,10 @@
 * ``pcg``: preconditioned conjugate gradients (Hestenes-Stiefel) for SPD A with the SPD
   preconditioner A_H^{-1}; x_0 = 0; stop when ||b - A x_k||_2 / ||b||_2 <= tol on the
   recursive residual, then report the true residual.
+* ``fpcg``: the same with the flexible beta_k = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k of
+  inexact-preconditioner CG (Golub and Ye, 1999). It is not in the paper; it is the outer loop
+  read for a preconditioner applied in single precision, where z = M(r) is not exactly linear.
+  With a fixed symmetric M it equals ``pcg`` in exact arithmetic (r_{k+1}^T z_k = 0).
 
 ``A`` is anything with ``@`` (a SciPy sparse matrix), ``M`` a callable r -> z.
 """
@@ -41,6 +45,35 @@ def pcg(A, b, M, tol=1e-10, maxiter=1000):
         z = M(r)
         rz_new = r @ z
         beta = rz_new / rz
+        rz = rz_new
+        p = z + beta * p
+    true_rel = np.linalg.norm(b - A @ x) / nb
+    return x, it, true_rel
+
+
+def fpcg(A, b, M, tol=1e-10, maxiter=1000):
+    b = np.asarray(b, dtype=np.float64)
+    x = np.zeros_like(b)
+    r = b.copy()
+    nb = np.linalg.norm(b)
+    if nb == 0.0:
+        return x, 0, 0.0
+    z = M(r)
+    p = z.copy()
+    rz = r @ z
+    it = 0
+    while it < maxiter:
+        q = A @ p
+        alpha = rz / (p @ q)
+        x += alpha * p
+        r -= alpha * q
+        it += 1
+        if np.linalg.norm(r) / nb <= tol:
+            break
+        z_old = z
+        z = M(r)
+        rz_new = r @ z
+        beta = (rz_new - r @ z_old) / rz
         rz = rz_new
         p = z + beta * p
     true_rel = np.linalg.norm(b - A @ x) / nb

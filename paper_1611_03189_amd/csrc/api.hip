@@ -67,6 +67,8 @@ void hsolve_default_options(hsolve_options* o) {
     o->max_iter = 1000;
     o->krylov = HSOLVE_PCG;
     o->stream = nullptr;
+    o->apply_prec = 64;
+    o->restart = 200;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -80,7 +82,8 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
     if (!(o.eps >= 0.0) || !std::isfinite(o.eps) || o.leaf_size < 1 ||
         (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC) || o.dim < 0 || o.dim > 3 ||
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
-        !(o.tol >= 0.0) || o.krylov != HSOLVE_PCG)
+        !(o.tol >= 0.0) || (o.krylov != HSOLVE_PCG && o.krylov != HSOLVE_FPCG && o.krylov != HSOLVE_GMRES) ||
+        (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1)
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;
     hsolve_plan plan = new (std::nothrow) hsolve_plan_s();
@@ -91,6 +94,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         P.n = n;
         P.nnz = row_ptr[n];
         P.opt = o;
+        P.apply32 = o.apply_prec == 32;
         P.stream = static_cast<hipStream_t>(o.stream);
         P.row_ptr.assign(row_ptr, row_ptr + n + 1);
         P.col_idx.assign(col_idx, col_idx + P.nnz);
@@ -156,7 +160,11 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
     hsolve_status st = run(plan, "solve", [&] {
         std::vector<int> its(nrhs);
         std::vector<double> rel(nrhs);
-        hs::pcg(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, its.data(), rel.data());
+        if (P.opt.krylov == HSOLVE_GMRES)
+            hs::gmres(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.restart, its.data(), rel.data());
+        else
+            hs::pcg(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.krylov == HSOLVE_FPCG, its.data(),
+                    rel.data());
         HS_HIP(hipStreamSynchronize(P.stream));
         int most = 0;
         double worst = 0.0;

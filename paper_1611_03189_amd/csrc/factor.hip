@@ -625,6 +625,27 @@ void factor(Plan& P, const double* d_values_in) {
                 throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
             }
     }
+    if (P.apply32) {
+        // single-precision copies of the solve-phase blocks, rounded once from the FP64 factor
+        std::vector<DemoteTask> dt;
+        double elems = 0.0;
+        for (int d = 0; d < nlev; ++d)
+            for (NodeNum& nn : P.num[d].node) {
+                nn.Gm32 = nullptr;
+                if (!nn.Gm || nn.m == 0) continue;
+                const long long cnt = (long long)nn.ldG * nn.m;
+                nn.Gm32 = P.fpool.alloc_n<float>(size_t(cnt));
+                dt.push_back(DemoteTask{nn.Gm, nn.Gm32, cnt});
+                elems += double(cnt);
+            }
+        for (size_t i = 0; i < dt.size(); i += 65535) {
+            const int cnt = int(std::min<size_t>(65535, dt.size() - i));
+            std::vector<DemoteTask> part(dt.begin() + i, dt.begin() + i + cnt);
+            launch_demote(P.stage.upload_vec(part, P.spool, st), cnt, elems * cnt / dt.size(), st);
+        }
+        HS_HIP(hipStreamSynchronize(st));
+        P.stage.reset();
+    }
     build_apply_schedule(P);
     HS_HIP(hipStreamSynchronize(st));
     P.factored = true;

@@ -36,6 +36,11 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+__device__ inline float wave_sum(float v) {
+    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
+    return v;
+}
+
 __device__ inline double wave_max(double v) {
     for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
     return v;

@@ -147,6 +147,7 @@ inline uint64_t bkey(int i, int j) {
 struct NodeNum {
     int m = 0, k = 0, ntot = 0, ka = 0;
     double* Gm = nullptr;
+    float* Gm32 = nullptr;     // single-precision copy for the FP32 solve phase
     int ldG = 0;
     std::vector<int> noff;     // row offset of each neighbour inside T_N
 };
@@ -205,15 +206,21 @@ struct FwdTarget {           // V[dst + i] += sign * sum_c Gc[i, :] V[src_c + :]
 };
 
 struct FwdContrib {
-    const double* G;         // first row of the contributing rows, column-major
+    const void* G;           // first row of the contributing rows, column-major (double or float)
     long long src;           // start of phi_s in V
     int ldG, m;
 };
 
 struct BwdNode {             // x_s = Gm^T [phi_s; -x_N; x_r], written at dst of X
-    const double* G;
+    const void* G;           // double or float, as the solve vectors
     long long dst;
     int ldG, m, rows, seg_begin, seg_end, pad;
+};
+
+struct DemoteTask {          // dst[i] = float(src[i]), i < count
+    const double* src;
+    float* dst;
+    long long count;
 };
 
 struct BwdSeg {              // sign * (buf ? X : V)[off .. off + len)
@@ -268,8 +275,9 @@ struct Plan {
         BwdSeg* bwd_s = nullptr;
     };
     std::vector<std::vector<ColourSched>> sched;   // sched[d][c]
-    double* d_V = nullptr;                          // forward right-hand sides (phi)
-    double* d_X = nullptr;                          // backward solutions (x)
+    bool apply32 = false;                           // solve phase in single precision
+    void* d_V = nullptr;                            // forward right-hand sides (phi)
+    void* d_X = nullptr;                            // backward solutions (x)
     int V_cols = 0;
     double* d_scalars = nullptr;                    // dot-product results
     double* h_scalars = nullptr;                    // pinned
@@ -277,6 +285,8 @@ struct Plan {
     double* d_kscal = nullptr;                      // PCG scalars per column + dot partials
     int* d_kflag = nullptr;                         // PCG: column still iterating
     int krylov_cols = 0;
+    double* d_gmres = nullptr;                      // GMRES: V (restart+1), Z (restart), w, r, x
+    int gmres_restart = 0;
     int h_scalar_cols = 0;
 
     // device memory held by the plan (pattern arrays, values, pools)
@@ -303,7 +313,9 @@ void factor(Plan& P, const double* d_values);
 void build_apply_schedule(Plan& P);
 void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
-         int* its, double* rel);
+         bool flexible, int* its, double* rel);
+void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+           int restart, int* its, double* rel);
 void spmv(Plan& P, const double* x, double* y);
 
 // kernels.hip: launch wrappers (all asynchronous on stream s)
@@ -327,14 +339,21 @@ void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const d
                          const int32_t* super_first, double* const* blk_ptr,
                          const int32_t* blk_ld, const int32_t* blk_col,
                          const int32_t* blk_begin, int n, hipStream_t s);
-void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, double* V,
+// solve phase in the storage type T of the factor copy it reads (double, or float for the
+// single-precision solve); vectors enter and leave it in double
+template <typename T>
+void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, T* V,
                 int64_t ldv, int nrhs, double bytes, hipStream_t s);
-void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const double* V,
-                double* X, int64_t ldv, int nrhs, double bytes, hipStream_t s);
-void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, const int32_t* perm,
+template <typename T>
+void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const T* V,
+                T* X, int64_t ldv, int nrhs, double bytes, hipStream_t s);
+template <typename T>
+void launch_gather_perm(const double* src, int lds, T* dst, int64_t ldd, const int32_t* perm,
                         int n, int nrhs, hipStream_t s);   // dst[p] = src[perm[p]]
-void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
+template <typename T>
+void launch_scatter_perm(const T* src, int64_t lds, double* dst, int ldd,
                          const int32_t* perm, int n, int nrhs, hipStream_t s); // dst[perm[p]] = src[p]
+void launch_demote(const DemoteTask* d_tasks, int ntasks, double elems, hipStream_t s);
 void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y, int n, int64_t nnz, hipStream_t s);
 constexpr int DOTM_BLOCKS = 512;   // partial sums per column of a batched dot product
@@ -346,10 +365,16 @@ void launch_dots(const double* A, const double* B, int64_t ld, int n, int nrhs, 
 void launch_axpy2_multi(double* X, const double* P, double* R, const double* Q, int64_t ld, int n, int nrhs,
                         const double* num, const double* den, const int* active, hipStream_t s);
 void launch_xpby_multi(double* P, const double* Z, int64_t ld, int n, int nrhs, const double* num,
-                       const double* den, const int* active, hipStream_t s);
+                       const double* sub, const double* den, const int* active, hipStream_t s);
 void launch_pcg_flags(const double* rr, const double* nb, double tol, int* active, double* dst,
                       const double* src, int nrhs, hipStream_t s);
 void launch_copy_scalars(double* dst, const double* src, int n, hipStream_t s);
-void launch_fill(double* p, double v, int64_t n, hipStream_t s);
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s);
+// restarted GMRES: y += sign * (*a) * x; y = s * x; r = b - w; x += Z y (y: device, k entries)
+void launch_axpy_dev(double* y, const double* x, const double* a, double sign, int n, hipStream_t s);
+void launch_scale(double* y, const double* x, double sc, int n, hipStream_t s);
+void launch_sub(double* r, const double* b, const double* w, int n, hipStream_t s);
+void launch_gemv_acc(double* x, const double* Z, int64_t ldz, const double* y, int k, int n, hipStream_t s);
 
 }  // namespace hs

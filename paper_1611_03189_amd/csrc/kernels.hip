@@ -212,22 +212,23 @@ void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const d
 // 64 rows of a target; the four waves split the columns of every contribution.
 constexpr int FWD_ROWS = WAVE;
 
+template <typename T>
 __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdContrib* contrib,
-                                            double* V, int64_t ldv, int nrhs) {
+                                            T* V, int64_t ldv, int nrhs) {
     const FwdTarget t = targets[blockIdx.y];
     const int r0 = blockIdx.x * FWD_ROWS;
     if (r0 >= t.len) return;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int i = r0 + lane;
-    __shared__ double part[NT / WAVE][WAVE];
+    __shared__ T part[NT / WAVE][WAVE];
     for (int c = 0; c < nrhs; ++c) {
-        double* Vc = V + size_t(c) * ldv;
-        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        T* Vc = V + size_t(c) * ldv;
+        T acc[4] = {T(0), T(0), T(0), T(0)};
         if (i < t.len) {
             for (int q = t.c_begin; q < t.c_end; ++q) {
                 const FwdContrib f = contrib[q];
-                const double* x = Vc + f.src;
-                const HS_G double* g = gp(f.G) + i;
+                const T* x = Vc + f.src;
+                const HS_G T* g = gp(static_cast<const T*>(f.G)) + i;
                 int j = wv;
                 for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
 #pragma unroll
@@ -242,9 +243,9 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
         part[wv][lane] = (acc[0] + acc[1]) + (acc[2] + acc[3]);
         __syncthreads();
         if (wv == 0 && i < t.len) {
-            double s = 0.0;
+            T s = T(0);
             for (int w = 0; w < NT / WAVE; ++w) s += part[w][lane];
-            Vc[t.dst + i] += t.sign * s;
+            Vc[t.dst + i] += T(t.sign) * s;
         }
         __syncthreads();
     }
@@ -255,38 +256,39 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
 // column's result does not depend on the others.
 constexpr int APPLY_RC = 8;
 
+template <typename T>
 __global__ __launch_bounds__(NT) void k_fwd_m(const FwdTarget* targets, const FwdContrib* contrib,
-                                              double* V, int64_t ldv, int nrhs) {
+                                              T* V, int64_t ldv, int nrhs) {
     const FwdTarget t = targets[blockIdx.y];
     const int r0 = blockIdx.x * FWD_ROWS, c0 = blockIdx.z * APPLY_RC;
     if (r0 >= t.len) return;
     const int nc = min(APPLY_RC, nrhs - c0);
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
     const int i = r0 + lane;
-    __shared__ double part[APPLY_RC][NT / WAVE][WAVE];
-    double acc[APPLY_RC][4];
+    __shared__ T part[APPLY_RC][NT / WAVE][WAVE];
+    T acc[APPLY_RC][4];
 #pragma unroll
     for (int c = 0; c < APPLY_RC; ++c)
 #pragma unroll
-        for (int u = 0; u < 4; ++u) acc[c][u] = 0.0;
+        for (int u = 0; u < 4; ++u) acc[c][u] = T(0);
     if (i < t.len) {
         for (int q = t.c_begin; q < t.c_end; ++q) {
             const FwdContrib f = contrib[q];
-            const double* x = V + size_t(c0) * ldv + f.src;
-            const HS_G double* g = gp(f.G) + i;
+            const T* x = V + size_t(c0) * ldv + f.src;
+            const HS_G T* g = gp(static_cast<const T*>(f.G)) + i;
             int j = wv;
             for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int jj = j + u * (NT / WAVE);
-                    const double gv = g[size_t(jj) * f.ldG];
+                    const T gv = g[size_t(jj) * f.ldG];
 #pragma unroll
                     for (int c = 0; c < APPLY_RC; ++c)
                         if (c < nc) acc[c][u] += gv * x[size_t(c) * ldv + jj];
                 }
             }
             for (; j < f.m; j += NT / WAVE) {
-                const double gv = g[size_t(j) * f.ldG];
+                const T gv = g[size_t(j) * f.ldG];
 #pragma unroll
                 for (int c = 0; c < APPLY_RC; ++c)
                     if (c < nc) acc[c][0] += gv * x[size_t(c) * ldv + j];
@@ -298,27 +300,32 @@ __global__ __launch_bounds__(NT) void k_fwd_m(const FwdTarget* targets, const Fw
     __syncthreads();
     if (wv == 0 && i < t.len) {
         for (int c = 0; c < nc; ++c) {
-            double s = 0.0;
+            T s = T(0);
             for (int w = 0; w < NT / WAVE; ++w) s += part[c][w][lane];
-            V[size_t(c0 + c) * ldv + t.dst + i] += t.sign * s;
+            V[size_t(c0 + c) * ldv + t.dst + i] += T(t.sign) * s;
         }
     }
 }
 
-void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, double* V, int64_t ldv,
+template <typename T>
+void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, T* V, int64_t ldv,
                 int nrhs, double bytes, hipStream_t s) {
     if (nt <= 0 || max_len <= 0) return;
-    ProfScope ps("k_fwd", bytes, s);
+    ProfScope ps(sizeof(T) == 8 ? "k_fwd" : "k_fwd_f32", bytes, s);
     if (nrhs == 1) {
-        hipLaunchKernelGGL(k_fwd, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt), dim3(NT), 0, s, t, c, V,
+        hipLaunchKernelGGL(k_fwd<T>, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt), dim3(NT), 0, s, t, c, V,
                            ldv, nrhs);
         check_launch("k_fwd");
     } else {
-        hipLaunchKernelGGL(k_fwd_m, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt, (nrhs + APPLY_RC - 1) / APPLY_RC),
+        hipLaunchKernelGGL(k_fwd_m<T>, dim3((max_len + FWD_ROWS - 1) / FWD_ROWS, nt, (nrhs + APPLY_RC - 1) / APPLY_RC),
                            dim3(NT), 0, s, t, c, V, ldv, nrhs);
         check_launch("k_fwd_m");
     }
 }
+template void launch_fwd<double>(const FwdTarget*, const FwdContrib*, int, int, double*, int64_t, int, double,
+                                 hipStream_t);
+template void launch_fwd<float>(const FwdTarget*, const FwdContrib*, int, int, float*, int64_t, int, double,
+                                hipStream_t);
 
 // Backward: x_s = Gm^T v with v = [phi_s; -x_N; x_r] gathered into LDS (phi from V, the
 // solutions from X), written to X. Each workgroup takes BWD_COLS columns of one node (two
@@ -326,36 +333,37 @@ void launch_fwd(const FwdTarget* t, const FwdContrib* c, int nt, int max_len, do
 constexpr int BWD_MAX_ROWS = 6144;
 constexpr int BWD_COLS = 8;
 
-__global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* segs, const double* V,
-                                            double* X, int64_t ldv, int nrhs) {
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* segs, const T* V,
+                                            T* X, int64_t ldv, int nrhs) {
     const BwdNode nd = nodes[blockIdx.y];
     const int j0 = blockIdx.x * BWD_COLS;
     if (j0 >= nd.m) return;
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    __shared__ double v[BWD_MAX_ROWS];
+    __shared__ T v[BWD_MAX_ROWS];
     for (int c = 0; c < nrhs; ++c) {
-        const double* Vc = V + size_t(c) * ldv;
-        double* Xc = X + size_t(c) * ldv;
+        const T* Vc = V + size_t(c) * ldv;
+        T* Xc = X + size_t(c) * ldv;
         int pos = 0;
         for (int q = nd.seg_begin; q < nd.seg_end; ++q) {
             const BwdSeg sg = segs[q];
-            const double* src = (sg.buf ? Xc : Vc) + sg.off;
-            for (int i = threadIdx.x; i < sg.len; i += NT) v[pos + i] = sg.sign * src[i];
+            const T* src = (sg.buf ? Xc : Vc) + sg.off;
+            for (int i = threadIdx.x; i < sg.len; i += NT) v[pos + i] = T(sg.sign) * src[i];
             pos += sg.len;
         }
         __syncthreads();
         for (int jj = wv; jj < BWD_COLS; jj += NT / WAVE) {
             const int j = j0 + jj;
             if (j >= nd.m) break;
-            const HS_G double* g = gp(nd.G) + size_t(j) * nd.ldG;
-            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            const HS_G T* g = gp(static_cast<const T*>(nd.G)) + size_t(j) * nd.ldG;
+            T a[8] = {T(0), T(0), T(0), T(0), T(0), T(0), T(0), T(0)};
             int i = lane;
             for (; i + 7 * WAVE < nd.rows; i += 8 * WAVE) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u) a[u] += g[i + u * WAVE] * v[i + u * WAVE];
             }
             for (; i < nd.rows; i += WAVE) a[0] += g[i] * v[i];
-            const double acc = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+            const T acc = wave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
             if (lane == 0) Xc[nd.dst + j] = acc;
         }
         __syncthreads();
@@ -368,22 +376,23 @@ __global__ __launch_bounds__(NT) void k_bwd(const BwdNode* nodes, const BwdSeg* 
 // lane's remaining rows in a[0]).
 constexpr int BWD_CHUNK = 512;
 
-__global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg* segs, const double* V,
-                                              double* X, int64_t ldv, int nrhs) {
+template <typename T>
+__global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg* segs, const T* V,
+                                              T* X, int64_t ldv, int nrhs) {
     const BwdNode nd = nodes[blockIdx.y];
     const int j0 = blockIdx.x * BWD_COLS, c0 = blockIdx.z * APPLY_RC;
     if (j0 >= nd.m) return;
     const int nc = min(APPLY_RC, nrhs - c0);
     const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
-    __shared__ double v[APPLY_RC][BWD_CHUNK];
+    __shared__ T v[APPLY_RC][BWD_CHUNK];
     constexpr int JW = BWD_COLS / (NT / WAVE);           // output columns per wave
-    double a[JW][APPLY_RC][8];
+    T a[JW][APPLY_RC][8];
 #pragma unroll
     for (int q = 0; q < JW; ++q)
 #pragma unroll
         for (int c = 0; c < APPLY_RC; ++c)
 #pragma unroll
-            for (int u = 0; u < 8; ++u) a[q][c][u] = 0.0;
+            for (int u = 0; u < 8; ++u) a[q][c][u] = T(0);
     for (int r0 = 0; r0 < nd.rows; r0 += BWD_CHUNK) {
         const int r1 = min(nd.rows, r0 + BWD_CHUNK);
         __syncthreads();
@@ -394,8 +403,8 @@ __global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg
             for (int e = threadIdx.x; e < APPLY_RC * (hi - lo); e += NT) {
                 const int c = e / (hi - lo), r = lo + e % (hi - lo);
                 if (c < nc) {
-                    const double* src = (sg.buf ? X : V) + size_t(c0 + c) * ldv + sg.off;
-                    v[c][r - r0] = sg.sign * src[r - pos];
+                    const T* src = (sg.buf ? X : V) + size_t(c0 + c) * ldv + sg.off;
+                    v[c][r - r0] = T(sg.sign) * src[r - pos];
                 }
             }
             pos += sg.len;
@@ -405,19 +414,19 @@ __global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg
         for (int q = 0; q < JW; ++q) {
             const int j = j0 + wv + q * (NT / WAVE);
             if (j >= nd.m) break;
-            const HS_G double* g = gp(nd.G) + size_t(j) * nd.ldG;
+            const HS_G T* g = gp(static_cast<const T*>(nd.G)) + size_t(j) * nd.ldG;
             if (r0 + lane + 7 * WAVE < nd.rows) {           // this lane's rows of the block all exist
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int i = r0 + lane + u * WAVE;
-                    const double gv = g[i];
+                    const T gv = g[i];
 #pragma unroll
                     for (int c = 0; c < APPLY_RC; ++c)
                         if (c < nc) a[q][c][u] += gv * v[c][i - r0];
                 }
             } else {                                        // the rest, in a[0] (as k_bwd)
                 for (int i = r0 + lane; i < r1; i += WAVE) {
-                    const double gv = g[i];
+                    const T gv = g[i];
 #pragma unroll
                     for (int c = 0; c < APPLY_RC; ++c)
                         if (c < nc) a[q][c][0] += gv * v[c][i - r0];
@@ -430,59 +439,93 @@ __global__ __launch_bounds__(NT) void k_bwd_m(const BwdNode* nodes, const BwdSeg
         const int j = j0 + wv + q * (NT / WAVE);
 #pragma unroll
         for (int c = 0; c < APPLY_RC; ++c) {
-            const double acc = wave_sum(((a[q][c][0] + a[q][c][1]) + (a[q][c][2] + a[q][c][3])) +
+            const T acc = wave_sum(((a[q][c][0] + a[q][c][1]) + (a[q][c][2] + a[q][c][3])) +
                                         ((a[q][c][4] + a[q][c][5]) + (a[q][c][6] + a[q][c][7])));
             if (lane == 0 && j < nd.m && c < nc) X[size_t(c0 + c) * ldv + nd.dst + j] = acc;
         }
     }
 }
 
-void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const double* V, double* X,
+template <typename T>
+void launch_bwd(const BwdNode* nodes, const BwdSeg* segs, int nn, int max_m, const T* V, T* X,
                 int64_t ldv, int nrhs, double bytes, hipStream_t s) {
     if (nn <= 0 || max_m <= 0) return;
-    ProfScope ps("k_bwd", bytes, s);
+    ProfScope ps(sizeof(T) == 8 ? "k_bwd" : "k_bwd_f32", bytes, s);
     if (nrhs == 1) {
-        hipLaunchKernelGGL(k_bwd, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn), dim3(NT), 0, s, nodes, segs,
+        hipLaunchKernelGGL(k_bwd<T>, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn), dim3(NT), 0, s, nodes, segs,
                            V, X, ldv, nrhs);
         check_launch("k_bwd");
     } else {
-        hipLaunchKernelGGL(k_bwd_m, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn, (nrhs + APPLY_RC - 1) / APPLY_RC),
+        hipLaunchKernelGGL(k_bwd_m<T>, dim3((max_m + BWD_COLS - 1) / BWD_COLS, nn, (nrhs + APPLY_RC - 1) / APPLY_RC),
                            dim3(NT), 0, s, nodes, segs, V, X, ldv, nrhs);
         check_launch("k_bwd_m");
     }
 }
+template void launch_bwd<double>(const BwdNode*, const BwdSeg*, int, int, const double*, double*, int64_t, int,
+                                 double, hipStream_t);
+template void launch_bwd<float>(const BwdNode*, const BwdSeg*, int, int, const float*, float*, int64_t, int,
+                                double, hipStream_t);
 
 // ---------------------------------------------------------------------------------
 // Permutations, SpMV, BLAS-1
 // ---------------------------------------------------------------------------------
-__global__ void k_gather_perm(const double* src, int lds, double* dst, int64_t ldd,
+// dst[p] = src[perm[p]] (into the solve vector, in its storage type)
+template <typename T>
+__global__ void k_gather_perm(const double* src, int lds, T* dst, int64_t ldd,
                               const int32_t* perm, int n, int nrhs) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int u = perm[p];
-    for (int c = 0; c < nrhs; ++c) dst[p + c * ldd] = src[u + size_t(c) * lds];
+    for (int c = 0; c < nrhs; ++c) dst[p + c * ldd] = T(src[u + size_t(c) * lds]);
 }
 
-void launch_gather_perm(const double* src, int lds, double* dst, int64_t ldd, const int32_t* perm,
+template <typename T>
+void launch_gather_perm(const double* src, int lds, T* dst, int64_t ldd, const int32_t* perm,
                         int n, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_gather_perm, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
+    hipLaunchKernelGGL(k_gather_perm<T>, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
                        ldd, perm, n, nrhs);
     check_launch("k_gather_perm");
 }
+template void launch_gather_perm<double>(const double*, int, double*, int64_t, const int32_t*, int, int,
+                                         hipStream_t);
+template void launch_gather_perm<float>(const double*, int, float*, int64_t, const int32_t*, int, int,
+                                        hipStream_t);
 
-__global__ void k_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
+// dst[perm[p]] = src[p] (out of the solve vector, widened to double)
+template <typename T>
+__global__ void k_scatter_perm(const T* src, int64_t lds, double* dst, int ldd,
                                const int32_t* perm, int n, int nrhs) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int u = perm[p];
-    for (int c = 0; c < nrhs; ++c) dst[u + size_t(c) * ldd] = src[p + c * lds];
+    for (int c = 0; c < nrhs; ++c) dst[u + size_t(c) * ldd] = double(src[p + c * lds]);
 }
 
-void launch_scatter_perm(const double* src, int64_t lds, double* dst, int ldd,
+template <typename T>
+void launch_scatter_perm(const T* src, int64_t lds, double* dst, int ldd,
                          const int32_t* perm, int n, int nrhs, hipStream_t s) {
-    hipLaunchKernelGGL(k_scatter_perm, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
+    hipLaunchKernelGGL(k_scatter_perm<T>, dim3((n + NT - 1) / NT), dim3(NT), 0, s, src, lds, dst,
                        ldd, perm, n, nrhs);
     check_launch("k_scatter_perm");
+}
+template void launch_scatter_perm<double>(const double*, int64_t, double*, int, const int32_t*, int, int,
+                                          hipStream_t);
+template void launch_scatter_perm<float>(const float*, int64_t, double*, int, const int32_t*, int, int,
+                                         hipStream_t);
+
+// Rounds factor blocks to single precision for the FP32 solve phase: one task per block
+// (blockIdx.y), round to nearest.
+__global__ __launch_bounds__(NT) void k_demote(const DemoteTask* tasks) {
+    const DemoteTask t = tasks[blockIdx.y];
+    for (int64_t i = blockIdx.x * int64_t(NT) + threadIdx.x; i < t.count; i += int64_t(gridDim.x) * NT)
+        t.dst[i] = float(t.src[i]);
+}
+
+void launch_demote(const DemoteTask* d_tasks, int ntasks, double elems, hipStream_t s) {
+    if (ntasks <= 0) return;
+    ProfScope ps("k_demote", 12.0 * elems, s);
+    hipLaunchKernelGGL(k_demote, dim3(64, ntasks), dim3(NT), 0, s, d_tasks);
+    check_launch("k_demote");
 }
 
 __global__ void k_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
@@ -503,18 +546,22 @@ void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* v
     check_launch("k_spmv");
 }
 
-__global__ void k_fill(double* p, double v, int64_t n) {
+template <typename T>
+__global__ void k_fill(T* p, T v, int64_t n) {
     for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
          i += int64_t(gridDim.x) * blockDim.x)
         p[i] = v;
 }
 
-void launch_fill(double* p, double v, int64_t n, hipStream_t s) {
+template <typename T>
+void launch_fill(T* p, T v, int64_t n, hipStream_t s) {
     if (n <= 0) return;
     int64_t nb = (n + NT - 1) / NT;
     if (nb > 4096) nb = 4096;
-    hipLaunchKernelGGL(k_fill, dim3(unsigned(nb)), dim3(NT), 0, s, p, v, n);
+    hipLaunchKernelGGL(k_fill<T>, dim3(unsigned(nb)), dim3(NT), 0, s, p, v, n);
     check_launch("k_fill");
 }
+template void launch_fill<double>(double*, double, int64_t, hipStream_t);
+template void launch_fill<float>(float*, float, int64_t, hipStream_t);
 
 }  // namespace hs

@@ -91,18 +91,20 @@ void launch_axpy2_multi(double* X, const double* P, double* R, const double* Q, 
     check_launch("k_axpy2_multi");
 }
 
-// P(:, c) = Z(:, c) + (num[c] / den[c]) P(:, c), active columns only
+// P(:, c) = Z(:, c) + beta_c P(:, c), active columns only, with beta_c = num[c] / den[c], or
+// (num[c] - sub[c]) / den[c] when sub is given (the flexible form of beta)
 __global__ void k_xpby_multi(double* P, const double* Z, int64_t ld, int n, const double* num,
-                             const double* den, const int* active) {
+                             const double* sub, const double* den, const int* active) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     const int c = blockIdx.y;
     if (i >= n || !active[c]) return;
-    P[i + c * ld] = Z[i + c * ld] + (num[c] / den[c]) * P[i + c * ld];
+    const double beta = sub ? (num[c] - sub[c]) / den[c] : num[c] / den[c];
+    P[i + c * ld] = Z[i + c * ld] + beta * P[i + c * ld];
 }
 
 void launch_xpby_multi(double* P, const double* Z, int64_t ld, int n, int nrhs, const double* num,
-                       const double* den, const int* active, hipStream_t s) {
-    hipLaunchKernelGGL(k_xpby_multi, dim3((n + NT - 1) / NT, nrhs), dim3(NT), 0, s, P, Z, ld, n, num, den,
+                       const double* sub, const double* den, const int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_xpby_multi, dim3((n + NT - 1) / NT, nrhs), dim3(NT), 0, s, P, Z, ld, n, num, sub, den,
                        active);
     check_launch("k_xpby_multi");
 }
@@ -132,6 +134,57 @@ __global__ void k_copy_scalars(double* dst, const double* src, int n) {
 void launch_copy_scalars(double* dst, const double* src, int n, hipStream_t s) {
     hipLaunchKernelGGL(k_copy_scalars, dim3((n + NT - 1) / NT), dim3(NT), 0, s, dst, src, n);
     check_launch("k_copy_scalars");
+}
+
+// ---------------------------------------------------------------------------------
+// Restarted GMRES (one column): Arnoldi vector updates with coefficients on the device
+// ---------------------------------------------------------------------------------
+// y += sign * (*a) * x
+__global__ void k_axpy_dev(double* y, const double* x, const double* a, double sign, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] += (sign * a[0]) * x[i];
+}
+
+void launch_axpy_dev(double* y, const double* x, const double* a, double sign, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_axpy_dev, dim3((n + NT - 1) / NT), dim3(NT), 0, s, y, x, a, sign, n);
+    check_launch("k_axpy_dev");
+}
+
+// y = sc * x
+__global__ void k_scale(double* y, const double* x, double sc, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = sc * x[i];
+}
+
+void launch_scale(double* y, const double* x, double sc, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_scale, dim3((n + NT - 1) / NT), dim3(NT), 0, s, y, x, sc, n);
+    check_launch("k_scale");
+}
+
+// r = b - w
+__global__ void k_sub(double* r, const double* b, const double* w, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) r[i] = b[i] - w[i];
+}
+
+void launch_sub(double* r, const double* b, const double* w, int n, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub, dim3((n + NT - 1) / NT), dim3(NT), 0, s, r, b, w, n);
+    check_launch("k_sub");
+}
+
+// x += Z y, Z: n x k (ld ldz), y: k entries on the device; the terms are added in column order
+__global__ void k_gemv_acc(double* x, const double* Z, int64_t ldz, const double* y, int k, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += Z[i + j * ldz] * y[j];
+    x[i] += acc;
+}
+
+void launch_gemv_acc(double* x, const double* Z, int64_t ldz, const double* y, int k, int n, hipStream_t s) {
+    if (k <= 0) return;
+    hipLaunchKernelGGL(k_gemv_acc, dim3((n + NT - 1) / NT), dim3(NT), 0, s, x, Z, ldz, y, k, n);
+    check_launch("k_gemv_acc");
 }
 
 }  // namespace hs

@@ -16,6 +16,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstring>
 #include <map>
 
 #include "hs_internal.h"
@@ -41,6 +42,12 @@ void build_apply_schedule(Plan& P) {
         if (d == L - 1) return P.leaf_off[2 * s];
         return P.num[d + 1].red_off[2 * s];
     };
+    // the factor copy the solve phase reads: Gm (double) or its single-precision copy
+    const double w = P.apply32 ? 4.0 : 8.0;
+    auto grow = [&](const NodeNum& nn, int row) -> const void* {
+        if (P.apply32) return nn.Gm32 + row;
+        return nn.Gm + row;
+    };
     double bytes = 0.0;
     P.sched.assign(nlev, {});
     for (int d = nlev - 1; d >= 0; --d) {
@@ -62,15 +69,15 @@ void build_apply_schedule(Plan& P) {
                     const int len = red ? LN.ksz[nb] : LN.msz[nb];
                     auto& e = tg[dst];
                     e.first = FwdTarget{dst, len, -1, 0, 0};
-                    e.second.push_back(FwdContrib{nn.Gm + nn.m + nn.noff[t], src, nn.ldG, nn.m});
+                    e.second.push_back(FwdContrib{grow(nn, nn.m + nn.noff[t]), src, nn.ldG, nn.m});
                 }
                 if (nn.k) {
                     const int64_t dst = LN.red_off[s];
                     auto& e = tg[dst];
                     e.first = FwdTarget{dst, nn.k, +1, 0, 0};
-                    e.second.push_back(FwdContrib{nn.Gm + nn.m + nn.ntot, src, nn.ldG, nn.m});
+                    e.second.push_back(FwdContrib{grow(nn, nn.m + nn.ntot), src, nn.ldG, nn.m});
                 }
-                BwdNode b{nn.Gm, src, nn.ldG, nn.m, nn.m + nn.ntot + nn.k, int(bs.size()), 0, 0};
+                BwdNode b{grow(nn, 0), src, nn.ldG, nn.m, nn.m + nn.ntot + nn.k, int(bs.size()), 0, 0};
                 bs.push_back(BwdSeg{src, nn.m, +1, 0, 0});
                 for (size_t t = 0; t < S.N[s].size(); ++t) {
                     const int nb = S.N[s][t];
@@ -83,8 +90,8 @@ void build_apply_schedule(Plan& P) {
                 bn.push_back(b);
                 max_rows = std::max(max_rows, b.rows);
                 // factor reads: forward rows m.. of Gm, backward all rows; vectors twice
-                bytes += 8.0 * (double(nn.ntot + nn.k) * nn.m + double(nn.ldG) * nn.m);
-                bytes += 8.0 * 2.0 * (2.0 * nn.m + 2.0 * nn.ntot + 2.0 * nn.k);
+                bytes += w * (double(nn.ntot + nn.k) * nn.m + double(nn.ldG) * nn.m);
+                bytes += w * 2.0 * (2.0 * nn.m + 2.0 * nn.ntot + 2.0 * nn.k);
             }
             std::vector<FwdTarget> ft;
             std::vector<FwdContrib> fc;
@@ -100,8 +107,8 @@ void build_apply_schedule(Plan& P) {
             Plan::ColourSched& cs = P.sched[d][c];
             for (int s : S.colours[c]) {
                 const NodeNum& nn = LN.node[s];
-                cs.fwd_bytes += 8.0 * (double(nn.ntot + nn.k) * nn.m + nn.m + 2.0 * (nn.ntot + nn.k));
-                cs.bwd_bytes += 8.0 * (double(nn.ldG) * nn.m + nn.ldG + nn.m);
+                cs.fwd_bytes += w * (double(nn.ntot + nn.k) * nn.m + nn.m + 2.0 * (nn.ntot + nn.k));
+                cs.bwd_bytes += w * (double(nn.ldG) * nn.m + nn.ldG + nn.m);
             }
             cs.nfwd = int(ft.size());
             cs.max_len = max_len;
@@ -115,7 +122,7 @@ void build_apply_schedule(Plan& P) {
                 throw Error{HSOLVE_ERR_INVALID, "super node with too many neighbour rows for the solve kernel"};
         }
     }
-    P.stats.apply_bytes = bytes + 16.0 * P.n;
+    P.stats.apply_bytes = bytes + (8.0 + w) * P.n;
     HS_HIP(hipStreamSynchronize(st));
     P.stage.reset();
     P.d_scalars = P.apool.alloc_n<double>(2 + 2 * 512 + 16);
@@ -123,33 +130,41 @@ void build_apply_schedule(Plan& P) {
 
 static void ensure_V(Plan& P, int nrhs) {
     if (P.d_V && P.V_cols >= nrhs) return;
-    P.d_V = P.apool.alloc_n<double>(size_t(P.vlen) * nrhs);
-    P.d_X = P.apool.alloc_n<double>(size_t(P.vlen) * nrhs);
+    const size_t bytes = (P.apply32 ? sizeof(float) : sizeof(double)) * size_t(P.vlen) * nrhs;
+    P.d_V = P.apool.alloc(bytes);
+    P.d_X = P.apool.alloc(bytes);
     P.V_cols = nrhs;
 }
 
-// z = A_H^{-1} r for nrhs columns (device pointers, original unknown order)
-void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
-    if (!P.factored) throw Error{HSOLVE_ERR_STATE, "apply before factor"};
+template <typename T>
+static void apply_t(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
     hipStream_t st = P.stream;
-    ensure_V(P, nrhs);
     const int L = P.L, nlev = std::max(L, 1);
     const int64_t ldv = P.vlen;
-    for (int c = 0; c < nrhs; ++c)
-        launch_fill(P.d_V + size_t(c) * ldv + P.n, 0.0, P.vlen - P.n, st);
-    launch_gather_perm(r, ldr, P.d_V, ldv, P.d_perm, P.n, nrhs, st);
+    T* V = static_cast<T*>(P.d_V);
+    T* X = static_cast<T*>(P.d_X);
+    for (int c = 0; c < nrhs; ++c) launch_fill<T>(V + size_t(c) * ldv + P.n, T(0), P.vlen - P.n, st);
+    launch_gather_perm<T>(r, ldr, V, ldv, P.d_perm, P.n, nrhs, st);
     for (int d = nlev - 1; d >= 0; --d)
         for (size_t c = 0; c < P.sched[d].size(); ++c) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_fwd(cs.fwd_t, cs.fwd_c, cs.nfwd, cs.max_len, P.d_V, ldv, nrhs, cs.fwd_bytes * nrhs, st);
+            launch_fwd<T>(cs.fwd_t, cs.fwd_c, cs.nfwd, cs.max_len, V, ldv, nrhs, cs.fwd_bytes * nrhs, st);
         }
     for (int d = 0; d < nlev; ++d)
         for (size_t c = P.sched[d].size(); c-- > 0;) {
             const Plan::ColourSched& cs = P.sched[d][c];
-            launch_bwd(cs.bwd_n, cs.bwd_s, cs.nbwd, cs.max_m, P.d_V, P.d_X, ldv, nrhs, cs.bwd_bytes * nrhs,
-                       st);
+            launch_bwd<T>(cs.bwd_n, cs.bwd_s, cs.nbwd, cs.max_m, V, X, ldv, nrhs, cs.bwd_bytes * nrhs, st);
         }
-    launch_scatter_perm(P.d_X, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
+    launch_scatter_perm<T>(X, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
+}
+
+// z = A_H^{-1} r for nrhs columns (device pointers, original unknown order); the sweeps run in
+// the precision of the factor copy the plan keeps for them
+void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
+    if (!P.factored) throw Error{HSOLVE_ERR_STATE, "apply before factor"};
+    ensure_V(P, nrhs);
+    if (P.apply32) apply_t<float>(P, nrhs, r, ldr, z, ldz);
+    else apply_t<double>(P, nrhs, r, ldr, z, ldz);
 }
 
 void spmv(Plan& P, const double* x, double* y) {
@@ -160,8 +175,12 @@ void spmv(Plan& P, const double* x, double* y) {
 // column stops changing once ||r_k|| <= tol ||b|| (by the recursion). One SpMV, one apply and
 // one scalar read-back per iteration for the whole block. its[c] and rel[c] receive the
 // iteration count and the final recursive relative residual of column c.
+// flexible: beta_k = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k (Polak-Ribiere form), which keeps the
+// iteration convergent when the preconditioner is applied in lower precision; r_{k+1}^T z_k is
+// taken before the apply overwrites z_k. With an exact symmetric preconditioner it equals the
+// standard beta in exact arithmetic.
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
-         int* its, double* rel) {
+         bool flexible, int* its, double* rel) {
     hipStream_t st = P.stream;
     const int n = P.n;
     const int64_t ld = n;
@@ -187,6 +206,7 @@ void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double
     double* pq = rz + nrhs;
     double* rr = pq + nrhs;
     double* rzn = rr + nrhs;
+    double* rzo = rzn + nrhs;                   // flexible: r_{k+1}^T z_k
     double* part = rzn + 2 * nrhs;              // DOTM_BLOCKS partial sums per column
     int* active = P.d_kflag;
     double* h = P.h_scalars;                    // host: ||b||, rr, active (as doubles)
@@ -241,12 +261,123 @@ void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double
             any = any || live[c];
         }
         if (!any) break;
+        if (flexible) launch_dots(R, Z, ld, n, nrhs, part, rzo, st);
         apply(P, nrhs, R, n, Z, n);
         launch_dots(R, Z, ld, n, nrhs, part, rzn, st);
-        launch_xpby_multi(Pv, Z, ld, n, nrhs, rzn, rz, active, st);
+        launch_xpby_multi(Pv, Z, ld, n, nrhs, rzn, flexible ? rzo : nullptr, rz, active, st);
         launch_copy_scalars(rz, rzn, nrhs, st);
     }
     copy_out();
+}
+
+// Restarted GMRES, right-preconditioned (A M y = b, x = M y), one column at a time, x0 = 0:
+// Arnoldi with modified Gram-Schmidt (coefficients stay on the device), the preconditioned
+// basis Z kept so that x += Z y also holds when M varies slightly between calls (single-
+// precision solve phase); Givens rotations and the small triangular solve on the host, one
+// read-back of the new Hessenberg column per step. Stops when the residual estimate |g_{j+1}|
+// reaches tol ||b|| (the true residual for right preconditioning, up to rounding); rel[c] is
+// the true relative residual recomputed at the end.
+void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+           int restart, int* its, double* rel) {
+    hipStream_t st = P.stream;
+    const int n = P.n;
+    const int m = std::max(1, restart);
+    if (!P.d_gmres || P.gmres_restart < m) {
+        P.d_gmres = P.apool.alloc_n<double>(size_t(n) * (2 * size_t(m) + 4) + size_t(m + 2) + DOTM_BLOCKS + 8);
+        P.gmres_restart = m;
+    }
+    if (!P.h_scalars || P.h_scalar_cols < m + 8) {
+        if (P.h_scalars) HS_HIP(hipHostFree(P.h_scalars));
+        HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_scalars), sizeof(double) * 3 * size_t(m + 8) + 64,
+                             hipHostMallocDefault));
+        P.h_scalar_cols = m + 8;
+    }
+    double* Vb = P.d_gmres;                          // n x (m + 1)
+    double* Zb = Vb + size_t(n) * (m + 1);           // n x m
+    double* w = Zb + size_t(n) * m;
+    double* r = w + n;
+    double* X = r + n;
+    double* hcol = X + n;                            // m + 2 Hessenberg entries of one column
+    double* part = hcol + (m + 2);
+    double* h = P.h_scalars;
+    auto dot = [&](const double* a, const double* bb, double* out) { launch_dots(a, bb, n, n, 1, part, out, st); };
+    auto read = [&](const double* src, int cnt) {
+        HS_HIP(hipMemcpyAsync(h, src, sizeof(double) * cnt, hipMemcpyDeviceToHost, st));
+        HS_HIP(hipStreamSynchronize(st));
+    };
+    std::vector<double> H(size_t(m + 1) * m), cs(m), sn(m), g(m + 1), y(m);
+    for (int c = 0; c < nrhs; ++c) {
+        const double* bc = b + size_t(c) * ldb;
+        launch_fill<double>(X, 0.0, n, st);
+        dot(bc, bc, hcol);
+        read(hcol, 1);
+        const double nb = std::sqrt(h[0]);
+        int total = 0;
+        while (nb > 0.0 && total < max_iter) {
+            launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, X, w, n, P.nnz, st);
+            launch_sub(r, bc, w, n, st);
+            dot(r, r, hcol);
+            read(hcol, 1);
+            const double beta = std::sqrt(h[0]);
+            if (beta / nb <= tol) break;
+            const int mm = std::min(m, max_iter - total);
+            std::fill(H.begin(), H.end(), 0.0);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            launch_scale(Vb, r, 1.0 / beta, n, st);
+            int jd = 0;
+            for (int j = 0; j < mm; ++j) {
+                double* vj = Vb + size_t(n) * j;
+                double* zj = Zb + size_t(n) * j;
+                apply(P, 1, vj, n, zj, n);
+                launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, zj, w, n, P.nnz, st);
+                for (int i = 0; i <= j; ++i) {
+                    dot(w, Vb + size_t(n) * i, hcol + i);
+                    launch_axpy_dev(w, Vb + size_t(n) * i, hcol + i, -1.0, n, st);
+                }
+                dot(w, w, hcol + j + 1);
+                read(hcol, j + 2);
+                double* Hj = H.data() + size_t(j) * (m + 1);   // column j, m + 1 rows
+                for (int i = 0; i <= j; ++i) Hj[i] = h[i];
+                Hj[j + 1] = std::sqrt(h[j + 1]);
+                if (Hj[j + 1] > 0.0) launch_scale(Vb + size_t(n) * (j + 1), w, 1.0 / Hj[j + 1], n, st);
+                for (int i = 0; i < j; ++i) {
+                    const double t = cs[i] * Hj[i] + sn[i] * Hj[i + 1];
+                    Hj[i + 1] = -sn[i] * Hj[i] + cs[i] * Hj[i + 1];
+                    Hj[i] = t;
+                }
+                const double den = std::hypot(Hj[j], Hj[j + 1]);
+                cs[j] = Hj[j] / den;
+                sn[j] = Hj[j + 1] / den;
+                Hj[j] = den;
+                Hj[j + 1] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                ++total;
+                jd = j + 1;
+                if (std::fabs(g[j + 1]) / nb <= tol) break;
+            }
+            for (int i = jd - 1; i >= 0; --i) {      // back substitution with the triangle of H
+                double t = g[i];
+                for (int k = i + 1; k < jd; ++k) t -= H[size_t(k) * (m + 1) + i] * y[k];
+                y[i] = t / H[size_t(i) * (m + 1) + i];
+            }
+            std::memcpy(h, y.data(), sizeof(double) * jd);
+            HS_HIP(hipMemcpyAsync(hcol, h, sizeof(double) * jd, hipMemcpyHostToDevice, st));
+            launch_gemv_acc(X, Zb, n, hcol, jd, n, st);
+            HS_HIP(hipStreamSynchronize(st));        // h is reused as a read-back buffer
+            if (std::fabs(g[jd]) / nb <= tol) break;
+        }
+        // true residual
+        launch_spmv(P.d_row_ptr, P.d_col_idx, P.d_values, X, w, n, P.nnz, st);
+        launch_sub(r, bc, w, n, st);
+        dot(r, r, hcol);
+        read(hcol, 1);
+        its[c] = total;
+        rel[c] = nb > 0.0 ? std::sqrt(h[0]) / nb : 0.0;
+        HS_HIP(hipMemcpyAsync(x + size_t(c) * ldx, X, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    }
+    HS_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace hs

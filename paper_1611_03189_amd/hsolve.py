@@ -20,6 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hsolve.h")
 
 LORASP = 0
 GC = 1
+KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2}
 
 STATUS = {
     0: "HSOLVE_OK", 1: "HSOLVE_NOT_CONVERGED", -1: "HSOLVE_ERR_INVALID",
@@ -43,6 +44,7 @@ class Options(ctypes.Structure):
         ("leaf_size", c_int), ("eps", c_double), ("variant", c_int), ("nvec", c_int),
         ("phi", POINTER(c_double)), ("dim", c_int), ("coords", POINTER(c_double)),
         ("tol", c_double), ("max_iter", c_int), ("krylov", c_int), ("stream", c_void_p),
+        ("apply_prec", c_int), ("restart", c_int),
     ]
 
 
@@ -148,7 +150,7 @@ class HSolver:
 
     def __init__(self, row_ptr, col_idx, coords=None, leaf: int = 16, eps: float = 1e-2,
                  variant: str = "gc", phi=None, tol: float = 1e-10, max_iter: int = 1000,
-                 stream=None):
+                 stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -161,6 +163,9 @@ class HSolver:
         opt.variant = {"gc": GC, "lorasp": LORASP}[variant] if isinstance(variant, str) else int(variant)
         opt.tol = float(tol)
         opt.max_iter = int(max_iter)
+        opt.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
+        opt.apply_prec = int(apply_prec)
+        opt.restart = int(restart)
         self._keep = []
         if coords is not None:
             c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(self.n, -1))

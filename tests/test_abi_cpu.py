@@ -86,6 +86,18 @@ def test_analyze_rejects_bad_input(lib):
     bad[-1] = p.n + 5
     with pytest.raises(H.HSolveError):
         H.HSolver(p.row_ptr, bad, coords=p.coords)
+    for kw in ({"apply_prec": 16}, {"krylov": 3}, {"krylov": "gmres", "restart": 0}):
+        with pytest.raises(H.HSolveError) as e:
+            H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
+        assert e.value.status == -1, kw
+
+
+def test_options_accept_solver_variants(lib):
+    p = pb.poisson(6, 2)
+    for kw in ({"apply_prec": 32, "krylov": "fpcg"}, {"krylov": "gmres", "restart": 30},
+               {"apply_prec": 64, "krylov": "pcg"}):
+        with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
+            assert S._h
 
 
 def test_state_errors_without_factor(lib):

@@ -1,0 +1,158 @@
+"""Single-precision solve phase and the other outer iterations, GPU vs the FP64 oracle.
+
+FP32 solve phase: the factor is computed in FP64 and its solve-phase blocks are rounded to
+FP32. The bar derives from the arithmetic: the sweeps are a chain of dense products, so the
+relative error of z is bounded by a small multiple of u32 = 2^-24 times kappa(A_H), and
+kappa(A_H) ~ kappa(A) for these tolerances (Example 1); kappa(A) comes from the closed-form
+Poisson spectrum. The bar is 20 kappa u32, and the result must also differ from the FP64
+apply by more than FP64 rounding (the single-precision sweeps really ran).
+Outer loops: flexible PCG and GMRES reach the 1e-10 true residual (computed on the host in
+FP64), with iteration counts within one of the oracle's (FP64) or within three of FP64 PCG
+(FP32 solve phase).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1611_03189_amd import problems as pb
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_03189_amd import hsolve as H  # noqa: E402
+
+TOL = 1e-10
+U32 = 2.0 ** -24
+
+
+def say(*a):
+    print("[gpu-case]", *a, file=sys.stderr, flush=True)
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def kappa_poisson(N, dim):
+    """Closed-form condition number of the constant-coefficient FD Laplacian."""
+    lo = dim * (2.0 - 2.0 * np.cos(np.pi / (N + 1)))
+    hi = dim * (2.0 - 2.0 * np.cos(N * np.pi / (N + 1)))
+    return hi / lo
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("name,N,dim,leaf", [
+    ("c1_poisson2d_32_leaf16", 32, 2, 16),
+    ("poisson3d_16_leaf64", 16, 3, 64),
+])
+def test_fp32_apply_close_to_oracle(name, N, dim, leaf):
+    say("fp32 apply", name)
+    p = pb.poisson(N, dim)
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=1e-2, variant=O.GC)
+    r = pb.rhs(p.n, 3, 31)
+    z_ref = O.apply(F, r)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2, apply_prec=32,
+                  krylov="fpcg")
+    S.factor(dev(p.values))
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
+    z = S.apply(dev(r)).cpu().numpy()
+    z1 = S.apply(dev(r[:, 1])).cpu().numpy()
+    bar = 20.0 * kappa_poisson(N, dim) * U32
+    e = rel(z, z_ref)
+    say("fp32 apply", name, "rel", e, "bar", bar)
+    assert 1e-12 < e <= bar, (e, bar)
+    assert np.array_equal(z1, z[:, 1])              # columns independent, as in FP64
+    S.close()
+
+
+@pytest.mark.parametrize("name,make,leaf,eps", [
+    ("c1_poisson2d_32", lambda: pb.poisson(32, 2), 16, 1e-2),
+    ("lognormal2d_64_s2", lambda: pb.lognormal(64, 2, 2.0, 1002), 16, 1e-2),
+    ("poisson3d_16_leaf64", lambda: pb.poisson(16, 3), 64, 1e-2),
+])
+def test_flexible_pcg(name, make, leaf, eps):
+    say("fpcg", name)
+    p = make()
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 2, 2005)
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=eps, variant=O.GC)
+    M = lambda r: O.apply(F, r)                      # noqa: E731
+    ref = [O.fpcg(A, b[:, c], M, tol=TOL) for c in range(2)]
+    its64 = [O.pcg(A, b[:, c], M, tol=TOL)[1] for c in range(2)]
+    for prec in (64, 32):
+        S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=eps, krylov="fpcg",
+                      apply_prec=prec)
+        S.factor(dev(p.values))
+        x, st = S.solve(dev(b))
+        x = x.cpu().numpy()
+        for c in range(2):
+            true_rel = np.linalg.norm(b[:, c] - A @ x[:, c]) / np.linalg.norm(b[:, c])
+            assert true_rel <= 2 * TOL, (prec, c, true_rel)
+        if prec == 64:
+            assert abs(st["iterations"] - max(r[1] for r in ref)) <= 1, (st, [r[1] for r in ref])
+            for c in range(2):
+                assert rel(x[:, c], ref[c][0]) < 1e-8
+        else:
+            assert st["iterations"] <= max(its64) + 3, (st, its64)
+        say("fpcg", name, prec, "iterations", st["iterations"])
+        S.close()
+
+
+@pytest.mark.parametrize("name,make,leaf,eps,variant", [
+    ("c1_poisson2d_32_lorasp_eps0.2", lambda: pb.poisson(32, 2), 8, 0.2, "lorasp"),
+    ("lognormal2d_48_s2_gc", lambda: pb.lognormal(48, 2, 2.0, 1002), 8, 1e-2, "gc"),
+])
+def test_gmres_matches_oracle(name, make, leaf, eps, variant):
+    say("gmres", name)
+    p = make()
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 2, 2007)
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=eps,
+                 variant=O.GC if variant == "gc" else O.LORASP)
+    ref = [O.gmres(A, b[:, c], lambda r: O.apply(F, r), tol=TOL) for c in range(2)]
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=eps, variant=variant,
+                  krylov="gmres", restart=200)
+    S.factor(dev(p.values))
+    x, st = S.solve(dev(b))
+    x = x.cpu().numpy()
+    x0, _ = S.solve(dev(b[:, 0]))
+    assert np.array_equal(x0.cpu().numpy(), x[:, 0])   # columns are solved independently
+    kappa = np.linalg.cond(p.dense())
+    for c in range(2):
+        true_rel = np.linalg.norm(b[:, c] - A @ x[:, c]) / np.linalg.norm(b[:, c])
+        assert true_rel <= 2 * TOL, (c, true_rel)
+        # both residuals <= 1e-10 bound each error by kappa * 1e-10
+        assert rel(x[:, c], ref[c][0]) <= 4 * kappa * TOL, (c, rel(x[:, c], ref[c][0]))
+    assert abs(st["iterations"] - max(r[1] for r in ref)) <= 1, (st, [r[1] for r in ref])
+    S.close()
+
+
+def test_gmres_restart_and_fp32_apply():
+    """A restart length below the iteration count, and the FP32 solve phase inside GMRES."""
+    say("gmres restart fp32")
+    p = pb.lognormal(48, 2, 2.0, 1002)
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 1, 2009)[:, 0]
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=0.1, variant=O.LORASP)
+    xr, itr, _ = O.gmres(A, b, lambda r: O.apply(F, r), tol=TOL, restart=3)
+    for prec in (64, 32):
+        S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8, eps=0.1, variant="lorasp",
+                      krylov="gmres", restart=3, apply_prec=prec)
+        S.factor(dev(p.values))
+        x, st = S.solve(dev(b))
+        x = x.cpu().numpy()
+        true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+        assert true_rel <= 2 * TOL, (prec, true_rel)
+        if prec == 64:
+            assert abs(st["iterations"] - itr) <= 1, (st, itr)
+        say("gmres restart 3", prec, st["iterations"], itr)
+        S.close()

@@ -426,6 +426,52 @@ def test_gmres_matches_scipy_and_direct():
     assert np.linalg.norm(x - xs) / np.linalg.norm(xd) < 1e-7
 
 
+def test_fpcg_with_identity_is_textbook_cg():
+    """Flexible beta with M = I: plain CG (SciPy) on the SPD Poisson matrix."""
+    p = pb.poisson(16, 2)
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 1, 24)[:, 0]
+    x, it, rel = O.fpcg(A, b, lambda r: r.copy(), tol=1e-10)
+    count = []
+    xs, info = spla.cg(A, b, rtol=1e-10, atol=0.0, callback=lambda xk: count.append(1))
+    assert info == 0 and rel <= 1e-9
+    assert abs(len(count) - it) <= 1
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-8
+
+
+def test_fpcg_with_fixed_preconditioner_matches_scipy_cg():
+    """A fixed SPD M gives r_{k+1}^T z_k = 0, so the flexible beta is the standard one."""
+    p = pb.lognormal(32, 2, 1.0, 21)
+    A = p.to_scipy()
+    F = _factor(p, 8, 0.1, O.GC)
+    b = pb.rhs(p.n, 1, 22)[:, 0]
+    x, it, rel = O.fpcg(A, b, lambda r: O.apply(F, r), tol=1e-10)
+    Mop = spla.LinearOperator(A.shape, matvec=lambda r: O.apply(F, r))
+    count = []
+    xs, info = spla.cg(A, b, rtol=1e-10, atol=0.0, M=Mop, callback=lambda xk: count.append(1))
+    assert info == 0 and rel <= 1e-10
+    assert abs(len(count) - it) <= 1
+    assert np.linalg.norm(x - xs) / np.linalg.norm(xs) < 1e-8
+
+
+def test_fpcg_converges_with_single_precision_preconditioner():
+    """z = M(r) evaluated in float32 (factor blocks and vectors rounded): the flexible
+    iteration still reaches 1e-10, within a few iterations of the exact preconditioner."""
+    p = pb.poisson(32, 2)
+    A = p.to_scipy()
+    F = _factor(p, 8, 1e-2, O.GC)
+    b = pb.rhs(p.n, 1, 25)[:, 0]
+
+    def m32(r):
+        z = O.apply(F, r.astype(np.float32).astype(np.float64))
+        return z.astype(np.float32).astype(np.float64)
+
+    _, it64, _ = O.pcg(A, b, lambda r: O.apply(F, r), tol=1e-10)
+    x, it, rel = O.fpcg(A, b, m32, tol=1e-10)
+    assert rel <= 1e-9
+    assert it <= it64 + 3
+
+
 @pytest.mark.slow
 def test_convergence_trend_gc_flat_lorasp_grows():
     """Tables 1-2 (§7.1): GC iteration counts grow much more slowly with n than LoRaSp's,
