@@ -119,12 +119,56 @@ def serving(count: int, slots: int) -> dict:
             "closed_loop": closed, "open_loop": opened}
 
 
+def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
+    """Other solver settings, each timed as one factor + solve after one warm-up: on the same
+    64^3 system the FP32 solve phase with flexible PCG and FP64 GMRES; the 2-D lognormal 256^2
+    system (sigma 2, leaf 16) in FP64 PCG and with the FP32 solve phase."""
+    A3 = p.to_scipy()
+    b3 = torch.from_numpy(b_host).cuda()
+
+    def run(prob, wl, values, A, bh, bd, xref=None, **kw):
+        S = H.HSolver(prob.row_ptr, prob.col_idx, coords=prob.coords, leaf=wl["leaf"], eps=wl["eps"],
+                      variant="gc", tol=1e-10, **kw)
+        S.factor(values)
+        S.solve(bd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.factor(values)
+        x, st = S.solve(bd)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        xh = x.cpu().numpy()
+        r = {"ms": round(ms, 3), "factor_ms": round(st["t_factor"] * 1e3, 3),
+             "solve_ms": round(st["t_solve"] * 1e3, 3), "iterations": st["iterations"],
+             "true_rel_residual": float(np.linalg.norm(bh - A @ xh) / np.linalg.norm(bh)),
+             "converged": st["converged"]}
+        if xref is not None:
+            r["rel_diff_vs_fp64_pcg"] = float(np.linalg.norm(xh - xref) / np.linalg.norm(xref))
+        S.close()
+        return r, xh
+
+    out = {}
+    out["c3_fp32_solve_fpcg"], _ = run(p, w, vals, A3, b_host, b3, x64, apply_prec=32, krylov="fpcg")
+    out["c3_gmres"], _ = run(p, w, vals, A3, b_host, b3, x64, krylov="gmres")
+    p2, w2 = pb.workload("c2_lognormal2d_256")
+    v2 = torch.from_numpy(p2.values).cuda()
+    b2h = pb.rhs(p2.n, 1, 2002)[:, 0]
+    b2 = torch.from_numpy(b2h).cuda()
+    A2 = p2.to_scipy()
+    out["c2_lognormal2d_256_fp64_pcg"], x2 = run(p2, w2, v2, A2, b2h, b2)
+    out["c2_lognormal2d_256_fp32_solve_fpcg"], _ = run(p2, w2, v2, A2, b2h, b2, x2, apply_prec=32,
+                                                       krylov="fpcg")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the other solver settings (FP32 solve phase, GMRES, 2-D lognormal 256^2)")
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -240,6 +284,8 @@ def main() -> int:
         "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
                     for e in sorted(prof, key=lambda e: -e["ms"])],
     }
+    if not args.no_variants:
+        out["variants"] = variants(H, pb, np, torch, p, w, vals, b_host, xs)
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:

@@ -145,15 +145,26 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
         if (tau != 0.0) {
             double* T22 = H + size_t(j + 1) * ld + (j + 1);
             double pv_part = 0.0;
-            for (int i = tid; i < len; i += NT) {
-                const double acc = tau * dot_rows(T22 + i, ld, S.v, len);
-                S.w[i] = acc;
-                pv_part += acc * S.v[i];
+            // two adjacent lanes per row, each over half of the columns
+            const int hl = len / 2;
+            for (int tb = 0; tb < 2 * len; tb += NT) {       // uniform trip count (the shuffle)
+                const int t = tb + tid;
+                const int i = min(t >> 1, len - 1), c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
+                double acc = (t < 2 * len) ? dot_rows(T22 + i + size_t(c0) * ld, ld, S.v + c0, c1 - c0) : 0.0;
+                acc += __shfl_xor(acc, 1, WAVE);
+                if (t < 2 * len && !(t & 1)) {
+                    acc *= tau;
+                    S.w[i] = acc;
+                    pv_part += acc * S.v[i];
+                }
             }
             const double K = 0.5 * tau * block_sum(pv_part, S.red);
             for (int i = tid; i < len; i += NT) S.w[i] -= K * S.v[i];
             __syncthreads();
-            for (int i = tid; i < len; i += NT) rank2_row(T22 + i, ld, S.v[i], S.w[i], S.v, S.w, len);
+            for (int t = tid; t < 2 * len; t += NT) {
+                const int i = t >> 1, c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
+                rank2_row(T22 + i + size_t(c0) * ld, ld, S.v[i], S.w[i], S.v + c0, S.w + c0, c1 - c0);
+            }
             if (nbr > 0) {
                 double* B1 = Bl + (j + 1);
                 double dots[4] = {0.0, 0.0, 0.0, 0.0};
@@ -182,42 +193,89 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
 // are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
-// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
-// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+// matrix takes the rank-2 nb update once per panel. Only the lower triangle of the trailing
+// matrix is read and updated. LDS: Vl, Wl (TRI_NB x nn, column c at c nn, absolute rows),
+// Pp (4 x nn per-wave row sums of the matrix-vector step) and S.v (its column sums).
 constexpr int TRI_NB = 12;
 
-// One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
-// stride ld, len >= 2). Lane l takes the row pairs (2l + 128k, 2l + 128k + 1), k < KM, loaded
-// as one 16-byte access; SB columns are taken at a time with every load issued before the
-// products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
+// Sum over the wave left in lane 63 only (the DPP steps of wave_sum without the read-back).
+__device__ inline double wave_sum_last(double v) {
+    v += dpp_move<DPP_QUAD_1032>(v, 0.0);
+    v += dpp_move<DPP_QUAD_2301>(v, 0.0);
+    v += dpp_move<DPP_ROR4>(v, 0.0);
+    v += dpp_move<DPP_ROR8>(v, 0.0);
+    v += dpp_move<DPP_BCAST15, 0xA>(v, 0.0);
+    v += dpp_move<DPP_BCAST31, 0xC>(v, 0.0);
+    return v;
+}
+
+// One wave's share of y = A v for a symmetric len x len A of which only the lower triangle
+// (rows >= columns) is read: column l adds A(l.., l) v_l to rows l.. (into acc, per lane) and
+// A(l+1.., l)^T v(l+1..) to row l (a wave sum, written to yt[l] by lane 63). The wave takes
+// the column chunks of SB starting at SB (wv + 4 t); lane l holds the row pairs
+// (2 lane + 128 k, +1), k < KM, loaded as one 16-byte access where any row of the pair is
+// on or below the diagonal; a pair past len - 2 is read as (len - 2, len - 1). len >= 2.
 template <int KM>
-__device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
-                                 int lane, double* acc) {
+__device__ inline void symv_lower(const HS_G double* A, int ld, const double* v, int len, int wv, int lane,
+                                  double (&acc)[KM][2], double* yt) {
     constexpr int SB = (KM <= 2) ? 16 : 8;
+    int rl[KM];                        // first row of the 16-byte load
+    int row[KM][2];                    // row each slot stands for (-1: none)
+    double vr[KM][2];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
-    int rr[KM];
+    for (int k = 0; k < KM; ++k) {
+        const int r0 = 2 * lane + 128 * k;
+        rl[k] = min(r0, len - 2);
+        row[k][0] = (r0 <= len - 2) ? r0 : -1;
+        row[k][1] = (r0 + 1 <= len - 1) ? r0 + 1 : (r0 == len - 1 ? len - 1 : -1);
 #pragma unroll
-    for (int k = 0; k < KM; ++k) rr[k] = min(2 * lane + 128 * k, len - 2);
-    for (int l0 = cb; l0 < ce; l0 += SB) {
+        for (int h = 0; h < 2; ++h) {
+            vr[k][h] = row[k][h] >= 0 ? v[row[k][h]] : 0.0;
+            acc[k][h] = 0.0;
+        }
+    }
+    const int nch = (len + SB - 1) / SB;
+    for (int ch = wv; ch < nch; ch += NT / WAVE) {
+        const int l0 = ch * SB;
         double a[SB][KM][2];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            const HS_G double* cl = A + size_t(min(l0 + u, ce - 1)) * ld;
+            const int l = min(l0 + u, len - 1);
+            const HS_G double* cl = A + size_t(l) * ld;
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                a[u][k][0] = cl[rr[k]];
-                a[u][k][1] = cl[rr[k] + 1];
+                if (row[k][1] >= l) {
+                    a[u][k][0] = cl[rl[k]];
+                    a[u][k][1] = cl[rl[k] + 1];
+                } else {
+                    a[u][k][0] = 0.0;
+                    a[u][k][1] = 0.0;
+                }
             }
         }
+        double t[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            const double vl = (l0 + u < ce) ? v[l0 + u] : 0.0;
+            const int l = l0 + u;
+            const double vl = (l < len) ? v[l] : 0.0;
+            double tu = 0.0;
 #pragma unroll
-            for (int k = 0; k < KM; ++k) {
-                acc[2 * k] += a[u][k][0] * vl;
-                acc[2 * k + 1] += a[u][k][1] * vl;
-            }
+            for (int k = 0; k < KM; ++k)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const int r = row[k][h];
+                    const double x = a[u][k][h];
+                    if (r >= l) acc[k][h] += x * vl;
+                    if (r > l) tu += x * vr[k][h];
+                }
+            t[u] = tu;
+        }
+#pragma unroll
+        for (int u = 0; u < SB; ++u) t[u] = wave_sum_last(t[u]);
+        if (lane == WAVE - 1) {
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (l0 + u < len) yt[l0 + u] = t[u];
         }
     }
 }
@@ -253,8 +311,9 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
 // are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
-// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
-// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+// matrix takes the rank-2 nb update once per panel. Only the lower triangle of the trailing
+// matrix is read and updated. LDS: Vl, Wl (TRI_NB x nn, column c at c nn, absolute rows),
+// Pp (4 x nn per-wave row sums of the matrix-vector step) and S.v (its column sums).
 template <class SH>
 __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double* Bl, int bst, int nbr,
                                    double* Vl, double* Wl, double* Pp, long long* prof = nullptr) {
@@ -314,61 +373,54 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             const double* v = Vl + i * nn + (j + 1);          // trailing coordinates
             double* wcol = Wl + i * nn;
             if (tau != 0.0) {
-                // y = A(j+1:, j+1:) v, columns split over the waves, row pairs over the lanes
+                // t1 = W(j+1:, :i)^T v, t2 = V(j+1:, :i)^T v: wave wv takes products wv, wv + 4, ..
+                for (int g = wv; g < 2 * i; g += NT / WAVE) {
+                    const double* P = (g < i) ? Wl + g * nn + j + 1 : Vl + (g - i) * nn + j + 1;
+                    double a = 0.0;
+                    for (int r = lane; r < len; r += WAVE) a += P[r] * v[r];
+                    a = wave_sum_last(a);
+                    if (lane == WAVE - 1) S.tt[g] = a;
+                }
+                // y = A(j+1:, j+1:) v from the lower triangle: per-wave row sums in Pp, the
+                // transposed column sums in S.v
                 {
                     const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
-                    const int cw = (len + 3) / 4, cbeg = wv * cw, cend = min(len, cbeg + cw);
-                    double acc[8];
-                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
-                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        case 2: symv_part<2>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        case 3: symv_part<3>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        default: symv_part<4>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                    }
+                    auto put = [&](auto& acc) {
+                        constexpr int KM = sizeof(acc) / sizeof(acc[0]);
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int r0 = 2 * lane + 128 * k;
-                        if (r0 < len) {
+                        for (int k = 0; k < KM; ++k) {
+                            const int r0 = 2 * lane + 128 * k;
                             if (r0 <= len - 2) {
-                                Pp[wv * nn + r0] = acc[2 * k];
-                                Pp[wv * nn + r0 + 1] = acc[2 * k + 1];
-                            } else {                        // last row of an odd length
-                                Pp[wv * nn + r0] = acc[2 * k + 1];
+                                Pp[wv * nn + r0] = acc[k][0];
+                                Pp[wv * nn + r0 + 1] = acc[k][1];
+                            } else if (r0 == len - 1) {
+                                Pp[wv * nn + r0] = acc[k][1];
                             }
                         }
+                    };
+                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
+                        case 1: { double acc[1][2]; symv_lower<1>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
+                        case 2: { double acc[2][2]; symv_lower<2>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
+                        case 3: { double acc[3][2]; symv_lower<3>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
+                        default: { double acc[4][2]; symv_lower<4>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
                     }
-                }
-                // t1 = W(j+1:, :i)^T v, t2 = V(j+1:, :i)^T v: eight lanes per product
-                {
-                    const int g = tid / 8, sub = tid % 8;
-                    double a0 = 0.0, a1 = 0.0;
-                    if (g < 2 * i) {
-                        const double* P = (g < i) ? Wl + g * nn + j + 1 : Vl + (g - i) * nn + j + 1;
-                        int r = sub;
-#pragma unroll 4
-                        for (; r + 8 < len; r += 16) {
-                            a0 += P[r] * v[r];
-                            a1 += P[r + 8] * v[r + 8];
-                        }
-                        for (; r < len; r += 8) a0 += P[r] * v[r];
-                    }
-                    double a = a0 + a1;
-                    a += __shfl_xor(a, 1, WAVE);
-                    a += __shfl_xor(a, 2, WAVE);
-                    a += __shfl_xor(a, 4, WAVE);
-                    if (sub == 0 && g < 2 * i) S.tt[g] = a;
                 }
                 __syncthreads();
+                phase(6);
                 phase(2);
                 double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 for (int r = tid; r < len; r += NT) {
-                    double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
+                    double y = ((Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r])) + S.v[r];
 #pragma unroll
                     for (int c = 0; c < TRI_NB - 1; ++c)
                         if (c < i) y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
                     const double w = tau * y;
                     S.w[r] = w;
                     pv[0] += w * v[r];
+                }
+                if (prof) {
+                    __syncthreads();
+                    phase(7);
                 }
                 // v^T w and the border rows' products with v, one reduction
                 double* B1 = nbr ? Bl + (j + 1) : nullptr;
@@ -393,15 +445,17 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             __syncthreads();
             phase(4);
         }
-        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T: 64 x 64 block tiles,
-        // thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w (LDS reads of
-        // consecutive rows by consecutive lanes, no bank conflicts); clamped reads at the edge
+        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T on the 64 x 64 block
+        // tiles on and below the diagonal (the upper triangle is never read again), column of
+        // tiles by column; thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w
+        // (LDS reads of consecutive rows by consecutive lanes, no bank conflicts); clamped reads
+        // at the edge
         {
             const int t0 = j0 + nb, tn = nn - t0, Tb = (tn + 63) / 64;
             const int tx = tid % 16, ty = tid / 16;
-            // tile bt + 1 is loaded before tile bt is computed
-            auto tile_idx = [&](int bt, int* ri, int* si, bool* okr, bool* oks) {
-                const int rb = t0 + 64 * (bt % Tb), sb = t0 + 64 * (bt / Tb);
+            // tile (rk, sk) is loaded before the previous one is computed
+            auto tile_idx = [&](int rk, int sk, int* ri, int* si, bool* okr, bool* oks) {
+                const int rb = t0 + 64 * rk, sb = t0 + 64 * sk;
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     okr[u] = rb + tx + 16 * u < nn;
@@ -413,14 +467,16 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             int ri[4], si[4], rn[4], sn[4];
             bool okr[4], oks[4], okrn[4], oksn[4];
             double nxt[4][4];
+            int rk = 0, sk = 0;                        // next tile
+            const int ntile = Tb * (Tb + 1) / 2;
             if (Tb > 0) {
-                tile_idx(0, rn, sn, okrn, oksn);
+                tile_idx(0, 0, rn, sn, okrn, oksn);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
             }
-            for (int bt = 0; bt < Tb * Tb; ++bt) {
+            for (int bt = 0; bt < ntile; ++bt) {
                 double acc[4][4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -431,8 +487,9 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
 #pragma unroll
                     for (int w = 0; w < 4; ++w) acc[u][w] = nxt[u][w];
                 }
-                if (bt + 1 < Tb * Tb) {
-                    tile_idx(bt + 1, rn, sn, okrn, oksn);
+                if (++rk == Tb) rk = ++sk;
+                if (bt + 1 < ntile) {
+                    tile_idx(rk, sk, rn, sn, okrn, oksn);
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -463,7 +520,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
         phase(5);
     }
     if (prof && tid == 0)
-        for (int k = 0; k < 6; ++k) prof[k] = pc[k];
+        for (int k = 0; k < 8; ++k) prof[k] = pc[k];
     for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
     if (tid == 0) {
         if (nn >= 2) {
@@ -1316,15 +1373,22 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     {
         ProfScope ps("k_comp_bisect", 0.0, s);
         // lanes per eigenvalue from the number of eigenvalues the launch can hold
+        // lanes per eigenvalue: the widest group that keeps the launch within one wave per SIMD
+        // (64 K lanes), so that a launch with few nodes still fills the chip
         const double total = double(max_m) * ntasks;
-        if (total <= 1024.0) {
-            hipLaunchKernelGGL(k_comp_bisect<64>, dim3((max_m + NT / 64 - 1) / (NT / 64), ntasks), dim3(NT), 0,
-                               s, d_tasks);
-        } else if (total <= 8192.0) {
-            hipLaunchKernelGGL(k_comp_bisect<8>, dim3((max_m + NT / 8 - 1) / (NT / 8), ntasks), dim3(NT), 0,
-                               s, d_tasks);
-        } else {
-            hipLaunchKernelGGL(k_comp_bisect<1>, dim3((max_m + NT - 1) / NT, ntasks), dim3(NT), 0, s, d_tasks);
+        int lpe = 64;
+        while (lpe > 1 && total * lpe > 65536.0) lpe /= 2;
+        auto go = [&](auto kern, int l) {
+            hipLaunchKernelGGL(kern, dim3((max_m + NT / l - 1) / (NT / l), ntasks), dim3(NT), 0, s, d_tasks);
+        };
+        switch (lpe) {
+            case 64: go(k_comp_bisect<64>, 64); break;
+            case 32: go(k_comp_bisect<32>, 32); break;
+            case 16: go(k_comp_bisect<16>, 16); break;
+            case 8: go(k_comp_bisect<8>, 8); break;
+            case 4: go(k_comp_bisect<4>, 4); break;
+            case 2: go(k_comp_bisect<2>, 2); break;
+            default: go(k_comp_bisect<1>, 1); break;
         }
         check_launch("k_comp_bisect");
     }

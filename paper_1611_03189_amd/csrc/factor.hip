@@ -602,16 +602,17 @@ void factor(Plan& P, const double* d_values_in) {
                 std::fprintf(stderr, "trace d=%2d c=%2zu nodes=%5zu comp=%5zu max_m=%4d max_wt=%5d max_k=%4d  A=%8.2f ms  B=%8.2f ms",
                              d, c, nodes.size(), comp.size(), mm, mw, mk, tc1 - tc0, now_ms() - tc1);
                 long long ph[7] = {0, 0, 0, 0, 0, 0, 0};
-                long long tp[6] = {0, 0, 0, 0, 0, 0};
+                long long tp[8] = {0, 0, 0, 0, 0, 0, 0, 0};
                 for (size_t q2 = 0; q2 < stamps.size() / 16; ++q2) {
                     for (int k = 0; k < 7; ++k)
                         ph[k] = std::max(ph[k], stamps[16 * q2 + k + 1] - stamps[16 * q2 + k]);
-                    for (int k = 0; k < 6; ++k) tp[k] = std::max(tp[k], stamps[16 * q2 + 8 + k]);
+                    for (int k = 0; k < 8; ++k) tp[k] = std::max(tp[k], stamps[16 * q2 + 8 + k]);
                 }
                 std::fprintf(stderr, "  kcycles load %lld tri0 %lld gcref %lld tri %lld lmax %lld count %lld"
-                             " | tri: col %lld refl %lld symv %lld pv %lld wb %lld trail %lld\n",
+                             " | tri: col %lld refl %lld symv %lld t12 %lld comb %lld red %lld wb %lld trail %lld\n",
                              ph[0] / 1000, ph[1] / 1000, ph[2] / 1000, ph[3] / 1000, ph[4] / 1000, ph[5] / 1000,
-                             tp[0] / 1000, tp[1] / 1000, tp[2] / 1000, tp[3] / 1000, tp[4] / 1000, tp[5] / 1000);
+                             tp[0] / 1000, tp[1] / 1000, tp[6] / 1000, tp[2] / 1000, tp[7] / 1000, tp[3] / 1000,
+                             tp[4] / 1000, tp[5] / 1000);
             }
         }
         // end of level: surface pivot failures of the last colour

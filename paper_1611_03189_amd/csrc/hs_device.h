@@ -31,19 +31,55 @@ inline void check_launch(const char* name) {
         throw Error{HSOLVE_ERR_DEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e)};
 }
 
-__device__ inline double wave_sum(double v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
+// Wave-wide reductions with DPP: two quad permutations and two rotations by 4 and 8 leave
+// every lane with the total of its row of 16; two row broadcasts (lane 15 into rows 1 and 3,
+// lane 31 into rows 2 and 3) gather the four rows in lane 63, which is read back as a
+// uniform value, so every lane returns the same, bitwise identical result.
+template <int CTRL, int ROWS = 0xF>
+__device__ inline double dpp_move(double v, double fill) {
+    const int lo = __builtin_amdgcn_update_dpp(__double2loint(fill), __double2loint(v), CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(__double2hiint(fill), __double2hiint(v), CTRL, ROWS, 0xF, false);
+    return __hiloint2double(hi, lo);
 }
 
-__device__ inline float wave_sum(float v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, WAVE);
-    return v;
+template <int CTRL, int ROWS = 0xF>
+__device__ inline float dpp_move(float v, float fill) {
+    return __int_as_float(
+        __builtin_amdgcn_update_dpp(__float_as_int(fill), __float_as_int(v), CTRL, ROWS, 0xF, false));
+}
+
+__device__ inline double lane63(double v) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), WAVE - 1);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), WAVE - 1);
+    return __hiloint2double(hi, lo);
+}
+
+__device__ inline float lane63(float v) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), WAVE - 1));
+}
+
+constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_ROR4 = 0x124, DPP_ROR8 = 0x128,
+              DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+template <class T>
+__device__ inline T wave_sum(T v) {
+    v += dpp_move<DPP_QUAD_1032>(v, T(0));
+    v += dpp_move<DPP_QUAD_2301>(v, T(0));
+    v += dpp_move<DPP_ROR4>(v, T(0));
+    v += dpp_move<DPP_ROR8>(v, T(0));
+    v += dpp_move<DPP_BCAST15, 0xA>(v, T(0));
+    v += dpp_move<DPP_BCAST31, 0xC>(v, T(0));
+    return lane63(v);
 }
 
 __device__ inline double wave_max(double v) {
-    for (int o = WAVE / 2; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, WAVE));
-    return v;
+    v = fmax(v, dpp_move<DPP_QUAD_1032>(v, v));
+    v = fmax(v, dpp_move<DPP_QUAD_2301>(v, v));
+    v = fmax(v, dpp_move<DPP_ROR4>(v, v));
+    v = fmax(v, dpp_move<DPP_ROR8>(v, v));
+    v = fmax(v, dpp_move<DPP_BCAST15, 0xA>(v, v));
+    v = fmax(v, dpp_move<DPP_BCAST31, 0xC>(v, v));
+    return lane63(v);
 }
 
 // Orders the memory accesses of the lanes of one wave around divergent code (a result that
