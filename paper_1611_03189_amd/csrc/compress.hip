@@ -193,9 +193,8 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
 // are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
-// matrix takes the rank-2 nb update once per panel. Only the lower triangle of the trailing
-// matrix is read and updated. LDS: Vl, Wl (TRI_NB x nn, column c at c nn, absolute rows),
-// Pp (4 x nn per-wave row sums of the matrix-vector step) and S.v (its column sums).
+// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
+// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
 constexpr int TRI_NB = 12;
 
 // Sum over the wave left in lane 63 only (the DPP steps of wave_sum without the read-back).
@@ -209,73 +208,38 @@ __device__ inline double wave_sum_last(double v) {
     return v;
 }
 
-// One wave's share of y = A v for a symmetric len x len A of which only the lower triangle
-// (rows >= columns) is read: column l adds A(l.., l) v_l to rows l.. (into acc, per lane) and
-// A(l+1.., l)^T v(l+1..) to row l (a wave sum, written to yt[l] by lane 63). The wave takes
-// the column chunks of SB starting at SB (wv + 4 t); lane l holds the row pairs
-// (2 lane + 128 k, +1), k < KM, loaded as one 16-byte access where any row of the pair is
-// on or below the diagonal; a pair past len - 2 is read as (len - 2, len - 1). len >= 2.
+// One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
+// stride ld, len >= 2). Lane l takes the row pairs (2l + 128k, 2l + 128k + 1), k < KM, loaded
+// as one 16-byte access; SB columns are taken at a time with every load issued before the
+// products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
 template <int KM>
-__device__ inline void symv_lower(const HS_G double* A, int ld, const double* v, int len, int wv, int lane,
-                                  double (&acc)[KM][2], double* yt) {
+__device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
+                                 int lane, double* acc) {
     constexpr int SB = (KM <= 2) ? 16 : 8;
-    int rl[KM];                        // first row of the 16-byte load
-    int row[KM][2];                    // row each slot stands for (-1: none)
-    double vr[KM][2];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) {
-        const int r0 = 2 * lane + 128 * k;
-        rl[k] = min(r0, len - 2);
-        row[k][0] = (r0 <= len - 2) ? r0 : -1;
-        row[k][1] = (r0 + 1 <= len - 1) ? r0 + 1 : (r0 == len - 1 ? len - 1 : -1);
+    for (int k = 0; k < 8; ++k) acc[k] = 0.0;
+    int rr[KM];
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            vr[k][h] = row[k][h] >= 0 ? v[row[k][h]] : 0.0;
-            acc[k][h] = 0.0;
-        }
-    }
-    const int nch = (len + SB - 1) / SB;
-    for (int ch = wv; ch < nch; ch += NT / WAVE) {
-        const int l0 = ch * SB;
+    for (int k = 0; k < KM; ++k) rr[k] = min(2 * lane + 128 * k, len - 2);
+    for (int l0 = cb; l0 < ce; l0 += SB) {
         double a[SB][KM][2];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            const int l = min(l0 + u, len - 1);
-            const HS_G double* cl = A + size_t(l) * ld;
+            const HS_G double* cl = A + size_t(min(l0 + u, ce - 1)) * ld;
 #pragma unroll
             for (int k = 0; k < KM; ++k) {
-                if (row[k][1] >= l) {
-                    a[u][k][0] = cl[rl[k]];
-                    a[u][k][1] = cl[rl[k] + 1];
-                } else {
-                    a[u][k][0] = 0.0;
-                    a[u][k][1] = 0.0;
-                }
+                a[u][k][0] = cl[rr[k]];
+                a[u][k][1] = cl[rr[k] + 1];
             }
         }
-        double t[SB];
 #pragma unroll
         for (int u = 0; u < SB; ++u) {
-            const int l = l0 + u;
-            const double vl = (l < len) ? v[l] : 0.0;
-            double tu = 0.0;
+            const double vl = (l0 + u < ce) ? v[l0 + u] : 0.0;
 #pragma unroll
-            for (int k = 0; k < KM; ++k)
-#pragma unroll
-                for (int h = 0; h < 2; ++h) {
-                    const int r = row[k][h];
-                    const double x = a[u][k][h];
-                    if (r >= l) acc[k][h] += x * vl;
-                    if (r > l) tu += x * vr[k][h];
-                }
-            t[u] = tu;
-        }
-#pragma unroll
-        for (int u = 0; u < SB; ++u) t[u] = wave_sum_last(t[u]);
-        if (lane == WAVE - 1) {
-#pragma unroll
-            for (int u = 0; u < SB; ++u)
-                if (l0 + u < len) yt[l0 + u] = t[u];
+            for (int k = 0; k < KM; ++k) {
+                acc[2 * k] += a[u][k][0] * vl;
+                acc[2 * k + 1] += a[u][k][1] * vl;
+            }
         }
     }
 }
@@ -311,9 +275,8 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
 // are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
-// matrix takes the rank-2 nb update once per panel. Only the lower triangle of the trailing
-// matrix is read and updated. LDS: Vl, Wl (TRI_NB x nn, column c at c nn, absolute rows),
-// Pp (4 x nn per-wave row sums of the matrix-vector step) and S.v (its column sums).
+// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
+// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
 template <class SH>
 __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double* Bl, int bst, int nbr,
                                    double* Vl, double* Wl, double* Pp, long long* prof = nullptr) {
@@ -381,28 +344,28 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                     a = wave_sum_last(a);
                     if (lane == WAVE - 1) S.tt[g] = a;
                 }
-                // y = A(j+1:, j+1:) v from the lower triangle: per-wave row sums in Pp, the
-                // transposed column sums in S.v
+                // y = A(j+1:, j+1:) v, columns split over the waves, row pairs over the lanes
                 {
                     const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
-                    auto put = [&](auto& acc) {
-                        constexpr int KM = sizeof(acc) / sizeof(acc[0]);
+                    const int cw = (len + 3) / 4, cbeg = wv * cw, cend = min(len, cbeg + cw);
+                    double acc[8];
+                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
+                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        case 2: symv_part<2>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        case 3: symv_part<3>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                        default: symv_part<4>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                    }
 #pragma unroll
-                        for (int k = 0; k < KM; ++k) {
-                            const int r0 = 2 * lane + 128 * k;
+                    for (int k = 0; k < 4; ++k) {
+                        const int r0 = 2 * lane + 128 * k;
+                        if (r0 < len) {
                             if (r0 <= len - 2) {
-                                Pp[wv * nn + r0] = acc[k][0];
-                                Pp[wv * nn + r0 + 1] = acc[k][1];
-                            } else if (r0 == len - 1) {
-                                Pp[wv * nn + r0] = acc[k][1];
+                                Pp[wv * nn + r0] = acc[2 * k];
+                                Pp[wv * nn + r0 + 1] = acc[2 * k + 1];
+                            } else {                        // last row of an odd length
+                                Pp[wv * nn + r0] = acc[2 * k + 1];
                             }
                         }
-                    };
-                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
-                        case 1: { double acc[1][2]; symv_lower<1>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
-                        case 2: { double acc[2][2]; symv_lower<2>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
-                        case 3: { double acc[3][2]; symv_lower<3>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
-                        default: { double acc[4][2]; symv_lower<4>(A0, ld, v, len, wv, lane, acc, S.v); put(acc); break; }
                     }
                 }
                 __syncthreads();
@@ -410,7 +373,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 phase(2);
                 double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 for (int r = tid; r < len; r += NT) {
-                    double y = ((Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r])) + S.v[r];
+                    double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
 #pragma unroll
                     for (int c = 0; c < TRI_NB - 1; ++c)
                         if (c < i) y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
@@ -445,17 +408,15 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             __syncthreads();
             phase(4);
         }
-        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T on the 64 x 64 block
-        // tiles on and below the diagonal (the upper triangle is never read again), column of
-        // tiles by column; thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w
-        // (LDS reads of consecutive rows by consecutive lanes, no bank conflicts); clamped reads
-        // at the edge
+        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T: 64 x 64 block tiles,
+        // thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w (LDS reads of
+        // consecutive rows by consecutive lanes, no bank conflicts); clamped reads at the edge
         {
             const int t0 = j0 + nb, tn = nn - t0, Tb = (tn + 63) / 64;
             const int tx = tid % 16, ty = tid / 16;
-            // tile (rk, sk) is loaded before the previous one is computed
-            auto tile_idx = [&](int rk, int sk, int* ri, int* si, bool* okr, bool* oks) {
-                const int rb = t0 + 64 * rk, sb = t0 + 64 * sk;
+            // tile bt + 1 is loaded before tile bt is computed
+            auto tile_idx = [&](int bt, int* ri, int* si, bool* okr, bool* oks) {
+                const int rb = t0 + 64 * (bt % Tb), sb = t0 + 64 * (bt / Tb);
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     okr[u] = rb + tx + 16 * u < nn;
@@ -467,16 +428,14 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             int ri[4], si[4], rn[4], sn[4];
             bool okr[4], oks[4], okrn[4], oksn[4];
             double nxt[4][4];
-            int rk = 0, sk = 0;                        // next tile
-            const int ntile = Tb * (Tb + 1) / 2;
             if (Tb > 0) {
-                tile_idx(0, 0, rn, sn, okrn, oksn);
+                tile_idx(0, rn, sn, okrn, oksn);
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
 #pragma unroll
                     for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
             }
-            for (int bt = 0; bt < ntile; ++bt) {
+            for (int bt = 0; bt < Tb * Tb; ++bt) {
                 double acc[4][4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -487,9 +446,8 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
 #pragma unroll
                     for (int w = 0; w < 4; ++w) acc[u][w] = nxt[u][w];
                 }
-                if (++rk == Tb) rk = ++sk;
-                if (bt + 1 < ntile) {
-                    tile_idx(rk, sk, rn, sn, okrn, oksn);
+                if (bt + 1 < Tb * Tb) {
+                    tile_idx(bt + 1, rn, sn, okrn, oksn);
 #pragma unroll
                     for (int u = 0; u < 4; ++u)
 #pragma unroll
@@ -846,16 +804,24 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
     };
     stamp(0);
-    double gm = 0.0;
-    for (int e = tid; e < m * m; e += NT) gm = fmax(gm, fabs(G[e]));
-    const double gmax = block_max(gm, S.red);
+    double gm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    {
+        int e = tid;
+        for (; e + 7 * NT < m * m; e += 8 * NT) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) gm[u] = fmax(gm[u], fabs(G[e + u * NT]));
+        }
+        for (; e < m * m; e += NT) gm[0] = fmax(gm[0], fabs(G[e]));
+    }
+    const double gmax = block_max(fmax(fmax(fmax(gm[0], gm[1]), fmax(gm[2], gm[3])),
+                                       fmax(fmax(gm[4], gm[5]), fmax(gm[6], gm[7]))), S.red);
     const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
     double fro = 0.0;
-    for (int e = tid; e < m * m; e += NT) {
-        const double g = G[e] * gscale;
-        H[(e % m) + (e / m) * ld] = g;
+    copy_block(H, ld, G, m, m, m, [&](double x, int, int) {
+        const double g = x * gscale;
         fro += g * g;
-    }
+        return g;
+    });
     fro = sqrt(block_sum(fro, S.red));
     stamp(1);
     // GC with at most 4 kept vectors: lambda_max(G) comes from the bordered tridiagonal form
@@ -900,7 +866,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         }
         // reflectors H_t with (H_{q-1}..H_0) U1 = [R; 0]; project G on the complement of U1
         if (!bordered)
-            for (int e = tid; e < m * m; e += NT) H[(e % m) + (e / m) * ld] = G[e] * gscale;
+            copy_block(H, ld, G, m, m, m, [&](double x, int, int) { return x * gscale; });
         __syncthreads();
         double* x = S.v;        // free until the next tridiagonalisation
         for (int t = 0; t < q; ++t) {

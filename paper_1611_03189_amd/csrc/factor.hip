@@ -70,9 +70,13 @@ struct Batch {
     void flush_copies(Plan& P) {
         if (copies.empty()) return;
         double bytes = 0.0;
-        for (const CopyTask& c : copies) bytes += 16.0 * c.rows * c.cols;
+        int max_cols = 0;
+        for (const CopyTask& c : copies) {
+            bytes += 16.0 * c.rows * c.cols;
+            max_cols = std::max(max_cols, c.cols);
+        }
         CopyTask* d = P.stage.upload_vec(copies, P.spool, P.stream);
-        launch_copy(d, int(copies.size()), bytes, P.stream);
+        launch_copy(d, int(copies.size()), max_cols, bytes, P.stream);
         copies.clear();
     }
     void flush_gemm(Plan& P) {

@@ -82,6 +82,47 @@ __device__ inline double wave_max(double v) {
     return lane63(v);
 }
 
+// dst(i, c) = f(src(i, c), i, c) over a rows x cols column-major block by the whole
+// workgroup: consecutive threads take consecutive elements (coalesced), and each thread
+// issues eight loads before its stores, so the copy is not bound by one load's latency.
+template <class PD, class PS, class F>
+__device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int rows, int cols, F f) {
+    const int total = rows * cols;
+    if (total <= 0) return;
+    const int dq = NT / rows, dr = NT % rows;
+    int e = threadIdx.x, i = e % rows, c = e / rows;
+    auto step = [&]() {
+        i += dr;
+        c += dq;
+        if (i >= rows) {
+            i -= rows;
+            ++c;
+        }
+    };
+    for (; e + 7 * NT < total; e += 8 * NT) {
+        int ii[8], cc[8];
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            ii[u] = i;
+            cc[u] = c;
+            v[u] = src[i + size_t(c) * lds];
+            step();
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) dst[ii[u] + size_t(cc[u]) * ldd] = f(v[u], ii[u], cc[u]);
+    }
+    for (; e < total; e += NT) {
+        dst[i + size_t(c) * ldd] = f(src[i + size_t(c) * lds], i, c);
+        step();
+    }
+}
+
+template <class PD, class PS>
+__device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int rows, int cols) {
+    copy_block(dst, ldd, src, lds, rows, cols, [](double x, int, int) { return x; });
+}
+
 // Orders the memory accesses of the lanes of one wave around divergent code (a result that
 // one lane wrote to LDS is read by the others afterwards).
 __device__ inline void wave_sync() {

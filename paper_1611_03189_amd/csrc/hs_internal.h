@@ -319,7 +319,7 @@ void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, doub
 void spmv(Plan& P, const double* x, double* y);
 
 // kernels.hip: launch wrappers (all asynchronous on stream s)
-void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t s);
+void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s);
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
                  int ntiles, double flops, hipStream_t s);
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,

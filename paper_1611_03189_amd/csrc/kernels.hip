@@ -14,38 +14,42 @@ namespace hs {
 // ---------------------------------------------------------------------------------
 // Copies
 // ---------------------------------------------------------------------------------
+// One workgroup per COPY_COLS columns of the destination of one task (blockIdx.y), so that
+// large blocks spread over many CUs.
+constexpr int COPY_COLS = 32;
+
 __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
     const CopyTask t = tasks[blockIdx.x];
+    const int j0 = blockIdx.y * COPY_COLS;
+    if (j0 >= t.cols) return;
+    const int nc = min(COPY_COLS, t.cols - j0);
     const HS_G double* src = gp(t.src);
     HS_G double* dst = gp(t.dst);
     __shared__ double tile[32][33];
     if (!t.trans) {
-        for (int j = 0; j < t.cols; ++j)
-            for (int i = threadIdx.x; i < t.rows; i += NT)
-                dst[i + size_t(j) * t.ldd] = src[i + size_t(j) * t.lds];
+        copy_block(dst + size_t(j0) * t.ldd, t.ldd, src + size_t(j0) * t.lds, t.lds, t.rows, nc);
         return;
     }
-    // dst(i,j) = src(j,i), through 32x32 tiles
+    // dst(i, j) = src(j, i) for the columns j0 .. j0 + nc of dst, through 32 x 32 tiles
     const int tx = threadIdx.x % 32, ty = threadIdx.x / 32;   // 32 x 8
-    for (int i0 = 0; i0 < t.rows; i0 += 32)
-        for (int j0 = 0; j0 < t.cols; j0 += 32) {
-            for (int r = ty; r < 32; r += 8) {           // read src rows j0+r? src is cols x rows
-                int si = j0 + tx, sj = i0 + r;               // src(si, sj)
-                if (si < t.cols && sj < t.rows) tile[r][tx] = src[si + size_t(sj) * t.lds];
-            }
-            __syncthreads();
-            for (int r = ty; r < 32; r += 8) {
-                int di = i0 + tx, dj = j0 + r;               // dst(di, dj) = src(dj, di)
-                if (di < t.rows && dj < t.cols) dst[di + size_t(dj) * t.ldd] = tile[tx][r];
-            }
-            __syncthreads();
+    for (int i0 = 0; i0 < t.rows; i0 += 32) {
+        for (int r = ty; r < 32; r += 8) {
+            const int si = j0 + tx, sj = i0 + r;               // src(si, sj), si < cols, sj < rows
+            if (tx < nc && sj < t.rows) tile[r][tx] = src[si + size_t(sj) * t.lds];
         }
+        __syncthreads();
+        for (int r = ty; r < 32; r += 8) {
+            const int di = i0 + tx, dj = j0 + r;               // dst(di, dj) = src(dj, di)
+            if (di < t.rows && r < nc) dst[di + size_t(dj) * t.ldd] = tile[tx][r];
+        }
+        __syncthreads();
+    }
 }
 
-void launch_copy(const CopyTask* d_tasks, int ntasks, double bytes, hipStream_t s) {
-    if (ntasks <= 0) return;
+void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s) {
+    if (ntasks <= 0 || max_cols <= 0) return;
     ProfScope ps("k_copy", bytes, s);
-    hipLaunchKernelGGL(k_copy, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+    hipLaunchKernelGGL(k_copy, dim3(ntasks, (max_cols + COPY_COLS - 1) / COPY_COLS), dim3(NT), 0, s, d_tasks);
     check_launch("k_copy");
 }
 

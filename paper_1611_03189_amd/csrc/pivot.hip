@@ -30,10 +30,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     const int ldw = m + 1;
     const HS_G double* A = gp(T.A);
     HS_G double* Ainv = gp(T.Ainv);
-    for (int e = tid; e < m * m; e += NT) {
-        const int i = e % m, j = e / m;
-        W[i + j * ldw] = A[i + size_t(j) * T.lda];
-    }
+    copy_block(W, ldw, A, T.lda, m, m);
     if (tid == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < m; ++j) {
@@ -191,10 +188,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     };
     stamp(0);
     const size_t ld = size_t(m);
-    for (size_t e = tid; e < ld * m; e += NT) {
-        const size_t i = e % ld, j = e / ld;
-        W[e] = A[i + j * T.lda];
-    }
+    copy_block(W, ld, A, T.lda, m, m);
     if (tid == 0) bad = 0;
     __syncthreads();
     stamp(1);
@@ -203,10 +197,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     for (int jb = 0; jb < m; jb += PIV_NB) {
         const int nb = min(PIV_NB, m - jb);
         const int r = m - jb;                        // panel rows (diagonal block first)
-        for (int e = tid; e < r * nb; e += NT) {
-            const int i = e % r, c = e / r;
-            Pn[i + c * r] = W[(jb + i) + (jb + c) * ld];
-        }
+        copy_block(Pn, r, W + jb + jb * ld, ld, r, nb);
         __syncthreads();
         // L11 and its inverse by the whole workgroup
         block_potrf_trinv32(Pn, r, nb, X11, &bad);
@@ -308,10 +299,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             const int i = e % PIV_NB, c = e / PIV_NB;
             X11[i + c * l11] = (i < nb && c < nb && i >= c) ? W[(jb + i) + (jb + c) * ld] : 0.0;
         }
-        for (int e = tid; e < t * nb; e += NT) {
-            const int i = e % t, c = e / t;
-            Pn[i + c * t] = W[(jb + nb + i) + (jb + c) * ld];
-        }
+        copy_block(Pn, t, W + (jb + nb) + jb * ld, ld, t, nb);
         __syncthreads();
         rows_times_x11<false>(Pn, t, 0, t, nb, X11);     // Y = L21 X11
         __syncthreads();
