@@ -408,70 +408,91 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             __syncthreads();
             phase(4);
         }
-        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T: 64 x 64 block tiles,
-        // thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w (LDS reads of
-        // consecutive rows by consecutive lanes, no bank conflicts); clamped reads at the edge
+        // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T on the FP64 matrix
+        // cores: 64 x 64 tiles, wave wv takes the 32 x 32 quarter (rows 32 (wv % 2), columns
+        // 32 (wv / 2)) as 2 x 2 blocks of v_mfma_f64_16x16x4f64 with K = 2 nb (V and W side by
+        // side, padded to a multiple of 4). The product is formed transposed (operand A runs
+        // over the tile's columns, operand B over its rows), so that lane l's accumulator
+        // register t is C(l % 16, l / 16 + 4 t) of its block: 16 consecutive rows per column.
+        // The next tile's entries are loaded before the current tile is multiplied; rows and
+        // columns past nn are read clamped and never stored.
         {
             const int t0 = j0 + nb, tn = nn - t0, Tb = (tn + 63) / 64;
-            const int tx = tid % 16, ty = tid / 16;
-            // tile bt + 1 is loaded before tile bt is computed
-            auto tile_idx = [&](int bt, int* ri, int* si, bool* okr, bool* oks) {
-                const int rb = t0 + 64 * (bt % Tb), sb = t0 + 64 * (bt / Tb);
+            const int qr = 32 * (wv % 2), qc = 32 * (wv / 2);
+            const int li = lane % 16, lk = lane / 16;
+            const int ksteps = (2 * nb + 3) / 4;
+            int rr[2], cc[2][4];
+            dbl4 nxt[2][2];
+            auto tile_pos = [&](int bt) {
+                const int rb = t0 + 64 * (bt % Tb) + qr, sb = t0 + 64 * (bt / Tb) + qc;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    okr[u] = rb + tx + 16 * u < nn;
-                    oks[u] = sb + ty + 16 * u < nn;
-                    ri[u] = min(rb + tx + 16 * u, nn - 1);
-                    si[u] = min(sb + ty + 16 * u, nn - 1);
-                }
+                for (int bi = 0; bi < 2; ++bi) rr[bi] = rb + 16 * bi + li;
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) cc[bj][t] = sb + 16 * bj + lk + 4 * t;
             };
-            int ri[4], si[4], rn[4], sn[4];
-            bool okr[4], oks[4], okrn[4], oksn[4];
-            double nxt[4][4];
+            auto load_tile = [&]() {
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            nxt[bi][bj][t] = H[min(rr[bi], nn - 1) + size_t(min(cc[bj][t], nn - 1)) * ld];
+            };
             if (Tb > 0) {
-                tile_idx(0, rn, sn, okrn, oksn);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
+                tile_pos(0);
+                load_tile();
             }
             for (int bt = 0; bt < Tb * Tb; ++bt) {
-                double acc[4][4];
+                dbl4 acc[2][2];
+                int r_cur[2], c_cur[2][4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    ri[u] = rn[u];
-                    si[u] = sn[u];
-                    okr[u] = okrn[u];
-                    oks[u] = oksn[u];
+                for (int bi = 0; bi < 2; ++bi) {
+                    r_cur[bi] = rr[bi];
 #pragma unroll
-                    for (int w = 0; w < 4; ++w) acc[u][w] = nxt[u][w];
+                    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = nxt[bi][bj];
                 }
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) c_cur[bj][t] = cc[bj][t];
+                // operand columns and rows of this lane: s (tile column) for A, r (tile row) for B
+                int sa[2], rbq[2];
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) sa[bj] = min(c_cur[bj][0] - lk + li, nn - 1);
+#pragma unroll
+                for (int bi = 0; bi < 2; ++bi) rbq[bi] = min(r_cur[bi], nn - 1);
                 if (bt + 1 < Tb * Tb) {
-                    tile_idx(bt + 1, rn, sn, okrn, oksn);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int w = 0; w < 4; ++w) nxt[u][w] = H[rn[u] + size_t(sn[w]) * ld];
+                    tile_pos(bt + 1);
+                    load_tile();
                 }
-                for (int c = 0; c < nb; ++c) {
-                    double vr[4], wr[4], vs[4], ws[4];
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    const int kk = 4 * ks + lk;           // this lane's K index
+                    const bool kv = kk < 2 * nb;
+                    const int c = kv ? (kk < nb ? kk : kk - nb) : 0;
+                    const double* Ps = (kk < nb) ? Wl : Vl;   // B panel: [W, V] over tile columns
+                    const double* Pr = (kk < nb) ? Vl : Wl;   // A panel: [V, W] over tile rows
+                    double a[2], b[2];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        vr[u] = Vl[c * nn + ri[u]];
-                        wr[u] = Wl[c * nn + ri[u]];
-                        vs[u] = Vl[c * nn + si[u]];
-                        ws[u] = Wl[c * nn + si[u]];
-                    }
+                    for (int bj = 0; bj < 2; ++bj) a[bj] = kv ? -Ps[c * nn + sa[bj]] : 0.0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int bi = 0; bi < 2; ++bi) b[bi] = kv ? Pr[c * nn + rbq[bi]] : 0.0;
 #pragma unroll
-                        for (int w = 0; w < 4; ++w) acc[u][w] -= vr[u] * ws[w] + wr[u] * vs[w];
+                    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                        for (int bj = 0; bj < 2; ++bj)
+                            acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bj], b[bi], acc[bi][bj], 0, 0, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-                    for (int w = 0; w < 4; ++w)
-                        if (okr[u] && oks[w]) H[ri[u] + size_t(si[w]) * ld] = acc[u][w];
+                    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                        for (int t = 0; t < 4; ++t)
+                            if (r_cur[bi] < nn && c_cur[bj][t] < nn)
+                                H[r_cur[bi] + size_t(c_cur[bj][t]) * ld] = acc[bi][bj][t];
             }
         }
         __syncthreads();

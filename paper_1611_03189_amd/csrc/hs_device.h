@@ -31,6 +31,9 @@ inline void check_launch(const char* name) {
         throw Error{HSOLVE_ERR_DEVICE, std::string("launch of ") + name + ": " + hipGetErrorString(e)};
 }
 
+// operand / accumulator type of v_mfma_f64_16x16x4f64
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
 // Wave-wide reductions with DPP: two quad permutations and two rotations by 4 and 8 leave
 // every lane with the total of its row of 16; two row broadcasts (lane 15 into rows 1 and 3,
 // lane 31 into rows 2 and 3) gather the four rows in lane 63, which is read back as a

@@ -8,8 +8,8 @@
 //                A^{-1} = X^T X written to both triangles.
 // k_chol_inv_blk larger blocks (up to PIV_MAX rows) in a global work matrix, blocked by
 //                PIV_NB columns: the current panel is factored in LDS, the trailing
-//                matrix is updated with 4x4 register tiles; the inverse is blocked the
-//                same way (X21 = -X22 L21 X11, right to left). X = L^{-1} is left in the
+//                matrix is updated on the FP64 matrix cores; the inverse is blocked the
+//                same way (X21 = -X22 L21 X11, right to left, also on the matrix cores). X = L^{-1} is left in the
 //                work matrix (upper triangle zeroed) for the product A^{-1} = X^T X, which
 //                the caller forms with the grouped GEMM over many workgroups.
 #include "hs_device.h"
@@ -210,14 +210,24 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             const int i = e % r, c = e / r;
             W[(jb + i) + (jb + c) * ld] = (i < nb) ? X11[i + c * l11] : Pn[i + c * r];
         }
-        // trailing update W22 -= L21 L21^T, L21 = Pn(nb.., :): 64 x 64 block tiles on and below
-        // the diagonal, thread (tx, ty) of 16 x 16 takes rows tx + 16u and columns ty + 16w;
-        // the next tile is loaded before the current one is computed
+        // trailing update W22 -= L21 L21^T, L21 = Pn(nb.., :), on the FP64 matrix cores: the
+        // 64 x 64 tiles on and below the diagonal (column of tiles by column), wave wv takes
+        // the 32 x 32 quarter (rows 32 (wv % 2), columns 32 (wv / 2)) as 2 x 2 blocks of
+        // v_mfma_f64_16x16x4f64 over K = nb. The product is formed transposed (operand A over
+        // the tile's columns, B over its rows) so that lane l's accumulator register u is
+        // W22(l % 16, l / 16 + 4 u) of its block. The next tile is loaded before the current
+        // one is multiplied; rows and columns past the matrix are read clamped, never stored.
         {
             const int t = r - nb;
             const int Tb = (t + 63) / 64, ntile = Tb * (Tb + 1) / 2;
-            const int tx = tid % 16, ty = tid / 16;
-            auto tile_rc = [&](int bt, int* pr, int* pc, bool* okr, bool* okc) {
+            const int lane = tid % WAVE, wv = tid / WAVE;
+            const int li = lane % 16, lk = lane / 16;
+            const int qr = 32 * (wv % 2), qc = 32 * (wv / 2);
+            const int ksteps = (nb + 3) / 4;
+            HS_G double* W22 = W + (jb + nb) + (jb + nb) * ld;
+            int rr[2], cc[2][4];
+            dbl4 nxt[2][2];
+            auto tile_pos = [&](int bt) {
                 int bj = 0, rem = bt;                 // column-major order of the lower tiles
                 while (rem >= Tb - bj) {
                     rem -= Tb - bj;
@@ -225,60 +235,69 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                 }
                 const int bi = bj + rem;
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const int ii = 64 * bi + tx + 16 * u, jj = 64 * bj + ty + 16 * u;
-                    okr[u] = ii < t;
-                    okc[u] = jj < t;
-                    pr[u] = nb + min(ii, t - 1);      // panel rows (clamped)
-                    pc[u] = nb + min(jj, t - 1);
-                }
+                for (int x = 0; x < 2; ++x) rr[x] = 64 * bi + qr + 16 * x + li;
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) cc[y][u] = 64 * bj + qc + 16 * y + lk + 4 * u;
             };
-            int pr[4], pc[4], prn[4], pcn[4];
-            bool okr[4], okc[4], okrn[4], okcn[4];
-            double nxt[4][4];
+            auto load_tile = [&]() {
+#pragma unroll
+                for (int x = 0; x < 2; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            nxt[x][y][u] = W22[min(rr[x], t - 1) + size_t(min(cc[y][u], t - 1)) * ld];
+            };
             if (ntile > 0) {
-                tile_rc(0, prn, pcn, okrn, okcn);
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v) nxt[u][v] = W[(jb + prn[u]) + (jb + pcn[v]) * ld];
+                tile_pos(0);
+                load_tile();
             }
             for (int bt = 0; bt < ntile; ++bt) {
-                double acc[4][4];
+                dbl4 acc[2][2];
+                int r_cur[2], c_cur[2][4];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    pr[u] = prn[u];
-                    pc[u] = pcn[u];
-                    okr[u] = okrn[u];
-                    okc[u] = okcn[u];
+                for (int x = 0; x < 2; ++x) {
+                    r_cur[x] = rr[x];
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) acc[u][v] = nxt[u][v];
+                    for (int y = 0; y < 2; ++y) acc[x][y] = nxt[x][y];
                 }
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) c_cur[y][u] = cc[y][u];
+                int sa[2], rb[2];                       // panel rows of this lane's operands
+#pragma unroll
+                for (int y = 0; y < 2; ++y) sa[y] = nb + min(c_cur[y][0] - lk + li, t - 1);
+#pragma unroll
+                for (int x = 0; x < 2; ++x) rb[x] = nb + min(r_cur[x], t - 1);
                 if (bt + 1 < ntile) {
-                    tile_rc(bt + 1, prn, pcn, okrn, okcn);
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) nxt[u][v] = W[(jb + prn[u]) + (jb + pcn[v]) * ld];
+                    tile_pos(bt + 1);
+                    load_tile();
                 }
-#pragma unroll 2
-                for (int k = 0; k < nb; ++k) {
-                    double a[4], b[4];
+                for (int ks = 0; ks < ksteps; ++ks) {
+                    const int k = 4 * ks + lk;
+                    const bool kv = k < nb;
+                    const int kc = kv ? k : 0;
+                    double a[2], b[2];
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) {
-                        a[u] = Pn[pr[u] + k * r];
-                        b[u] = Pn[pc[u] + k * r];
-                    }
+                    for (int y = 0; y < 2; ++y) a[y] = kv ? -Pn[sa[y] + kc * r] : 0.0;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u)
+                    for (int x = 0; x < 2; ++x) b[x] = kv ? Pn[rb[x] + kc * r] : 0.0;
 #pragma unroll
-                        for (int v = 0; v < 4; ++v) acc[u][v] -= a[u] * b[v];
+                    for (int x = 0; x < 2; ++x)
+#pragma unroll
+                        for (int y = 0; y < 2; ++y)
+                            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[y], b[x], acc[x][y], 0, 0, 0);
                 }
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int x = 0; x < 2; ++x)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        if (okr[u] && okc[v]) W[(jb + pr[u]) + (jb + pc[v]) * ld] = acc[u][v];
+                    for (int y = 0; y < 2; ++y)
+#pragma unroll
+                        for (int u = 0; u < 4; ++u)
+                            if (r_cur[x] < t && c_cur[y][u] < t) W22[r_cur[x] + size_t(c_cur[y][u]) * ld] = acc[x][y][u];
             }
         }
         __syncthreads();
@@ -303,84 +322,55 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
         __syncthreads();
         rows_times_x11<false>(Pn, t, 0, t, nb, X11);     // Y = L21 X11
         __syncthreads();
-        // X21 = -X22 Y, X22 = the lower-triangular inverse already in W; tiles of 4 rows x 8 cols
-        const int Tr = (t + 3) / 4, Tc = (nb + 7) / 8;
-        for (int idx = tid; idx < Tr * Tc; idx += NT) {
-            const int i0 = 4 * (idx % Tr), c0 = 8 * (idx / Tr);
-            double acc[4][8];
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 8; ++v) acc[u][v] = 0.0;
+        // X21 = -X22 Y on the FP64 matrix cores, X22 = the lower-triangular inverse already in W
+        // (its stale upper part is masked): 64-row blocks of X21, wave wv takes rows 16 wv ..
+        // 16 wv + 15 of the block and the nb <= 32 columns as two 16 x 16 blocks; K runs over
+        // the columns l of X22 up to the block's last row. Formed transposed (operand A over
+        // the columns of Y, B over the rows of X22) so that lane l's register u is
+        // X21(l % 16, l / 16 + 4 u) of its block. Four K steps are loaded ahead.
+        {
+            const int lane = tid % WAVE, wv = tid / WAVE;
+            const int li = lane % 16, lk = lane / 16;
             const HS_G double* X22 = W + (jb + nb) + (jb + nb) * ld;
-            // columns l <= i0: every row of the tile takes part. Rows past t and columns
-            // past nb read clamped (in-bounds) entries; their sums are never stored.
-            int xr[4], yc[8];
+            for (int i0 = 0; i0 < t; i0 += 64) {
+                const int i = i0 + 16 * wv + li;             // this lane's row (operand B)
+                const int ic = min(i, t - 1);
+                const int kend = min(i0 + 64, t);
+                const int nks = (kend + 3) / 4;
+                dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
+                auto ldb = [&](int ks) {
+                    const int l = 4 * ks + lk;
+                    return (l < kend && l <= i && i < t) ? X22[ic + size_t(min(l, t - 1)) * ld] : 0.0;
+                };
+                double bq[4];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) xr[u] = min(i0 + u, t - 1);
+                for (int q = 0; q < 4; ++q) bq[q] = ldb(q);
+                for (int ks0 = 0; ks0 < nks; ks0 += 4) {
+                    double bc[4];
 #pragma unroll
-            for (int v = 0; v < 8; ++v) yc[v] = min(c0 + v, nb - 1) * t;
-            const int lend = min(i0, t - 1);
-            int l = 0;
-            if (l + 3 <= lend) {
-                double xn[4][4];                    // next batch of columns, loaded ahead
+                    for (int q = 0; q < 4; ++q) bc[q] = bq[q];
 #pragma unroll
-                for (int q = 0; q < 4; ++q)
+                    for (int q = 0; q < 4; ++q) bq[q] = ldb(ks0 + 4 + q);
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) xn[q][u] = X22[xr[u] + size_t(l + q) * ld];
-                for (; l + 3 <= lend; l += 4) {
-                    double x[4][4], y[4][8];
+                    for (int q = 0; q < 4; ++q) {
+                        const int l = 4 * (ks0 + q) + lk;
+                        const int lc = min(l, t - 1);
 #pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u) x[q][u] = xn[q][u];
-                    if (l + 7 <= lend) {
-#pragma unroll
-                        for (int q = 0; q < 4; ++q)
-#pragma unroll
-                            for (int u = 0; u < 4; ++u) xn[q][u] = X22[xr[u] + size_t(l + 4 + q) * ld];
+                        for (int y = 0; y < 2; ++y) {
+                            const int c = 16 * y + li;
+                            const double av = (l < kend && c < nb) ? Pn[lc + min(c, nb - 1) * t] : 0.0;
+                            acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bc[q], acc[y], 0, 0, 0);
+                        }
                     }
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int v = 0; v < 8; ++v) y[q][v] = Pn[l + q + yc[v]];
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-#pragma unroll
-                        for (int u = 0; u < 4; ++u)
-#pragma unroll
-                            for (int v = 0; v < 8; ++v) acc[u][v] += x[q][u] * y[q][v];
                 }
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+#pragma unroll
+                    for (int u = 0; u < 4; ++u) {
+                        const int c = 16 * y + lk + 4 * u;
+                        if (i < t && c < nb) W[(jb + nb + i) + (jb + c) * ld] = -acc[y][u];
+                    }
             }
-            for (; l <= lend; ++l) {
-                double x[4], y[8];
-#pragma unroll
-                for (int u = 0; u < 4; ++u) x[u] = X22[xr[u] + size_t(l) * ld];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) y[v] = Pn[l + yc[v]];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
-            }
-            // columns i0 < l <= i0 + 3: only rows u with l <= i0 + u
-            for (int l2 = i0 + 1; l2 <= i0 + 3 && l2 < t; ++l2) {
-                double x[4], y[8];
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    x[u] = (i0 + u < t && l2 <= i0 + u) ? X22[(i0 + u) + size_t(l2) * ld] : 0.0;
-#pragma unroll
-                for (int v = 0; v < 8; ++v) y[v] = (c0 + v < nb) ? Pn[l2 + (c0 + v) * t] : 0.0;
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-#pragma unroll
-                    for (int v = 0; v < 8; ++v) acc[u][v] += x[u] * y[v];
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u)
-#pragma unroll
-                for (int v = 0; v < 8; ++v)
-                    if (i0 + u < t && c0 + v < nb) W[(jb + nb + i0 + u) + (jb + c0 + v) * ld] = -acc[u][v];
         }
         __syncthreads();
     }
