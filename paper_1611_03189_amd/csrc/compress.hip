@@ -1020,11 +1020,12 @@ __device__ __forceinline__ void sturm_counts(const double* d, const double* e, i
 // lanes per eigenvalue, each lane evaluating BIS_NX points per round (BIS_NX LPE points in
 // all), until the bracket is narrower than 2 eps ||T|| (the accuracy of the counts). Wide
 // groups finish in few rounds (latency) for few nodes; narrow groups do less total work
-// (throughput) when a launch holds many nodes.
-constexpr int BIS_NX = 4;
-
+// (throughput) when a launch holds many nodes. A lane's BIS_NX recurrences are interleaved:
+// several hide the latency of one division chain when the groups are narrow, while wide
+// groups take one point per lane (the lanes already give many points per round).
 template <int LPE>
 __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
+    constexpr int BIS_NX = LPE >= 16 ? 1 : (LPE >= 4 ? 2 : 4);
     __shared__ double d[CMP_MAX], e[CMP_MAX];
     const CompressTask T = tasks[blockIdx.y];
     CmpWork Wk(T.work, T.m);
