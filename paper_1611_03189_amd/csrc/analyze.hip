@@ -22,6 +22,8 @@
 #include <algorithm>
 #include <numeric>
 
+#include <string>
+
 #include "hs_internal.h"
 
 namespace hs {
@@ -126,6 +128,14 @@ void analyze(Plan& P) {
     P.L = depth_for(n, std::max(1, P.opt.leaf_size));
     bisect(P);
     const int L = P.L;
+    // the first super nodes are sibling pairs of leaves (the whole matrix when L = 0); larger
+    // ones appear later only when ranks grow, which the factorization checks
+    for (int s = 0; s < (L > 0 ? (1 << (L - 1)) : 1); ++s) {
+        const int m = (L > 0) ? P.leaf_off[2 * s + 2] - P.leaf_off[2 * s] : n;
+        if (m > MAX_SUPER)
+            throw Error{HSOLVE_ERR_INVALID, "leaf pairs larger than " + std::to_string(MAX_SUPER) +
+                                                " unknowns (reduce leaf_size)"};
+    }
 
     // leaf of every unknown, and the unique leaf-level block pairs
     std::vector<int> leaf_of(n);

@@ -357,6 +357,7 @@ void launch_demote(const DemoteTask* d_tasks, int ntasks, double elems, hipStrea
 void launch_spmv(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                  const double* x, double* y, int n, int64_t nnz, hipStream_t s);
 constexpr int DOTM_BLOCKS = 512;   // partial sums per column of a batched dot product
+constexpr int MAX_SUPER = 512;     // largest super node the compression and pivot kernels take
 void launch_spmv_multi(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                        const double* X, int64_t ldx, double* Y, int64_t ldy, int n, int nrhs,
                        int64_t nnz, hipStream_t s);

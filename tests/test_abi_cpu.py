@@ -86,6 +86,12 @@ def test_analyze_rejects_bad_input(lib):
     bad[-1] = p.n + 5
     with pytest.raises(H.HSolveError):
         H.HSolver(p.row_ptr, bad, coords=p.coords)
+    # first super nodes (pairs of leaves) above the 512 the kernels take: rejected by the analysis
+    big = pb.poisson(16, 3)
+    with pytest.raises(H.HSolveError) as e:
+        H.HSolver(big.row_ptr, big.col_idx, coords=big.coords, leaf=600)
+    assert e.value.status == -1
+    H.HSolver(big.row_ptr, big.col_idx, coords=big.coords, leaf=256).close()   # pairs of 512
     for kw in ({"apply_prec": 16}, {"krylov": 3}, {"krylov": "gmres", "restart": 0}):
         with pytest.raises(H.HSolveError) as e:
             H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
