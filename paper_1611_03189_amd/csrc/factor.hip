@@ -80,7 +80,15 @@ struct Batch {
         launch_copy(d, int(copies.size()), max_cols, bytes, P.stream);
         copies.clear();
     }
-    void flush_gemm(Plan& P) {
+    // The tables always travel on the plan's stream; with side set, the launch goes to the
+    // side stream once it has waited for them.
+    static hipStream_t to_side(Plan& P, bool side) {
+        if (!side) return P.stream;
+        HS_HIP(hipEventRecord(P.ev_ready, P.stream));
+        HS_HIP(hipStreamWaitEvent(P.side, P.ev_ready, 0));
+        return P.side;
+    }
+    void flush_gemm(Plan& P, bool side = false) {
         if (!tiles.empty()) {
             double flops = 0.0;
             for (const GemmTask& t : gt)
@@ -97,13 +105,13 @@ struct Batch {
             GemmTask* dt = reinterpret_cast<GemmTask*>(dbase);
             GemmTerm* dterm = reinterpret_cast<GemmTerm*>(dbase + o1);
             GemmTile* dtile = reinterpret_cast<GemmTile*>(dbase + o2);
-            launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, P.stream);
+            launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, to_side(P, side));
         }
         gt.clear();
         terms.clear();
         tiles.clear();
     }
-    void flush_chol(Plan& P, int* d_fail) {
+    void flush_chol(Plan& P, int* d_fail, bool side = false) {
         if (chol.empty()) return;
         for (int big = 0; big < 2; ++big) {       // LDS-resident blocks, then large ones
             std::vector<CholTask> part;
@@ -124,8 +132,9 @@ struct Batch {
                 for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 4 * q;
             }
             CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
-            launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, P.stream);
+            launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
             if (d_stamp) {
+                if (side) HS_HIP(hipStreamSynchronize(P.side));
                 std::vector<long long> h(4 * part.size());
                 HS_HIP(hipMemcpy(h.data(), d_stamp, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
                 long long ph[3] = {0, 0, 0};
@@ -137,7 +146,7 @@ struct Batch {
             if (big) {      // A^{-1} = X^T X, X = L^{-1} left in the work matrices
                 for (const CholTask& c : part) gemm(c.Ainv, c.ldi, c.m, c.m, 1.0, 0.0, c.work, c.m, 1,
                                                     c.work, c.m, 0, c.m);
-                flush_gemm(P);
+                flush_gemm(P, side);
             }
         }
         chol.clear();
@@ -166,6 +175,12 @@ void factor(Plan& P, const double* d_values_in) {
     P.krylov_cols = 0;
     P.d_scalars = nullptr;
     P.sched.clear();
+    if (!P.side) {      // second stream for the pivot blocks (default priority)
+        HS_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+        HS_HIP(hipEventCreateWithFlags(&P.ev_ready, hipEventDisableTiming));
+        HS_HIP(hipEventCreateWithFlags(&P.ev_done, hipEventDisableTiming));
+    }
+    HS_HIP(hipStreamSynchronize(P.side));
     HS_HIP(hipStreamSynchronize(st));
     P.stage.reset();
     P.fpool.reset();
@@ -320,6 +335,21 @@ void factor(Plan& P, const double* d_values_in) {
             const std::vector<int>& nodes = S.colours[c];
             P.spool.reset();    // stream order: the previous colour's kernels run first
             const double tc0 = trace ? now_ms() : 0.0;
+            // --- pivot blocks: Cholesky and inverse of every A_ss of the colour on the side
+            // stream, overlapped with the compression below (which does not read A_ss); the
+            // inverses land in Ainv (ld m) and join the plan's stream in phase B
+            std::vector<double*> Ainv(nodes.size(), nullptr);
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const int s = nodes[q];
+                const int m = LN.msz[s];
+                Block* dg = live.find(s, s);
+                if (!dg) throw Error{HSOLVE_ERR_DEVICE, "internal: missing diagonal block"};
+                Ainv[q] = P.spool.alloc_n<double>(size_t(m) * m);
+                B.chol.push_back(CholTask{dg->p, Ainv[q], nullptr, nullptr, dg->ld, m, m, s});
+                flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
+            }
+            B.flush_chol(P, d_fail, true);
+            HS_HIP(hipEventRecord(P.ev_done, P.side));
             // --- phase A: compression of the nodes with well-separated blocks
             struct CompNode { int s, slot, wt; double *Asw, *U; };
             std::vector<CompNode> comp;
@@ -455,12 +485,10 @@ void factor(Plan& P, const double* d_values_in) {
                     if (nb < s) B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 0);
                     else B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
                 }
-                Block* dg = live.find(s, s);
-                B.chol.push_back(CholTask{dg->p, nn.Gm, nullptr, nullptr, dg->ld, nn.ldG, m, s});
-                flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
+                B.copy(Ainv[q], m, nn.Gm, nn.ldG, m, m, 0);      // A_ss^-1 into rows 0..m-1 of Gm
             }
+            HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
             B.flush_copies(P);
-            B.flush_chol(P, d_fail);
             // Y = A_ss^-1 U, S = U^T Y
             for (size_t q = 0; q < nodes.size(); ++q) {
                 const int s = nodes[q];

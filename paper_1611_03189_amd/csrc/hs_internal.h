@@ -241,6 +241,8 @@ struct Plan {
     std::vector<double> coords, phi;   // copies (phi column-major n x nvec)
     int nphi = 0;                      // preserved vectors (0 for LoRaSp)
     hipStream_t stream = nullptr;
+    hipStream_t side = nullptr;        // factorization: pivot blocks beside the compression
+    hipEvent_t ev_ready = nullptr, ev_done = nullptr;
 
     // tree
     int L = 0;

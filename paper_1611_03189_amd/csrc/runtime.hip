@@ -162,6 +162,12 @@ ProfScope::~ProfScope() {
 }
 
 Plan::~Plan() {
+    if (side) {
+        (void)hipStreamSynchronize(side);
+        (void)hipStreamDestroy(side);
+    }
+    if (ev_ready) (void)hipEventDestroy(ev_ready);
+    if (ev_done) (void)hipEventDestroy(ev_done);
     if (d_row_ptr) (void)hipFree(d_row_ptr);
     if (d_col_idx) (void)hipFree(d_col_idx);
     if (d_values) (void)hipFree(d_values);
