@@ -690,8 +690,10 @@ __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
     const int tid = threadIdx.x;
     const double pivmin = S.scal[2];
     if (q <= 2) {
-        constexpr int NX = 4, NP = NX * NT;
-        for (int round = 0; round < 5; ++round) {      // (NP + 1)^5 > 2^50
+        // one point per thread: with one wave per SIMD the interleaved recurrences of several
+        // points are bound by instruction issue, one recurrence by its latency only
+        constexpr int NX = 1, NP = NX * NT;
+        for (int round = 0; round < 7; ++round) {      // (NP + 1)^7 > 2^56
             double x[NX];
             int cnt[NX];
 #pragma unroll
