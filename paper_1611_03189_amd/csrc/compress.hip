@@ -802,6 +802,135 @@ __device__ void reflect_two_sided(PH H, int ld, int m, PV v, double tau, SH& S) 
 }
 
 
+// H <- Q^T H Q for Q = H_0 H_1 .. H_{q-1}, H_t = I - tau_t v_t v_t^T (the GC reflectors, q <= 8,
+// v_t at gcv + t m), in two passes over H instead of two per reflector: with the compact
+// form Q = I - V T V^T (T upper triangular, T_tt = tau_t, T(0:t, t) = -tau_t T(0:t, 0:t)
+// V(:, 0:t)^T v_t), Y = H V and Wm = Y T - V (T^T (V^T Y) T) / 2, the result is
+// H - Wm V^T - V Wm^T. LDS (the dynamic buffer, free before the tridiagonalisation): V, Y, Wm
+// (m x q each) and T, V^T V, V^T Y, T^T (V^T Y) T (q x q each).
+template <class SH>
+__device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_G double* gcv,
+                                 const HS_G double* gct, double* buf, SH& S) {
+    const int tid = threadIdx.x;
+    double* Vs = buf;
+    double* Y = Vs + size_t(q) * m;
+    double* Wm = Y + size_t(q) * m;
+    double* Ts = Wm + size_t(q) * m;          // q x q, (a, b) at a + 8 b
+    double* VV = Ts + 64;
+    double* VY = VV + 64;
+    double* Z = VY + 64;
+    for (int e = tid; e < q * m; e += NT) Vs[e] = gcv[e];
+    __syncthreads();
+    // Y = H V: two adjacent lanes per row, each over half of the columns
+    const int hm = m / 2;
+    for (int tb = 0; tb < 2 * m; tb += NT) {             // uniform trip count (the shuffle)
+        const int t = tb + tid;
+        const int i = min(t >> 1, m - 1), c0 = (t & 1) ? hm : 0, c1 = (t & 1) ? m : hm;
+        double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (t < 2 * m) {
+            int l = c0;
+            for (; l + 4 <= c1; l += 4) {
+                double h[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) h[u] = H[i + size_t(l + u) * ld];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+#pragma unroll
+                    for (int b = 0; b < 8; ++b)
+                        if (b < q) acc[b] += h[u] * Vs[(l + u) + b * m];
+            }
+            for (; l < c1; ++l) {
+                const double h = H[i + size_t(l) * ld];
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (b < q) acc[b] += h * Vs[l + b * m];
+            }
+        }
+#pragma unroll
+        for (int b = 0; b < 8; ++b) acc[b] += __shfl_xor(acc[b], 1, WAVE);
+        if (t < 2 * m && !(t & 1)) {
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b < q) Y[i + b * m] = acc[b];
+        }
+    }
+    __syncthreads();
+    // V^T V and V^T Y: one thread per entry (q^2 <= 64 of each)
+    if (tid < 2 * q * q) {
+        const int w = tid / (q * q), a = (tid % (q * q)) % q, b = (tid % (q * q)) / q;
+        const double* R = w ? Y : Vs;
+        double acc = 0.0;
+        for (int l = 0; l < m; ++l) acc += Vs[l + a * m] * R[l + b * m];
+        (w ? VY : VV)[a + 8 * b] = acc;
+    }
+    __syncthreads();
+    if (tid == 0) {                                       // T, forward (columns left to right)
+        for (int b = 0; b < q; ++b) {
+            const double tb = gct[b];
+            for (int a = 0; a < b; ++a) {
+                double acc = 0.0;
+                for (int c = a; c < b; ++c) acc += Ts[a + 8 * c] * VV[c + 8 * b];
+                Ts[a + 8 * b] = -tb * acc;
+            }
+            Ts[b + 8 * b] = tb;
+            for (int a = b + 1; a < q; ++a) Ts[a + 8 * b] = 0.0;
+        }
+        double TM[64];                                    // (V^T Y) T, then Z = T^T (V^T Y) T
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+                double acc = 0.0;
+                for (int c = 0; c <= b; ++c) acc += VY[a + 8 * c] * Ts[c + 8 * b];
+                TM[a + 8 * b] = acc;
+            }
+        for (int a = 0; a < q; ++a)
+            for (int b = 0; b < q; ++b) {
+                double acc = 0.0;
+                for (int c = 0; c <= a; ++c) acc += Ts[c + 8 * a] * TM[c + 8 * b];
+                Z[a + 8 * b] = acc;
+            }
+    }
+    __syncthreads();
+    for (int i = tid; i < m; i += NT)                     // Wm = Y T - V Z / 2
+        for (int b = 0; b < q; ++b) {
+            double acc = 0.0;
+            for (int c = 0; c <= b; ++c) acc += Y[i + c * m] * Ts[c + 8 * b];
+            for (int c = 0; c < q; ++c) acc -= 0.5 * Vs[i + c * m] * Z[c + 8 * b];
+            Wm[i + b * m] = acc;
+        }
+    __syncthreads();
+    // H -= Wm V^T + V Wm^T: two adjacent lanes per row, row values in registers
+    for (int t = tid; t < 2 * m; t += NT) {
+        const int i = t >> 1, c0 = (t & 1) ? hm : 0, c1 = (t & 1) ? m : hm;
+        double wi[8], vi[8];
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            wi[b] = (b < q) ? Wm[i + b * m] : 0.0;
+            vi[b] = (b < q) ? Vs[i + b * m] : 0.0;
+        }
+        int l = c0;
+        for (; l + 4 <= c1; l += 4) {
+            double h[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) h[u] = H[i + size_t(l + u) * ld];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+#pragma unroll
+                for (int b = 0; b < 8; ++b)
+                    if (b < q) h[u] -= wi[b] * Vs[(l + u) + b * m] + vi[b] * Wm[(l + u) + b * m];
+                H[i + size_t(l + u) * ld] = h[u];
+            }
+        }
+        for (; l < c1; ++l) {
+            double h = H[i + size_t(l) * ld];
+#pragma unroll
+            for (int b = 0; b < 8; ++b)
+                if (b < q) h -= wi[b] * Vs[l + b * m] + vi[b] * Wm[l + b * m];
+            H[i + size_t(l) * ld] = h;
+        }
+    }
+    __syncthreads();
+}
+
 template <bool LDS, int MAXN>
 __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
                                                     int* rank) {
@@ -919,7 +1048,13 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             }
             if (tid == 0) Wk.gct[t] = tau;
             __syncthreads();
-            if (tau != 0.0) reflect_two_sided(H, ld, m, vt, tau, S);
+            // in LDS one reflector at a time; a matrix in global memory takes them together below
+            if (LDS || q > 8) {
+                if (tau != 0.0) reflect_two_sided(H, ld, m, vt, tau, S);
+            }
+        }
+        if constexpr (!LDS) {
+            if (q > 0 && q <= 8) gc_block_reflect(H, ld, m, q, Wk.gcv, Wk.gct, lds, S);
         }
         stamp(3);
         const int nt = m - q;
