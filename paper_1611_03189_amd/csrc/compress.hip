@@ -17,8 +17,9 @@
 //                  most four kept vectors by multisection on the tridiagonal form bordered
 //                  by the kept directions, which is similar to G; otherwise G itself is
 //                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
-//   k_comp_bisect  (many workgroups, one wave per kept eigenvalue) multisection to eps ||T||;
-//   k_comp_vectors (many workgroups, one wave per kept eigenvalue) inverse iteration in LDS;
+//   k_comp_bisect  (1 to 64 lanes per kept eigenvalue) multisection to eps ||T||;
+//   k_comp_vectors (one lane per kept eigenvalue) / k_comp_vectors_wave (one wave each)
+//                  inverse iteration;
 //   k_comp_orth    the vectors of each cluster of eigenvalues closer than 1e-7 ||T|| made
 //                  orthonormal (they span the cluster's invariant subspace);
 //   k_comp_wy      block reflector factors T of the tridiagonalisation (compact WY form);
@@ -36,10 +37,12 @@ constexpr int CMP_MAX = 512;            // largest super node the compression ac
 
 // Per-node global work layout (doubles): reflectors H (m x m, ld m) | d, e, tau, lam (4m) |
 // GC reflectors (16 m) + their tau (16) | info (8) | block reflector factors T (WY_NB x WY_NB
-// per block of WY_NB tridiagonalisation reflectors). Size: cmp_work_doubles(m).
+// per block of WY_NB tridiagonalisation reflectors) | inverse-iteration vectors and factors
+// (4 m doubles per eigenvalue slot, slots padded to a multiple of 64, lane-interleaved).
+// Size: cmp_work_doubles(m).
 constexpr int WY_NB = CMP_WY_NB;
 struct CmpWork {
-    HS_G double *H, *d, *e, *tau, *lam, *gcv, *gct, *info, *wyT;
+    HS_G double *H, *d, *e, *tau, *lam, *gcv, *gct, *info, *wyT, *vs;
     __device__ CmpWork(double* wg, int m) {
         HS_G double* w = gp(wg);
         H = w;
@@ -51,6 +54,7 @@ struct CmpWork {
         gct = gcv + size_t(16) * m;
         info = gct + 16;
         wyT = info + 8;
+        vs = wyT + size_t(CMP_WY_NB) * CMP_WY_NB * ((m + CMP_WY_NB - 1) / CMP_WY_NB);
     }
 };
 enum { INF_Q, INF_K2, INF_NN, INF_TNORM, INF_PIVMIN, INF_LO, INF_HI, INF_DONE };
@@ -1210,10 +1214,128 @@ __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
     if (active && g == 0) Wk.lam[j] = 0.5 * (lo + hi);
 }
 
-// one wave per kept eigenvalue: inverse iteration with the tridiagonal, in trailing coordinates
-constexpr int VNT = 128;           // two waves per workgroup in k_comp_vectors
+// Inverse iteration for the kept eigenvalues, one lane per eigenvalue (VL per workgroup), in
+// trailing coordinates: three times, the LU factorisation with partial pivoting of T - lambda I
+// (the steps of tridiag_shift_factor) with the forward elimination applied to y on the way,
+// then the back substitution and the normalisation. Each lane keeps its vector and factors in
+// the node's work buffer, lane-interleaved (row i of all lanes is one coalesced access), and
+// reads eight rows ahead of its sequential recurrence.
+constexpr int VL = 64;
 
-__global__ __launch_bounds__(VNT) void k_comp_vectors(const CompressTask* tasks, int variant, int ldn) {
+__global__ __launch_bounds__(VL) void k_comp_vectors(const CompressTask* tasks) {
+    __shared__ double d[CMP_MAX], e[CMP_MAX];
+    const CompressTask T = tasks[blockIdx.y];
+    const int m = T.m;
+    CmpWork Wk(T.work, m);
+    const int k2 = int(Wk.info[INF_K2]), nn = int(Wk.info[INF_NN]), q = int(Wk.info[INF_Q]);
+    if (int(blockIdx.x) * VL >= k2 || nn <= 0) return;
+    for (int i = threadIdx.x; i < nn; i += VL) {
+        d[i] = Wk.d[i];
+        e[i] = Wk.e[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x;
+    const int c = blockIdx.x * VL + lane;
+    const bool act = c < k2;
+    const double lamc = Wk.lam[act ? c : k2 - 1];
+    const double tnorm = Wk.info[INF_TNORM];
+    const double tiny = DBL_EPSILON * (tnorm > 0.0 ? tnorm : 1.0);
+    HS_G double* base = Wk.vs + size_t(blockIdx.x) * 4 * size_t(m) * VL + lane;
+    auto at = [&](int f, int i) -> HS_G double& { return base[(size_t(f) * m + i) * VL]; };   // 0 y, 1 r0, 2 u1, 3 u2
+    for (int i = 0; i < nn; ++i) at(0, i) = start_value(i, c);
+    double inv = 1.0;
+    for (int it = 0; it < 3; ++it) {
+        double p0 = d[0] - lamc, p1 = nn > 1 ? e[0] : 0.0, p2 = 0.0;
+        double yc = at(0, 0) * inv;                 // current y_i after the earlier eliminations
+        for (int i0 = 0; i0 + 1 < nn; i0 += 8) {
+            const int nb = min(8, nn - 1 - i0);
+            double ynb[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < nb) ynb[u] = at(0, i0 + u + 1) * inv;
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (u >= nb) break;
+                const int i = i0 + u;
+                const double bb = e[i], a1 = d[i + 1] - lamc, c1 = (i + 2 < nn) ? e[i + 1] : 0.0;
+                const double yn = ynb[u];
+                double r0, u1, u2, ys, np0, np1;
+                if (fabs(bb) > fabs(p0) && fabs(bb) >= tiny) {      // rows i, i + 1 interchanged
+                    const double mu = p0 / bb;
+                    r0 = 1.0 / bb;
+                    u1 = a1;
+                    u2 = c1;
+                    np0 = p1 - mu * a1;
+                    np1 = p2 - mu * c1;
+                    ys = yn;
+                    yc = yc - mu * yn;
+                } else {
+                    if (fabs(p0) < tiny) p0 = (p0 < 0.0) ? -tiny : tiny;
+                    const double mu = bb / p0;
+                    r0 = 1.0 / p0;
+                    u1 = p1;
+                    u2 = p2;
+                    np0 = a1 - mu * p1;
+                    np1 = c1 - mu * p2;
+                    ys = yc;
+                    yc = yn - mu * yc;
+                }
+                at(1, i) = r0;
+                at(2, i) = u1;
+                at(3, i) = u2;
+                at(0, i) = ys;
+                p0 = np0;
+                p1 = np1;
+                p2 = 0.0;
+            }
+        }
+        const double rl = 1.0 / ((fabs(p0) < tiny) ? ((p0 < 0.0) ? -tiny : tiny) : p0);
+        // back substitution with the squared norm on the way
+        double y1 = yc * rl, y2 = 0.0;
+        at(0, nn - 1) = y1;
+        double nrm2 = y1 * y1;
+        if (nn >= 2) {
+            const double y0 = (at(0, nn - 2) - at(2, nn - 2) * y1) * at(1, nn - 2);
+            at(0, nn - 2) = y0;
+            nrm2 += y0 * y0;
+            y2 = y1;
+            y1 = y0;
+        }
+        for (int i0 = nn - 3; i0 >= 0; i0 -= 8) {
+            const int nb = min(8, i0 + 1);
+            double rr[8], ua[8], ub[8], yv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (u < nb) {
+                    rr[u] = at(1, i0 - u);
+                    ua[u] = at(2, i0 - u);
+                    ub[u] = at(3, i0 - u);
+                    yv[u] = at(0, i0 - u);
+                }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (u >= nb) break;
+                const double y0 = (yv[u] - ua[u] * y1 - ub[u] * y2) * rr[u];
+                at(0, i0 - u) = y0;
+                nrm2 += y0 * y0;
+                y2 = y1;
+                y1 = y0;
+            }
+        }
+        const double nrm = sqrt(nrm2);
+        inv = (nrm > 0.0 && isfinite(nrm)) ? 1.0 / nrm : 0.0;
+    }
+    if (act) {
+        HS_G double* col = gp(T.U) + size_t(q + c) * m + q;
+        for (int i = 0; i < nn; ++i) col[i] = at(0, i) * inv;
+    }
+}
+
+// The same inverse iteration with one wave per kept eigenvalue, the factors in LDS and the
+// recurrences run by lane 0: shorter latency per vector, for launches with few eigenvalues
+constexpr int VNT = 128;           // two waves per workgroup in k_comp_vectors_wave
+
+__global__ __launch_bounds__(VNT) void k_comp_vectors_wave(const CompressTask* tasks, int ldn) {
     // LDS (ldn >= every node's order): d, e, then per wave y, u0, u1, u2, mult and the
     // interchange flags
     extern __shared__ double lds[];
@@ -1519,10 +1641,15 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     }
     {
         ProfScope ps("k_comp_vectors", 0.0, s);
-        const int ldn = max_m;
-        const size_t bytes = sizeof(double) * (2 + 5 * (VNT / WAVE)) * size_t(ldn) + sizeof(int) * (VNT / WAVE) * size_t(ldn);
-        hipLaunchKernelGGL(k_comp_vectors, dim3((max_m + VNT / WAVE - 1) / (VNT / WAVE), ntasks), dim3(VNT),
-                           bytes, s, d_tasks, variant, ldn);
+        if (double(max_m) * ntasks >= 4096.0) {      // many eigenvalues: one lane each
+            hipLaunchKernelGGL(k_comp_vectors, dim3((max_m + VL - 1) / VL, ntasks), dim3(VL), 0, s, d_tasks);
+        } else {                                     // few: one wave each (latency)
+            const int ldn = max_m;
+            const size_t bytes = sizeof(double) * (2 + 5 * (VNT / WAVE)) * size_t(ldn) +
+                                 sizeof(int) * (VNT / WAVE) * size_t(ldn);
+            hipLaunchKernelGGL(k_comp_vectors_wave, dim3((max_m + VNT / WAVE - 1) / (VNT / WAVE), ntasks),
+                               dim3(VNT), bytes, s, d_tasks, ldn);
+        }
         check_launch("k_comp_vectors");
     }
     {

@@ -332,7 +332,8 @@ constexpr int LDS_MAX_M = 128;   // compression blocks up to this size work in L
 constexpr int CMP_WY_NB = 16;     // reflectors per block in the compression back-transformation
 // doubles of the per-node compression work buffer for a super node of m unknowns
 inline size_t cmp_work_doubles(int m) {
-    return size_t(m) * m + 32 * size_t(m) + 64 + size_t(CMP_WY_NB) * CMP_WY_NB * ((m + CMP_WY_NB - 1) / CMP_WY_NB);
+    return size_t(m) * m + 32 * size_t(m) + 64 + size_t(CMP_WY_NB) * CMP_WY_NB * ((m + CMP_WY_NB - 1) / CMP_WY_NB) +
+           4 * size_t(m) * (size_t(m + 63) / 64 * 64);
 }
 constexpr int PIV_LDS_MAX_M = 64; // pivot blocks up to this size are factored in LDS; larger
                                   // ones by the blocked kernel (panels of 32 columns)
