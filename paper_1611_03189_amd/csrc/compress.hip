@@ -1483,6 +1483,7 @@ __global__ __launch_bounds__(NT) void k_comp_wy(const CompressTask* tasks) {
 // tridiagonalisation blocks (B_b = I - V_b T_b V_b^T, applied last first) and W_gc the GC
 // reflectors. One workgroup per BT_COLS eigenvectors, held in LDS.
 constexpr int BT_COLS = 16;
+static_assert(BT_COLS == 16 && WY_NB == 16, "k_comp_bt forms 16 x 16 blocks on the matrix cores");
 
 __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int variant) {
     extern __shared__ double lds[];
@@ -1500,6 +1501,7 @@ __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int v
     const int ldv = nn + 1;
     double* Wm = Vs + size_t(WY_NB) * ldv;         // W = V^T Y then T W: WY_NB x BT_COLS
     double* Ts = Wm + WY_NB * BT_COLS;             // T: WY_NB x WY_NB (ld WY_NB + 1)
+    double* Wp = Ts + WY_NB * (WY_NB + 1);         // partial V^T Y of the four waves
     HS_G double* U = gp(T.U);
     for (int e = tid; e < BT_COLS * m; e += NT) {
         const int c = e / m, r = e % m;
@@ -1520,19 +1522,28 @@ __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int v
         const HS_G double* Tg = Wk.wyT + size_t(b) * WY_NB * WY_NB;
         for (int e = tid; e < WY_NB * WY_NB; e += NT) Ts[(e % WY_NB) + (e / WY_NB) * (WY_NB + 1)] = Tg[e];
         __syncthreads();
-        // W = V^T Y: WY_NB x BT_COLS dot products of length nn, two per thread
-        for (int p = tid; p < WY_NB * BT_COLS; p += NT) {
-            const int i = p % WY_NB, c = p / WY_NB;
-            double s0 = 0.0, s1 = 0.0;
-            const double* vi = Vs + i * ldv;
-            const double* yc = Yt + c * ldy;
-            int r = j0 + i + 1;                      // v_i is zero above its unit entry
-            for (; r + 1 < nn; r += 2) {
-                s0 += vi[r] * yc[r];
-                s1 += vi[r + 1] * yc[r + 1];
+        // W = V^T Y on the FP64 matrix cores (16 x 16, K = the rows from j0 + 1, where V is
+        // nonzero): the four waves take every fourth K step, then their partial sums are added
+        {
+            const int lane = tid % WAVE, wv = tid / WAVE, li = lane % 16, lk = lane / 16;
+            const int r0 = j0 + 1, nks = (nn - r0 + 3) / 4;
+            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+            for (int ks = wv; ks < nks; ks += NT / WAVE) {
+                const int r = r0 + 4 * ks + lk;
+                const bool ok = r < nn;
+                const double a = ok ? Vs[r + li * ldv] : 0.0;     // A(i, r) = V(r, i)
+                const double bv = ok ? Yt[r + li * ldy] : 0.0;    // B(r, c) = Y(r, c)
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
             }
-            if (r < nn) s0 += vi[r] * yc[r];
-            Wm[i + c * WY_NB] = s0 + s1;
+#pragma unroll
+            for (int t = 0; t < 4; ++t) Wp[wv * WY_NB * BT_COLS + (lk + 4 * t) + li * WY_NB] = acc[t];
+        }
+        __syncthreads();
+        for (int p = tid; p < WY_NB * BT_COLS; p += NT) {
+            double w = 0.0;
+#pragma unroll
+            for (int h = 0; h < NT / WAVE; ++h) w += Wp[h * WY_NB * BT_COLS + p];
+            Wm[p] = w;
         }
         __syncthreads();
         // W <- T W (T upper triangular)
@@ -1553,13 +1564,29 @@ __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int v
             if (p < WY_NB * BT_COLS) Wm[p] = tw[h];
         }
         __syncthreads();
-        // Y -= V W
-        for (int e = tid; e < nn * BT_COLS; e += NT) {
-            const int r = e % nn, c = e / nn;
-            double acc = 0.0;
-#pragma unroll 8
-            for (int i = 0; i < WY_NB; ++i) acc += Vs[r + i * ldv] * Wm[i + c * WY_NB];
-            Yt[r + c * ldy] -= acc;
+        // Y -= V W on the matrix cores, by blocks of 16 rows (wave wv takes every fourth block):
+        // D(c, r) = Y(r, c) - sum_i W(i, c) V(r, i), lane l's register t is (c = l / 16 + 4 t,
+        // r = l % 16 of the block)
+        {
+            const int lane = tid % WAVE, wv = tid / WAVE, li = lane % 16, lk = lane / 16;
+            for (int rb = wv * 16; rb < nn; rb += 16 * (NT / WAVE)) {
+                const int r = rb + li;
+                const int rc = min(r, nn - 1);
+                dbl4 acc;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) acc[t] = Yt[rc + (lk + 4 * t) * ldy];
+#pragma unroll
+                for (int ks = 0; ks < WY_NB / 4; ++ks) {
+                    const int i = 4 * ks + lk;
+                    const double a = -Wm[i + li * WY_NB];         // A(c, i) = -W(i, c)
+                    const double bv = Vs[rc + i * ldv];           // B(i, r) = V(r, i)
+                    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, bv, acc, 0, 0, 0);
+                }
+                if (r < nn) {
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) Yt[r + (lk + 4 * t) * ldy] = acc[t];
+                }
+            }
         }
     }
     __syncthreads();
@@ -1666,11 +1693,12 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     {
         ProfScope ps("k_comp_bt", 0.0, s);
         const size_t bytes = sizeof(double) * (size_t(BT_COLS) * (max_m + 1) + size_t(WY_NB) * (max_m + 1) +
-                                               WY_NB * BT_COLS + WY_NB * (WY_NB + 1));
+                                               WY_NB * BT_COLS + WY_NB * (WY_NB + 1) +
+                                               (NT / WAVE) * WY_NB * BT_COLS);
         static std::once_flag once;
         set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_bt),
                       sizeof(double) * (size_t(BT_COLS) * (CMP_MAX + 1) + size_t(WY_NB) * (CMP_MAX + 1) +
-                                        WY_NB * BT_COLS + WY_NB * (WY_NB + 1)));
+                                        WY_NB * BT_COLS + WY_NB * (WY_NB + 1) + (NT / WAVE) * WY_NB * BT_COLS));
         hipLaunchKernelGGL(k_comp_bt, dim3((max_m + BT_COLS - 1) / BT_COLS, ntasks), dim3(NT), bytes, s, d_tasks,
                            variant);
         check_launch("k_comp_bt");
