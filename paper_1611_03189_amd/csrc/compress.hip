@@ -66,7 +66,6 @@ struct CmpShared {
     double bord[4][MAXN];      // GC border rows C (q <= 4) of the bordered tridiagonal
     double dq[16];             // its leading q x q block D
     double red[NT / WAVE];
-    double red4[4 * (NT / WAVE)];
     double redp[2][5 * (NT / WAVE)];    // double-buffered sums of the blocked reduction
     double scal[4];
     int iscal[4];
@@ -100,18 +99,30 @@ __device__ inline void rank2_row(PA A, int ld, double vi, double wi, PV v, PW w,
     for (; l < len; ++l) A[size_t(l) * ld] -= vi * w[l] + wi * v[l];
 }
 
-// block-wide sums of v[0..nv), nv <= 4; results valid in every thread
-__device__ inline void block_sum4(double* v, int nv, double* red4) {
+// Block-wide sums of v[0..nv) (nv <= 5) with one barrier: the partial sums alternate between
+// two buffers, and a buffer is written again only after a later barrier.
+template <class SH>
+__device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    for (int r = 0; r < nv; ++r) v[r] = wave_sum(v[r]);
+    double* red = S.redp[parity];
+    parity ^= 1;
+#pragma unroll
+    for (int r = 0; r < 5; ++r)
+        if (r < nv) v[r] = wave_sum(v[r]);
+    if (lane == 0) {
+#pragma unroll
+        for (int r = 0; r < 5; ++r)
+            if (r < nv) red[r * (NT / WAVE) + w] = v[r];
+    }
     __syncthreads();
-    if (lane == 0)
-        for (int r = 0; r < nv; ++r) red4[r * (NT / WAVE) + w] = v[r];
-    __syncthreads();
-    for (int r = 0; r < nv; ++r) {
-        double s = 0.0;
-        for (int i = 0; i < NT / WAVE; ++i) s += red4[r * (NT / WAVE) + i];
-        v[r] = s;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) {
+        if (r < nv) {
+            double t = 0.0;
+#pragma unroll
+            for (int i = 0; i < NT / WAVE; ++i) t += red[r * (NT / WAVE) + i];
+            v[r] = t;
+        }
     }
 }
 
@@ -125,22 +136,27 @@ template <class SH>
 __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nullptr, int bst = 0,
                                int nbr = 0) {
     const int tid = threadIdx.x;
+    int parity = 0;
     for (int j = 0; j + 2 < nn; ++j) {
         double* col = H + size_t(j) * ld;
-        double part = 0.0;
-        for (int i = j + 2 + tid; i < nn; i += NT) part += col[i] * col[i];
-        const double xn2 = block_sum(part, S.red);
+        double nrm[1] = {0.0};
+        for (int i = j + 2 + tid; i < nn; i += NT) nrm[0] += col[i] * col[i];
+        block_sums_1b(nrm, 1, S, parity);
+        const double xn2 = nrm[0];
         const double alpha = col[j + 1];
-        double tau = 0.0, beta = alpha;
+        double tau = 0.0, beta = alpha, scal = 0.0;
         if (xn2 > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tau = (beta - alpha) / beta;
-            const double scal = 1.0 / (alpha - beta);
-            for (int i = j + 2 + tid; i < nn; i += NT) col[i] *= scal;
+            scal = 1.0 / (alpha - beta);
         }
-        __syncthreads();
         const int len = nn - j - 1;
-        for (int i = tid; i < len; i += NT) S.v[i] = (i == 0) ? 1.0 : (xn2 > 0.0 ? col[j + 1 + i] : 0.0);
+        // the reflector, kept scaled in col(j+2..) and in S.v (each thread its own entries)
+        for (int i = tid; i < len; i += NT) {
+            const double v = (i == 0) ? 1.0 : col[j + 1 + i] * scal;
+            if (i > 0) col[j + 1 + i] = v;
+            S.v[i] = v;
+        }
         if (tid == 0) {
             S.tau[j] = tau;
             S.e[j] = beta;
@@ -148,8 +164,9 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
         __syncthreads();
         if (tau != 0.0) {
             double* T22 = H + size_t(j + 1) * ld + (j + 1);
-            double pv_part = 0.0;
-            // two adjacent lanes per row, each over half of the columns
+            // w = tau A v (two adjacent lanes per row, each over half of the columns), then
+            // v^T w and the border rows' products with v in one reduction
+            double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             const int hl = len / 2;
             for (int tb = 0; tb < 2 * len; tb += NT) {       // uniform trip count (the shuffle)
                 const int t = tb + tid;
@@ -159,24 +176,28 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
                 if (t < 2 * len && !(t & 1)) {
                     acc *= tau;
                     S.w[i] = acc;
-                    pv_part += acc * S.v[i];
+                    pv[0] += acc * S.v[i];
                 }
             }
-            const double K = 0.5 * tau * block_sum(pv_part, S.red);
-            for (int i = tid; i < len; i += NT) S.w[i] -= K * S.v[i];
+            double* B1 = nbr ? Bl + (j + 1) : nullptr;
+            for (int l = tid; l < len; l += NT) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < nbr) pv[1 + r] += B1[r * bst + l] * S.v[l];
+            }
+            block_sums_1b(pv, 1 + nbr, S, parity);
+            const double K = 0.5 * tau * pv[0];
+            for (int t = tid; t < 2 * len; t += NT)        // the owners of S.w finish it
+                if (!(t & 1)) S.w[t >> 1] -= K * S.v[t >> 1];
+            for (int l = tid; l < len; l += NT) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    if (r < nbr) B1[r * bst + l] -= tau * pv[1 + r] * S.v[l];
+            }
             __syncthreads();
             for (int t = tid; t < 2 * len; t += NT) {
                 const int i = t >> 1, c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
                 rank2_row(T22 + i + size_t(c0) * ld, ld, S.v[i], S.w[i], S.v + c0, S.w + c0, c1 - c0);
-            }
-            if (nbr > 0) {
-                double* B1 = Bl + (j + 1);
-                double dots[4] = {0.0, 0.0, 0.0, 0.0};
-                for (int l = tid; l < len; l += NT)
-                    for (int r = 0; r < nbr; ++r) dots[r] += B1[r * bst + l] * S.v[l];
-                block_sum4(dots, nbr, S.red4);
-                for (int l = tid; l < len; l += NT)
-                    for (int r = 0; r < nbr; ++r) B1[r * bst + l] -= tau * dots[r] * S.v[l];
             }
             __syncthreads();
         }
@@ -193,12 +214,7 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
     __syncthreads();
 }
 
-// Blocked form of tridiagonalize for matrices in global memory (same outputs): reflectors
-// are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
-// updated, its product with each new reflector is corrected with the panel's earlier
-// reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
-// matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
-// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+// panel width of the blocked tridiagonalisation
 constexpr int TRI_NB = 12;
 
 // Sum over the wave left in lane 63 only (the DPP steps of wave_sum without the read-back).
@@ -244,33 +260,6 @@ __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, 
                 acc[2 * k] += a[u][k][0] * vl;
                 acc[2 * k + 1] += a[u][k][1] * vl;
             }
-        }
-    }
-}
-
-// Block-wide sums of v[0..nv) (nv <= 5) with one barrier: the partial sums alternate between
-// two buffers, and a buffer is written again only after a later barrier.
-template <class SH>
-__device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
-    const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
-    double* red = S.redp[parity];
-    parity ^= 1;
-#pragma unroll
-    for (int r = 0; r < 5; ++r)
-        if (r < nv) v[r] = wave_sum(v[r]);
-    if (lane == 0) {
-#pragma unroll
-        for (int r = 0; r < 5; ++r)
-            if (r < nv) red[r * (NT / WAVE) + w] = v[r];
-    }
-    __syncthreads();
-#pragma unroll
-    for (int r = 0; r < 5; ++r) {
-        if (r < nv) {
-            double t = 0.0;
-#pragma unroll
-            for (int i = 0; i < NT / WAVE; ++i) t += red[r * (NT / WAVE) + i];
-            v[r] = t;
         }
     }
 }
