@@ -78,6 +78,9 @@ typedef struct {
                                once to FP32; the sweeps read and accumulate in FP32 (vectors
                                enter and leave in FP64). Pair it with HSOLVE_FPCG or GMRES. */
     int restart;            /* HSOLVE_GMRES: Krylov vectors per cycle (200) */
+    int overlap_pivots;     /* 1 (default): the pivot blocks of a colour are factored on a
+                               second stream of the plan while the colour is compressed; 0: in
+                               order on opt.stream (for callers that run many plans at once) */
 } hsolve_options;
 
 typedef struct {

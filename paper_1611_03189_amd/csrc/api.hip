@@ -69,6 +69,7 @@ void hsolve_default_options(hsolve_options* o) {
     o->stream = nullptr;
     o->apply_prec = 64;
     o->restart = 200;
+    o->overlap_pivots = 1;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -83,7 +84,8 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC) || o.dim < 0 || o.dim > 3 ||
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
         !(o.tol >= 0.0) || (o.krylov != HSOLVE_PCG && o.krylov != HSOLVE_FPCG && o.krylov != HSOLVE_GMRES) ||
-        (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1)
+        (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1 ||
+        (o.overlap_pivots != 0 && o.overlap_pivots != 1))
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;
     hsolve_plan plan = new (std::nothrow) hsolve_plan_s();

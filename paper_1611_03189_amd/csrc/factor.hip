@@ -166,6 +166,7 @@ void factor(Plan& P, const double* d_values_in) {
     const bool gc = P.opt.variant == HSOLVE_GC;
     const int p = P.nphi;
     const double eps = P.opt.eps;
+    const bool overlap = P.opt.overlap_pivots != 0;
 
     P.factored = false;
     P.d_V = nullptr;
@@ -348,8 +349,8 @@ void factor(Plan& P, const double* d_values_in) {
                 B.chol.push_back(CholTask{dg->p, Ainv[q], nullptr, nullptr, dg->ld, m, m, s});
                 flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
             }
-            B.flush_chol(P, d_fail, true);
-            HS_HIP(hipEventRecord(P.ev_done, P.side));
+            B.flush_chol(P, d_fail, overlap);
+            if (overlap) HS_HIP(hipEventRecord(P.ev_done, P.side));
             // --- phase A: compression of the nodes with well-separated blocks
             struct CompNode { int s, slot, wt; double *Asw, *U; };
             std::vector<CompNode> comp;
@@ -487,7 +488,7 @@ void factor(Plan& P, const double* d_values_in) {
                 }
                 B.copy(Ainv[q], m, nn.Gm, nn.ldG, m, m, 0);      // A_ss^-1 into rows 0..m-1 of Gm
             }
-            HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
+            if (overlap) HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
             B.flush_copies(P);
             // Y = A_ss^-1 U, S = U^T Y
             for (size_t q = 0; q < nodes.size(); ++q) {

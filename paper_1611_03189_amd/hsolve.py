@@ -44,7 +44,7 @@ class Options(ctypes.Structure):
         ("leaf_size", c_int), ("eps", c_double), ("variant", c_int), ("nvec", c_int),
         ("phi", POINTER(c_double)), ("dim", c_int), ("coords", POINTER(c_double)),
         ("tol", c_double), ("max_iter", c_int), ("krylov", c_int), ("stream", c_void_p),
-        ("apply_prec", c_int), ("restart", c_int),
+        ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
     ]
 
 
@@ -150,7 +150,8 @@ class HSolver:
 
     def __init__(self, row_ptr, col_idx, coords=None, leaf: int = 16, eps: float = 1e-2,
                  variant: str = "gc", phi=None, tol: float = 1e-10, max_iter: int = 1000,
-                 stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200):
+                 stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200,
+                 overlap_pivots: bool = True):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -166,6 +167,7 @@ class HSolver:
         opt.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)
         opt.apply_prec = int(apply_prec)
         opt.restart = int(restart)
+        opt.overlap_pivots = 1 if overlap_pivots else 0
         self._keep = []
         if coords is not None:
             c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(self.n, -1))

@@ -101,7 +101,7 @@ def test_analyze_rejects_bad_input(lib):
 def test_options_accept_solver_variants(lib):
     p = pb.poisson(6, 2)
     for kw in ({"apply_prec": 32, "krylov": "fpcg"}, {"krylov": "gmres", "restart": 30},
-               {"apply_prec": 64, "krylov": "pcg"}):
+               {"apply_prec": 64, "krylov": "pcg"}, {"overlap_pivots": False}):
         with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
             assert S._h
 

@@ -217,3 +217,18 @@ def test_c3_full_size_properties():
     true_rel = np.linalg.norm(b - A @ x.cpu().numpy()) / np.linalg.norm(b)
     assert true_rel <= 2 * TOL and st["iterations"] <= 10, (true_rel, st)
     S.close()
+
+
+def test_pivot_overlap_does_not_change_results():
+    """The pivot blocks factored on the plan's second stream (default) or in order on its
+    stream run the same kernels on the same data: bitwise equal applies."""
+    say("pivot overlap on/off")
+    p = pb.poisson(20, 3)
+    r = torch.from_numpy(pb.rhs(p.n, 2, 47)).cuda()
+    out = []
+    for ov in (True, False):
+        S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=64, eps=1e-2, overlap_pivots=ov)
+        S.factor(torch.from_numpy(p.values).cuda())
+        out.append(S.apply(r).cpu().numpy())
+        S.close()
+    assert np.array_equal(out[0], out[1])
