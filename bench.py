@@ -210,7 +210,14 @@ def main() -> int:
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
+    # one more untimed step with every kernel timed: the kernel table and the dominant kernel;
+    # the timed steps then record that kernel alone (events around the others cost time)
     S.profile_begin()
+    step()
+    torch.cuda.synchronize()
+    prof_all = S.profile_end()
+    dom_name = max(prof_all, key=lambda e: e["ms"])["name"]
+    S.profile_begin(only=dom_name)
     times, fac = [], []
     t_start = time.perf_counter()
     for _ in range(args.steps):
@@ -240,7 +247,7 @@ def main() -> int:
     true_rel = float(np.linalg.norm(b_host - A @ xs) / np.linalg.norm(b_host))
     stats = S.stats()
 
-    dom = max(prof, key=lambda e: e["ms"])
+    dom = next(e for e in prof if e["name"] == dom_name)
     bound, unit = KERNEL_BOUND.get(dom["name"], ("alu", "flop"))
     per_launch_work = dom["work"] / dom["launches"]
     avg_s = dom["ms"] / dom["launches"] / 1e3
@@ -281,8 +288,8 @@ def main() -> int:
         "nrhs32": {"ms": round(ms32, 3), "ms_per_rhs": round(ms32 / 32, 3),
                    "pcg_iterations_max": st32["iterations"], "converged": st32["converged"]},
         "roofline": roofline,
-        "kernels": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
-                    for e in sorted(prof, key=lambda e: -e["ms"])],
+        "kernels_untimed_step": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in e.items()}
+                                 for e in sorted(prof_all, key=lambda e: -e["ms"])],
     }
     if not args.no_variants:
         out["variants"] = variants(H, pb, np, torch, p, w, vals, b_host, xs)

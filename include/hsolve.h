@@ -167,6 +167,9 @@ const char* hsolve_last_error(hsolve_plan plan);
  * launches, and summed algorithmic work (flops for k_gemm, k_chol_inv*, k_comp_reduce*; bytes
  * for k_copy, k_fwd, k_bwd, k_spmv). */
 hsolve_status hsolve_profile_begin(hsolve_plan plan);
+/* Record only the launches of the kernel named `kernel` (as hsolve_profile_entry reports
+ * it), so that the events of the others cost nothing; NULL or "" records every kernel. */
+hsolve_status hsolve_profile_only(hsolve_plan plan, const char* kernel);
 hsolve_status hsolve_profile_end(hsolve_plan plan, int32_t* nkernels);
 hsolve_status hsolve_profile_entry(hsolve_plan plan, int i, char* name, int cap, double* ms,
                                    int64_t* launches, double* work);

@@ -231,6 +231,12 @@ hsolve_status hsolve_profile_begin(hsolve_plan plan) {
     return HSOLVE_OK;
 }
 
+hsolve_status hsolve_profile_only(hsolve_plan plan, const char* kernel) {
+    if (!plan) return HSOLVE_ERR_INVALID;
+    plan->P.prof.only = kernel ? kernel : "";
+    return HSOLVE_OK;
+}
+
 hsolve_status hsolve_profile_end(hsolve_plan plan, int32_t* nkernels) {
     if (!plan) return HSOLVE_ERR_INVALID;
     plan->P.prof.on = false;

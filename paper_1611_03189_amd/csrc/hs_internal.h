@@ -92,6 +92,7 @@ class Profiler {
 public:
     ~Profiler();
     bool on = false;
+    std::string only;                  // record only launches of this kernel name (empty: all)
     void clear();
     void record(const char* name, double work, hipEvent_t a, hipEvent_t b);
     hipEvent_t event();

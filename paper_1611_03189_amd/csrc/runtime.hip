@@ -149,7 +149,7 @@ std::vector<ProfTotal> Profiler::totals() {
 }
 
 ProfScope::ProfScope(const char* n, double w, hipStream_t st) : name(n), work(w), s(st) {
-    if (t_prof && t_prof->on) {
+    if (t_prof && t_prof->on && (t_prof->only.empty() || t_prof->only == n)) {
         a = t_prof->event();
         HS_HIP(hipEventRecord(a, s));
     }

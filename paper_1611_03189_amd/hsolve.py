@@ -101,6 +101,7 @@ def load() -> ctypes.CDLL:
         "hsolve_ranks": (c_int, [P, c_int, POINTER(c_int32)]),
         "hsolve_node_factor": (c_int, [P, c_int, c_int, POINTER(c_int32), POINTER(c_double), c_int64]),
         "hsolve_profile_begin": (c_int, [P]),
+        "hsolve_profile_only": (c_int, [P, ctypes.c_char_p]),
         "hsolve_profile_end": (c_int, [P, POINTER(c_int32)]),
         "hsolve_profile_entry": (c_int, [P, c_int, ctypes.c_char_p, c_int, POINTER(c_double),
                                          POINTER(c_int64), POINTER(c_double)]),
@@ -255,7 +256,9 @@ class HSolver:
         return y
 
     # -- kernel timing ---------------------------------------------------------------
-    def profile_begin(self):
+    def profile_begin(self, only: str | None = None):
+        """Start recording kernel times; with `only`, launches of that kernel alone."""
+        _check(self._lib.hsolve_profile_only(self._h, only.encode() if only else None), "hsolve_profile_only")
         _check(self._lib.hsolve_profile_begin(self._h), "hsolve_profile_begin")
 
     def profile_end(self) -> list[dict]:
