@@ -54,8 +54,9 @@ typedef enum {
 
 enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
 /* outer iteration of hsolve_solve (§7): conjugate gradients with the standard or the
-   flexible beta, or right-preconditioned restarted GMRES */
-enum { HSOLVE_PCG = 0, HSOLVE_FPCG = 1, HSOLVE_GMRES = 2 };
+   flexible beta, right-preconditioned restarted GMRES, or the stationary iteration
+   x <- x + A_H^{-1} (b - A x) of §7.1 */
+enum { HSOLVE_PCG = 0, HSOLVE_FPCG = 1, HSOLVE_GMRES = 2, HSOLVE_STATIONARY = 3 };
 
 typedef struct {
     int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
@@ -71,7 +72,7 @@ typedef struct {
                                the unknown index as a 1-D coordinate */
     double tol;             /* hsolve_solve: stop at ||b - A x||_2 <= tol ||b||_2 (1e-10) */
     int max_iter;           /* hsolve_solve: iteration cap (1000) */
-    int krylov;             /* HSOLVE_PCG (default), HSOLVE_FPCG or HSOLVE_GMRES */
+    int krylov;             /* HSOLVE_PCG (default), HSOLVE_FPCG, HSOLVE_GMRES, HSOLVE_STATIONARY */
     void* stream;           /* hipStream_t or NULL */
     int apply_prec;         /* 64 (default) or 32: precision of the solve phase. With 32 the
                                factor is computed in FP64 and its solve-phase blocks are rounded
@@ -138,6 +139,8 @@ hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr,
  * equals its own single-column solve. FPCG takes beta = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k.
  * GMRES: right-preconditioned, restarted every opt.restart steps, modified Gram-Schmidt; the
  * columns are solved one after the other. Needs (2 restart + 4) n doubles of device memory.
+ * STATIONARY: x_{k+1} = x_k + A_H^{-1} (b - A x_k) from x_0 = 0, all columns together, until
+ * the true residual ||b - A x_k|| <= tol ||b|| (iterations counted as applies).
  * stats may be NULL; stats.iterations is the largest count over the columns and
  * stats.rel_residual the largest final relative residual (PCG: of the recursion; GMRES:
  * recomputed as ||b - A x|| / ||b||). HSOLVE_NOT_CONVERGED if max_iter is reached first

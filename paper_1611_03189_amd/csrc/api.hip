@@ -83,7 +83,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
     if (!(o.eps >= 0.0) || !std::isfinite(o.eps) || o.leaf_size < 1 ||
         (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC) || o.dim < 0 || o.dim > 3 ||
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
-        !(o.tol >= 0.0) || (o.krylov != HSOLVE_PCG && o.krylov != HSOLVE_FPCG && o.krylov != HSOLVE_GMRES) ||
+        !(o.tol >= 0.0) || (o.krylov < HSOLVE_PCG || o.krylov > HSOLVE_STATIONARY) ||
         (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1 ||
         (o.overlap_pivots != 0 && o.overlap_pivots != 1))
         return HSOLVE_ERR_INVALID;
@@ -162,7 +162,9 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
     hsolve_status st = run(plan, "solve", [&] {
         std::vector<int> its(nrhs);
         std::vector<double> rel(nrhs);
-        if (P.opt.krylov == HSOLVE_GMRES)
+        if (P.opt.krylov == HSOLVE_STATIONARY)
+            hs::stationary(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, its.data(), rel.data());
+        else if (P.opt.krylov == HSOLVE_GMRES)
             hs::gmres(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.restart, its.data(), rel.data());
         else
             hs::pcg(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.krylov == HSOLVE_FPCG, its.data(),

@@ -317,6 +317,8 @@ void build_apply_schedule(Plan& P);
 void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
          bool flexible, int* its, double* rel);
+void stationary(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+                int* its, double* rel);
 void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
            int restart, int* its, double* rel);
 void spmv(Plan& P, const double* x, double* y);
@@ -378,6 +380,10 @@ template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t s);
 // restarted GMRES: y += sign * (*a) * x; y = s * x; r = b - w; x += Z y (y: device, k entries)
 void launch_axpy_dev(double* y, const double* x, const double* a, double sign, int n, hipStream_t s);
+// stationary iteration, active columns only: X += Z; R = B - Q
+void launch_add_multi(double* X, const double* Z, int64_t ld, int n, int nrhs, const int* active, hipStream_t s);
+void launch_sub_multi(double* R, const double* B, int64_t ldb, const double* Q, int64_t ld, int n, int nrhs,
+                      const int* active, hipStream_t s);
 void launch_scale(double* y, const double* x, double sc, int n, hipStream_t s);
 void launch_sub(double* r, const double* b, const double* w, int n, hipStream_t s);
 void launch_gemv_acc(double* x, const double* Z, int64_t ldz, const double* y, int k, int n, hipStream_t s);

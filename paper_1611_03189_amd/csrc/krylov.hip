@@ -136,6 +136,32 @@ void launch_copy_scalars(double* dst, const double* src, int n, hipStream_t s) {
     check_launch("k_copy_scalars");
 }
 
+// X(:, c) += Z(:, c), active columns only (stationary iteration)
+__global__ void k_add_multi(double* X, const double* Z, int64_t ld, int n, const int* active) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < n && active[c]) X[i + c * ld] += Z[i + c * ld];
+}
+
+void launch_add_multi(double* X, const double* Z, int64_t ld, int n, int nrhs, const int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_add_multi, dim3((n + NT - 1) / NT, nrhs), dim3(NT), 0, s, X, Z, ld, n, active);
+    check_launch("k_add_multi");
+}
+
+// R(:, c) = B(:, c) - Q(:, c), active columns only
+__global__ void k_sub_multi(double* R, const double* B, int64_t ldb, const double* Q, int64_t ld, int n,
+                            const int* active) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int c = blockIdx.y;
+    if (i < n && active[c]) R[i + c * ld] = B[i + c * ldb] - Q[i + c * ld];
+}
+
+void launch_sub_multi(double* R, const double* B, int64_t ldb, const double* Q, int64_t ld, int n, int nrhs,
+                      const int* active, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_multi, dim3((n + NT - 1) / NT, nrhs), dim3(NT), 0, s, R, B, ldb, Q, ld, n, active);
+    check_launch("k_sub_multi");
+}
+
 // ---------------------------------------------------------------------------------
 // Restarted GMRES (one column): Arnoldi vector updates with coefficients on the device
 // ---------------------------------------------------------------------------------

@@ -270,6 +270,77 @@ void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double
     copy_out();
 }
 
+// Stationary iteration x_{k+1} = x_k + A_H^{-1}(b - A x_k), x_0 = 0 (§7.1), all columns
+// together: one apply, one SpMV and one read-back of the residual norms per iteration. A
+// column stops changing once ||b - A x_k|| <= tol ||b|| (the residual is the true one).
+void stationary(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
+                int* its, double* rel) {
+    hipStream_t st = P.stream;
+    const int n = P.n;
+    const int64_t ld = n;
+    if (!P.d_krylov || P.krylov_cols < nrhs) {
+        P.d_krylov = P.apool.alloc_n<double>(size_t(n) * 5 * nrhs);
+        P.d_kscal = P.apool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
+        P.d_kflag = P.apool.alloc_n<int>(size_t(nrhs));
+        P.krylov_cols = nrhs;
+    }
+    if (!P.h_scalars || P.h_scalar_cols < nrhs) {
+        if (P.h_scalars) HS_HIP(hipHostFree(P.h_scalars));
+        HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_scalars), sizeof(double) * 3 * size_t(nrhs) + 64,
+                             hipHostMallocDefault));
+        P.h_scalar_cols = nrhs;
+    }
+    double* R = P.d_krylov;
+    double* Z = R + size_t(n) * nrhs;
+    double* Q = Z + size_t(n) * nrhs;
+    double* X = Q + size_t(n) * nrhs;
+    double* rr = P.d_kscal;
+    double* part = rr + 6 * size_t(nrhs);
+    int* active = P.d_kflag;
+    double* h = P.h_scalars;
+    int* hact = reinterpret_cast<int*>(h + 2 * size_t(nrhs));
+    HS_HIP(hipMemcpy2DAsync(R, sizeof(double) * ld, b, sizeof(double) * size_t(ldb), sizeof(double) * n, nrhs,
+                            hipMemcpyDeviceToDevice, st));
+    launch_fill<double>(X, 0.0, int64_t(n) * nrhs, st);
+    launch_dots(R, R, ld, n, nrhs, part, rr, st);
+    HS_HIP(hipMemcpyAsync(h, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+    HS_HIP(hipStreamSynchronize(st));
+    std::vector<double> nb(nrhs);
+    bool any = false;
+    for (int c = 0; c < nrhs; ++c) {
+        nb[c] = std::sqrt(h[c]);
+        hact[c] = nb[c] > 0.0 ? 1 : 0;
+        any = any || hact[c];
+        its[c] = 0;
+        rel[c] = 0.0;
+    }
+    HS_HIP(hipMemcpyAsync(active, hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+    HS_HIP(hipStreamSynchronize(st));
+    std::vector<int> live(hact, hact + nrhs);
+    for (int it = 1; any && it <= max_iter; ++it) {
+        apply(P, nrhs, R, n, Z, n);
+        launch_add_multi(X, Z, ld, n, nrhs, active, st);
+        launch_spmv_multi(P.d_row_ptr, P.d_col_idx, P.d_values, X, ld, Q, ld, n, nrhs, P.nnz, st);
+        launch_sub_multi(R, b, ldb, Q, ld, n, nrhs, active, st);
+        launch_dots(R, R, ld, n, nrhs, part, rr, st);
+        HS_HIP(hipMemcpyAsync(h, rr, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
+        HS_HIP(hipStreamSynchronize(st));
+        any = false;
+        for (int c = 0; c < nrhs; ++c) {
+            if (!live[c]) continue;
+            its[c] = it;
+            rel[c] = std::sqrt(h[c]) / nb[c];
+            if (!(rel[c] > tol)) live[c] = 0;
+            hact[c] = live[c];
+            any = any || live[c];
+        }
+        HS_HIP(hipMemcpyAsync(active, hact, sizeof(int) * nrhs, hipMemcpyHostToDevice, st));
+        HS_HIP(hipStreamSynchronize(st));        // the host flags are rewritten next iteration
+    }
+    HS_HIP(hipMemcpy2DAsync(x, sizeof(double) * size_t(ldx), X, sizeof(double) * ld, sizeof(double) * n, nrhs,
+                            hipMemcpyDeviceToDevice, st));
+}
+
 // Restarted GMRES, right-preconditioned (A M y = b, x = M y), one column at a time, x0 = 0:
 // Arnoldi with modified Gram-Schmidt (coefficients stay on the device), the preconditioned
 // basis Z kept so that x += Z y also holds when M varies slightly between calls (single-

@@ -20,7 +20,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hsolve.h")
 
 LORASP = 0
 GC = 1
-KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2}
+KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2, "stationary": 3}
 
 STATUS = {
     0: "HSOLVE_OK", 1: "HSOLVE_NOT_CONVERGED", -1: "HSOLVE_ERR_INVALID",

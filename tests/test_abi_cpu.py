@@ -92,7 +92,7 @@ def test_analyze_rejects_bad_input(lib):
         H.HSolver(big.row_ptr, big.col_idx, coords=big.coords, leaf=600)
     assert e.value.status == -1
     H.HSolver(big.row_ptr, big.col_idx, coords=big.coords, leaf=256).close()   # pairs of 512
-    for kw in ({"apply_prec": 16}, {"krylov": 3}, {"krylov": "gmres", "restart": 0}):
+    for kw in ({"apply_prec": 16}, {"krylov": 4}, {"krylov": "gmres", "restart": 0}):
         with pytest.raises(H.HSolveError) as e:
             H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
         assert e.value.status == -1, kw
@@ -101,7 +101,7 @@ def test_analyze_rejects_bad_input(lib):
 def test_options_accept_solver_variants(lib):
     p = pb.poisson(6, 2)
     for kw in ({"apply_prec": 32, "krylov": "fpcg"}, {"krylov": "gmres", "restart": 30},
-               {"apply_prec": 64, "krylov": "pcg"}, {"overlap_pivots": False}):
+               {"apply_prec": 64, "krylov": "pcg"}, {"overlap_pivots": False}, {"krylov": "stationary"}):
         with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
             assert S._h
 

@@ -156,3 +156,44 @@ def test_gmres_restart_and_fp32_apply():
             assert abs(st["iterations"] - itr) <= 1, (st, itr)
         say("gmres restart 3", prec, st["iterations"], itr)
         S.close()
+
+
+@pytest.mark.parametrize("name,N,dim,leaf", [
+    ("c1_poisson2d_32_leaf16", 32, 2, 16),
+    ("poisson3d_16_leaf64", 16, 3, 64),
+])
+def test_stationary_iteration(name, N, dim, leaf):
+    """x_{k+1} = x_k + A_H^{-1}(b - A x_k) (§7.1): after three steps the GPU iterate equals the
+    oracle's (each step is an apply to 1e-10, so the iterates agree to a few 1e-10), and run to
+    the end both reach 1e-10 in the same number of steps (within one)."""
+    say("stationary", name)
+    p = pb.poisson(N, dim)
+    A = p.to_scipy()
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=1e-2, variant=O.GC)
+    b = pb.rhs(p.n, 2, 51)
+    x_ref = np.zeros_like(b)
+    for _ in range(3):
+        x_ref = x_ref + O.apply(F, b - A @ x_ref)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2, krylov="stationary", max_iter=3,
+                  tol=0.0)
+    S.factor(dev(p.values))
+    x, st = S.solve(dev(b))
+    assert not st["converged"] and st["iterations"] == 3
+    assert rel(x.cpu().numpy(), x_ref) <= 1e-9, rel(x.cpu().numpy(), x_ref)
+    S.close()
+    its_ref = []
+    for c in range(2):
+        xr = np.zeros(p.n)
+        for k in range(1, 100):
+            xr = xr + O.apply(F, b[:, c] - A @ xr)
+            if np.linalg.norm(b[:, c] - A @ xr) <= TOL * np.linalg.norm(b[:, c]):
+                break
+        its_ref.append(k)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2, krylov="stationary")
+    S.factor(dev(p.values))
+    x, st = S.solve(dev(b))
+    x = x.cpu().numpy()
+    for c in range(2):
+        assert np.linalg.norm(b[:, c] - A @ x[:, c]) <= 2 * TOL * np.linalg.norm(b[:, c])
+    assert st["converged"] and abs(st["iterations"] - max(its_ref)) <= 1, (st, its_ref)
+    S.close()
