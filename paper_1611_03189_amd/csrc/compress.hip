@@ -59,17 +59,22 @@ struct CmpWork {
 };
 enum { INF_Q, INF_K2, INF_NN, INF_TNORM, INF_PIVMIN, INF_LO, INF_HI, INF_DONE };
 
-template <int MAXN>
+// threads of the compression workgroup for matrices in global memory (8 waves: more loads
+// in flight in the matrix-vector products and two trailing-update tiles at a time)
+constexpr int CMP_GLOBAL_NT = 512;
+
+template <int MAXN, int NTH = NT>
 struct CmpShared {
+    static constexpr int nth = NTH;    // threads of the workgroup that shares it
     double d[MAXN], e[MAXN], tau[MAXN], v[MAXN], w[MAXN];
     double tt[32];
     double bord[4][MAXN];      // GC border rows C (q <= 4) of the bordered tridiagonal
     double dq[16];             // its leading q x q block D
-    double red[NT / WAVE];
-    double redp[2][5 * (NT / WAVE)];    // double-buffered sums of the blocked reduction
+    double red[NTH / WAVE];
+    double redp[2][5 * (NTH / WAVE)];    // double-buffered sums of the blocked reduction
     double scal[4];
     int iscal[4];
-    int pts[NT + 1];
+    int pts[NTH + 1];
 };
 
 // sum_l A(0, l) x[l] for the row starting at A (column stride ld), eight loads in flight
@@ -103,6 +108,7 @@ __device__ inline void rank2_row(PA A, int ld, double vi, double wi, PV v, PW w,
 // two buffers, and a buffer is written again only after a later barrier.
 template <class SH>
 __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
+    constexpr int NTH = SH::nth;
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     double* red = S.redp[parity];
     parity ^= 1;
@@ -112,7 +118,7 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
     if (lane == 0) {
 #pragma unroll
         for (int r = 0; r < 5; ++r)
-            if (r < nv) red[r * (NT / WAVE) + w] = v[r];
+            if (r < nv) red[r * (NTH / WAVE) + w] = v[r];
     }
     __syncthreads();
 #pragma unroll
@@ -120,7 +126,7 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
         if (r < nv) {
             double t = 0.0;
 #pragma unroll
-            for (int i = 0; i < NT / WAVE; ++i) t += red[r * (NT / WAVE) + i];
+            for (int i = 0; i < NTH / WAVE; ++i) t += red[r * (NTH / WAVE) + i];
             v[r] = t;
         }
     }
@@ -135,12 +141,13 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
 template <class SH>
 __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nullptr, int bst = 0,
                                int nbr = 0) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x;
     int parity = 0;
     for (int j = 0; j + 2 < nn; ++j) {
         double* col = H + size_t(j) * ld;
         double nrm[1] = {0.0};
-        for (int i = j + 2 + tid; i < nn; i += NT) nrm[0] += col[i] * col[i];
+        for (int i = j + 2 + tid; i < nn; i += NTH) nrm[0] += col[i] * col[i];
         block_sums_1b(nrm, 1, S, parity);
         const double xn2 = nrm[0];
         const double alpha = col[j + 1];
@@ -152,7 +159,7 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
         }
         const int len = nn - j - 1;
         // the reflector, kept scaled in col(j+2..) and in S.v (each thread its own entries)
-        for (int i = tid; i < len; i += NT) {
+        for (int i = tid; i < len; i += NTH) {
             const double v = (i == 0) ? 1.0 : col[j + 1 + i] * scal;
             if (i > 0) col[j + 1 + i] = v;
             S.v[i] = v;
@@ -168,7 +175,7 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
             // v^T w and the border rows' products with v in one reduction
             double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
             const int hl = len / 2;
-            for (int tb = 0; tb < 2 * len; tb += NT) {       // uniform trip count (the shuffle)
+            for (int tb = 0; tb < 2 * len; tb += NTH) {       // uniform trip count (the shuffle)
                 const int t = tb + tid;
                 const int i = min(t >> 1, len - 1), c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
                 double acc = (t < 2 * len) ? dot_rows(T22 + i + size_t(c0) * ld, ld, S.v + c0, c1 - c0) : 0.0;
@@ -180,29 +187,29 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
                 }
             }
             double* B1 = nbr ? Bl + (j + 1) : nullptr;
-            for (int l = tid; l < len; l += NT) {
+            for (int l = tid; l < len; l += NTH) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     if (r < nbr) pv[1 + r] += B1[r * bst + l] * S.v[l];
             }
             block_sums_1b(pv, 1 + nbr, S, parity);
             const double K = 0.5 * tau * pv[0];
-            for (int t = tid; t < 2 * len; t += NT)        // the owners of S.w finish it
+            for (int t = tid; t < 2 * len; t += NTH)        // the owners of S.w finish it
                 if (!(t & 1)) S.w[t >> 1] -= K * S.v[t >> 1];
-            for (int l = tid; l < len; l += NT) {
+            for (int l = tid; l < len; l += NTH) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
                     if (r < nbr) B1[r * bst + l] -= tau * pv[1 + r] * S.v[l];
             }
             __syncthreads();
-            for (int t = tid; t < 2 * len; t += NT) {
+            for (int t = tid; t < 2 * len; t += NTH) {
                 const int i = t >> 1, c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
                 rank2_row(T22 + i + size_t(c0) * ld, ld, S.v[i], S.w[i], S.v + c0, S.w + c0, c1 - c0);
             }
             __syncthreads();
         }
     }
-    for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
+    for (int j = tid; j < nn; j += NTH) S.d[j] = H[j + size_t(j) * ld];
     if (tid == 0) {
         if (nn >= 2) {
             S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
@@ -229,18 +236,18 @@ __device__ inline double wave_sum_last(double v) {
 }
 
 // One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
-// stride ld, len >= 2). Lane l takes the row pairs (2l + 128k, 2l + 128k + 1), k < KM, loaded
-// as one 16-byte access; SB columns are taken at a time with every load issued before the
-// products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
+// stride ld, len >= 2). Lane l takes the row pairs (r, r + 1), r = 2l + rofs + rstep k, k < KM,
+// loaded as one 16-byte access; SB columns are taken at a time with every load issued before
+// the products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
 template <int KM>
 __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
-                                 int lane, double* acc) {
-    constexpr int SB = (KM <= 2) ? 16 : 8;
+                                 int lane, int rofs, int rstep, double* acc) {
+    constexpr int SB = (KM == 1) ? 16 : 8;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     int rr[KM];
 #pragma unroll
-    for (int k = 0; k < KM; ++k) rr[k] = min(2 * lane + 128 * k, len - 2);
+    for (int k = 0; k < KM; ++k) rr[k] = min(2 * lane + rofs + rstep * k, len - 2);
     for (int l0 = cb; l0 < ce; l0 += SB) {
         double a[SB][KM][2];
 #pragma unroll
@@ -273,6 +280,7 @@ __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, 
 template <class SH>
 __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double* Bl, int bst, int nbr,
                                    double* Vl, double* Wl, double* Pp, long long* prof = nullptr) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int nref = nn - 2;
     int parity = 0;
@@ -294,7 +302,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             // the squared norm of rows j+2.. on the way
             double* cb = S.w;
             double nrm[1] = {0.0};
-            for (int r = j + tid; r < nn; r += NT) {
+            for (int r = j + tid; r < nn; r += NTH) {
                 double a = col[r];
 #pragma unroll
                 for (int c = 0; c < TRI_NB - 1; ++c)
@@ -314,7 +322,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 scal = 1.0 / (alpha - beta);
             }
             // reflector: kept in H(j+2.., j) for the back-transformation and in Vl(:, i)
-            for (int r = tid; r < nn; r += NT) {
+            for (int r = tid; r < nn; r += NTH) {
                 const double vr = (r <= j) ? 0.0 : (r == j + 1 ? 1.0 : cb[r] * scal);
                 Vl[i * nn + r] = vr;
                 if (r >= j + 2) col[r] = vr;
@@ -330,33 +338,40 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             double* wcol = Wl + i * nn;
             if (tau != 0.0) {
                 // t1 = W(j+1:, :i)^T v, t2 = V(j+1:, :i)^T v: wave wv takes products wv, wv + 4, ..
-                for (int g = wv; g < 2 * i; g += NT / WAVE) {
+                for (int g = wv; g < 2 * i; g += NTH / WAVE) {
                     const double* P = (g < i) ? Wl + g * nn + j + 1 : Vl + (g - i) * nn + j + 1;
                     double a = 0.0;
                     for (int r = lane; r < len; r += WAVE) a += P[r] * v[r];
                     a = wave_sum_last(a);
                     if (lane == WAVE - 1) S.tt[g] = a;
                 }
-                // y = A(j+1:, j+1:) v, columns split over the waves, row pairs over the lanes
+                // y = A(j+1:, j+1:) v: the columns in 4 groups, the 128-row blocks dealt round
+                // robin to the RG waves of a group, row pairs over the lanes; partial sums of
+                // column group g in Pp(g nn + r)
                 {
+                    constexpr int RG = NTH / WAVE / 4, KMX = (4 + RG - 1) / RG;
+                    const int cg = wv % 4, rg = wv / 4;
                     const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
-                    const int cw = (len + 3) / 4, cbeg = wv * cw, cend = min(len, cbeg + cw);
+                    const int cw = (len + 3) / 4, cbeg = cg * cw, cend = min(len, cbeg + cw);
+                    const int kb = (len + 127) / 128;                // row blocks (at most 4)
+                    const int km = (kb > rg) ? (kb - rg + RG - 1) / RG : 0;   // this wave's, uniform
                     double acc[8];
-                    switch ((len + 127) / 128) {          // row-pair blocks of 128 rows, uniform
-                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        case 2: symv_part<2>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        case 3: symv_part<3>(A0, ld, v, len, cbeg, cend, lane, acc); break;
-                        default: symv_part<4>(A0, ld, v, len, cbeg, cend, lane, acc); break;
+                    switch (km) {
+                        case 0: break;
+                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
+                        case 2: symv_part<(KMX < 2 ? KMX : 2)>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
+                        case 3: symv_part<(KMX < 3 ? KMX : 3)>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
+                        default: symv_part<KMX>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
                     }
 #pragma unroll
-                    for (int k = 0; k < 4; ++k) {
-                        const int r0 = 2 * lane + 128 * k;
-                        if (r0 < len) {
+                    for (int k = 0; k < KMX; ++k) {
+                        const int r0 = 2 * lane + 128 * (rg + RG * k);
+                        if (k < km && r0 < len) {
                             if (r0 <= len - 2) {
-                                Pp[wv * nn + r0] = acc[2 * k];
-                                Pp[wv * nn + r0 + 1] = acc[2 * k + 1];
+                                Pp[cg * nn + r0] = acc[2 * k];
+                                Pp[cg * nn + r0 + 1] = acc[2 * k + 1];
                             } else {                        // last row of an odd length
-                                Pp[wv * nn + r0] = acc[2 * k + 1];
+                                Pp[cg * nn + r0] = acc[2 * k + 1];
                             }
                         }
                     }
@@ -365,7 +380,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 phase(6);
                 phase(2);
                 double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-                for (int r = tid; r < len; r += NT) {
+                for (int r = tid; r < len; r += NTH) {
                     double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
 #pragma unroll
                     for (int c = 0; c < TRI_NB - 1; ++c)
@@ -380,7 +395,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 }
                 // v^T w and the border rows' products with v, one reduction
                 double* B1 = nbr ? Bl + (j + 1) : nullptr;
-                for (int l = tid; l < len; l += NT) {
+                for (int l = tid; l < len; l += NTH) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         if (r < nbr) pv[1 + r] += B1[r * bst + l] * v[l];
@@ -388,30 +403,33 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 block_sums_1b(pv, 1 + nbr, S, parity);
                 phase(3);
                 const double K = 0.5 * tau * pv[0];
-                for (int r = tid; r < nn; r += NT)
+                for (int r = tid; r < nn; r += NTH)
                     wcol[r] = (r <= j) ? 0.0 : S.w[r - j - 1] - K * v[r - j - 1];
-                for (int l = tid; l < len; l += NT) {
+                for (int l = tid; l < len; l += NTH) {
 #pragma unroll
                     for (int r = 0; r < 4; ++r)
                         if (r < nbr) B1[r * bst + l] -= tau * pv[1 + r] * v[l];
                 }
             } else {
-                for (int r = tid; r < nn; r += NT) wcol[r] = 0.0;
+                for (int r = tid; r < nn; r += NTH) wcol[r] = 0.0;
             }
             __syncthreads();
             phase(4);
         }
         // trailing matrix (rows and columns from t0 on) -= V W^T + W V^T on the FP64 matrix
-        // cores: 64 x 64 tiles, wave wv takes the 32 x 32 quarter (rows 32 (wv % 2), columns
-        // 32 (wv / 2)) as 2 x 2 blocks of v_mfma_f64_16x16x4f64 with K = 2 nb (V and W side by
-        // side, padded to a multiple of 4). The product is formed transposed (operand A runs
+        // cores: 64 x 64 tiles, taken by groups of 4 waves (NG groups, tiles g, g + NG, ..);
+        // wave wq of a group takes the 32 x 32 quarter (rows 32 (wq % 2), columns 32 (wq / 2))
+        // as 2 x 2 blocks of v_mfma_f64_16x16x4f64 with K = 2 nb (V and W side by side, padded
+        // to a multiple of 4). The product is formed transposed (operand A runs
         // over the tile's columns, operand B over its rows), so that lane l's accumulator
         // register t is C(l % 16, l / 16 + 4 t) of its block: 16 consecutive rows per column.
         // The next tile's entries are loaded before the current tile is multiplied; rows and
         // columns past nn are read clamped and never stored.
         {
+            constexpr int NG = NTH / WAVE / 4;
             const int t0 = j0 + nb, tn = nn - t0, Tb = (tn + 63) / 64;
-            const int qr = 32 * (wv % 2), qc = 32 * (wv / 2);
+            const int tg = wv / 4, wq = wv % 4;
+            const int qr = 32 * (wq % 2), qc = 32 * (wq / 2);
             const int li = lane % 16, lk = lane / 16;
             const int ksteps = (2 * nb + 3) / 4;
             int rr[2], cc[2][4];
@@ -434,11 +452,11 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                         for (int t = 0; t < 4; ++t)
                             nxt[bi][bj][t] = H[min(rr[bi], nn - 1) + size_t(min(cc[bj][t], nn - 1)) * ld];
             };
-            if (Tb > 0) {
-                tile_pos(0);
+            if (tg < Tb * Tb) {
+                tile_pos(tg);
                 load_tile();
             }
-            for (int bt = 0; bt < Tb * Tb; ++bt) {
+            for (int bt = tg; bt < Tb * Tb; bt += NG) {
                 dbl4 acc[2][2];
                 int r_cur[2], c_cur[2][4];
 #pragma unroll
@@ -457,8 +475,8 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 for (int bj = 0; bj < 2; ++bj) sa[bj] = min(c_cur[bj][0] - lk + li, nn - 1);
 #pragma unroll
                 for (int bi = 0; bi < 2; ++bi) rbq[bi] = min(r_cur[bi], nn - 1);
-                if (bt + 1 < Tb * Tb) {
-                    tile_pos(bt + 1);
+                if (bt + NG < Tb * Tb) {
+                    tile_pos(bt + NG);
                     load_tile();
                 }
                 for (int ks = 0; ks < ksteps; ++ks) {
@@ -493,7 +511,7 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
     }
     if (prof && tid == 0)
         for (int k = 0; k < 8; ++k) prof[k] = pc[k];
-    for (int j = tid; j < nn; j += NT) S.d[j] = H[j + size_t(j) * ld];
+    for (int j = tid; j < nn; j += NTH) S.d[j] = H[j + size_t(j) * ld];
     if (tid == 0) {
         if (nn >= 2) {
             S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
@@ -543,17 +561,19 @@ __device__ void tridiag_bounds(int nn, SH& S) {
 // largest eigenvalue by parallel multisection (after tridiag_bounds)
 template <class SH>
 __device__ double largest_eigenvalue(int nn, SH& S) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x;
     double lo = S.scal[0], hi = S.scal[1];
     const double pivmin = S.scal[2];
+    constexpr int NP = NTH < 256 ? NTH : 256;          // points per round (threads taking part)
     for (int round = 0; round < 10; ++round) {
-        const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
-        S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
+        const double x = lo + (hi - lo) * double(tid + 1) / double(NP + 1);
+        if (tid < NP) S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
         __syncthreads();
         int t = 0;
-        while (t < NT && !S.pts[t]) ++t;
-        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
-        const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
+        while (t < NP && !S.pts[t]) ++t;
+        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NP + 1);
+        const double xh = (t == NP) ? hi : lo + (hi - lo) * double(t + 1) / double(NP + 1);
         lo = xl;
         hi = xh;
         __syncthreads();
@@ -665,37 +685,43 @@ __device__ void bordered_counts2(const double* d, const double* e, int nn, const
 // block-wide minimum of an int
 template <class SH>
 __device__ inline int block_min_int(int v, SH& S) {
+    constexpr int NTH = SH::nth;
     for (int o = WAVE / 2; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, WAVE));
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
     __syncthreads();
     if (lane == 0) S.pts[w] = v;
     __syncthreads();
     int r = S.pts[0];
-    for (int i = 1; i < NT / WAVE; ++i) r = min(r, S.pts[i]);
+    for (int i = 1; i < NTH / WAVE; ++i) r = min(r, S.pts[i]);
     return r;
 }
 
 // largest eigenvalue of the bordered matrix by multisection of [lo, hi] (lo below it): each
-// round evaluates NP = 4 NT (two-row border) or NT points and keeps the subinterval where
-// the count above x drops to zero
+// round evaluates one point per thread on up to 256 threads (more waves per SIMD would slow
+// the latency-bound recurrences) and keeps the subinterval where the count above x drops to
+// zero
 template <class SH>
 __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x;
     const double pivmin = S.scal[2];
+    constexpr int NPT = NTH < 256 ? NTH : 256;        // threads taking part (points per round)
     if (q <= 2) {
         // one point per thread: with one wave per SIMD the interleaved recurrences of several
         // points are bound by instruction issue, one recurrence by its latency only
-        constexpr int NX = 1, NP = NX * NT;
+        constexpr int NX = 1, NP = NX * NPT;
         for (int round = 0; round < 7; ++round) {      // (NP + 1)^7 > 2^56
             double x[NX];
             int cnt[NX];
 #pragma unroll
             for (int k = 0; k < NX; ++k) x[k] = lo + (hi - lo) * double(NX * tid + k + 1) / double(NP + 1);
-            bordered_counts2<NX>(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin, cnt);
             int first = NP;                                   // first point with no eigenvalue above
+            if (tid < NPT) {
+                bordered_counts2<NX>(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin, cnt);
 #pragma unroll
-            for (int k = NX - 1; k >= 0; --k)
-                if (cnt[k] == 0) first = NX * tid + k;
+                for (int k = NX - 1; k >= 0; --k)
+                    if (cnt[k] == 0) first = NX * tid + k;
+            }
             const int t = block_min_int(first, S);
             const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NP + 1);
             const double xh = (t == NP) ? hi : lo + (hi - lo) * double(t + 1) / double(NP + 1);
@@ -704,12 +730,13 @@ __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
         }
         return 0.5 * (lo + hi);
     }
-    for (int round = 0; round < 7; ++round) {      // (NT + 1)^7 > 2^56
-        const double x = lo + (hi - lo) * double(tid + 1) / double(NT + 1);
-        const int first = (bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0) ? tid : NT;
+    for (int round = 0; round < 7; ++round) {      // (NPT + 1)^7 > 2^56
+        const double x = lo + (hi - lo) * double(tid + 1) / double(NPT + 1);
+        const int first =
+            (tid < NPT && bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0) ? tid : NPT;
         const int t = block_min_int(first, S);
-        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NT + 1);
-        const double xh = (t == NT) ? hi : lo + (hi - lo) * double(t + 1) / double(NT + 1);
+        const double xl = (t == 0) ? lo : lo + (hi - lo) * double(t) / double(NPT + 1);
+        const double xh = (t == NPT) ? hi : lo + (hi - lo) * double(t + 1) / double(NPT + 1);
         lo = xl;
         hi = xh;
     }
@@ -780,17 +807,18 @@ __device__ inline double start_value(int i, int c) {
 // Two-sided application of I - tau v v^T to the symmetric m x m matrix H.
 template <class SH, class PH, class PV>
 __device__ void reflect_two_sided(PH H, int ld, int m, PV v, double tau, SH& S) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x;
     double pv_part = 0.0;
-    for (int i = tid; i < m; i += NT) {
+    for (int i = tid; i < m; i += NTH) {
         const double acc = tau * dot_rows(H + i, ld, v, m);
         S.w[i] = acc;
         pv_part += acc * v[i];
     }
-    const double K = 0.5 * tau * block_sum(pv_part, S.red);
-    for (int i = tid; i < m; i += NT) S.w[i] -= K * v[i];
+    const double K = 0.5 * tau * block_sum<NTH>(pv_part, S.red);
+    for (int i = tid; i < m; i += NTH) S.w[i] -= K * v[i];
     __syncthreads();
-    for (int i = tid; i < m; i += NT) rank2_row(H + i, ld, v[i], S.w[i], v, S.w, m);
+    for (int i = tid; i < m; i += NTH) rank2_row(H + i, ld, v[i], S.w[i], v, S.w, m);
     __syncthreads();
 }
 
@@ -804,6 +832,7 @@ __device__ void reflect_two_sided(PH H, int ld, int m, PV v, double tau, SH& S) 
 template <class SH>
 __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_G double* gcv,
                                  const HS_G double* gct, double* buf, SH& S) {
+    constexpr int NTH = SH::nth;
     const int tid = threadIdx.x;
     double* Vs = buf;
     double* Y = Vs + size_t(q) * m;
@@ -812,11 +841,11 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
     double* VV = Ts + 64;
     double* VY = VV + 64;
     double* Z = VY + 64;
-    for (int e = tid; e < q * m; e += NT) Vs[e] = gcv[e];
+    for (int e = tid; e < q * m; e += NTH) Vs[e] = gcv[e];
     __syncthreads();
     // Y = H V: two adjacent lanes per row, each over half of the columns
     const int hm = m / 2;
-    for (int tb = 0; tb < 2 * m; tb += NT) {             // uniform trip count (the shuffle)
+    for (int tb = 0; tb < 2 * m; tb += NTH) {             // uniform trip count (the shuffle)
         const int t = tb + tid;
         const int i = min(t >> 1, m - 1), c0 = (t & 1) ? hm : 0, c1 = (t & 1) ? m : hm;
         double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
@@ -883,7 +912,7 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
             }
     }
     __syncthreads();
-    for (int i = tid; i < m; i += NT)                     // Wm = Y T - V Z / 2
+    for (int i = tid; i < m; i += NTH)                     // Wm = Y T - V Z / 2
         for (int b = 0; b < q; ++b) {
             double acc = 0.0;
             for (int c = 0; c <= b; ++c) acc += Y[i + c * m] * Ts[c + 8 * b];
@@ -892,7 +921,7 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
         }
     __syncthreads();
     // H -= Wm V^T + V Wm^T: two adjacent lanes per row, row values in registers
-    for (int t = tid; t < 2 * m; t += NT) {
+    for (int t = tid; t < 2 * m; t += NTH) {
         const int i = t >> 1, c0 = (t & 1) ? hm : 0, c1 = (t & 1) ? m : hm;
         double wi[8], vi[8];
 #pragma unroll
@@ -925,10 +954,11 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
 }
 
 template <bool LDS, int MAXN>
-__global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
+__global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
                                                     int* rank) {
+    constexpr int NTH = LDS ? NT : CMP_GLOBAL_NT;
     extern __shared__ double lds[];
-    __shared__ CmpShared<MAXN> S;
+    __shared__ CmpShared<MAXN, NTH> S;
     const CompressTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
     CmpWork Wk(T.work, m);
@@ -952,22 +982,22 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     double gm[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
     {
         int e = tid;
-        for (; e + 7 * NT < m * m; e += 8 * NT) {
+        for (; e + 7 * NTH < m * m; e += 8 * NTH) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) gm[u] = fmax(gm[u], fabs(G[e + u * NT]));
+            for (int u = 0; u < 8; ++u) gm[u] = fmax(gm[u], fabs(G[e + u * NTH]));
         }
-        for (; e < m * m; e += NT) gm[0] = fmax(gm[0], fabs(G[e]));
+        for (; e < m * m; e += NTH) gm[0] = fmax(gm[0], fabs(G[e]));
     }
-    const double gmax = block_max(fmax(fmax(fmax(gm[0], gm[1]), fmax(gm[2], gm[3])),
+    const double gmax = block_max<NTH>(fmax(fmax(fmax(gm[0], gm[1]), fmax(gm[2], gm[3])),
                                        fmax(fmax(gm[4], gm[5]), fmax(gm[6], gm[7]))), S.red);
     const double gscale = (gmax > 0.0 && isfinite(gmax)) ? 1.0 / gmax : 1.0;
     double fro = 0.0;
-    copy_block(H, ld, G, m, m, m, [&](double x, int, int) {
+    copy_block<NTH>(H, ld, G, m, m, m, [&](double x, int, int) {
         const double g = x * gscale;
         fro += g * g;
         return g;
     });
-    fro = sqrt(block_sum(fro, S.red));
+    fro = sqrt(block_sum<NTH>(fro, S.red));
     stamp(1);
     // GC with at most 4 kept vectors: lambda_max(G) comes from the bordered tridiagonal form
     // of the projected matrix (one tridiagonalisation); otherwise G is tridiagonalised first.
@@ -985,49 +1015,49 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             const HS_G double* z = gp(T.Z) + size_t(c) * m;
             HS_G double* u = U + size_t(q) * m;
             double part = 0.0;
-            for (int i = tid; i < m; i += NT) {
+            for (int i = tid; i < m; i += NTH) {
                 u[i] = z[i];
                 part += z[i] * z[i];
             }
-            const double nz = sqrt(block_sum(part, S.red));
+            const double nz = sqrt(block_sum<NTH>(part, S.red));
             if (nz == 0.0) continue;
             for (int pass = 0; pass < 2; ++pass)
                 for (int b = 0; b < q; ++b) {
                     const HS_G double* ub = U + size_t(b) * m;
                     double pp = 0.0;
-                    for (int i = tid; i < m; i += NT) pp += ub[i] * u[i];
-                    const double dot = block_sum(pp, S.red);
-                    for (int i = tid; i < m; i += NT) u[i] -= dot * ub[i];
+                    for (int i = tid; i < m; i += NTH) pp += ub[i] * u[i];
+                    const double dot = block_sum<NTH>(pp, S.red);
+                    for (int i = tid; i < m; i += NTH) u[i] -= dot * ub[i];
                     __syncthreads();
                 }
             part = 0.0;
-            for (int i = tid; i < m; i += NT) part += u[i] * u[i];
-            const double nu = sqrt(block_sum(part, S.red));
+            for (int i = tid; i < m; i += NTH) part += u[i] * u[i];
+            const double nu = sqrt(block_sum<NTH>(part, S.red));
             if (nu > 1e-10 * nz) {
-                for (int i = tid; i < m; i += NT) u[i] /= nu;
+                for (int i = tid; i < m; i += NTH) u[i] /= nu;
                 __syncthreads();
                 ++q;
             }
         }
         // reflectors H_t with (H_{q-1}..H_0) U1 = [R; 0]; project G on the complement of U1
         if (!bordered)
-            copy_block(H, ld, G, m, m, m, [&](double x, int, int) { return x * gscale; });
+            copy_block<NTH>(H, ld, G, m, m, m, [&](double x, int, int) { return x * gscale; });
         __syncthreads();
         double* x = S.v;        // free until the next tridiagonalisation
         for (int t = 0; t < q; ++t) {
-            for (int i = tid; i < m; i += NT) x[i] = U[i + size_t(t) * m];
+            for (int i = tid; i < m; i += NTH) x[i] = U[i + size_t(t) * m];
             __syncthreads();
             for (int b = 0; b < t; ++b) {
                 const HS_G double* vb = Wk.gcv + size_t(b) * m;
                 double pp = 0.0;
-                for (int i = tid; i < m; i += NT) pp += vb[i] * x[i];
-                const double dot = block_sum(pp, S.red) * Wk.gct[b];
-                for (int i = tid; i < m; i += NT) x[i] -= dot * vb[i];
+                for (int i = tid; i < m; i += NTH) pp += vb[i] * x[i];
+                const double dot = block_sum<NTH>(pp, S.red) * Wk.gct[b];
+                for (int i = tid; i < m; i += NTH) x[i] -= dot * vb[i];
                 __syncthreads();
             }
             double part = 0.0;
-            for (int i = t + 1 + tid; i < m; i += NT) part += x[i] * x[i];
-            const double xn2 = block_sum(part, S.red);
+            for (int i = t + 1 + tid; i < m; i += NTH) part += x[i] * x[i];
+            const double xn2 = block_sum<NTH>(part, S.red);
             const double alpha = x[t];
             HS_G double* vt = Wk.gcv + size_t(t) * m;
             double tau = 0.0;
@@ -1035,9 +1065,9 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
                 const double beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
                 tau = (beta - alpha) / beta;
                 const double scal = 1.0 / (alpha - beta);
-                for (int i = tid; i < m; i += NT) vt[i] = (i < t) ? 0.0 : (i == t ? 1.0 : x[i] * scal);
+                for (int i = tid; i < m; i += NTH) vt[i] = (i < t) ? 0.0 : (i == t ? 1.0 : x[i] * scal);
             } else {
-                for (int i = tid; i < m; i += NT) vt[i] = (i == t) ? 1.0 : 0.0;
+                for (int i = tid; i < m; i += NTH) vt[i] = (i == t) ? 1.0 : 0.0;
             }
             if (tid == 0) Wk.gct[t] = tau;
             __syncthreads();
@@ -1053,7 +1083,7 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
         const int nt = m - q;
         if (nt > 0) {
             if (bordered) {      // border rows move to LDS for the reduction
-                for (int i = tid; i < nt; i += NT)
+                for (int i = tid; i < nt; i += NTH)
                     for (int r = 0; r < q; ++r) S.bord[r][i] = H[r + size_t(q + i) * ld];
                 __syncthreads();
             }
@@ -1072,9 +1102,9 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
             // lower end: the largest diagonal entry of K (at most lambda_max); below the
             // largest eigenvalue of T the Sturm part of the count alone is already positive
             double dmax = -DBL_MAX;
-            for (int i = tid; i < nt; i += NT) dmax = fmax(dmax, S.d[i]);
+            for (int i = tid; i < nt; i += NTH) dmax = fmax(dmax, S.d[i]);
             if (tid < q) dmax = fmax(dmax, S.dq[tid + 4 * tid]);
-            dmax = block_max(dmax, S.red);
+            dmax = block_max<NTH>(dmax, S.red);
             const double lo = dmax - 4.0 * DBL_EPSILON * fro - 1e-300;
             const double hi = fro * (1.0 + 1e-12) + 1e-300;
             lam_max = bordered_largest(nt, q, lo, hi, S);
@@ -1097,17 +1127,17 @@ __global__ __launch_bounds__(NT) void k_comp_reduce(const CompressTask* tasks, i
     int k2 = S.iscal[3];
     if (variant == HSOLVE_LORASP && gmax == 0.0 && eps > 0.0) {
         // A_sw exactly zero: the kept direction is the first unit vector
-        for (int i = tid; i < m; i += NT) U[i] = (i == 0) ? 1.0 : 0.0;
+        for (int i = tid; i < m; i += NTH) U[i] = (i == 0) ? 1.0 : 0.0;
         k2 = 0;
         q = 1;
     }
-    for (int i = tid; i < nn; i += NT) {
+    for (int i = tid; i < nn; i += NTH) {
         Wk.d[i] = S.d[i];
         Wk.e[i] = S.e[i];
         Wk.tau[i] = S.tau[i];
     }
     if (LDS)
-        for (int e = tid; e < m * m; e += NT) Wk.H[e] = H[(e % m) + (e / m) * ld];
+        for (int e = tid; e < m * m; e += NTH) Wk.H[e] = H[(e % m) + (e / m) * ld];
     if (tid == 0) {
         Wk.info[INF_Q] = q;
         Wk.info[INF_K2] = k2;
@@ -1628,7 +1658,7 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
             const size_t bytes = size_t(2 * TRI_NB + 4) * CMP_MAX * sizeof(double);
             static std::once_flag once;
             set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>), bytes);
-            hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(NT), bytes, s, d_tasks,
+            hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(CMP_GLOBAL_NT), bytes, s, d_tasks,
                                variant, eps, d_rank);
             check_launch("k_comp_reduce<global>");
         }

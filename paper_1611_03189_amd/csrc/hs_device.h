@@ -88,11 +88,11 @@ __device__ inline double wave_max(double v) {
 // dst(i, c) = f(src(i, c), i, c) over a rows x cols column-major block by the whole
 // workgroup: consecutive threads take consecutive elements (coalesced), and each thread
 // issues eight loads before its stores, so the copy is not bound by one load's latency.
-template <class PD, class PS, class F>
+template <int NTH = NT, class PD, class PS, class F>
 __device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int rows, int cols, F f) {
     const int total = rows * cols;
     if (total <= 0) return;
-    const int dq = NT / rows, dr = NT % rows;
+    const int dq = NTH / rows, dr = NTH % rows;
     int e = threadIdx.x, i = e % rows, c = e / rows;
     auto step = [&]() {
         i += dr;
@@ -102,7 +102,7 @@ __device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int ro
             ++c;
         }
     };
-    for (; e + 7 * NT < total; e += 8 * NT) {
+    for (; e + 7 * NTH < total; e += 8 * NTH) {
         int ii[8], cc[8];
         double v[8];
 #pragma unroll
@@ -115,15 +115,15 @@ __device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int ro
 #pragma unroll
         for (int u = 0; u < 8; ++u) dst[ii[u] + size_t(cc[u]) * ldd] = f(v[u], ii[u], cc[u]);
     }
-    for (; e < total; e += NT) {
+    for (; e < total; e += NTH) {
         dst[i + size_t(c) * ldd] = f(src[i + size_t(c) * lds], i, c);
         step();
     }
 }
 
-template <class PD, class PS>
+template <int NTH = NT, class PD, class PS>
 __device__ inline void copy_block(PD dst, size_t ldd, PS src, size_t lds, int rows, int cols) {
-    copy_block(dst, ldd, src, lds, rows, cols, [](double x, int, int) { return x; });
+    copy_block<NTH>(dst, ldd, src, lds, rows, cols, [](double x, int, int) { return x; });
 }
 
 // Orders the memory accesses of the lanes of one wave around divergent code (a result that
@@ -133,7 +133,8 @@ __device__ inline void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// block-wide sum; `red` must hold NT/WAVE doubles; result valid in every thread
+// block-wide sum over NTH threads; `red` must hold NTH/WAVE doubles; result valid in every thread
+template <int NTH = NT>
 __device__ inline double block_sum(double v, double* red) {
     v = wave_sum(v);
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -141,10 +142,11 @@ __device__ inline double block_sum(double v, double* red) {
     if (lane == 0) red[w] = v;
     __syncthreads();
     double s = 0.0;
-    for (int i = 0; i < NT / WAVE; ++i) s += red[i];
+    for (int i = 0; i < NTH / WAVE; ++i) s += red[i];
     return s;
 }
 
+template <int NTH = NT>
 __device__ inline double block_max(double v, double* red) {
     v = wave_max(v);
     const int lane = threadIdx.x % WAVE, w = threadIdx.x / WAVE;
@@ -152,7 +154,7 @@ __device__ inline double block_max(double v, double* red) {
     if (lane == 0) red[w] = v;
     __syncthreads();
     double s = red[0];
-    for (int i = 1; i < NT / WAVE; ++i) s = fmax(s, red[i]);
+    for (int i = 1; i < NTH / WAVE; ++i) s = fmax(s, red[i]);
     return s;
 }
 
