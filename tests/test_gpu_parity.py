@@ -69,6 +69,33 @@ def test_apply_matches_oracle(name, make, leaf, eps, variant):
     S.close()
 
 
+def poly_phi(p, k):
+    """k smooth vectors on the grid coordinates (1, x, y, xy, x^2), columns of an n x k array."""
+    c = p.coords
+    x = (c - c.mean(0)) / np.ptp(c, 0)
+    cols = [np.ones(p.n), x[:, 0], x[:, 1], x[:, 0] * x[:, 1], x[:, 0] ** 2]
+    return np.asfortranarray(np.column_stack(cols[:k]))
+
+
+WIDE = [("gc_1vec", "gc", 1), ("gc_3vec", "gc", 3), ("gc_5vec", "gc", 5), ("lorasp", "lorasp", 0)]
+
+
+@pytest.mark.parametrize("name,variant,k", WIDE, ids=[c[0] for c in WIDE])
+def test_wide_super_nodes_match_oracle(name, variant, k):
+    """Leaves of 256 unknowns (2-D Poisson 64^2): the leaf compressions take the global-memory
+    form of the reduction (more than 128 unknowns per super node). With GC the kept vectors
+    enter as a bordered tridiagonal (1 vector: 2 columns of Z = [phi_s, A_sw phi_w]), as one
+    block reflector (3 vectors: 6 columns) and reflector by reflector (5 vectors: 10 columns)."""
+    say("wide", name)
+    p = pb.poisson(64, 2)
+    phi = poly_phi(p, k) if k > 1 else None
+    F, S, r, z_ref, z = run_pair(p, 256, 1e-2, variant, phi=phi)
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
+    assert rel(z, z_ref) <= TOL, (name, rel(z, z_ref))
+    S.close()
+
+
 @pytest.mark.parametrize("variant", ["gc", "lorasp"])
 def test_eps_zero_exact_on_gpu(variant):
     say("eps0", variant)
