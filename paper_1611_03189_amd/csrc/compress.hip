@@ -10,7 +10,8 @@
 //           eigenvectors of the projected Gram matrix (W G W^T)(q:, q:) with
 //           lambda > eps^2 lambda_max(G), mapped back by W^T; U = [U1, U2].
 // Eigen-solver, three kernels per batch of nodes:
-//   k_comp_reduce  (one workgroup per node) scale G by its largest entry (decisions are
+//   k_comp_reduce  (one workgroup per node: 256 threads when the matrix sits in LDS, 512
+//                  when it stays in global memory) scale G by its largest entry (decisions are
 //                  relative); GC basis and projection; Householder tridiagonalisation of the
 //                  projected matrix (unblocked in LDS when m <= CMP_LDS_MAX, blocked by
 //                  panels of TRI_NB reflectors for larger m). lambda_max(G): for GC with at

@@ -7,7 +7,7 @@
 
 namespace hs {
 
-constexpr int NT = 256;          // threads per workgroup (4 waves)
+constexpr int NT = 256;          // threads per workgroup (4 waves) unless a kernel states another count
 constexpr int WAVE = 64;
 
 // Global-memory pointers with an explicit address space. Pointers read from task tables
