@@ -963,7 +963,10 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
     const CompressTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
     CmpWork Wk(T.work, m);
-    const int ld = LDS ? m + 1 : m;
+    // in LDS a fixed odd column stride: the unrolled column offsets of the row products
+    // become immediate LDS offsets (fewer address instructions), and rows stay bank-spread
+    constexpr int LDL = MAXN + 1;
+    const int ld = LDS ? LDL : m;
     using HPtr = typename std::conditional<LDS, double*, HS_G double*>::type;
     HPtr H;
     if constexpr (LDS) H = lds;
@@ -972,7 +975,7 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
     const HS_G double* G = gp(T.G);
     // Householder tridiagonalisation: unblocked in LDS, blocked for global matrices
     auto tri = [&](HPtr A, int n, double* Bl, int nbr) {
-        if constexpr (LDS) tridiagonalize(A, ld, n, S, Bl, MAXN, nbr);
+        if constexpr (LDS) tridiagonalize(A, LDL, n, S, Bl, MAXN, nbr);
         else tridiagonalize_blk(A, ld, n, S, Bl, MAXN, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN,
                                 T.tstamp ? T.tstamp + 8 : nullptr);
     };
@@ -1651,7 +1654,7 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
             static std::once_flag once;
             set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<true, CMP_LDS_MAX>),
                           size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) * sizeof(double));
-            const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(double);
+            const size_t bytes = size_t(max_m) * (CMP_LDS_MAX + 1) * sizeof(double);
             hipLaunchKernelGGL((k_comp_reduce<true, CMP_LDS_MAX>), dim3(ntasks), dim3(NT), bytes, s,
                                d_tasks, variant, eps, d_rank);
             check_launch("k_comp_reduce<lds>");
