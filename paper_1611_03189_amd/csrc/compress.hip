@@ -222,8 +222,9 @@ __device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nu
     __syncthreads();
 }
 
-// panel width of the blocked tridiagonalisation
-constexpr int TRI_NB = 12;
+// panel width of the blocked tridiagonalisation (8 measured faster than 10 and 12 with 8 waves:
+// the per-column corrections with the panel shrink more than the trailing passes grow)
+constexpr int TRI_NB = 8;
 
 // Sum over the wave left in lane 63 only (the DPP steps of wave_sum without the read-back).
 __device__ inline double wave_sum_last(double v) {
