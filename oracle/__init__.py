@@ -25,11 +25,11 @@ the code that takes them.
 """
 from .tree import tree_depth, cluster_leaves, footprint_adjacency
 from .hsolver import (Factorization, NotSPDError, compress, pivot, eliminate_node,
-                      factor, apply, apply_matrix, LORASP, GC)
+                      factor, apply, apply_matrix, level_eps, LORASP, GC)
 from .krylov import pcg, fpcg, gmres, stationary
 
 __all__ = [
     "tree_depth", "cluster_leaves", "footprint_adjacency",
     "Factorization", "NotSPDError", "compress", "pivot", "eliminate_node", "factor",
-    "apply", "apply_matrix", "LORASP", "GC", "pcg", "gmres", "stationary",
+    "apply", "apply_matrix", "level_eps", "LORASP", "GC", "pcg", "gmres", "stationary",
 ]

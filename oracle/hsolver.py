@@ -97,7 +97,8 @@ def orth_columns(Z: np.ndarray, tol: float = ORTH_DROP_TOL) -> np.ndarray:
 
 
 def compress(A_sw: np.ndarray, eps: float, variant: int,
-             phi_s: np.ndarray | None = None, phi_w: np.ndarray | None = None) -> np.ndarray:
+             phi_s: np.ndarray | None = None, phi_w: np.ndarray | None = None,
+             margins: list | None = None) -> np.ndarray:
     """Orthonormal U (m x k) for the low-rank part of the well-separated block A_sw.
 
     LoRaSp: U = leading left singular vectors of A_sw with sigma_j > eps * sigma_1.
@@ -105,6 +106,10 @@ def compress(A_sw: np.ndarray, eps: float, variant: int,
             A_sw projected on the complement of U1, with sigma_j > eps * sigma_1(A_sw);
             U = [U1, U2]. Then A_sw phi_w and phi_s lie in span U (eq. preserve), so
             U U^T A_sw phi_w = A_sw phi_w and R U^T phi_s = A_ws phi_s (eq. compression_xy).
+
+    ``margins``, when given, receives min_j |sigma_j / sigma_1(A_sw) - eps| over the singular
+    values the threshold decides on (reading R16: a rank decided within ~1e-8 of the
+    threshold can flip under rounding, so a parity case must keep clear of it).
     """
     m, wt = A_sw.shape
     sigma1 = np.linalg.svd(A_sw, compute_uv=False)[0] if min(m, wt) > 0 else 0.0
@@ -126,6 +131,8 @@ def compress(A_sw: np.ndarray, eps: float, variant: int,
         k2 = cap                                        # R2: no truncation
     else:
         k2 = int(np.count_nonzero(sb[:cap] > eps * sigma1))
+        if margins is not None and cap > 0 and sigma1 > 0.0:
+            margins.append(float(np.min(np.abs(sb[:cap] / sigma1 - eps))))
     if U1.shape[1] + k2 == 0 and cap > 0:
         k2 = 1                                          # R5: keep at least one direction
         if sigma1 == 0.0:                               # A_sw exactly zero: first unit vector
@@ -234,12 +241,42 @@ class Factorization:
     eps: float
     variant: int
     root_chol: object = None      # only when L == 0
+    margins: list = field(default_factory=list)   # R16 margin of every thresholded compression
+    level_eps: dict = field(default_factory=dict)  # d -> compression tolerance used at depth d
 
     def ranks(self, d):
         return [self.levels[d].red_size.get(s, 0) for s in range(1 << d)]
 
+    @property
+    def tie_margin(self) -> float:
+        """Smallest |sigma_j / sigma_1 - eps| met by any rank decision (R16); inf if none."""
+        return min(self.margins) if self.margins else float("inf")
 
-def eliminate_node(st: LevelState, s: int, adj: set, eps: float, variant: int) -> NodeFactor:
+
+EPS_SCHEDULES = ("constant", "shrink", "grow")
+
+
+def level_eps(eps: float, schedule: str, d: int, L: int, n: int, dim: int) -> float:
+    """Compression tolerance at depth d (§7.1 "3D cases", Table 3 and the list before it).
+
+    The leaf level of the schedules is the first super-node depth lmax = L - 1.
+    constant: eps.  shrink: eps 2^((d - lmax)/3), the paper's adaptive GC choice (eps at the
+    leaves, smaller toward the root).  grow: eps h 2^((lmax - d)/3) with h = n^(-1/dim), the
+    paper's adaptive LoRaSp choice (small at the leaves, larger toward the root).
+    """
+    lmax = max(L - 1, 0)
+    if schedule == "constant":
+        return eps
+    if schedule == "shrink":
+        return eps * 2.0 ** ((d - lmax) / 3.0)
+    if schedule == "grow":
+        h = float(n) ** (-1.0 / max(1, dim))
+        return eps * h * 2.0 ** ((lmax - d) / 3.0)
+    raise ValueError(f"unknown eps schedule {schedule!r}")
+
+
+def eliminate_node(st: LevelState, s: int, adj: set, eps: float, variant: int,
+                   margins: list | None = None) -> NodeFactor:
     """Compress, extend and eliminate super node s of the current level state.
 
     §3.2: N(s) are the current nodes with a block to s that are neighbours of s, W(s)
@@ -255,7 +292,7 @@ def eliminate_node(st: LevelState, s: int, adj: set, eps: float, variant: int) -
         A_sW = np.hstack([st.blocks[(s, w)] for w in W])
         phi_s = st.phi.get(s)
         phi_W = np.vstack([st.phi[w] for w in W]) if variant != LORASP else None
-        U = compress(A_sW, eps, variant, phi_s, phi_W)
+        U = compress(A_sW, eps, variant, phi_s, phi_W, margins=margins)
         RT = U.T @ A_sW                               # R^T = U^T A_sw (eq. compression_sw)
     else:
         A_sW = np.zeros((m, 0))
@@ -322,11 +359,13 @@ def _leaf_blocks(row_ptr, col_idx, values, leaves, leaf_of, n):
 
 
 def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1e-2,
-           variant: int = GC, phi: np.ndarray | None = None) -> Factorization:
+           variant: int = GC, phi: np.ndarray | None = None,
+           eps_schedule: str = "constant") -> Factorization:
     """Algorithm "Setup": build the hierarchical factorization of the SPD matrix A.
 
     ``phi`` (n x p) are the vectors GC preserves; default is the constant vector
-    (GC-constant). Ignored for LoRaSp.
+    (GC-constant). Ignored for LoRaSp. ``eps_schedule`` picks the per-level tolerance
+    (see ``level_eps``; dim is the coordinate dimension, 1 without coordinates).
     """
     n = len(row_ptr) - 1
     L = tree_depth(n, leaf)
@@ -357,7 +396,12 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
             red.partners.setdefault(i, set()).add(j)
 
     levels = {}
+    margins: list = []
+    eps_at = {}
+    dim = 1 if coords is None else np.asarray(coords).reshape(n, -1).shape[1]
     for d in range(L - 1, -1, -1):
+        eps_d = level_eps(eps, eps_schedule, d, L, n, dim)
+        eps_at[d] = eps_d
         cur, child_size = _merge(red, d, variant)
         adj = footprint_adjacency(row_ptr, col_idx, leaf_of, L, d)
         super_size = dict(cur.size)
@@ -370,7 +414,7 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
                     colour.append(s)
             for s in colour:
                 before = {j: cur.state[j] for j in cur.partners.get(s, ())}
-                nf = eliminate_node(cur, s, adj, eps, variant)
+                nf = eliminate_node(cur, s, adj, eps_d, variant, margins)
                 nf.nbrs = [(nb, before[nb], A) for (nb, _, A) in nf.nbrs]
                 nf.Wstate = [before[w] for w in nf.W]
                 nodes[s] = nf
@@ -381,7 +425,8 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
                                 child_size=child_size,
                                 red_size={s: cur.size[s] for s in range(1 << d)})
         red = cur
-    return Factorization(n=n, L=L, leaves=leaves, levels=levels, eps=eps, variant=variant)
+    return Factorization(n=n, L=L, leaves=leaves, levels=levels, eps=eps, variant=variant,
+                         margins=margins, level_eps=eps_at)
 
 
 def _merge(red: LevelState, d: int, variant: int):

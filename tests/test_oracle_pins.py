@@ -195,6 +195,79 @@ def test_gc_compression_preserves_phi(eps):
     assert np.linalg.norm(B - U @ RT, 2) <= eps * np.linalg.norm(B, 2)
 
 
+def _gc_rank_is_minimal(B, phi_s, phi_w, eps):
+    """The GC basis U = [U1, U2] meets ||(I - U U^T) A_sw||_2 <= eps ||A_sw||_2 (§6, the bound
+    closing "Preserving a vector during compression") and no basis that holds U1 and one
+    column fewer does: by Eckart-Young the best such basis leaves sigma_{k2}((I - U1 U1^T) A_sw).
+    U1 is rebuilt here by LAPACK QR of [phi_s, A_sw phi_w], not by the oracle's routine."""
+    U = O.compress(B, eps, O.GC, phi_s, phi_w)
+    Z = np.column_stack([phi_s, B @ phi_w])
+    Q, Rq = np.linalg.qr(Z)
+    q = int(np.sum(np.abs(np.diag(Rq)) > 1e-10 * np.linalg.norm(Z, axis=0).max()))
+    Q = Q[:, :q]
+    k2 = U.shape[1] - q
+    nA = np.linalg.norm(B, 2)
+    # U1 spans the same space as the QR basis
+    assert np.linalg.norm(Q - U[:, :q] @ (U[:, :q].T @ Q)) < 1e-10
+    assert np.linalg.norm(B - U @ (U.T @ B), 2) <= eps * nA * (1 + 1e-12)
+    Bp = B - Q @ (Q.T @ B)
+    sp = np.linalg.svd(Bp, compute_uv=False)
+    if k2 >= 1:
+        # dropping the last U2 column breaks the bound, and so does any other choice of k2 - 1
+        Ud = U[:, :-1]
+        assert np.linalg.norm(B - Ud @ (Ud.T @ B), 2) > eps * nA
+        assert sp[k2 - 1] > eps * nA
+    assert (sp[k2] if k2 < len(sp) else 0.0) <= eps * nA * (1 + 1e-12)
+    return U, q, k2
+
+
+@pytest.mark.parametrize("eps", [1e-1, 1e-2, 1e-4])
+def test_gc_compression_rank_is_minimal(eps):
+    B = _smooth_block(30, 45, 2)
+    rng = np.random.default_rng(3)
+    _gc_rank_is_minimal(B, rng.standard_normal(30), rng.standard_normal(45), eps)
+
+
+def test_gc_threshold_is_relative_to_the_whole_block():
+    """Reading R1: the U2 threshold is eps * sigma_1(A_sw), not eps * sigma_1 of the projected
+    block. A block whose dominant part lies along the preserved vectors has a projected
+    sigma_1 far below sigma_1(A_sw); a threshold taken from the projected block would keep
+    more columns than the minimal count checked here."""
+    B0 = _smooth_block(30, 45, 5)
+    rng = np.random.default_rng(6)
+    phi_s, phi_w = np.ones(30), rng.uniform(0.5, 1.5, 45)
+    B = B0 + 1e3 * np.outer(phi_s, phi_w) / (np.linalg.norm(phi_s) * np.linalg.norm(phi_w))
+    U, q, k2 = _gc_rank_is_minimal(B, phi_s, phi_w, 1e-2)
+    Bp = B - U[:, :q] @ (U[:, :q].T @ B)
+    sp = np.linalg.svd(Bp, compute_uv=False)
+    assert sp[0] < 0.1 * np.linalg.norm(B, 2)
+    assert k2 < int(np.count_nonzero(sp > 1e-2 * sp[0]))
+
+
+def test_gc_rank_minimal_on_poisson_blocks(monkeypatch):
+    """The same bound and minimality on the well-separated blocks that a real factorization
+    compresses (3-D Poisson, GC-constant): every A_sw the oracle meets is recorded."""
+    import oracle.hsolver as OH
+    seen = []
+    orig = OH.compress
+
+    def rec(A_sw, eps, variant, phi_s=None, phi_w=None, **kw):
+        seen.append((A_sw.copy(), eps, np.array(phi_s, copy=True), np.array(phi_w, copy=True)))
+        return orig(A_sw, eps, variant, phi_s, phi_w, **kw)
+
+    monkeypatch.setattr(OH, "compress", rec)
+    p = pb.poisson(8, 3)
+    _factor(p, 8, 1e-2, O.GC)
+    assert len(seen) > 10
+    checked = 0
+    for A_sw, eps, ps, pw in seen:
+        if A_sw.shape[1] == 0 or not np.any(A_sw):
+            continue
+        _gc_rank_is_minimal(A_sw, ps[:, 0], pw[:, 0], eps)
+        checked += 1
+    assert checked > 10
+
+
 def test_compression_eps_zero_keeps_full_range():
     B = _smooth_block(12, 5, 4)
     for variant in (O.LORASP, O.GC):
@@ -472,6 +545,42 @@ def test_fpcg_converges_with_single_precision_preconditioner():
     assert it <= it64 + 3
 
 
+def test_stationary_with_exact_factor_takes_one_step():
+    """With eps = 0 the factorization is exact (equivalent-extension lemma, §4), so the
+    stationary iteration of §7.1 lands on x* after one step and stops there."""
+    p = pb.poisson(10, 2)
+    F = _factor(p, 8, 0.0, O.GC)
+    A = p.to_scipy()
+    b = pb.rhs(p.n, 1, 17)[:, 0]
+    x_star = np.linalg.solve(p.dense(), b)
+    x, its = O.stationary(A, b, lambda r: O.apply(F, r), x_star, tol=1e-6)
+    assert its == 1
+    assert np.linalg.norm(x - x_star) <= 1e-12 * np.linalg.norm(x_star)
+
+
+def test_stationary_counts_match_error_propagator():
+    """For a fixed M the error after k steps is (I - M A)^k e_0 (e_0 = -x*): the count the
+    loop returns is the first k where that closed form drops below tol, and its iterate
+    equals x* + (I - M A)^k e_0."""
+    p = pb.poisson(6, 2)
+    Ad = p.dense()
+    A = p.to_scipy()
+    Minv = np.diag(1.0 / np.diag(Ad))                   # Jacobi: a fixed SPD M
+    b = pb.rhs(p.n, 1, 19)[:, 0]
+    x_star = np.linalg.solve(Ad, b)
+    E = np.eye(p.n) - Minv @ Ad
+    e = -x_star
+    k_expect = None
+    for k in range(1, 2000):
+        e = E @ e
+        if np.linalg.norm(e) / np.linalg.norm(x_star) < 1e-6:
+            k_expect = k
+            break
+    x, its = O.stationary(A, b, lambda r: Minv @ r, x_star, tol=1e-6, maxiter=2000)
+    assert its == k_expect
+    assert np.linalg.norm(x - (x_star + e)) <= 1e-10 * np.linalg.norm(x_star)
+
+
 @pytest.mark.slow
 def test_convergence_trend_gc_flat_lorasp_grows():
     """Tables 1-2 (§7.1): GC iteration counts grow much more slowly with n than LoRaSp's,
@@ -521,3 +630,58 @@ def test_serving_stream_is_seeded_and_mixed():
     assert arr[0] == 0.0 and all(x <= y for x, y in zip(arr, arr[1:]))
     p, bb = pb.serving_problem(a[0])
     assert bb.shape == (p.n, a[0]["nrhs"])
+
+
+# ---------------------------------------------------------------------------
+# Per-level tolerance (§7.1 "3D cases", Table 3)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("N,leaf", [(16, 8), (32, 8), (16, 64)])
+def test_eps_schedules_match_the_papers_limits(N, leaf):
+    """Shrink (GC): eps at the leaf level whatever n is, O(h) at the root. Grow (LoRaSp):
+    eps h at the leaf level (Table 3's eps_lmax = 8 / n^(1/3) with eps = 8), a constant
+    independent of n at the root. For n = 2^L leaf both ends have closed forms."""
+    n = N ** 3
+    L = O.tree_depth(n, leaf)
+    assert n == (1 << L) * leaf
+    h = 1.0 / N
+    eps = 0.2
+    lmax = L - 1
+    assert O.level_eps(eps, "constant", 0, L, n, 3) == eps
+    assert O.level_eps(eps, "shrink", lmax, L, n, 3) == pytest.approx(eps, rel=1e-15)
+    assert O.level_eps(eps, "shrink", 0, L, n, 3) == pytest.approx(eps * h * (2 * leaf) ** (1 / 3), rel=1e-12)
+    assert O.level_eps(8.0, "grow", lmax, L, n, 3) == pytest.approx(8.0 / n ** (1 / 3), rel=1e-12)
+    assert O.level_eps(eps, "grow", 0, L, n, 3) == pytest.approx(eps * (2 * leaf) ** (-1 / 3), rel=1e-12)
+    for d in range(lmax):
+        assert O.level_eps(eps, "shrink", d, L, n, 3) < O.level_eps(eps, "shrink", d + 1, L, n, 3)
+        assert O.level_eps(eps, "grow", d, L, n, 3) > O.level_eps(eps, "grow", d + 1, L, n, 3)
+
+
+def test_shrink_schedule_leaf_level_equals_constant_and_bounds_hold(monkeypatch):
+    """With the shrinking schedule the first super-node level is compressed at eps itself, so
+    its ranks equal the constant-eps run's; every upper-level compression meets the §6 bound
+    and is minimal at its own level's tolerance; GC still preserves the constant vector."""
+    import oracle.hsolver as OH
+    p = pb.poisson(8, 3)
+    seen = []
+    orig = OH.compress
+
+    def rec(A_sw, eps, variant, phi_s=None, phi_w=None, **kw):
+        seen.append((A_sw.copy(), eps, np.array(phi_s, copy=True), np.array(phi_w, copy=True)))
+        return orig(A_sw, eps, variant, phi_s, phi_w, **kw)
+
+    F0 = _factor(p, 8, 0.1, O.GC)
+    monkeypatch.setattr(OH, "compress", rec)
+    F1 = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=0.1, variant=O.GC,
+                  eps_schedule="shrink")
+    L = F1.L
+    assert F1.ranks(L - 1) == F0.ranks(L - 1)
+    assert F1.level_eps[L - 1] == 0.1 and F1.level_eps[0] < 0.1
+    assert sorted({e for _, e, _, _ in seen}, reverse=True) == sorted(
+        {F1.level_eps[d] for d in F1.levels}, reverse=True)[:len({e for _, e, _, _ in seen})]
+    for A_sw, eps, ps, pw in seen:
+        if A_sw.shape[1] and np.any(A_sw):
+            _gc_rank_is_minimal(A_sw, ps[:, 0], pw[:, 0], eps)
+    one = np.ones(p.n)
+    assert np.allclose(O.apply(F1, p.to_scipy() @ one), one, atol=1e-10)
+    # smaller tolerances toward the root keep at least as many directions in total
+    assert sum(map(sum, (F1.ranks(d) for d in F1.levels))) >= sum(map(sum, (F0.ranks(d) for d in F0.levels)))
