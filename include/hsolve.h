@@ -25,8 +25,9 @@
  *     default stream); calls return after that work has finished.
  *   - A plan is not reentrant: calls on one plan must not overlap. Separate plans may
  *     be used from separate host threads.
- *   - Device memory for the factors is allocated by the library and released by
- *     hsolve_destroy (or by the next hsolve_factor on the same plan).
+ *   - Device memory comes from the caller: hsolve_analyze reports an upper bound, and
+ *     hsolve_factor takes an arena of that size (or of the size an earlier factorization
+ *     of the same values used). The library allocates only pinned host staging.
  */
 #ifndef HSOLVE_H
 #define HSOLVE_H
@@ -47,9 +48,12 @@ typedef enum {
     HSOLVE_ERR_NOT_SYMMETRIC = -2, /* the sparsity pattern is not symmetric */
     HSOLVE_ERR_NOT_SPD = -3,       /* a pivot block (or S = U^T A_ss^-1 U) failed Cholesky;
                                       stats.fail_level / fail_node name it */
-    HSOLVE_ERR_OOM = -4,           /* device allocation failed */
+    HSOLVE_ERR_OOM = -4,           /* the arena given to hsolve_factor is too small */
     HSOLVE_ERR_DEVICE = -5,        /* a HIP runtime call failed */
-    HSOLVE_ERR_STATE = -6          /* call out of order (e.g. apply before factor) */
+    HSOLVE_ERR_STATE = -6,         /* call out of order (e.g. apply before factor) */
+    HSOLVE_ERR_TOO_LARGE = -7      /* a merged super node grew beyond opt.max_super unknowns (the
+                                      ranks below it were larger than the plan was sized for);
+                                      stats.fail_level / fail_node name it */
 } hsolve_status;
 
 enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
@@ -57,6 +61,14 @@ enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
    flexible beta, right-preconditioned restarted GMRES, or the stationary iteration
    x <- x + A_H^{-1} (b - A x) of §7.1 */
 enum { HSOLVE_PCG = 0, HSOLVE_FPCG = 1, HSOLVE_GMRES = 2, HSOLVE_STATIONARY = 3 };
+/* compression tolerance per level (§7.1 "3D cases", Table 3); lmax = L - 1 is the depth of the
+   first super nodes and d the depth of the node compressed:
+   CONSTANT  eps everywhere;
+   SHRINK    eps 2^{(d - lmax)/3}: eps at the leaves, smaller toward the root (the paper's
+             adaptive choice for GC);
+   GROW      eps h 2^{(lmax - d)/3}, h = n^{-1/dim}: small at the leaves, larger toward the root
+             (the paper's adaptive choice for LoRaSp) */
+enum { HSOLVE_EPS_CONSTANT = 0, HSOLVE_EPS_SHRINK = 1, HSOLVE_EPS_GROW = 2 };
 
 typedef struct {
     int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
@@ -82,6 +94,16 @@ typedef struct {
     int overlap_pivots;     /* 1 (default): the pivot blocks of a colour are factored on a
                                second stream of the plan while the colour is compressed; 0: in
                                order on opt.stream (for callers that run many plans at once) */
+    int factor_prec;        /* 64 (default): arithmetic of the factorization */
+    int max_super;          /* largest super node, in unknowns, the plan admits (1..512, default
+                               512); it caps the ranks the arena bound of hsolve_analyze assumes */
+    int max_nrhs;           /* right-hand sides per batch the arena bound covers (default 32);
+                               hsolve_solve / hsolve_apply with more run in batches */
+    int eps_schedule;       /* HSOLVE_EPS_CONSTANT (default), HSOLVE_EPS_SHRINK, HSOLVE_EPS_GROW */
+    int cmp_lpe;            /* launch shape of the eigenvalue multisection: lanes per eigenvalue
+                               (1, 2, 4, ..., 64), 0 = chosen from the launch size (default) */
+    int cmp_vectors;        /* inverse iteration: 0 = chosen from the launch size (default),
+                               1 = one lane per eigenvalue, 2 = one wave per eigenvalue */
 } hsolve_options;
 
 typedef struct {
@@ -98,8 +120,9 @@ typedef struct {
     double apply_bytes;         /* algorithmic bytes read+written by one apply (1 rhs) */
     int fail_level;             /* for HSOLVE_ERR_NOT_SPD: depth and node of the failure */
     int fail_node;
-    int64_t device_bytes;       /* device memory held by the plan now (pattern, values, factors,
-                                   work pools); released by hsolve_destroy */
+    int64_t device_bytes;       /* arena bytes in use: pattern, values, factors, and the larger of
+                                   the factorization's transient regions and the solve workspace */
+    int64_t arena_bound;        /* the upper bound hsolve_analyze reported */
 } hsolve_stats;
 
 /* Fill *opt with the defaults listed above. */
@@ -107,38 +130,55 @@ void hsolve_default_options(hsolve_options* opt);
 
 /* Symbolic analysis (§2.1, §3, §3.1): clustering into 2^L leaves by recursive bisection,
  * footprint adjacency per level, simulated elimination (block fill, neighbour and
- * well-separated sets, colour order per level). Host only; no GPU work except the
- * upload of the pattern.
+ * well-separated sets, colour order per level), and the device memory a factorization of
+ * this pattern can need. Host only: no GPU work, no device memory.
  *   n        number of unknowns (>= 1)
  *   row_ptr  host, n+1 entries, row_ptr[0] = 0, nondecreasing
  *   col_idx  host, row_ptr[n] entries, each row sorted ascending, in [0, n), and the
  *            pattern structurally symmetric (HSOLVE_ERR_NOT_SYMMETRIC otherwise)
  *   opt      host, may be NULL for defaults
- *   out      receives the new plan (NULL on error) */
+ *   out      receives the new plan (NULL on error)
+ *   arena_bytes_upper_bound  may be NULL; receives the arena size that holds any
+ *            factorization of this pattern whose super nodes stay within opt.max_super,
+ *            together with the solve phase of opt.max_nrhs right-hand sides. It is found by
+ *            replaying the factorization's allocations with every rank at its largest
+ *            possible value, min(m_s, 2p + |W(s)|) (p preserved vectors, §6). */
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
-                             const hsolve_options* opt, hsolve_plan* out);
+                             const hsolve_options* opt, hsolve_plan* out,
+                             size_t* arena_bytes_upper_bound);
 
 /* Numeric factorization (Algorithm "Setup"; §3.2 compression, extension, elimination;
- * §6 GC compression). values: device, row_ptr[n] doubles in the pattern given to
- * hsolve_analyze; A must be symmetric positive definite. Replaces any previous
- * factorization of the plan. HSOLVE_ERR_NOT_SPD if a pivot block is not positive
- * definite (the plan then has no factorization). */
-hsolve_status hsolve_factor(hsolve_plan plan, const double* values);
+ * §6 GC compression).
+ *   values   host or device, row_ptr[n] doubles in the pattern given to hsolve_analyze;
+ *            A must be symmetric positive definite; NaN or Inf gives HSOLVE_ERR_INVALID
+ *   d_arena  device memory owned by the caller, 256-byte aligned (e.g. a torch.uint8 tensor
+ *            of the bound reported by hsolve_analyze); the plan keeps the pattern, values,
+ *            factors and solve-phase vectors in it and uses it until hsolve_destroy or the
+ *            next hsolve_factor. The library never allocates or frees device memory.
+ *   arena_bytes  its size; HSOLVE_ERR_OOM (nothing computed) when the factorization does not
+ *            fit. The analysis bound always fits; stats.device_bytes tells what one
+ *            factorization used, which also fits a refactorization of the same values.
+ * Replaces any previous factorization of the plan. HSOLVE_ERR_NOT_SPD if a pivot block is
+ * not positive definite, HSOLVE_ERR_TOO_LARGE if a super node exceeds opt.max_super (the
+ * plan then has no factorization). */
+hsolve_status hsolve_factor(hsolve_plan plan, const double* values, void* d_arena, size_t arena_bytes);
 
 /* Preconditioner application z = A_H^{-1} r (Algorithm "Solve"): forward
  * substitution, restriction, parent-level solve, prolongation and backward substitution
  * in reverse elimination order, level by level. r, z: device, n x nrhs column-major;
- * r and z may not overlap. */
+ * r and z may not overlap. The solve vectors come from the arena (batches of columns when
+ * it does not hold all of them at once). */
 hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
                            int ldz);
 
 /* Solve A x = b preconditioned with A_H^{-1} (x0 = 0) to the relative residual opt.tol, with
- * the outer iteration opt.krylov. b, x: device, n x nrhs column-major.
+ * the outer iteration opt.krylov. b, x: device, n x nrhs column-major. A column of b with a
+ * NaN or Inf gives HSOLVE_ERR_INVALID.
  * PCG / FPCG: the columns advance together (one batched SpMV and apply per iteration), each
  * with its own scalars, and a column stops changing once it has converged, so every column
  * equals its own single-column solve. FPCG takes beta = r_{k+1}^T (z_{k+1} - z_k) / r_k^T z_k.
  * GMRES: right-preconditioned, restarted every opt.restart steps, modified Gram-Schmidt; the
- * columns are solved one after the other. Needs (2 restart + 4) n doubles of device memory.
+ * columns are solved one after the other. Needs (2 restart + 4) n doubles of the arena.
  * STATIONARY: x_{k+1} = x_k + A_H^{-1} (b - A x_k) from x_0 = 0, all columns together, until
  * the true residual ||b - A x_k|| <= tol ||b|| (iterations counted as applies).
  * stats may be NULL; stats.iterations is the largest count over the columns and
@@ -151,10 +191,14 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
 /* y = A x with the matrix of the last hsolve_factor. x, y: device, n entries. */
 hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y);
 
+/* Change the stream the plan's GPU work runs on (hipStream_t or NULL), e.g. when a request
+ * loop hands an analysed plan to the slot that runs it. Not while a call on the plan runs. */
+hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream);
+
 /* Counters of the plan (levels, colours, ranks, bytes, flops, timings). */
 hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats);
 
-/* Release the plan and all device memory it owns. NULL is accepted. */
+/* Release the plan (host memory; the arena stays the caller's). NULL is accepted. */
 hsolve_status hsolve_destroy(hsolve_plan plan);
 
 /* Static, human-readable name of a status code. */

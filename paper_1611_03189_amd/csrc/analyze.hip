@@ -132,9 +132,9 @@ void analyze(Plan& P) {
     // ones appear later only when ranks grow, which the factorization checks
     for (int s = 0; s < (L > 0 ? (1 << (L - 1)) : 1); ++s) {
         const int m = (L > 0) ? P.leaf_off[2 * s + 2] - P.leaf_off[2 * s] : n;
-        if (m > MAX_SUPER)
-            throw Error{HSOLVE_ERR_INVALID, "leaf pairs larger than " + std::to_string(MAX_SUPER) +
-                                                " unknowns (reduce leaf_size)"};
+        if (m > P.opt.max_super)
+            throw Error{HSOLVE_ERR_INVALID, "leaf pairs larger than max_super = " +
+                                                std::to_string(P.opt.max_super) + " unknowns (reduce leaf_size)"};
     }
 
     // leaf of every unknown, and the unique leaf-level block pairs

@@ -70,12 +70,19 @@ void hsolve_default_options(hsolve_options* o) {
     o->apply_prec = 64;
     o->restart = 200;
     o->overlap_pivots = 1;
+    o->factor_prec = 64;
+    o->max_super = hs::MAX_SUPER;
+    o->max_nrhs = 32;
+    o->eps_schedule = HSOLVE_EPS_CONSTANT;
+    o->cmp_lpe = 0;
+    o->cmp_vectors = 0;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
-                             const hsolve_options* opt, hsolve_plan* out) {
+                             const hsolve_options* opt, hsolve_plan* out, size_t* arena_bytes_upper_bound) {
     if (!out) return HSOLVE_ERR_INVALID;
     *out = nullptr;
+    if (arena_bytes_upper_bound) *arena_bytes_upper_bound = 0;
     if (n < 1 || !row_ptr || !col_idx) return HSOLVE_ERR_INVALID;
     hsolve_options o;
     if (opt) o = *opt;
@@ -85,7 +92,11 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
         !(o.tol >= 0.0) || (o.krylov < HSOLVE_PCG || o.krylov > HSOLVE_STATIONARY) ||
         (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1 ||
-        (o.overlap_pivots != 0 && o.overlap_pivots != 1))
+        (o.overlap_pivots != 0 && o.overlap_pivots != 1) || o.factor_prec != 64 ||
+        o.max_super < 1 || o.max_super > hs::MAX_SUPER || o.max_nrhs < 1 ||
+        o.eps_schedule < HSOLVE_EPS_CONSTANT || o.eps_schedule > HSOLVE_EPS_GROW ||
+        !(o.cmp_lpe == 0 || (o.cmp_lpe >= 1 && o.cmp_lpe <= 64 && (o.cmp_lpe & (o.cmp_lpe - 1)) == 0)) ||
+        o.cmp_vectors < 0 || o.cmp_vectors > 2)
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;
     hsolve_plan plan = new (std::nothrow) hsolve_plan_s();
@@ -119,6 +130,8 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         }
         P.opt.phi = nullptr;
         hs::analyze(P);
+        hs::size_arena(P);
+        P.stats.arena_bound = int64_t(P.arena_bound);
         P.stats.levels = P.L;
         P.stats.colours = P.total_colours;
         P.stats.fail_level = P.stats.fail_node = -1;
@@ -128,15 +141,18 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         return st;
     }
     plan->P.stats.t_analyze = seconds_since(t0);
+    if (arena_bytes_upper_bound) *arena_bytes_upper_bound = plan->P.arena_bound;
     *out = plan;
     return HSOLVE_OK;
 }
 
-hsolve_status hsolve_factor(hsolve_plan plan, const double* values) {
-    if (!plan || !values) return HSOLVE_ERR_INVALID;
+hsolve_status hsolve_factor(hsolve_plan plan, const double* values, void* d_arena, size_t arena_bytes) {
+    if (!plan || !values || !d_arena) return HSOLVE_ERR_INVALID;
+    Plan& P = plan->P;
+    P.factored = false;
     return run(plan, "factor", [&] {
-        hs::upload_pattern(plan->P);
-        hs::factor(plan->P, values);
+        hs::bind_arena(P, d_arena, arena_bytes);
+        hs::factor(P, values);
     });
 }
 
@@ -146,8 +162,12 @@ hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr,
         return HSOLVE_ERR_INVALID;
     if (!plan->P.factored) return HSOLVE_ERR_STATE;
     return run(plan, "apply", [&] {
-        hs::apply(plan->P, nrhs, r, ldr, z, ldz);
-        HS_HIP(hipStreamSynchronize(plan->P.stream));
+        Plan& P = plan->P;
+        hs::begin_workspace(P);
+        const int batch = hs::solve_batch(P, nrhs, -1);
+        for (int c0 = 0; c0 < nrhs; c0 += batch)
+            hs::apply(P, std::min(batch, nrhs - c0), r + size_t(c0) * ldr, ldr, z + size_t(c0) * ldz, ldz);
+        HS_HIP(hipStreamSynchronize(P.stream));
     });
 }
 
@@ -162,13 +182,21 @@ hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb,
     hsolve_status st = run(plan, "solve", [&] {
         std::vector<int> its(nrhs);
         std::vector<double> rel(nrhs);
-        if (P.opt.krylov == HSOLVE_STATIONARY)
-            hs::stationary(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, its.data(), rel.data());
-        else if (P.opt.krylov == HSOLVE_GMRES)
-            hs::gmres(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.restart, its.data(), rel.data());
-        else
-            hs::pcg(P, nrhs, b, ldb, x, ldx, P.opt.tol, P.opt.max_iter, P.opt.krylov == HSOLVE_FPCG, its.data(),
-                    rel.data());
+        hs::begin_workspace(P);
+        const int batch = hs::solve_batch(P, nrhs, P.opt.krylov);
+        for (int c0 = 0; c0 < nrhs; c0 += batch) {
+            const int nc = std::min(batch, nrhs - c0);
+            const double* bc = b + size_t(c0) * ldb;
+            double* xc = x + size_t(c0) * ldx;
+            if (P.opt.krylov == HSOLVE_STATIONARY)
+                hs::stationary(P, nc, bc, ldb, xc, ldx, P.opt.tol, P.opt.max_iter, its.data() + c0, rel.data() + c0);
+            else if (P.opt.krylov == HSOLVE_GMRES)
+                hs::gmres(P, nc, bc, ldb, xc, ldx, P.opt.tol, P.opt.max_iter, P.opt.restart, its.data() + c0,
+                          rel.data() + c0);
+            else
+                hs::pcg(P, nc, bc, ldb, xc, ldx, P.opt.tol, P.opt.max_iter, P.opt.krylov == HSOLVE_FPCG,
+                        its.data() + c0, rel.data() + c0);
+        }
         HS_HIP(hipStreamSynchronize(P.stream));
         int most = 0;
         double worst = 0.0;
@@ -196,6 +224,13 @@ hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y) {
     });
 }
 
+hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream) {
+    if (!plan) return HSOLVE_ERR_INVALID;
+    plan->P.stream = static_cast<hipStream_t>(stream);
+    plan->P.opt.stream = stream;
+    return HSOLVE_OK;
+}
+
 hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats) {
     if (!plan || !stats) return HSOLVE_ERR_INVALID;
     hs::Plan& P = plan->P;
@@ -206,7 +241,7 @@ hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats) {
 
 hsolve_status hsolve_destroy(hsolve_plan plan) {
     if (!plan) return HSOLVE_OK;
-    if (plan->P.d_row_ptr) (void)hipStreamSynchronize(plan->P.stream);   // GPU used
+    if (plan->P.arena) (void)hipStreamSynchronize(plan->P.stream);   // GPU used
     delete plan;
     return HSOLVE_OK;
 }
@@ -221,6 +256,7 @@ const char* hsolve_status_string(hsolve_status s) {
         case HSOLVE_ERR_OOM: return "HSOLVE_ERR_OOM";
         case HSOLVE_ERR_DEVICE: return "HSOLVE_ERR_DEVICE";
         case HSOLVE_ERR_STATE: return "HSOLVE_ERR_STATE";
+        case HSOLVE_ERR_TOO_LARGE: return "HSOLVE_ERR_TOO_LARGE";
     }
     return "HSOLVE_UNKNOWN_STATUS";
 }

@@ -1644,7 +1644,7 @@ __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int v
 }
 
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps, int* d_rank,
-                     double flops, bool lds, int max_m, hipStream_t s) {
+                     double flops, bool lds, int max_m, int force_lpe, int force_vectors, hipStream_t s) {
     if (ntasks <= 0) return;
     if (max_m > CMP_MAX)
         throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
@@ -1676,6 +1676,7 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
         const double total = double(max_m) * ntasks;
         int lpe = 64;
         while (lpe > 1 && total * lpe > 65536.0) lpe /= 2;
+        if (force_lpe > 0) lpe = force_lpe;      // a fixed launch shape (tests, tuning)
         auto go = [&](auto kern, int l) {
             hipLaunchKernelGGL(kern, dim3((max_m + NT / l - 1) / (NT / l), ntasks), dim3(NT), 0, s, d_tasks);
         };
@@ -1692,7 +1693,8 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
     }
     {
         ProfScope ps("k_comp_vectors", 0.0, s);
-        if (double(max_m) * ntasks >= 4096.0) {      // many eigenvalues: one lane each
+        const bool lane = force_vectors ? force_vectors == 1 : double(max_m) * ntasks >= 4096.0;
+        if (lane) {                                  // many eigenvalues: one lane each
             hipLaunchKernelGGL(k_comp_vectors, dim3((max_m + VL - 1) / VL, ntasks), dim3(VL), 0, s, d_tasks);
         } else {                                     // few: one wave each (latency)
             const int ldn = max_m;

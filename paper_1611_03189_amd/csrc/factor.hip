@@ -38,6 +38,7 @@ struct Live {
 
 struct Batch {
     bool trace_pivots = false;
+    bool dry = false;                 // replay: tables are counted, nothing is launched
     std::vector<CopyTask> copies;
     std::vector<GemmTask> gt;
     std::vector<GemmTerm> terms;
@@ -77,13 +78,13 @@ struct Batch {
             max_cols = std::max(max_cols, c.cols);
         }
         CopyTask* d = P.stage.upload_vec(copies, P.spool, P.stream);
-        launch_copy(d, int(copies.size()), max_cols, bytes, P.stream);
+        if (!dry) launch_copy(d, int(copies.size()), max_cols, bytes, P.stream);
         copies.clear();
     }
     // The tables always travel on the plan's stream; with side set, the launch goes to the
     // side stream once it has waited for them.
     static hipStream_t to_side(Plan& P, bool side) {
-        if (!side) return P.stream;
+        if (!side || P.dry) return P.stream;
         HS_HIP(hipEventRecord(P.ev_ready, P.stream));
         HS_HIP(hipStreamWaitEvent(P.side, P.ev_ready, 0));
         return P.side;
@@ -105,7 +106,7 @@ struct Batch {
             GemmTask* dt = reinterpret_cast<GemmTask*>(dbase);
             GemmTerm* dterm = reinterpret_cast<GemmTerm*>(dbase + o1);
             GemmTile* dtile = reinterpret_cast<GemmTile*>(dbase + o2);
-            launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, to_side(P, side));
+            if (!dry) launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, to_side(P, side));
         }
         gt.clear();
         terms.clear();
@@ -132,8 +133,8 @@ struct Batch {
                 for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 4 * q;
             }
             CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
-            launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
-            if (d_stamp) {
+            if (!dry) launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
+            if (d_stamp && !dry) {
                 if (side) HS_HIP(hipStreamSynchronize(P.side));
                 std::vector<long long> h(4 * part.size());
                 HS_HIP(hipMemcpy(h.data(), d_stamp, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
@@ -157,16 +158,38 @@ size_t blk_bytes(int r, int c) { return ((size_t(r) * c * sizeof(double)) + 255)
 
 }  // namespace
 
-void factor(Plan& P, const double* d_values_in) {
+// Compression tolerance of the super nodes of depth d (§7.1, "3D cases", Table 3). The
+// first super-node depth lmax = L - 1 is the leaf level of the schedules.
+//   HSOLVE_EPS_CONSTANT  eps on every level;
+//   HSOLVE_EPS_SHRINK    eps 2^{(d - lmax)/3}: eps at the leaves, smaller toward the root
+//                        (the paper's adaptive GC choice);
+//   HSOLVE_EPS_GROW      eps h 2^{(lmax - d)/3} with h = n^{-1/dim}: small at the leaves,
+//                        larger toward the root (the paper's adaptive LoRaSp choice).
+double level_eps(const Plan& P, int d) {
+    const double eps = P.opt.eps;
+    const int lmax = std::max(P.L - 1, 0);
+    switch (P.opt.eps_schedule) {
+        case HSOLVE_EPS_SHRINK: return eps * std::exp2((d - lmax) / 3.0);
+        case HSOLVE_EPS_GROW: {
+            const double h = std::pow(double(P.n), -1.0 / std::max(1, P.opt.dim));
+            return eps * h * std::exp2((lmax - d) / 3.0);
+        }
+        default: return eps;
+    }
+}
+
+void factor(Plan& P, const double* values_in) {
     using clk = std::chrono::steady_clock;
     const auto t0 = clk::now();
+    const bool dry = P.dry;
     hipStream_t st = P.stream;
     const int L = P.L;
     const int nlev = std::max(L, 1);
     const bool gc = P.opt.variant == HSOLVE_GC;
     const int p = P.nphi;
-    const double eps = P.opt.eps;
-    const bool overlap = P.opt.overlap_pivots != 0;
+    const int q_gc = gc ? 2 * p : 0;   // columns of [phi_s, A_sw phi_w]
+    const bool overlap = P.opt.overlap_pivots != 0 && !dry;
+    const int max_super = P.opt.max_super;
 
     P.factored = false;
     P.d_V = nullptr;
@@ -174,35 +197,44 @@ void factor(Plan& P, const double* d_values_in) {
     P.V_cols = 0;
     P.d_krylov = nullptr;
     P.krylov_cols = 0;
-    P.d_scalars = nullptr;
+    P.d_gmres = nullptr;          // the GMRES basis lived in the workspace that is reset below
+    P.gmres_restart = 0;
     P.sched.clear();
-    if (!P.side) {      // second stream for the pivot blocks (default priority)
-        HS_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
-        HS_HIP(hipEventCreateWithFlags(&P.ev_ready, hipEventDisableTiming));
-        HS_HIP(hipEventCreateWithFlags(&P.ev_done, hipEventDisableTiming));
+    if (!dry) {
+        if (!P.side) {      // second stream for the pivot blocks (default priority)
+            HS_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
+            HS_HIP(hipEventCreateWithFlags(&P.ev_ready, hipEventDisableTiming));
+            HS_HIP(hipEventCreateWithFlags(&P.ev_done, hipEventDisableTiming));
+        }
+        if (!P.h_flags)
+            HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_flags), sizeof(int) * (size_t(2) << nlev) + 64,
+                                 hipHostMallocDefault));
+        HS_HIP(hipStreamSynchronize(P.side));
+        HS_HIP(hipStreamSynchronize(st));
+        // host or device values (unified addressing decides the direction)
+        HS_HIP(hipMemcpyAsync(P.d_values, values_in, size_t(P.nnz) * sizeof(double), hipMemcpyDefault, st));
     }
-    HS_HIP(hipStreamSynchronize(P.side));
-    HS_HIP(hipStreamSynchronize(st));
+    int* d_bad = P.fpool.alloc_n<int>(1);
+    if (!dry) {
+        launch_check_finite(P.d_values, P.nnz, d_bad, st);
+        HS_HIP(hipMemcpyAsync(P.h_flags, d_bad, sizeof(int), hipMemcpyDeviceToHost, st));
+        HS_HIP(hipStreamSynchronize(st));
+        if (P.h_flags[0]) throw Error{HSOLVE_ERR_INVALID, "matrix values contain NaN or Inf"};
+    }
     P.stage.reset();
-    P.fpool.reset();
+    P.stage.dry = dry;
     P.lpool[0].reset();
     P.lpool[1].reset();
     P.spool.reset();
-    P.apool.reset();
-    HS_HIP(hipMemcpyAsync(P.d_values, d_values_in, size_t(P.nnz) * sizeof(double),
-                          hipMemcpyDeviceToDevice, st));
 
     P.num.assign(nlev, LevelNum{});
     Live lives[2];
     std::vector<std::vector<double*>> phi_sup(nlev), phi_red(nlev);
     double flops = 0.0;
     int max_rank = 0;
-    int* h_flags = nullptr;     // pinned: fail flags of the level + ranks of the colour
-    HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&h_flags), sizeof(int) * (size_t(2) << nlev) + 64,
-                         hipHostMallocDefault));
-    struct HostFree { int* p; ~HostFree() { if (p) (void)hipHostFree(p); } } hf{h_flags};
+    int* h_flags = P.h_flags;   // fail flags of the level + ranks of the colour
 
-    const bool trace = std::getenv("HSOLVE_TRACE") != nullptr;
+    const bool trace = !dry && std::getenv("HSOLVE_TRACE") != nullptr;
     auto now_ms = [&] { return std::chrono::duration<double, std::milli>(clk::now() - t0).count(); };
     for (int d = nlev - 1; d >= 0; --d) {
         const LevelSym& S = P.sym[d];
@@ -217,18 +249,32 @@ void factor(Plan& P, const double* d_values_in) {
             if (L == 0) LN.msz[s] = P.n;
             else if (first) LN.msz[s] = P.leaf_off[2 * s + 2] - P.leaf_off[2 * s];
             else LN.msz[s] = P.num[d + 1].ksz[2 * s] + P.num[d + 1].ksz[2 * s + 1];
+            if (LN.msz[s] > max_super) {
+                // the replay bounds the merged size by the cap; a factorization that exceeds it
+                // stops here (its arena and kernels were sized for max_super)
+                if (dry) LN.msz[s] = max_super;
+                else {
+                    P.stats.fail_level = d;
+                    P.stats.fail_node = s;
+                    throw Error{HSOLVE_ERR_TOO_LARGE,
+                                "super node of " + std::to_string(LN.msz[s]) + " unknowns at depth " +
+                                    std::to_string(d) + " exceeds max_super = " + std::to_string(max_super)};
+                }
+            }
         }
+        const double eps = level_eps(P, d);
         Live& live = lives[d & 1];
         live.map.clear();
-        Pool& lp = P.lpool[d & 1];
+        Region& lp = P.lpool[d & 1];
         lp.reset();
         phi_sup[d].assign(nd, nullptr);
         phi_red[d].assign(nd, nullptr);
         P.spool.reset();
         int* d_fail = lp.alloc_n<int>(nd);
-        HS_HIP(hipMemsetAsync(d_fail, 0, sizeof(int) * nd, st));
+        if (!dry) HS_HIP(hipMemsetAsync(d_fail, 0, sizeof(int) * nd, st));
         Batch B;
         B.trace_pivots = trace;
+        B.dry = dry;
 
         // ---- blocks of the level at its start: diagonal + upper partners, one zeroed region
         size_t region = 0;
@@ -239,7 +285,7 @@ void factor(Plan& P, const double* d_values_in) {
                 if (j > s) region += blk_bytes(LN.msz[s], LN.msz[j]);
         }
         char* base = static_cast<char*>(lp.alloc(region));
-        launch_fill(reinterpret_cast<double*>(base), 0.0, int64_t(region / sizeof(double)), st);
+        if (!dry) launch_fill(reinterpret_cast<double*>(base), 0.0, int64_t(region / sizeof(double)), st);
         std::vector<int32_t> blk_begin(nd + 1, 0), blk_col, blk_ld;
         std::vector<double*> blk_ptr;
         {
@@ -266,11 +312,14 @@ void factor(Plan& P, const double* d_values_in) {
             std::vector<int32_t> super_first(nd, 0);
             if (L > 0)
                 for (int s = 0; s < nd; ++s) super_first[s] = P.leaf_off[2 * s];
-            launch_leaf_scatter(P.d_row_ptr, P.d_col_idx, P.d_values, P.d_iperm, P.d_pos_super, P.stage.upload_vec(super_first, P.spool, st),
-                                P.stage.upload_vec(blk_ptr, P.spool, st),
-                                P.stage.upload_vec(blk_ld, P.spool, st),
-                                P.stage.upload_vec(blk_col, P.spool, st),
-                                P.stage.upload_vec(blk_begin, P.spool, st), P.n, st);
+            const int32_t* d_sf = P.stage.upload_vec(super_first, P.spool, st);
+            double* const* d_bp = P.stage.upload_vec(blk_ptr, P.spool, st);
+            const int32_t* d_bl = P.stage.upload_vec(blk_ld, P.spool, st);
+            const int32_t* d_bc = P.stage.upload_vec(blk_col, P.spool, st);
+            const int32_t* d_bb = P.stage.upload_vec(blk_begin, P.spool, st);
+            if (!dry)
+                launch_leaf_scatter(P.d_row_ptr, P.d_col_idx, P.d_values, P.d_iperm, P.d_pos_super, d_sf, d_bp,
+                                    d_bl, d_bc, d_bb, P.n, st);
             if (gc) {
                 std::vector<double> h(size_t(P.n) * p);
                 size_t off = 0;
@@ -358,8 +407,6 @@ void factor(Plan& P, const double* d_values_in) {
             for (int s : nodes) {
                 if (S.W[s].empty()) continue;
                 const int m = LN.msz[s];
-                if (m > 512)
-                    throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
                 int wt = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) wt += cursize(S.W[s][t], S.Wred[s][t]);
                 double* Asw = P.spool.alloc_n<double>(size_t(m) * wt);
@@ -421,23 +468,32 @@ void factor(Plan& P, const double* d_values_in) {
                     part.push_back(ct);
                 }
                 if (part.empty()) continue;
-                launch_compress(P.stage.upload_vec(part, P.spool, st), int(part.size()), P.opt.variant,
-                                eps, d_rank, cflops, !big, max_m, st);
+                const CompressTask* d_part = P.stage.upload_vec(part, P.spool, st);
+                if (!dry)
+                    launch_compress(d_part, int(part.size()), P.opt.variant, eps, d_rank, cflops, !big, max_m,
+                                    P.opt.cmp_lpe, P.opt.cmp_vectors, st);
             }
-            HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
-            if (!comp.empty())
-                HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size(),
-                                      hipMemcpyDeviceToHost, st));
-            HS_HIP(hipStreamSynchronize(st));
-            P.stage.reset();
-            for (int s = 0; s < nd; ++s)
-                if (h_flags[s]) {
-                    P.stats.fail_level = d;
-                    P.stats.fail_node = s;
-                    throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
-                }
+            if (!dry) {
+                // the pivot blocks of this colour may still run on the side stream: their failure
+                // flags are read only after it has finished (the compression keeps overlapping)
+                if (overlap) HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
+                HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
+                if (!comp.empty())
+                    HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size(),
+                                          hipMemcpyDeviceToHost, st));
+                HS_HIP(hipStreamSynchronize(st));
+                P.stage.reset();
+                for (int s = 0; s < nd; ++s)
+                    if (h_flags[s]) {
+                        P.stats.fail_level = d;
+                        P.stats.fail_node = s;
+                        throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
+                    }
+            }
             for (const CompNode& cn : comp) {
-                const int k = h_flags[nd + cn.slot];
+                // the replay takes the largest rank the compression can return:
+                // |U1| + k2 <= min(m, 2p + |W|) (R5: at least one column)
+                const int k = dry ? std::max(1, std::min(LN.msz[cn.s], q_gc + cn.wt)) : h_flags[nd + cn.slot];
                 if (k < 0 || k > LN.msz[cn.s])
                     throw Error{HSOLVE_ERR_DEVICE,
                                 "eigen-solver did not converge (level " + std::to_string(d) + ", node " +
@@ -488,7 +544,6 @@ void factor(Plan& P, const double* d_values_in) {
                 }
                 B.copy(Ainv[q], m, nn.Gm, nn.ldG, m, m, 0);      // A_ss^-1 into rows 0..m-1 of Gm
             }
-            if (overlap) HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
             B.flush_copies(P);
             // Y = A_ss^-1 U, S = U^T Y
             for (size_t q = 0; q < nodes.size(); ++q) {
@@ -659,15 +714,17 @@ void factor(Plan& P, const double* d_values_in) {
             }
         }
         // end of level: surface pivot failures of the last colour
-        HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
-        HS_HIP(hipStreamSynchronize(st));
+        if (!dry) {
+            HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
+            HS_HIP(hipStreamSynchronize(st));
+            for (int s = 0; s < nd; ++s)
+                if (h_flags[s]) {
+                    P.stats.fail_level = d;
+                    P.stats.fail_node = s;
+                    throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
+                }
+        }
         P.stage.reset();
-        for (int s = 0; s < nd; ++s)
-            if (h_flags[s]) {
-                P.stats.fail_level = d;
-                P.stats.fail_node = s;
-                throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
-            }
     }
     if (P.apply32) {
         // single-precision copies of the solve-phase blocks, rounded once from the FP64 factor
@@ -685,12 +742,14 @@ void factor(Plan& P, const double* d_values_in) {
         for (size_t i = 0; i < dt.size(); i += 65535) {
             const int cnt = int(std::min<size_t>(65535, dt.size() - i));
             std::vector<DemoteTask> part(dt.begin() + i, dt.begin() + i + cnt);
-            launch_demote(P.stage.upload_vec(part, P.spool, st), cnt, elems * cnt / dt.size(), st);
+            const DemoteTask* d_part = P.stage.upload_vec(part, P.spool, st);
+            if (!dry) launch_demote(d_part, cnt, elems * cnt / dt.size(), st);
         }
-        HS_HIP(hipStreamSynchronize(st));
+        if (!dry) HS_HIP(hipStreamSynchronize(st));
         P.stage.reset();
     }
     build_apply_schedule(P);
+    if (dry) return;
     HS_HIP(hipStreamSynchronize(st));
     P.factored = true;
     P.stats.factor_flops = flops;
@@ -701,6 +760,44 @@ void factor(Plan& P, const double* d_values_in) {
     P.stats.fail_level = -1;
     P.stats.fail_node = -1;
     P.stats.t_factor = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+// Arena bound (hsolve_analyze): replay the factorization on the host with every rank at its
+// largest possible value, min(m, 2p + |W|), and every merged super node capped at max_super.
+// Each allocation of a real factorization is then no larger than its counterpart in the
+// replay (the sequence of allocations depends only on the symbolic schedule, their sizes grow
+// with m, k and |W|), so the replay's high-water marks bound the regions of any factorization
+// that succeeds. The solve phase reuses the transient regions, or needs max_nrhs columns.
+void size_arena(Plan& P) {
+    const size_t inf = size_t(1) << 60;
+    const int n = P.n;
+    P.pattern_bytes = align256(sizeof(int64_t) * (size_t(n) + 1)) + align256(sizeof(int32_t) * std::max<size_t>(1, P.nnz)) +
+                      align256(sizeof(double) * std::max<size_t>(1, P.nnz)) + align256(sizeof(int32_t) * 3 * size_t(n));
+    P.fpool.init(nullptr, inf, "factor data");
+    P.lpool[0].init(nullptr, inf, "live blocks (even depths)");
+    P.lpool[1].init(nullptr, inf, "live blocks (odd depths)");
+    P.spool.init(nullptr, inf, "per-colour scratch");
+    P.dry = true;
+    struct Back {
+        Plan& P;
+        ~Back() {
+            P.dry = false;
+            P.stage.dry = false;
+            P.num.clear();
+            P.sched.clear();
+            P.factored = false;
+        }
+    } back{P};
+    factor(P, nullptr);
+    P.cap_live[0] = P.lpool[0].high_water();
+    P.cap_live[1] = P.lpool[1].high_water();
+    P.cap_scratch = P.spool.high_water();
+    P.bound_factor = P.fpool.high_water();
+    const int nr = std::max(1, P.opt.max_nrhs);
+    const size_t ws = std::max(solve_ws_bytes(P, nr, P.opt.krylov), solve_ws_bytes(P, nr, -1));
+    const size_t trans = P.cap_live[0] + P.cap_live[1] + P.cap_scratch;
+    P.arena_bound = P.pattern_bytes + P.bound_factor + std::max(trans, ws);
+    P.vlen = 0;
 }
 
 }  // namespace hs

@@ -32,40 +32,48 @@ struct Error {
     } while (0)
 
 // ---------------------------------------------------------------------------------
-// Device memory: chunked bump allocators (256-byte aligned)
+// Device memory: bump allocators over parts of the caller's arena (256-byte aligned).
+// In a dry run (base == nullptr) a region only counts bytes: the analysis replays the
+// factorization's allocations with upper-bound sizes to size the arena.
 // ---------------------------------------------------------------------------------
-class Pool {
+class Region {
 public:
-    explicit Pool(size_t chunk = size_t(64) << 20) : chunk_(chunk) {}
-    ~Pool();
-    Pool(const Pool&) = delete;
-    Pool& operator=(const Pool&) = delete;
+    void init(char* base, size_t cap, const char* name) {
+        base_ = base;
+        cap_ = cap;
+        name_ = name;
+        off_ = high_ = 0;
+    }
     void* alloc(size_t bytes);
     template <class T> T* alloc_n(size_t n) { return static_cast<T*>(alloc(n * sizeof(T))); }
-    void reset();      // reuse all chunks from the start (stream order keeps this safe)
-    void release();    // free every chunk
+    void reset() { off_ = 0; }     // reuse from the start (stream order keeps this safe)
     size_t high_water() const { return high_; }
-    size_t in_use() const;
-    size_t reserved() const;   // device bytes held by the chunks
+    size_t in_use() const { return off_; }
+    size_t capacity() const { return cap_; }
+    char* base() const { return base_; }
+    char* top() const { return base_ + off_; }
 
 private:
-    struct Chunk { char* p; size_t size; };
-    std::vector<Chunk> chunks_;
-    size_t cur_ = 0, off_ = 0, chunk_, high_ = 0, used_before_ = 0;
+    char* base_ = nullptr;
+    size_t cap_ = 0, off_ = 0, high_ = 0;
+    const char* name_ = "";
 };
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Pinned host staging + device copy of small task tables.
 class Staging {
 public:
     ~Staging();
     // copies `bytes` from src into pinned memory and enqueues an H2D copy into dst_pool;
-    // returns the device pointer
-    void* upload(const void* src, size_t bytes, Pool& dst_pool, hipStream_t s);
-    template <class T> T* upload_vec(const std::vector<T>& v, Pool& pool, hipStream_t s) {
+    // returns the device pointer. In a dry run only the device bytes are counted.
+    void* upload(const void* src, size_t bytes, Region& dst_pool, hipStream_t s);
+    template <class T> T* upload_vec(const std::vector<T>& v, Region& pool, hipStream_t s) {
         if (v.empty()) return nullptr;
         return static_cast<T*>(upload(v.data(), v.size() * sizeof(T), pool, s));
     }
     void reset() { off_ = 0; }   // only after a stream synchronisation
+    bool dry = false;
 
 private:
     char* host_ = nullptr;
@@ -251,7 +259,11 @@ struct Plan {
     std::vector<LevelSym> sym;                     // sym[d], d = 0 .. L-1
     int total_colours = 0;
 
-    // device copies of the pattern
+    // pattern in pinned host memory (copied into the arena by every factorization)
+    int64_t* h_row_ptr = nullptr;
+    int32_t* h_col_idx = nullptr;
+    int32_t* h_perm = nullptr;         // [perm (n) | iperm (n) | super node of each position (n)]
+    // device copies of the pattern, in the arena
     int64_t* d_row_ptr = nullptr;
     int32_t* d_col_idx = nullptr;
     double* d_values = nullptr;
@@ -261,12 +273,25 @@ struct Plan {
 
     // numeric factor
     bool factored = false;
+    bool dry = false;                  // replaying the factorization to size the arena
     std::vector<LevelNum> num;         // num[d]
     int64_t vlen = 0;                  // length of one solve-vector column
-    Pool fpool{size_t(256) << 20};     // factor data (kept)
-    Pool lpool[2]{Pool(size_t(256) << 20), Pool(size_t(256) << 20)};  // live blocks by depth parity
-    Pool spool{size_t(128) << 20};     // per-step scratch
-    Pool apool{size_t(16) << 20};      // apply schedule + vectors
+    // Arena layout: [pattern | factor data + apply schedule (fpool, grows up) ... |
+    //                live blocks of even depths | of odd depths | per-colour scratch]
+    // The three transient regions have the capacities the dry run of the analysis found;
+    // after the factorization they are free, and the solve phase takes its vectors from
+    // everything above the factor data (wpool).
+    char* arena = nullptr;
+    size_t arena_bytes = 0;
+    size_t pattern_bytes = 0;          // device bytes of the pattern part
+    size_t cap_live[2] = {0, 0}, cap_scratch = 0;   // transient capacities (dry run)
+    size_t bound_factor = 0;           // dry-run high water of the factor region
+    size_t arena_bound = 0;            // what hsolve_analyze reports
+    int* h_flags = nullptr;            // pinned: pivot failure flags + ranks of a colour
+    Region fpool;                      // factor data and apply schedule (kept)
+    Region lpool[2];                   // live blocks by depth parity
+    Region spool;                      // per-colour scratch
+    Region wpool;                      // solve phase: vectors and Krylov workspace
     Staging stage;
 
     // apply schedule (device), per level and colour
@@ -282,7 +307,6 @@ struct Plan {
     void* d_V = nullptr;                            // forward right-hand sides (phi)
     void* d_X = nullptr;                            // backward solutions (x)
     int V_cols = 0;
-    double* d_scalars = nullptr;                    // dot-product results
     double* h_scalars = nullptr;                    // pinned
     double* d_krylov = nullptr;                     // PCG vectors (R, Z, P, Q, X blocks)
     double* d_kscal = nullptr;                      // PCG scalars per column + dot partials
@@ -292,13 +316,11 @@ struct Plan {
     int gmres_restart = 0;
     int h_scalar_cols = 0;
 
-    // device memory held by the plan (pattern arrays, values, pools)
+    // arena bytes used by the last factorization and its solves
     size_t device_bytes() const {
-        size_t s = fpool.reserved() + lpool[0].reserved() + lpool[1].reserved() + spool.reserved() +
-                   apool.reserved();
-        if (d_row_ptr) s += sizeof(int64_t) * (size_t(n) + 1) + (sizeof(int32_t) + sizeof(double)) * size_t(nnz) +
-                            sizeof(int32_t) * 3 * size_t(n);
-        return s;
+        if (!arena) return 0;
+        return pattern_bytes + fpool.high_water() +
+               std::max(cap_live[0] + cap_live[1] + cap_scratch, wpool.high_water());
     }
     hsolve_stats stats{};
     Profiler prof;
@@ -309,11 +331,18 @@ struct Plan {
 // analyze.hip (host only)
 void analyze(Plan& P);
 // runtime.hip
-void upload_pattern(Plan& P);
-// factor.hip
-void factor(Plan& P, const double* d_values);
+void pin_pattern(Plan& P);                       // pinned host copy of the pattern (analysis)
+void bind_arena(Plan& P, void* arena, size_t bytes);   // carve the regions, upload the pattern
+size_t solve_ws_bytes(const Plan& P, int nrhs, int krylov);   // solve-phase workspace
+int solve_batch(const Plan& P, int nrhs, int krylov);          // columns per batch that fit
+// factor.hip: the numeric factorization; with P.dry set, a replay on the host that only
+// counts the bytes of every allocation, with upper-bound sizes (no GPU work)
+void factor(Plan& P, const double* values);
+void size_arena(Plan& P);
+double level_eps(const Plan& P, int d);          // compression tolerance of depth d
 // solve.hip
 void build_apply_schedule(Plan& P);
+void begin_workspace(Plan& P);
 void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
          bool flexible, int* its, double* rel);
@@ -330,7 +359,8 @@ void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTil
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, double flops, bool lds, int max_m, hipStream_t s);
+                     int* d_rank, double flops, bool lds, int max_m, int force_lpe, int force_vectors,
+                     hipStream_t s);
 constexpr int LDS_MAX_M = 128;   // compression blocks up to this size work in LDS
 constexpr int CMP_WY_NB = 16;     // reflectors per block in the compression back-transformation
 // doubles of the per-node compression work buffer for a super node of m unknowns
@@ -378,6 +408,7 @@ void launch_pcg_flags(const double* rr, const double* nb, double tol, int* activ
 void launch_copy_scalars(double* dst, const double* src, int n, hipStream_t s);
 template <typename T>
 void launch_fill(T* p, T v, int64_t n, hipStream_t s);
+void launch_check_finite(const double* v, int64_t n, int* flag, hipStream_t s);   // *flag = any non-finite
 // restarted GMRES: y += sign * (*a) * x; y = s * x; r = b - w; x += Z y (y: device, k entries)
 void launch_axpy_dev(double* y, const double* x, const double* a, double sign, int n, hipStream_t s);
 // stationary iteration, active columns only: X += Z; R = B - Q

@@ -567,5 +567,25 @@ void launch_fill(T* p, T v, int64_t n, hipStream_t s) {
 }
 template void launch_fill<double>(double*, double, int64_t, hipStream_t);
 template void launch_fill<float>(float*, float, int64_t, hipStream_t);
+template void launch_fill<int>(int*, int, int64_t, hipStream_t);
+
+// flag = 1 when some v[i] is NaN or infinite (flag starts at 0; racing writers store the
+// same value)
+__global__ void k_nonfinite(const double* v, int64_t n, int* flag) {
+    bool bad = false;
+    for (int64_t i = blockIdx.x * int64_t(blockDim.x) + threadIdx.x; i < n;
+         i += int64_t(gridDim.x) * blockDim.x)
+        bad |= !isfinite(v[i]);
+    if (bad) *flag = 1;
+}
+
+void launch_check_finite(const double* v, int64_t n, int* flag, hipStream_t s) {
+    launch_fill<int>(flag, 0, 1, s);
+    if (n <= 0) return;
+    int64_t nb = (n + NT - 1) / NT;
+    if (nb > 2048) nb = 2048;
+    hipLaunchKernelGGL(k_nonfinite, dim3(unsigned(nb)), dim3(NT), 0, s, v, n, flag);
+    check_launch("k_nonfinite");
+}
 
 }  // namespace hs

@@ -112,27 +112,40 @@ void build_apply_schedule(Plan& P) {
             }
             cs.nfwd = int(ft.size());
             cs.max_len = max_len;
-            cs.fwd_t = P.stage.upload_vec(ft, P.apool, st);
-            cs.fwd_c = P.stage.upload_vec(fc, P.apool, st);
+            cs.fwd_t = P.stage.upload_vec(ft, P.fpool, st);
+            cs.fwd_c = P.stage.upload_vec(fc, P.fpool, st);
             cs.nbwd = int(bn.size());
             for (const BwdNode& b : bn) cs.max_m = std::max(cs.max_m, b.m);
-            cs.bwd_n = P.stage.upload_vec(bn, P.apool, st);
-            cs.bwd_s = P.stage.upload_vec(bs, P.apool, st);
-            if (max_rows > 6144)
+            cs.bwd_n = P.stage.upload_vec(bn, P.fpool, st);
+            cs.bwd_s = P.stage.upload_vec(bs, P.fpool, st);
+            if (max_rows > 6144 && !P.dry)
                 throw Error{HSOLVE_ERR_INVALID, "super node with too many neighbour rows for the solve kernel"};
         }
     }
     P.stats.apply_bytes = bytes + (8.0 + w) * P.n;
-    HS_HIP(hipStreamSynchronize(st));
+    if (!P.dry) HS_HIP(hipStreamSynchronize(st));
     P.stage.reset();
-    P.d_scalars = P.apool.alloc_n<double>(2 + 2 * 512 + 16);
+}
+
+// The solve phase of one API call takes its vectors from the arena above the factor data
+// (the transient regions of the factorization are free by then); calls on a plan do not
+// overlap, so each call starts the workspace afresh.
+void begin_workspace(Plan& P) {
+    char* end = P.arena + P.arena_bytes;
+    P.wpool.init(P.fpool.top(), size_t(end - P.fpool.top()), "solve workspace");
+    P.d_V = P.d_X = nullptr;
+    P.V_cols = 0;
+    P.d_krylov = nullptr;
+    P.krylov_cols = 0;
+    P.d_gmres = nullptr;
+    P.gmres_restart = 0;
 }
 
 static void ensure_V(Plan& P, int nrhs) {
     if (P.d_V && P.V_cols >= nrhs) return;
     const size_t bytes = (P.apply32 ? sizeof(float) : sizeof(double)) * size_t(P.vlen) * nrhs;
-    P.d_V = P.apool.alloc(bytes);
-    P.d_X = P.apool.alloc(bytes);
+    P.d_V = P.wpool.alloc(bytes);
+    P.d_X = P.wpool.alloc(bytes);
     P.V_cols = nrhs;
 }
 
@@ -185,9 +198,9 @@ void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double
     const int n = P.n;
     const int64_t ld = n;
     if (!P.d_krylov || P.krylov_cols < nrhs) {
-        P.d_krylov = P.apool.alloc_n<double>(size_t(n) * 5 * nrhs);
-        P.d_kscal = P.apool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
-        P.d_kflag = P.apool.alloc_n<int>(size_t(nrhs));
+        P.d_krylov = P.wpool.alloc_n<double>(size_t(n) * 5 * nrhs);
+        P.d_kscal = P.wpool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
+        P.d_kflag = P.wpool.alloc_n<int>(size_t(nrhs));
         P.krylov_cols = nrhs;
     }
     if (!P.h_scalars || P.h_scalar_cols < nrhs) {
@@ -222,6 +235,8 @@ void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double
     HS_HIP(hipMemcpyAsync(h, bb, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     HS_HIP(hipStreamSynchronize(st));
     bool any = false;
+    for (int c = 0; c < nrhs; ++c)
+        if (!std::isfinite(h[c])) throw Error{HSOLVE_ERR_INVALID, "right-hand side contains NaN or Inf"};
     for (int c = 0; c < nrhs; ++c) {
         h[c] = std::sqrt(h[c]);
         hact[c] = h[c] > 0.0 ? 1 : 0;
@@ -279,9 +294,9 @@ void stationary(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx,
     const int n = P.n;
     const int64_t ld = n;
     if (!P.d_krylov || P.krylov_cols < nrhs) {
-        P.d_krylov = P.apool.alloc_n<double>(size_t(n) * 5 * nrhs);
-        P.d_kscal = P.apool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
-        P.d_kflag = P.apool.alloc_n<int>(size_t(nrhs));
+        P.d_krylov = P.wpool.alloc_n<double>(size_t(n) * 5 * nrhs);
+        P.d_kscal = P.wpool.alloc_n<double>(size_t(nrhs) * (6 + DOTM_BLOCKS));
+        P.d_kflag = P.wpool.alloc_n<int>(size_t(nrhs));
         P.krylov_cols = nrhs;
     }
     if (!P.h_scalars || P.h_scalar_cols < nrhs) {
@@ -307,6 +322,8 @@ void stationary(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx,
     HS_HIP(hipStreamSynchronize(st));
     std::vector<double> nb(nrhs);
     bool any = false;
+    for (int c = 0; c < nrhs; ++c)
+        if (!std::isfinite(h[c])) throw Error{HSOLVE_ERR_INVALID, "right-hand side contains NaN or Inf"};
     for (int c = 0; c < nrhs; ++c) {
         nb[c] = std::sqrt(h[c]);
         hact[c] = nb[c] > 0.0 ? 1 : 0;
@@ -354,7 +371,7 @@ void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, doub
     const int n = P.n;
     const int m = std::max(1, restart);
     if (!P.d_gmres || P.gmres_restart < m) {
-        P.d_gmres = P.apool.alloc_n<double>(size_t(n) * (2 * size_t(m) + 4) + size_t(m + 2) + DOTM_BLOCKS + 8);
+        P.d_gmres = P.wpool.alloc_n<double>(size_t(n) * (2 * size_t(m) + 4) + size_t(m + 2) + DOTM_BLOCKS + 8);
         P.gmres_restart = m;
     }
     if (!P.h_scalars || P.h_scalar_cols < m + 8) {
@@ -382,6 +399,7 @@ void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, doub
         launch_fill<double>(X, 0.0, n, st);
         dot(bc, bc, hcol);
         read(hcol, 1);
+        if (!std::isfinite(h[0])) throw Error{HSOLVE_ERR_INVALID, "right-hand side contains NaN or Inf"};
         const double nb = std::sqrt(h[0]);
         int total = 0;
         while (nb > 0.0 && total < max_iter) {

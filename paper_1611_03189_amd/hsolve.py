@@ -2,8 +2,10 @@
 
 Argument marshalling only: every step of the factorization and of the solve runs in the
 HIP library ``libhsolve.so`` built from ``csrc/`` (``python -m paper_1611_03189_amd.build``).
-PyTorch provides device memory and the stream. If the library is missing, importing the
-functions that need it raises ``RuntimeError``; there is no fallback.
+PyTorch provides device memory and the stream: the factorization runs in an arena, a
+``torch.uint8`` tensor of the size ``hsolve_analyze`` bounds (or one the caller passes). If
+the library is missing, importing the functions that need it raises ``RuntimeError``; there
+is no fallback.
 """
 from __future__ import annotations
 
@@ -21,11 +23,12 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hsolve.h")
 LORASP = 0
 GC = 1
 KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2, "stationary": 3}
+EPS_SCHEDULE = {"constant": 0, "shrink": 1, "grow": 2}
 
 STATUS = {
     0: "HSOLVE_OK", 1: "HSOLVE_NOT_CONVERGED", -1: "HSOLVE_ERR_INVALID",
     -2: "HSOLVE_ERR_NOT_SYMMETRIC", -3: "HSOLVE_ERR_NOT_SPD", -4: "HSOLVE_ERR_OOM",
-    -5: "HSOLVE_ERR_DEVICE", -6: "HSOLVE_ERR_STATE",
+    -5: "HSOLVE_ERR_DEVICE", -6: "HSOLVE_ERR_STATE", -7: "HSOLVE_ERR_TOO_LARGE",
 }
 
 
@@ -45,6 +48,8 @@ class Options(ctypes.Structure):
         ("phi", POINTER(c_double)), ("dim", c_int), ("coords", POINTER(c_double)),
         ("tol", c_double), ("max_iter", c_int), ("krylov", c_int), ("stream", c_void_p),
         ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
+        ("factor_prec", c_int), ("max_super", c_int), ("max_nrhs", c_int), ("eps_schedule", c_int),
+        ("cmp_lpe", c_int), ("cmp_vectors", c_int),
     ]
 
 
@@ -54,7 +59,7 @@ class Stats(ctypes.Structure):
         ("t_factor", c_double), ("t_solve", c_double), ("levels", c_int), ("colours", c_int),
         ("max_rank", c_int), ("factor_bytes", c_int64), ("factor_flops", c_double),
         ("apply_bytes", c_double), ("fail_level", c_int), ("fail_node", c_int),
-        ("device_bytes", c_int64),
+        ("device_bytes", c_int64), ("arena_bound", c_int64),
     ]
 
     def as_dict(self) -> dict:
@@ -84,12 +89,14 @@ def load() -> ctypes.CDLL:
     P = c_void_p
     sig = {
         "hsolve_default_options": (None, [POINTER(Options)]),
-        "hsolve_analyze": (c_int, [c_int, POINTER(c_int64), POINTER(c_int32), POINTER(Options), POINTER(P)]),
-        "hsolve_factor": (c_int, [P, P]),
+        "hsolve_analyze": (c_int, [c_int, POINTER(c_int64), POINTER(c_int32), POINTER(Options), POINTER(P),
+                                   POINTER(ctypes.c_size_t)]),
+        "hsolve_factor": (c_int, [P, P, P, ctypes.c_size_t]),
         "hsolve_apply": (c_int, [P, c_int, P, c_int, P, c_int]),
         "hsolve_solve": (c_int, [P, c_int, P, c_int, P, c_int, POINTER(Stats)]),
         "hsolve_spmv": (c_int, [P, P, P]),
         "hsolve_get_stats": (c_int, [P, POINTER(Stats)]),
+        "hsolve_set_stream": (c_int, [P, P]),
         "hsolve_destroy": (c_int, [P]),
         "hsolve_status_string": (ctypes.c_char_p, [c_int]),
         "hsolve_depth": (c_int, [P]),
@@ -141,23 +148,38 @@ def _dev(t, torch):
     return t.contiguous()
 
 
+def _cols(t, n, torch, what):
+    """A float64 CUDA tensor of n rows as (nrhs, n) row-major = n x nrhs column-major."""
+    t = _dev(t, torch)
+    if t.dim() not in (1, 2) or t.shape[0] != n or t.numel() == 0:
+        raise ValueError(f"{what}: expected a vector of {n} entries or an {n} x nrhs matrix, got "
+                         f"shape {tuple(t.shape)}")
+    vec = t.dim() == 1
+    M = t.reshape(n, -1) if vec else t
+    return M.t().contiguous(), vec
+
+
 class HSolver:
     """One analysed sparse SPD pattern with (after :meth:`factor`) its hierarchical factor.
 
     ``row_ptr``/``col_idx``: CSR pattern (host arrays, symmetric, sorted rows);
     ``coords`` (n x dim) drive the bisection; ``variant`` is ``"gc"`` (default) or
     ``"lorasp"``; ``phi`` (n x p) are the vectors GC preserves (default: constant).
+    ``arena_bound`` is the device memory a factorization of this pattern can need.
     """
 
     def __init__(self, row_ptr, col_idx, coords=None, leaf: int = 16, eps: float = 1e-2,
                  variant: str = "gc", phi=None, tol: float = 1e-10, max_iter: int = 1000,
                  stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200,
-                 overlap_pivots: bool = True):
+                 overlap_pivots: bool = True, factor_prec: int = 64, max_super: int = 512,
+                 max_nrhs: int = 32, eps_schedule: str = "constant", cmp_lpe: int = 0,
+                 cmp_vectors: int = 0):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
         self.col_idx = np.ascontiguousarray(col_idx, dtype=np.int32)
         self.n = len(self.row_ptr) - 1
+        self.nnz = int(self.row_ptr[-1])
         opt = Options()
         lib.hsolve_default_options(ctypes.byref(opt))
         opt.leaf_size = int(leaf)
@@ -169,6 +191,12 @@ class HSolver:
         opt.apply_prec = int(apply_prec)
         opt.restart = int(restart)
         opt.overlap_pivots = 1 if overlap_pivots else 0
+        opt.factor_prec = int(factor_prec)
+        opt.max_super = int(max_super)
+        opt.max_nrhs = int(max_nrhs)
+        opt.eps_schedule = EPS_SCHEDULE[eps_schedule] if isinstance(eps_schedule, str) else int(eps_schedule)
+        opt.cmp_lpe = int(cmp_lpe)
+        opt.cmp_vectors = int(cmp_vectors)
         self._keep = []
         if coords is not None:
             c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(self.n, -1))
@@ -183,18 +211,23 @@ class HSolver:
         self.stream = stream
         opt.stream = c_void_p(stream.cuda_stream) if stream is not None else None
         h = c_void_p()
+        bound = ctypes.c_size_t()
         _check(lib.hsolve_analyze(self.n, self.row_ptr.ctypes.data_as(POINTER(c_int64)),
-                                  _i32p(self.col_idx), ctypes.byref(opt), ctypes.byref(h)),
+                                  _i32p(self.col_idx), ctypes.byref(opt), ctypes.byref(h),
+                                  ctypes.byref(bound)),
                "hsolve_analyze")
         self._h = h
+        self.arena_bound = int(bound.value)
         self._keep.clear()          # analyze copied coordinates and phi
         self.values = None
+        self.arena = None
 
     # -- lifecycle -----------------------------------------------------------------
     def close(self):
         if getattr(self, "_h", None):
             self._lib.hsolve_destroy(self._h)
             self._h = None
+        self.arena = None
 
     def __del__(self):
         try:
@@ -209,22 +242,41 @@ class HSolver:
         self.close()
 
     # -- numeric -------------------------------------------------------------------
-    def factor(self, values):
+    def factor(self, values, arena=None):
+        """Factor with the CSR values (nnz float64, host or device). ``arena`` is a CUDA
+        uint8 tensor the plan works in (kept until the next factor or close); by default one
+        of ``arena_bound`` bytes is made once and reused."""
         import torch
-        v = _dev(values, torch)
+        if isinstance(values, torch.Tensor) and values.is_cuda:
+            v = values
+            if v.dtype != torch.float64:
+                raise TypeError("hsolve works on float64 data")
+            v = v.contiguous()
+        else:
+            v = np.ascontiguousarray(values, dtype=np.float64)
+        if v.reshape(-1).shape[0] != self.nnz:
+            raise ValueError(f"values: expected {self.nnz} entries, got {v.reshape(-1).shape[0]}")
+        if arena is None:
+            arena = self.arena
+            if arena is None or arena.numel() < self.arena_bound:
+                self.arena = None
+                arena = torch.empty(max(self.arena_bound, 256), dtype=torch.uint8, device="cuda")
+        elif not (isinstance(arena, torch.Tensor) and arena.is_cuda and arena.dtype == torch.uint8
+                  and arena.is_contiguous()):
+            raise TypeError("arena must be a contiguous CUDA uint8 tensor")
+        self.arena = arena
         self.values = v
-        _check(self._lib.hsolve_factor(self._h, c_void_p(v.data_ptr())), "hsolve_factor",
-               self._lib, self._h)
+        ptr = c_void_p(v.data_ptr()) if isinstance(v, torch.Tensor) else v.ctypes.data_as(c_void_p)
+        _check(self._lib.hsolve_factor(self._h, ptr, c_void_p(arena.data_ptr()), arena.numel()),
+               "hsolve_factor", self._lib, self._h)
         return self
 
     def apply(self, r, out=None):
         import torch
-        r = _dev(r, torch)
-        vec = r.dim() == 1
-        R = r.reshape(self.n, -1) if vec else r
-        # column-major n x nrhs == a (nrhs, n) row-major tensor
-        Rc = R.t().contiguous()
+        Rc, vec = _cols(r, self.n, torch, "apply")
         Z = torch.empty_like(Rc) if out is None else out
+        if Z.shape != Rc.shape or not Z.is_contiguous() or Z.dtype != torch.float64 or not Z.is_cuda:
+            raise ValueError("apply: out must be a contiguous float64 CUDA tensor of shape (nrhs, n)")
         _check(self._lib.hsolve_apply(self._h, Rc.shape[0], c_void_p(Rc.data_ptr()), self.n,
                                       c_void_p(Z.data_ptr()), self.n), "hsolve_apply",
                self._lib, self._h)
@@ -233,10 +285,7 @@ class HSolver:
 
     def solve(self, b):
         import torch
-        b = _dev(b, torch)
-        vec = b.dim() == 1
-        B = b.reshape(self.n, -1) if vec else b
-        Bc = B.t().contiguous()
+        Bc, vec = _cols(b, self.n, torch, "solve")
         X = torch.empty_like(Bc)
         st = Stats()
         status = _check(self._lib.hsolve_solve(self._h, Bc.shape[0], c_void_p(Bc.data_ptr()), self.n,
@@ -250,10 +299,19 @@ class HSolver:
     def spmv(self, x):
         import torch
         x = _dev(x, torch)
+        if x.numel() != self.n:
+            raise ValueError(f"spmv: expected {self.n} entries, got {x.numel()}")
+        x = x.reshape(-1)
         y = torch.empty_like(x)
         _check(self._lib.hsolve_spmv(self._h, c_void_p(x.data_ptr()), c_void_p(y.data_ptr())),
-               "hsolve_spmv")
+               "hsolve_spmv", self._lib, self._h)
         return y
+
+    def set_stream(self, stream):
+        """Run the plan's later GPU work on `stream` (a torch.cuda.Stream or None)."""
+        self.stream = stream
+        _check(self._lib.hsolve_set_stream(self._h, c_void_p(stream.cuda_stream) if stream is not None else None),
+               "hsolve_set_stream")
 
     # -- kernel timing ---------------------------------------------------------------
     def profile_begin(self, only: str | None = None):

@@ -1,18 +1,17 @@
 """Request loop: a stream of SPD systems A x = b solved on one GPU with continuous batching.
 
-Requests (a matrix with 1..8 right-hand sides and an arrival time) enter a queue as they
-arrive. A fixed set of slots, each a host thread with its own HIP stream, take the oldest
-waiting request whose device-memory estimate fits the free budget, run the symbolic
-analysis, the factorization and one batched PCG solve of all its right-hand sides through
-the C ABI (the factors stay resident for all of them), then destroy the plan and return
-its memory. Work of different slots overlaps on the device; the library calls release the
-interpreter lock, so the slot threads run concurrently.
+Requests (a matrix with 1..8 right-hand sides and an arrival time) are analysed as they
+arrive (host symbolic analysis, which also bounds the device memory the request can need).
+A fixed set of slots, each a host thread with its own HIP stream, take the oldest analysed
+request whose bound fits the free budget, give it an arena of that size, run the
+factorization and one batched solve of all its right-hand sides through the C ABI (the
+factors stay resident for all of them), then destroy the plan and return its arena. Work of
+different slots overlaps on the device; the library calls release the interpreter lock, so
+the slot and analysis threads run concurrently.
 
-Admission: a request's device footprint is estimated as bytes_per_unknown * n, with the
-ratio taken from the requests already finished (the largest ratio seen, times a margin;
-an initial guess before any has finished). A request is admitted when its estimate fits
-in the budget left by the running ones; the budget is charged with the measured footprint
-once the factorization is done.
+Admission: a request is admitted when its arena bound (hsolve_analyze) fits in the budget
+left by the running ones, or when nothing runs; the budget is charged with exactly that
+arena, the device memory the request holds, and the same amount is returned when it ends.
 
 Every result depends only on its own request: the kernels are deterministic and a plan
 shares no device state with another, so a request gives the same bits alone and in the
@@ -90,105 +89,146 @@ class RequestLoop:
     """Continuous-batching request loop over `slots` concurrent HIP streams. The plans factor
     their pivot blocks in order on their slot's stream (overlap_pivots=False): with several
     requests in flight the GPU is already shared, and a second stream per plan only adds
-    queue contention (measured: about 10% fewer solves/s with it)."""
+    queue contention (measured: about 10% fewer solves/s with it). `analysers` host threads
+    run the symbolic analyses as requests arrive."""
 
-    def __init__(self, slots: int = 4, memory_budget: int | None = None,
-                 bytes_per_unknown: float = 16e3, margin: float = 1.25, overlap_pivots: bool = False):
-        import torch
+    def __init__(self, slots: int = 4, memory_budget: int | None = None, overlap_pivots: bool = False,
+                 analysers: int = 2, solver_factory=None):
         self.slots = slots
         self.overlap_pivots = overlap_pivots
+        self.analysers = max(1, analysers)
+        self._factory = solver_factory
         if memory_budget is None:
+            import torch
             free, _ = torch.cuda.mem_get_info()
             memory_budget = int(0.8 * free)
         self.budget = memory_budget
-        self.bpu = bytes_per_unknown
-        self.margin = margin
-        self.streams = [torch.cuda.Stream() for _ in range(slots)]
+        self.streams = None
 
-    def _estimate(self, req: Request) -> int:
-        return int(self.bpu * self.margin * req.n)
+    def _solver(self, r: Request):
+        if self._factory is not None:
+            return self._factory(r)
+        return H.HSolver(r.row_ptr, r.col_idx, coords=r.coords, leaf=r.leaf, eps=r.eps, variant=r.variant,
+                         tol=1e-10, overlap_pivots=self.overlap_pivots, max_nrhs=max(1, r.b.shape[1]))
+
+    def _execute(self, S, r: Request, stream):
+        """Factor and solve one admitted request on `stream`; returns (x, stats, device bytes)."""
+        import torch
+        with torch.cuda.stream(stream):
+            S.set_stream(stream)
+            arena = torch.empty(max(S.arena_bound, 256), dtype=torch.uint8, device="cuda")
+            B = torch.from_numpy(np.ascontiguousarray(r.b)).to("cuda")
+            stream.synchronize()
+            S.factor(r.values, arena=arena)          # host values: copied into the arena
+            X, st = S.solve(B)
+            x = X.cpu().numpy()
+            dev = int(S.stats()["device_bytes"])
+        return x, st, dev
 
     def run(self, requests: list[Request], realtime: bool = True) -> RunSummary:
         """Serve `requests`; with realtime, a request becomes visible at its arrival time."""
-        import torch
-        pending = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
-        waiting: deque[Request] = deque()
+        if self.streams is None and self._factory is None:
+            import torch
+            self.streams = [torch.cuda.Stream() for _ in range(self.slots)]
+        order = deque(sorted(requests, key=lambda r: (r.arrival, r.rid)))
+        waiting: list = []                 # analysed: (request, solver, bound)
         lock = threading.Condition()
-        state = {"used": 0, "running": 0, "error": None}
+        state = {"used": 0, "running": 0, "analysed": 0, "error": None, "peak_used": 0}
         summary = RunSummary()
+        total = len(requests)
         t0 = time.perf_counter()
 
         def now() -> float:
             return time.perf_counter() - t0
 
-        def take(slot: int) -> Request | None:
+        def fail(e):
+            with lock:
+                if state["error"] is None:
+                    state["error"] = e
+                lock.notify_all()
+
+        def analyser():
+            while True:
+                with lock:
+                    if state["error"] is not None or not order:
+                        return
+                    r = order.popleft()
+                if realtime:
+                    delay = r.arrival - now()
+                    if delay > 0:
+                        time.sleep(delay)
+                try:
+                    S = self._solver(r)
+                except Exception as e:           # surfaced to the caller after the run
+                    fail(e)
+                    return
+                with lock:
+                    waiting.append((r, S, int(S.arena_bound)))
+                    waiting.sort(key=lambda w: (w[0].arrival, w[0].rid))
+                    state["analysed"] += 1
+                    lock.notify_all()
+
+        def take():
+            """The oldest analysed request whose arena bound fits the free budget (or any, when
+            nothing runs), with the amount charged for it."""
             with lock:
                 while True:
                     if state["error"] is not None:
                         return None
-                    while pending and (not realtime or pending[0].arrival <= now()):
-                        waiting.append(pending.popleft())
-                    for i, r in enumerate(waiting):
-                        need = self._estimate(r)
+                    for i, (r, S, need) in enumerate(waiting):
                         if state["used"] + need <= self.budget or state["running"] == 0:
                             del waiting[i]
                             state["used"] += need
+                            state["peak_used"] = max(state["peak_used"], state["used"])
                             state["running"] += 1
-                            return r
-                    if not pending and not waiting:
+                            return r, S, need
+                    if state["analysed"] == total and not waiting:
                         return None
-                    timeout = None
-                    if pending and realtime:
-                        timeout = max(0.0, pending[0].arrival - now())
-                    lock.wait(timeout=timeout if timeout is not None else 0.05)
+                    lock.wait(timeout=0.05)
 
         def worker(slot: int):
-            torch.cuda.set_device(0)
-            stream = self.streams[slot]
+            if self.streams is not None:
+                import torch
+                torch.cuda.set_device(0)
+            stream = self.streams[slot] if self.streams is not None else None
             while True:
-                r = take(slot)
-                if r is None:
+                got = take()
+                if got is None:
                     return
-                est = self._estimate(r)
+                r, S, charged = got
                 t_start = now()
                 try:
-                    with torch.cuda.stream(stream):
-                        S = H.HSolver(r.row_ptr, r.col_idx, coords=r.coords, leaf=r.leaf, eps=r.eps,
-                                      variant=r.variant, tol=1e-10, stream=stream,
-                                      overlap_pivots=self.overlap_pivots)
-                        vals = torch.from_numpy(r.values).to("cuda", non_blocking=False)
-                        B = torch.from_numpy(np.ascontiguousarray(r.b)).to("cuda")
-                        stream.synchronize()
-                        S.factor(vals)
-                        X, st = S.solve(B)
-                        x = X.cpu().numpy()
-                        dev = int(S.stats()["device_bytes"])
-                        S.close()
+                    x, st, dev = self._execute(S, r, stream)
                     t_done = now()
-                except Exception as e:          # surfaced to the caller after the run
+                except Exception as e:           # surfaced to the caller after the run
                     with lock:
-                        state["error"] = e
-                        state["used"] -= est
+                        state["used"] -= charged
                         state["running"] -= 1
-                        lock.notify_all()
+                    fail(e)
                     return
+                finally:
+                    S.close()
                 with lock:
-                    state["used"] -= est
+                    state["used"] -= charged
                     state["running"] -= 1
-                    self.bpu = max(self.bpu, dev / max(1, r.n))
                     summary.results.append(Result(r.rid, x.reshape(r.n, -1), st["iterations"], st["converged"],
                                                   st["rel_residual"], dev, r.arrival, t_start, t_done, slot))
                     lock.notify_all()
 
-        threads = [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.slots)]
+        threads = [threading.Thread(target=analyser, daemon=True) for _ in range(self.analysers)]
+        threads += [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.slots)]
         for th in threads:
             th.start()
         for th in threads:
             th.join()
+        for _, S, _ in waiting:
+            S.close()
         if state["error"] is not None:
             raise state["error"]
         summary.makespan = now()
         summary.results.sort(key=lambda r: r.rid)
+        self.last_peak_used = state["peak_used"]
+        self.last_final_used = state["used"]
         return summary
 
 

@@ -114,3 +114,64 @@ def test_state_errors_without_factor(lib):
         assert lib.hsolve_solve(S._h, 1, dummy, p.n, dummy, p.n, None) == -6
         assert lib.hsolve_ranks(S._h, 0, np.zeros(1, np.int32).ctypes.data_as(
             ctypes.POINTER(ctypes.c_int32))) == -6
+
+
+def test_new_options_are_checked(lib):
+    p = pb.poisson(6, 2)
+    for kw in ({"factor_prec": 16}, {"max_super": 0}, {"max_super": 513}, {"max_nrhs": 0},
+               {"eps_schedule": 3}, {"cmp_lpe": 3}, {"cmp_lpe": 128}, {"cmp_vectors": 3}):
+        with pytest.raises(H.HSolveError) as e:
+            H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
+        assert e.value.status == -1, kw
+    for kw in ({"eps_schedule": "shrink"}, {"eps_schedule": "grow"}, {"cmp_lpe": 8, "cmp_vectors": 1},
+               {"cmp_lpe": 1, "cmp_vectors": 2}, {"max_super": 64, "max_nrhs": 4}):
+        with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
+            assert S.arena_bound > 0
+
+
+def test_arena_bound_is_monotone_in_the_caps(lib):
+    """The analysis replays the factorization with every rank at its largest value; a lower
+    super-node cap or fewer right-hand sides can only shrink that replay."""
+    p = pb.poisson(16, 3)
+    bounds = []
+    for ms in (512, 256, 128):
+        with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, eps=1e-2, max_super=ms) as S:
+            bounds.append(S.arena_bound)
+    assert bounds[0] >= bounds[1] >= bounds[2] > 0
+    with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, max_nrhs=1) as S1, \
+            H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, max_nrhs=256) as S2:
+        assert S1.arena_bound <= S2.arena_bound
+        # at least the CSR pattern and values, and the first level's dense diagonal blocks
+        L = S1.depth
+        _, off = S1.leaf_order()
+        diag = sum(8 * (off[2 * s + 2] - off[2 * s]) ** 2 for s in range(1 << (L - 1)))
+        assert S1.arena_bound >= 12 * p.nnz + diag
+
+
+def test_arena_too_small_or_misaligned_is_rejected_before_gpu_work(lib):
+    """The arena checks run on the host before any device call: a too-small arena gives
+    HSOLVE_ERR_OOM, a misaligned one HSOLVE_ERR_INVALID, and the plan stays unfactored."""
+    p = pb.poisson(8, 2)
+    with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8) as S:
+        vals = np.ascontiguousarray(p.values)
+        fake = ctypes.c_void_p(1 << 40)                  # never dereferenced
+        assert lib.hsolve_factor(S._h, vals.ctypes.data_as(ctypes.c_void_p), fake, 4096) == -4
+        assert b"arena too small" in lib.hsolve_last_error(S._h)
+        assert lib.hsolve_factor(S._h, vals.ctypes.data_as(ctypes.c_void_p), ctypes.c_void_p((1 << 40) + 8),
+                                 S.arena_bound) == -1
+        assert lib.hsolve_factor(S._h, vals.ctypes.data_as(ctypes.c_void_p), None, S.arena_bound) == -1
+        dummy = ctypes.c_void_p(1)
+        assert lib.hsolve_apply(S._h, 1, dummy, p.n, dummy, p.n) == -6
+
+
+def test_binding_checks_shapes_before_the_library(lib):
+    """Sizes the C ABI cannot see (it takes no lengths) are checked in the binding."""
+    torch = pytest.importorskip("torch")
+    p = pb.poisson(6, 2)
+    with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8) as S:
+        with pytest.raises(ValueError):
+            S.factor(np.ones(p.nnz - 1))
+        if not torch.cuda.is_available():
+            return
+        with pytest.raises(ValueError):
+            S.apply(torch.ones(p.n - 1, dtype=torch.float64, device="cuda"))

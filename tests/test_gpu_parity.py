@@ -28,11 +28,13 @@ def say(*a):
     print("[gpu-case]", *a, file=sys.stderr, flush=True)
 
 
-def run_pair(p, leaf, eps, variant, nrhs=2, seed=7, phi=None, coords="grid"):
+def run_pair(p, leaf, eps, variant, nrhs=2, seed=7, phi=None, coords="grid", F=None, **kw):
     c = p.coords if coords == "grid" else None
-    F = O.factor(p.row_ptr, p.col_idx, p.values, c, leaf=leaf, eps=eps,
-                 variant=O.GC if variant == "gc" else O.LORASP, phi=phi)
-    S = H.HSolver(p.row_ptr, p.col_idx, coords=c, leaf=leaf, eps=eps, variant=variant, phi=phi)
+    if F is None:
+        F = O.factor(p.row_ptr, p.col_idx, p.values, c, leaf=leaf, eps=eps,
+                     variant=O.GC if variant == "gc" else O.LORASP, phi=phi,
+                     eps_schedule=kw.get("eps_schedule", "constant"))
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=c, leaf=leaf, eps=eps, variant=variant, phi=phi, **kw)
     S.factor(torch.from_numpy(p.values).cuda())
     r = pb.rhs(p.n, nrhs, seed)
     z_ref = O.apply(F, r)
@@ -42,6 +44,22 @@ def run_pair(p, leaf, eps, variant, nrhs=2, seed=7, phi=None, coords="grid"):
 
 def rel(a, b):
     return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+def max_rel(a, b):
+    """Largest entry error relative to the largest entry: the max-norm companion of rel()."""
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def check_parity(F, S, z, z_ref, name, tol=TOL):
+    """The FP64 bar: equal rank vectors (only where no rank decision sat within 1e-8 of the
+    threshold, reading R16), and z within tol of the oracle in the 2-norm and the max-norm."""
+    say(name, f"tie margin {F.tie_margin:.2e} rel {rel(z, z_ref):.2e} max_rel {max_rel(z, z_ref):.2e}")
+    assert F.tie_margin > 1e-8, (name, "rank decision too close to the threshold; change the case")
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
+    assert rel(z, z_ref) <= tol, (name, rel(z, z_ref))
+    assert max_rel(z, z_ref) <= tol, (name, max_rel(z, z_ref))
 
 
 PARITY = [
@@ -63,9 +81,7 @@ def test_apply_matches_oracle(name, make, leaf, eps, variant):
     say(name)
     p = make()
     F, S, r, z_ref, z = run_pair(p, leaf, eps, variant)
-    for d in F.levels:
-        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
-    assert rel(z, z_ref) <= TOL, (name, rel(z, z_ref))
+    check_parity(F, S, z, z_ref, name)
     S.close()
 
 
@@ -90,9 +106,7 @@ def test_wide_super_nodes_match_oracle(name, variant, k):
     p = pb.poisson(64, 2)
     phi = poly_phi(p, k) if k > 1 else None
     F, S, r, z_ref, z = run_pair(p, 256, 1e-2, variant, phi=phi)
-    for d in F.levels:
-        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
-    assert rel(z, z_ref) <= TOL, (name, rel(z, z_ref))
+    check_parity(F, S, z, z_ref, name)
     S.close()
 
 

@@ -1,0 +1,143 @@
+"""GPU path vs the FP64 oracle where the compression runs its other kernel forms, and at the
+full sizes of the named workloads.
+
+* Every launch shape of the eigen-solver inside the compression: the multisection with 1 to
+  64 lanes per eigenvalue and both inverse-iteration kernels (one lane, or one wave, per
+  eigenvalue), forced on cases whose super nodes take the LDS reduction (128 unknowns) and
+  the global-memory reduction (200 unknowns).
+* 256^2 lognormal diffusion (sigma = 2, leaf 16, eps 1e-2): ranks, z and PCG.
+* 64^3 Poisson (leaf 64, eps 1e-2, the benchmarked workload): ranks of every depth, z for a
+  seeded r and the PCG count against the oracle's stored results (tests/golden/, written by
+  make_c3_golden.py from the oracle alone).
+* The per-level tolerance schedules.
+Each case prints its name and the compression kernels it ran before the checks.
+"""
+import functools
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1611_03189_amd import problems as pb
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("no GPU", allow_module_level=True)
+
+from paper_1611_03189_amd import hsolve as H  # noqa: E402
+
+from test_gpu_parity import TOL, check_parity, max_rel, rel, run_pair, say  # noqa: E402
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "c3_poisson3d_64_oracle.npz")
+
+SHAPE_CASES = {
+    "lds_m128": (lambda: pb.poisson(16, 3), 64, 1e-2),          # 3-D, super nodes of 128
+    "global_m200": (lambda: pb.poisson(40, 2), 100, 1e-2),      # 2-D, super nodes of 200
+}
+
+
+@functools.lru_cache(maxsize=None)
+def _oracle_case(key):
+    make, leaf, eps = SHAPE_CASES[key]
+    p = make()
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=eps, variant=O.GC)
+    return p, F
+
+
+def compression_kernels(S):
+    """Names of the compression kernels the last factorization ran (from the kernel timer)."""
+    return sorted({e["name"] for e in S.profile_end() if e["name"].startswith("k_comp")})
+
+
+@pytest.mark.parametrize("vectors", [1, 2], ids=["lane_per_eigenvalue", "wave_per_eigenvalue"])
+@pytest.mark.parametrize("lpe", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("case", sorted(SHAPE_CASES))
+def test_every_eigensolver_launch_shape_matches_oracle(case, lpe, vectors):
+    say("launch shape", case, f"lpe={lpe}", f"vectors={vectors}")
+    p, F = _oracle_case(case)
+    _, leaf, eps = SHAPE_CASES[case]
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=eps, cmp_lpe=lpe, cmp_vectors=vectors)
+    S.profile_begin()
+    S.factor(torch.from_numpy(p.values).cuda())
+    say("kernels", compression_kernels(S))
+    r = pb.rhs(p.n, 2, 7)
+    z = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+    check_parity(F, S, z, O.apply(F, r), f"{case}/lpe{lpe}/v{vectors}")
+    S.close()
+
+
+def _kappa(A):
+    import scipy.sparse.linalg as spla
+    lmax = spla.eigsh(A, k=1, which="LA", return_eigenvectors=False, tol=1e-6)[0]
+    lmin = spla.eigsh(A.tocsc(), k=1, sigma=0.0, which="LM", return_eigenvectors=False, tol=1e-6)[0]
+    return float(lmax / lmin)
+
+
+def test_c2_lognormal_256_matches_oracle():
+    """256^2 lognormal sigma = 2 (kappa(A) about 1e8): ranks at every depth, z, and PCG. The
+    bar is max(1e-10, 100 kappa u): the apply is a chain of dense products whose rounding is
+    amplified by the condition of A_H, which Example 1 puts near kappa(A)."""
+    say("c2_lognormal2d_256")
+    p, w = pb.workload("c2_lognormal2d_256")
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=w["leaf"], eps=w["eps"], variant=O.GC)
+    A = p.to_scipy()
+    kappa = _kappa(A)
+    tol = max(TOL, 100 * kappa * np.finfo(float).eps / 2)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=w["leaf"], eps=w["eps"])
+    S.profile_begin()
+    S.factor(torch.from_numpy(p.values).cuda())
+    say("kernels", compression_kernels(S), f"kappa {kappa:.2e} tol {tol:.1e}")
+    r = pb.rhs(p.n, 1, 7)
+    z = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+    check_parity(F, S, z, O.apply(F, r), "c2", tol=tol)
+    b = pb.rhs(p.n, 1, 2002)[:, 0]
+    x_ref, it_ref, rel_ref = O.pcg(A, b, lambda v: O.apply(F, v), tol=TOL)
+    x, st = S.solve(torch.from_numpy(b).cuda())
+    x = x.cpu().numpy()
+    true_rel = np.linalg.norm(b - A @ x) / np.linalg.norm(b)
+    say("c2 pcg", st["iterations"], it_ref, f"{true_rel:.2e} {rel_ref:.2e}")
+    assert st["converged"] and true_rel <= 2 * TOL and rel_ref <= 2 * TOL
+    assert abs(st["iterations"] - it_ref) <= 1
+    S.close()
+
+
+@pytest.mark.slow
+def test_c3_poisson_64_matches_stored_oracle():
+    say("c3_poisson3d_64 vs stored oracle")
+    if not os.path.exists(GOLDEN):
+        pytest.skip("tests/golden/c3_poisson3d_64_oracle.npz missing (make_c3_golden.py)")
+    g = np.load(GOLDEN)
+    p, w = pb.workload("c3_poisson3d_64")
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=w["leaf"], eps=w["eps"])
+    S.profile_begin()
+    S.factor(torch.from_numpy(p.values).cuda())
+    say("kernels", compression_kernels(S), f"stored tie margin {float(g['tie_margin']):.2e}")
+    assert float(g["tie_margin"]) > 1e-8
+    L = int(g["depth"])
+    assert S.depth == L
+    for d in range(L):
+        assert S.ranks(d).tolist() == g[f"ranks_{d}"].tolist(), d
+    r = pb.rhs(p.n, 1, 7)[:, 0]
+    z = S.apply(torch.from_numpy(r).cuda()).cpu().numpy()
+    say("c3", f"rel {rel(z, g['z']):.2e} max_rel {max_rel(z, g['z']):.2e}")
+    assert rel(z, g["z"]) <= TOL and max_rel(z, g["z"]) <= TOL
+    b = pb.rhs(p.n, 1, 2003)[:, 0]
+    x, st = S.solve(torch.from_numpy(b).cuda())
+    true_rel = np.linalg.norm(b - p.to_scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
+    assert st["converged"] and true_rel <= 2 * TOL
+    assert abs(st["iterations"] - int(g["pcg_iterations"])) <= 1
+    S.close()
+
+
+@pytest.mark.parametrize("schedule,eps,variant", [("shrink", 0.1, "gc"), ("grow", 2.0, "lorasp"),
+                                                  ("shrink", 1e-2, "gc")])
+def test_eps_schedules_match_oracle(schedule, eps, variant):
+    say("eps schedule", schedule, eps, variant)
+    p = pb.poisson(16, 3)
+    F, S, r, z_ref, z = run_pair(p, 8, eps, variant, eps_schedule=schedule)
+    check_parity(F, S, z, z_ref, f"{schedule}/{eps}/{variant}")
+    S.close()

@@ -51,7 +51,7 @@ def test_request_loop_admission_respects_budget():
     say("serve_budget")
     from paper_1611_03189_amd.serve import RequestLoop
     reqs = _requests()[:3]
-    loop = RequestLoop(slots=3, memory_budget=1, bytes_per_unknown=1e4)
+    loop = RequestLoop(slots=3, memory_budget=1)
     out = loop.run(reqs, realtime=False)
     assert len(out.results) == 3 and all(r.converged for r in out.results)
     spans = sorted((r.t_start, r.t_done) for r in out.results)
