@@ -171,6 +171,16 @@ hsolve_status hsolve_factor(hsolve_plan plan, const double* values, void* d_aren
 hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
                            int ldz);
 
+/* hsolve_apply for callers that cannot allocate (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid allocation): the same z = A_H^{-1} r, bitwise, with the two
+ * solve vectors in a static device scratch of the library (64 MiB per GPU, held until the
+ * process ends) instead of the arena. No device or host allocation, no kernel timing.
+ * HSOLVE_ERR_OOM when 2 * (n + sum of ranks) * nrhs values (8 bytes each, 4 with
+ * apply_prec = 32) exceed the scratch. All plans on one GPU share its scratch, which keeps the
+ * last call's contents: calls that overlap on one GPU (any plans, any host threads) race. */
+hsolve_status hsolve_apply_static(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
+                                  int ldz);
+
 /* Solve A x = b preconditioned with A_H^{-1} (x0 = 0) to the relative residual opt.tol, with
  * the outer iteration opt.krylov. b, x: device, n x nrhs column-major. A column of b with a
  * NaN or Inf gives HSOLVE_ERR_INVALID.

@@ -171,6 +171,31 @@ hsolve_status hsolve_apply(hsolve_plan plan, int nrhs, const double* r, int ldr,
     });
 }
 
+hsolve_status hsolve_apply_static(hsolve_plan plan, int nrhs, const double* r, int ldr, double* z,
+                                  int ldz) {
+    if (!plan || !r || !z || nrhs < 1 || ldr < plan->P.n || ldz < plan->P.n)
+        return HSOLVE_ERR_INVALID;
+    if (!plan->P.factored) return HSOLVE_ERR_STATE;
+    struct Args {
+        hsolve_plan plan;
+        int nrhs;
+        const double* r;
+        int ldr;
+        double* z;
+        int ldz;
+    } args{plan, nrhs, r, ldr, z, ldz};
+    // no kernel timing here: its events would be created on first use
+    hs::Profiler* prev = hs::t_prof;
+    hs::t_prof = nullptr;
+    hsolve_status st = guard(plan, "apply_static", [](void* a) {
+        const Args& q = *static_cast<const Args*>(a);
+        hs::apply_static(q.plan->P, q.nrhs, q.r, q.ldr, q.z, q.ldz);
+        HS_HIP(hipStreamSynchronize(q.plan->P.stream));
+    }, &args);
+    hs::t_prof = prev;
+    return st;
+}
+
 hsolve_status hsolve_solve(hsolve_plan plan, int nrhs, const double* b, int ldb, double* x,
                            int ldx, hsolve_stats* stats) {
     if (!plan || !b || !x || nrhs < 1 || ldb < plan->P.n || ldx < plan->P.n)

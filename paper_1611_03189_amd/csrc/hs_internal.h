@@ -343,6 +343,8 @@ double level_eps(const Plan& P, int d);          // compression tolerance of dep
 // solve.hip
 void build_apply_schedule(Plan& P);
 void begin_workspace(Plan& P);
+constexpr size_t APPLY_SCRATCH_BYTES = size_t(64) << 20;   // static scratch of hsolve_apply_static
+void apply_static(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
 void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
          bool flexible, int* its, double* rel);

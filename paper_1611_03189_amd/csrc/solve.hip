@@ -18,6 +18,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 
 #include "hs_internal.h"
 
@@ -178,6 +179,54 @@ void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
     ensure_V(P, nrhs);
     if (P.apply32) apply_t<float>(P, nrhs, r, ldr, z, ldz);
     else apply_t<double>(P, nrhs, r, ldr, z, ldz);
+}
+
+// ---------------------------------------------------------------------------------
+// Apply with the solve vectors in the library's static device scratch (hsolve_apply_static):
+// for callers that cannot allocate. `scratch` is a file-scope device array; host code uses
+// only the address hipGetSymbolAddress returns for the current device (the array's name is
+// a host-side stand-in, not a device address). Every plan on a GPU shares that GPU's copy.
+// ---------------------------------------------------------------------------------
+static __device__ __align__(256) char scratch[APPLY_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+}  // namespace
+
+static void* scratch_on_current_device() {
+    int dev = 0;
+    HS_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= MAX_DEVICES) throw Error{HSOLVE_ERR_DEVICE, "device index out of range"};
+    std::lock_guard<std::mutex> lock(g_scratch_mutex);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        HS_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        if (!p) throw Error{HSOLVE_ERR_DEVICE, "no device address for the static scratch"};
+        g_scratch_ptr[dev] = p;
+    }
+    return g_scratch_ptr[dev];
+}
+
+// z = A_H^{-1} r with V and X in the static scratch: the same kernels and schedule as apply(),
+// no workspace from the arena and no allocation. The red segments of V are cleared by the
+// apply itself, so the scratch's previous contents do not matter.
+void apply_static(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
+    if (!P.factored) throw Error{HSOLVE_ERR_STATE, "apply before factor"};
+    const size_t w = P.apply32 ? sizeof(float) : sizeof(double);
+    const size_t half = align256(w * size_t(P.vlen) * nrhs);
+    if (2 * half > APPLY_SCRATCH_BYTES)
+        throw Error{HSOLVE_ERR_OOM, "the solve vectors need " + std::to_string(2 * half) +
+                                        " bytes; the static scratch holds " + std::to_string(APPLY_SCRATCH_BYTES)};
+    char* base = static_cast<char*>(scratch_on_current_device());
+    P.d_V = base;
+    P.d_X = base + half;
+    P.V_cols = nrhs;
+    apply(P, nrhs, r, ldr, z, ldz);
+    // later calls on the plan must not take these pointers for their arena workspace
+    P.d_V = P.d_X = nullptr;
+    P.V_cols = 0;
 }
 
 void spmv(Plan& P, const double* x, double* y) {

@@ -93,6 +93,7 @@ def load() -> ctypes.CDLL:
                                    POINTER(ctypes.c_size_t)]),
         "hsolve_factor": (c_int, [P, P, P, ctypes.c_size_t]),
         "hsolve_apply": (c_int, [P, c_int, P, c_int, P, c_int]),
+        "hsolve_apply_static": (c_int, [P, c_int, P, c_int, P, c_int]),
         "hsolve_solve": (c_int, [P, c_int, P, c_int, P, c_int, POINTER(Stats)]),
         "hsolve_spmv": (c_int, [P, P, P]),
         "hsolve_get_stats": (c_int, [P, POINTER(Stats)]),
@@ -279,6 +280,20 @@ class HSolver:
             raise ValueError("apply: out must be a contiguous float64 CUDA tensor of shape (nrhs, n)")
         _check(self._lib.hsolve_apply(self._h, Rc.shape[0], c_void_p(Rc.data_ptr()), self.n,
                                       c_void_p(Z.data_ptr()), self.n), "hsolve_apply",
+               self._lib, self._h)
+        Z = Z.t()
+        return Z.reshape(-1) if vec else Z
+
+    def apply_static(self, r, out=None):
+        """As :meth:`apply`, through hsolve_apply_static (solve vectors in the library's static
+        device scratch; nothing allocated by the library)."""
+        import torch
+        Rc, vec = _cols(r, self.n, torch, "apply_static")
+        Z = torch.empty_like(Rc) if out is None else out
+        if Z.shape != Rc.shape or not Z.is_contiguous() or Z.dtype != torch.float64 or not Z.is_cuda:
+            raise ValueError("apply_static: out must be a contiguous float64 CUDA tensor of shape (nrhs, n)")
+        _check(self._lib.hsolve_apply_static(self._h, Rc.shape[0], c_void_p(Rc.data_ptr()), self.n,
+                                             c_void_p(Z.data_ptr()), self.n), "hsolve_apply_static",
                self._lib, self._h)
         Z = Z.t()
         return Z.reshape(-1) if vec else Z
