@@ -104,6 +104,9 @@ typedef struct {
                                (1, 2, 4, ..., 64), 0 = chosen from the launch size (default) */
     int cmp_vectors;        /* inverse iteration: 0 = chosen from the launch size (default),
                                1 = one lane per eigenvalue, 2 = one wave per eigenvalue */
+    int apply_graph;        /* 1 (default): the forward and backward sweeps of an apply are
+                               captured once per workspace as a HIP graph and replayed; 0: the
+                               launches are issued one by one */
 } hsolve_options;
 
 typedef struct {
@@ -204,6 +207,23 @@ hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y);
 /* Change the stream the plan's GPU work runs on (hipStream_t or NULL), e.g. when a request
  * loop hands an analysed plan to the slot that runs it. Not while a call on the plan runs. */
 hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream);
+
+/* ---- Autotuning of the grouped GEMM (Schur updates, Gram matrices, pivot products) ----
+ * The GEMM runs in one of HSOLVE_GEMM_VARIANTS output-tile shapes (0: 64x64 with K steps of
+ * 16, 1: 64x64/32, 2: 128x64/16, 3: 128x128/16); every shape gives the same bits. A launch
+ * falls into one of HSOLVE_GEMM_BUCKETS buckets: its number of 64x64 output tiles (< 32,
+ * < 256, < 2048, more) times its mean inner dimension (<= 64, <= 256, more), bucket =
+ * 3 * tile_class + k_class. hsolve_tune_gemm times every shape on a synthetic launch of each
+ * bucket and keeps the fastest for the process: d_work is caller device memory of at least
+ * hsolve_tune_workspace_bytes(); choice (HSOLVE_GEMM_BUCKETS entries) and ms
+ * (HSOLVE_GEMM_BUCKETS x HSOLVE_GEMM_VARIANTS, best of three) may be NULL. Untuned, every
+ * bucket uses shape 0. hsolve_set_gemm_choice installs a saved choice. Neither may run
+ * while a factorization is in flight. */
+#define HSOLVE_GEMM_VARIANTS 4
+#define HSOLVE_GEMM_BUCKETS 12
+size_t hsolve_tune_workspace_bytes(void);
+hsolve_status hsolve_tune_gemm(void* d_work, size_t work_bytes, void* stream, int32_t* choice, double* ms);
+hsolve_status hsolve_set_gemm_choice(const int32_t* choice);
 
 /* Counters of the plan (levels, colours, ranks, bytes, flops, timings). */
 hsolve_status hsolve_get_stats(hsolve_plan plan, hsolve_stats* stats);

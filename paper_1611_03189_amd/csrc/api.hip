@@ -76,6 +76,7 @@ void hsolve_default_options(hsolve_options* o) {
     o->eps_schedule = HSOLVE_EPS_CONSTANT;
     o->cmp_lpe = 0;
     o->cmp_vectors = 0;
+    o->apply_graph = 1;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -96,7 +97,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         o.max_super < 1 || o.max_super > hs::MAX_SUPER || o.max_nrhs < 1 ||
         o.eps_schedule < HSOLVE_EPS_CONSTANT || o.eps_schedule > HSOLVE_EPS_GROW ||
         !(o.cmp_lpe == 0 || (o.cmp_lpe >= 1 && o.cmp_lpe <= 64 && (o.cmp_lpe & (o.cmp_lpe - 1)) == 0)) ||
-        o.cmp_vectors < 0 || o.cmp_vectors > 2)
+        o.cmp_vectors < 0 || o.cmp_vectors > 2 || (o.apply_graph != 0 && o.apply_graph != 1))
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;
     hsolve_plan plan = new (std::nothrow) hsolve_plan_s();
@@ -247,6 +248,26 @@ hsolve_status hsolve_spmv(hsolve_plan plan, const double* x, double* y) {
         hs::spmv(plan->P, x, y);
         HS_HIP(hipStreamSynchronize(plan->P.stream));
     });
+}
+
+size_t hsolve_tune_workspace_bytes(void) { return hs::tune_workspace_bytes(); }
+
+hsolve_status hsolve_tune_gemm(void* d_work, size_t work_bytes, void* stream, int32_t* choice, double* ms) {
+    if (!d_work) return HSOLVE_ERR_INVALID;
+    return run(nullptr, "tune_gemm", [&] {
+        std::vector<int> c(hs::GEMM_BUCKETS, 0);
+        hs::tune_gemm(d_work, work_bytes, static_cast<hipStream_t>(stream), c.data(), ms);
+        if (choice)
+            for (int b = 0; b < hs::GEMM_BUCKETS; ++b) choice[b] = c[b];
+    });
+}
+
+hsolve_status hsolve_set_gemm_choice(const int32_t* choice) {
+    if (!choice) return HSOLVE_ERR_INVALID;
+    for (int b = 0; b < hs::GEMM_BUCKETS; ++b)
+        if (choice[b] < 0 || choice[b] >= hs::GEMM_VARIANTS) return HSOLVE_ERR_INVALID;
+    for (int b = 0; b < hs::GEMM_BUCKETS; ++b) hs::set_gemm_variant(b, choice[b]);
+    return HSOLVE_OK;
 }
 
 hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream) {

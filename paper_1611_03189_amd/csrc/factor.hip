@@ -56,12 +56,7 @@ struct Batch {
         terms.push_back(GemmTerm{A, B, lda, ldb, K, tA, tB, 0});
         gt.back().t_end = int(terms.size());
     }
-    void close() {
-        const GemmTask& t = gt.back();
-        const int id = int(gt.size()) - 1;
-        for (int ti = 0; ti * 64 < t.M; ++ti)
-            for (int tj = 0; tj * 64 < t.N; ++tj) tiles.push_back(GemmTile{id, ti, tj, 0});
-    }
+    void close() {}   // output tiles are laid out at flush time, in the launch's tile shape
     void gemm(double* C, int ldc, int M, int N, double alpha, double beta, const double* A,
               int lda, int tA, const double* B, int ldb, int tB, int K) {
         if (M <= 0 || N <= 0) return;
@@ -90,10 +85,20 @@ struct Batch {
         return P.side;
     }
     void flush_gemm(Plan& P, bool side = false) {
+        double flops = 0.0, mn = 0.0, tiles64 = 0.0;
+        for (const GemmTask& t : gt) {
+            for (int q = t.t_begin; q < t.t_end; ++q) flops += 2.0 * t.M * t.N * terms[q].K;
+            mn += double(t.M) * t.N;
+            tiles64 += double((t.M + 63) / 64) * double((t.N + 63) / 64);
+        }
+        // tile shape: the autotuned choice for this launch's size bucket; the replay lays out
+        // the 64 x 64 tiles, the most of any shape, so its table bounds every choice
+        const int variant = dry ? 0 : gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0));
+        const GemmShape sh = GEMM_SHAPES[variant];
+        for (size_t id = 0; id < gt.size(); ++id)
+            for (int ti = 0; ti * sh.tm < gt[id].M; ++ti)
+                for (int tj = 0; tj * sh.tn < gt[id].N; ++tj) tiles.push_back(GemmTile{int(id), ti, tj, 0});
         if (!tiles.empty()) {
-            double flops = 0.0;
-            for (const GemmTask& t : gt)
-                for (int q = t.t_begin; q < t.t_end; ++q) flops += 2.0 * t.M * t.N * terms[q].K;
             // the three tables in one upload (one copy on the stream instead of three)
             auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
             const size_t o1 = al(sizeof(GemmTask) * gt.size());
@@ -106,7 +111,7 @@ struct Batch {
             GemmTask* dt = reinterpret_cast<GemmTask*>(dbase);
             GemmTerm* dterm = reinterpret_cast<GemmTerm*>(dbase + o1);
             GemmTile* dtile = reinterpret_cast<GemmTile*>(dbase + o2);
-            if (!dry) launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, to_side(P, side));
+            if (!dry) launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, variant, to_side(P, side));
         }
         gt.clear();
         terms.clear();
@@ -201,6 +206,7 @@ void factor(Plan& P, const double* values_in) {
     P.gmres_restart = 0;
     P.sched.clear();
     if (!dry) {
+        clear_graphs(P);      // they replay the previous factorization's schedule
         if (!P.side) {      // second stream for the pivot blocks (default priority)
             HS_HIP(hipStreamCreateWithFlags(&P.side, hipStreamNonBlocking));
             HS_HIP(hipEventCreateWithFlags(&P.ev_ready, hipEventDisableTiming));

@@ -188,9 +188,25 @@ struct GemmTerm {
     int lda, ldb, K, transA, transB, pad;
 };
 
-struct GemmTile {            // one 64 x 64 tile of a task
+struct GemmTile {            // one output tile of a task (the launch's tile shape)
     int task, ti, tj, pad;
 };
+
+// Tile shapes of the grouped GEMM and the autotuned choice per size bucket. A launch's bucket
+// is decided by its number of 64 x 64 output tiles and its mean inner dimension.
+struct GemmShape {
+    int tm, tn, tk;
+};
+constexpr int GEMM_VARIANTS = 4;
+extern const GemmShape GEMM_SHAPES[GEMM_VARIANTS];
+constexpr int GEMM_TILE_BUCKETS = 4;       // 64x64 tiles: < 32, < 256, < 2048, more
+constexpr int GEMM_K_BUCKETS = 3;          // mean K: <= 64, <= 256, more
+constexpr int GEMM_BUCKETS = GEMM_TILE_BUCKETS * GEMM_K_BUCKETS;
+int gemm_bucket(double tiles64, double mean_k);
+int gemm_variant(int bucket);              // the tuned choice (0 until tuned)
+void set_gemm_variant(int bucket, int variant);
+size_t tune_workspace_bytes();
+void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* ms);
 
 struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1}
     double* A;
@@ -315,6 +331,14 @@ struct Plan {
     double* d_gmres = nullptr;                      // GMRES: V (restart+1), Z (restart), w, r, x
     int gmres_restart = 0;
     int h_scalar_cols = 0;
+    struct Graph {                                  // captured apply sweeps for one workspace
+        const void* V;
+        const void* X;
+        int nrhs;
+        hipGraphExec_t exec;
+    };
+    std::vector<Graph> graphs;
+    hipStream_t cap = nullptr;                      // capture stream of the sweeps
 
     // arena bytes used by the last factorization and its solves
     size_t device_bytes() const {
@@ -345,7 +369,8 @@ void build_apply_schedule(Plan& P);
 void begin_workspace(Plan& P);
 constexpr size_t APPLY_SCRATCH_BYTES = size_t(64) << 20;   // static scratch of hsolve_apply_static
 void apply_static(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
-void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz);
+void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz, bool graph = true);
+void clear_graphs(Plan& P);      // drop the captured sweeps (factor, destroy)
 void pcg(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
          bool flexible, int* its, double* rel);
 void stationary(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, double tol, int max_iter,
@@ -357,7 +382,7 @@ void spmv(Plan& P, const double* x, double* y);
 // kernels.hip: launch wrappers (all asynchronous on stream s)
 void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s);
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, double flops, hipStream_t s);
+                 int ntiles, double flops, int variant, hipStream_t s);
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,

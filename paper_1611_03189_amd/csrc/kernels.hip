@@ -54,47 +54,56 @@ void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes
 }
 
 // ---------------------------------------------------------------------------------
-// Grouped GEMM on the FP64 matrix cores: 64 x 64 output tiles, 256 threads (4 waves, each
-// 32 x 32 = 2 x 2 blocks of v_mfma_f64_16x16x4f64), K in steps of 16 through two LDS
-// buffers, the next K step loaded into registers while the current one is multiplied.
+// Grouped GEMM on the FP64 matrix cores: TM x TN output tiles, 256 threads (4 waves in a
+// 2 x 2 grid, each (TM/2) x (TN/2) = BX x BY blocks of v_mfma_f64_16x16x4f64), K in steps of
+// TK through two LDS buffers, the next K step loaded into registers while the current one is
+// multiplied. Every shape adds the k products of an output element in the same order (k
+// ascending, four per instruction), so all shapes give the same bits; the autotuner picks
+// one per size bucket.
 // Operand layout of the instruction (per lane l of the wave): A(l % 16, l / 16),
 // B(l / 16, l % 16); result register r holds C(l / 16 + 4 r, l % 16).
 // ---------------------------------------------------------------------------------
-constexpr int TM = 64, TN = 64, TK = 16;
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 
 struct GemmStep {            // position in the concatenated K loop of a task's terms
     int term, k0;
 };
 
+template <int TM, int TN, int TK>
 __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
                                              const GemmTile* tiles) {
+    constexpr int BX = TM / 32, BY = TN / 32;              // 16 x 16 blocks per wave
+    constexpr int LA = TM * TK / NT, LB = TN * TK / NT;    // loads per thread and K step
+    static_assert(LA * NT == TM * TK && LB * NT == TN * TK, "tile");
     const GemmTile tl = tiles[blockIdx.x];
     const GemmTask T = tasks[tl.task];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     __shared__ double As[2][TK][TM + 1];
     __shared__ double Bs[2][TK][TN + 1];
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
-    dbl4 acc[2][2];
+    dbl4 acc[BX][BY];
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BX; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < BY; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 
-    // registers of one K step: 4 A and 4 B elements per thread
-    double ra[4], rb[4];
+    double ra[LA], rb[LB];
     auto load_step = [&](GemmStep st) {
         const GemmTerm g = terms[st.term];
         const HS_G double* gA = gp(g.A);
         const HS_G double* gB = gp(g.B);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < LA; ++q) {
             const int e = tid + NT * q;
             int ii, kk;
             if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
             const int gi = i0 + ii, gk = st.k0 + kk;
             ra[q] = (gi < T.M && gk < g.K) ? (g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda])
                                            : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + NT * q;
             int jj, kb;
             if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
             const int gj = j0 + jj, gkb = st.k0 + kb;
@@ -105,11 +114,15 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
     auto store_step = [&](GemmStep st, int buf) {
         const GemmTerm g = terms[st.term];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
+        for (int q = 0; q < LA; ++q) {
             const int e = tid + NT * q;
             int ii, kk;
             if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
             As[buf][kk][ii] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < LB; ++q) {
+            const int e = tid + NT * q;
             int jj, kb;
             if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
             Bs[buf][kb][jj] = rb[q];
@@ -125,7 +138,7 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
     };
     GemmStep cur{T.t_begin, 0};
     while (cur.term < T.t_end && terms[cur.term].K <= 0) ++cur.term;
-    const int wr = (wv / 2) * 32, wc = (wv % 2) * 32;    // this wave's 32 x 32 sub-tile
+    const int wr = (wv / 2) * (TM / 2), wc = (wv % 2) * (TN / 2);    // this wave's sub-tile
     const int fr = lane % 16, fk = lane / 16;
     int buf = 0;
     if (cur.term < T.t_end) load_step(cur);
@@ -136,15 +149,15 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
         if (nxt.term < T.t_end) load_step(nxt);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
-            double af[2], bf[2];
+            double af[BX], bf[BY];
 #pragma unroll
-            for (int x = 0; x < 2; ++x) af[x] = As[buf][kk + fk][wr + 16 * x + fr];
+            for (int x = 0; x < BX; ++x) af[x] = As[buf][kk + fk][wr + 16 * x + fr];
 #pragma unroll
-            for (int y = 0; y < 2; ++y) bf[y] = Bs[buf][kk + fk][wc + 16 * y + fr];
+            for (int y = 0; y < BY; ++y) bf[y] = Bs[buf][kk + fk][wc + 16 * y + fr];
 #pragma unroll
-            for (int x = 0; x < 2; ++x)
+            for (int x = 0; x < BX; ++x)
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < BY; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
         }
         cur = nxt;
@@ -152,9 +165,9 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
     }
     HS_G double* C = gp(T.C);
 #pragma unroll
-    for (int x = 0; x < 2; ++x)
+    for (int x = 0; x < BX; ++x)
 #pragma unroll
-        for (int y = 0; y < 2; ++y)
+        for (int y = 0; y < BY; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + 16 * x + fk + 4 * r, j = j0 + wc + 16 * y + fr;
@@ -166,11 +179,18 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
             }
 }
 
+const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16}, {64, 64, 32}, {128, 64, 16}, {128, 128, 16}};
+
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, double flops, hipStream_t s) {
+                 int ntiles, double flops, int variant, hipStream_t s) {
     if (ntiles <= 0) return;
     ProfScope ps("k_gemm", flops, s);
-    hipLaunchKernelGGL(k_gemm, dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles);
+    switch (variant) {
+        case 1: hipLaunchKernelGGL((k_gemm<64, 64, 32>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 2: hipLaunchKernelGGL((k_gemm<128, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 3: hipLaunchKernelGGL((k_gemm<128, 128, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        default: hipLaunchKernelGGL((k_gemm<64, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+    }
     check_launch("k_gemm");
 }
 

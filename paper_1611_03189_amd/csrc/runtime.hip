@@ -201,6 +201,8 @@ ProfScope::~ProfScope() {
 }
 
 Plan::~Plan() {
+    clear_graphs(*this);
+    if (cap) (void)hipStreamDestroy(cap);
     if (side) {
         (void)hipStreamSynchronize(side);
         (void)hipStreamDestroy(side);

@@ -150,15 +150,13 @@ static void ensure_V(Plan& P, int nrhs) {
     P.V_cols = nrhs;
 }
 
+// The sweeps of one apply on V / X: zero the red segments, forward colour by colour from the
+// leaves up, backward from the root down.
 template <typename T>
-static void apply_t(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
-    hipStream_t st = P.stream;
+static void sweeps(Plan& P, int nrhs, T* V, T* X, hipStream_t st) {
     const int L = P.L, nlev = std::max(L, 1);
     const int64_t ldv = P.vlen;
-    T* V = static_cast<T*>(P.d_V);
-    T* X = static_cast<T*>(P.d_X);
     for (int c = 0; c < nrhs; ++c) launch_fill<T>(V + size_t(c) * ldv + P.n, T(0), P.vlen - P.n, st);
-    launch_gather_perm<T>(r, ldr, V, ldv, P.d_perm, P.n, nrhs, st);
     for (int d = nlev - 1; d >= 0; --d)
         for (size_t c = 0; c < P.sched[d].size(); ++c) {
             const Plan::ColourSched& cs = P.sched[d][c];
@@ -169,16 +167,64 @@ static void apply_t(Plan& P, int nrhs, const double* r, int ldr, double* z, int 
             const Plan::ColourSched& cs = P.sched[d][c];
             launch_bwd<T>(cs.bwd_n, cs.bwd_s, cs.nbwd, cs.max_m, V, X, ldv, nrhs, cs.bwd_bytes * nrhs, st);
         }
+}
+
+// The sweeps as one HIP graph, captured on the plan's capture stream the first time a
+// (V, X, nrhs) triple is seen after a factorization and replayed on the plan's stream after
+// that: the 2 x (colours) dependent launches of an apply are submitted as one. The graph
+// holds kernel nodes only (the red segments are zeroed by a fill kernel, not a memset).
+template <typename T>
+static hipGraphExec_t sweep_graph(Plan& P, int nrhs, T* V, T* X) {
+    for (const Plan::Graph& g : P.graphs)
+        if (g.V == V && g.X == X && g.nrhs == nrhs) return g.exec;
+    if (!P.cap) HS_HIP(hipStreamCreateWithFlags(&P.cap, hipStreamNonBlocking));
+    if (P.graphs.size() >= 8) {      // a few workspaces at most; drop the oldest
+        (void)hipGraphExecDestroy(P.graphs.front().exec);
+        P.graphs.erase(P.graphs.begin());
+    }
+    hipGraph_t graph = nullptr;
+    HS_HIP(hipStreamBeginCapture(P.cap, hipStreamCaptureModeThreadLocal));
+    try {
+        sweeps<T>(P, nrhs, V, X, P.cap);
+    } catch (...) {
+        (void)hipStreamEndCapture(P.cap, &graph);
+        if (graph) (void)hipGraphDestroy(graph);
+        throw;
+    }
+    HS_HIP(hipStreamEndCapture(P.cap, &graph));
+    hipGraphExec_t exec = nullptr;
+    const hipError_t e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) throw Error{HSOLVE_ERR_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(e)};
+    P.graphs.push_back(Plan::Graph{V, X, nrhs, exec});
+    return exec;
+}
+
+template <typename T>
+static void apply_t(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz, bool graph) {
+    hipStream_t st = P.stream;
+    const int64_t ldv = P.vlen;
+    T* V = static_cast<T*>(P.d_V);
+    T* X = static_cast<T*>(P.d_X);
+    launch_gather_perm<T>(r, ldr, V, ldv, P.d_perm, P.n, nrhs, st);
+    // kernel timing records every launch: it takes the eager path
+    if (graph && P.opt.apply_graph && !(t_prof && t_prof->on)) HS_HIP(hipGraphLaunch(sweep_graph<T>(P, nrhs, V, X), st));
+    else sweeps<T>(P, nrhs, V, X, st);
     launch_scatter_perm<T>(X, ldv, z, ldz, P.d_perm, P.n, nrhs, st);
+}
+
+void clear_graphs(Plan& P) {
+    for (Plan::Graph& g : P.graphs) (void)hipGraphExecDestroy(g.exec);
+    P.graphs.clear();
 }
 
 // z = A_H^{-1} r for nrhs columns (device pointers, original unknown order); the sweeps run in
 // the precision of the factor copy the plan keeps for them
-void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz) {
+void apply(Plan& P, int nrhs, const double* r, int ldr, double* z, int ldz, bool graph) {
     if (!P.factored) throw Error{HSOLVE_ERR_STATE, "apply before factor"};
     ensure_V(P, nrhs);
-    if (P.apply32) apply_t<float>(P, nrhs, r, ldr, z, ldz);
-    else apply_t<double>(P, nrhs, r, ldr, z, ldz);
+    if (P.apply32) apply_t<float>(P, nrhs, r, ldr, z, ldz, graph);
+    else apply_t<double>(P, nrhs, r, ldr, z, ldz, graph);
 }
 
 // ---------------------------------------------------------------------------------
@@ -223,7 +269,7 @@ void apply_static(Plan& P, int nrhs, const double* r, int ldr, double* z, int ld
     P.d_V = base;
     P.d_X = base + half;
     P.V_cols = nrhs;
-    apply(P, nrhs, r, ldr, z, ldz);
+    apply(P, nrhs, r, ldr, z, ldz, /*graph=*/false);     // instantiating a graph would allocate
     // later calls on the plan must not take these pointers for their arena workspace
     P.d_V = P.d_X = nullptr;
     P.V_cols = 0;

@@ -49,7 +49,7 @@ class Options(ctypes.Structure):
         ("tol", c_double), ("max_iter", c_int), ("krylov", c_int), ("stream", c_void_p),
         ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
         ("factor_prec", c_int), ("max_super", c_int), ("max_nrhs", c_int), ("eps_schedule", c_int),
-        ("cmp_lpe", c_int), ("cmp_vectors", c_int),
+        ("cmp_lpe", c_int), ("cmp_vectors", c_int), ("apply_graph", c_int),
     ]
 
 
@@ -98,6 +98,9 @@ def load() -> ctypes.CDLL:
         "hsolve_spmv": (c_int, [P, P, P]),
         "hsolve_get_stats": (c_int, [P, POINTER(Stats)]),
         "hsolve_set_stream": (c_int, [P, P]),
+        "hsolve_tune_workspace_bytes": (ctypes.c_size_t, []),
+        "hsolve_tune_gemm": (c_int, [P, ctypes.c_size_t, P, POINTER(c_int32), POINTER(c_double)]),
+        "hsolve_set_gemm_choice": (c_int, [POINTER(c_int32)]),
         "hsolve_destroy": (c_int, [P]),
         "hsolve_status_string": (ctypes.c_char_p, [c_int]),
         "hsolve_depth": (c_int, [P]),
@@ -160,6 +163,35 @@ def _cols(t, n, torch, what):
     return M.t().contiguous(), vec
 
 
+GEMM_SHAPES = [(64, 64, 16), (64, 64, 32), (128, 64, 16), (128, 128, 16)]
+GEMM_BUCKETS = 12
+
+
+def tune_gemm(stream=None) -> dict:
+    """Time every tile shape of the grouped GEMM on each size bucket (hsolve_tune_gemm) and
+    keep the fastest for the process; returns the choice and the timings."""
+    import torch
+    lib = load()
+    work = torch.empty(int(lib.hsolve_tune_workspace_bytes()), dtype=torch.uint8, device="cuda")
+    choice = np.zeros(GEMM_BUCKETS, dtype=np.int32)
+    ms = np.zeros(GEMM_BUCKETS * len(GEMM_SHAPES))
+    _check(lib.hsolve_tune_gemm(c_void_p(work.data_ptr()), work.numel(),
+                                c_void_p(stream.cuda_stream) if stream is not None else None,
+                                _i32p(choice), ms.ctypes.data_as(POINTER(c_double))), "hsolve_tune_gemm")
+    torch.cuda.synchronize()
+    del work
+    return {"choice": choice.tolist(), "shapes": [list(x) for x in GEMM_SHAPES],
+            "ms": ms.reshape(GEMM_BUCKETS, len(GEMM_SHAPES)).round(4).tolist()}
+
+
+def set_gemm_choice(choice) -> None:
+    """Install a tile-shape choice per bucket (e.g. one saved from tune_gemm)."""
+    c = np.ascontiguousarray(choice, dtype=np.int32)
+    if c.shape != (GEMM_BUCKETS,):
+        raise ValueError(f"expected {GEMM_BUCKETS} entries")
+    _check(load().hsolve_set_gemm_choice(_i32p(c)), "hsolve_set_gemm_choice")
+
+
 class HSolver:
     """One analysed sparse SPD pattern with (after :meth:`factor`) its hierarchical factor.
 
@@ -174,7 +206,7 @@ class HSolver:
                  stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200,
                  overlap_pivots: bool = True, factor_prec: int = 64, max_super: int = 512,
                  max_nrhs: int = 32, eps_schedule: str = "constant", cmp_lpe: int = 0,
-                 cmp_vectors: int = 0):
+                 cmp_vectors: int = 0, apply_graph: bool = True):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -198,6 +230,7 @@ class HSolver:
         opt.eps_schedule = EPS_SCHEDULE[eps_schedule] if isinstance(eps_schedule, str) else int(eps_schedule)
         opt.cmp_lpe = int(cmp_lpe)
         opt.cmp_vectors = int(cmp_vectors)
+        opt.apply_graph = 1 if apply_graph else 0
         self._keep = []
         if coords is not None:
             c = np.ascontiguousarray(np.asarray(coords, dtype=np.float64).reshape(self.n, -1))
