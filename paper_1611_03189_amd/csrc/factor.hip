@@ -518,6 +518,32 @@ void factor(Plan& P, const double* values_in) {
                                      hipMemcpyDeviceToHost));
                 }
             }
+            // The eigenvectors of nearly equal eigenvalues come from independent inverse
+            // iterations and are orthogonal only to about u ||G|| / gap. One Newton-Schulz step
+            // towards the polar factor, U <- U (3 I - U^T U) / 2, restores U^T U = I to second
+            // order on the matrix cores; it keeps span(U), so the GC vectors stay in it.
+            {
+                std::vector<double*> Wsc(comp.size(), nullptr);
+                for (CompNode& cn : comp) {
+                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
+                    if (k < 2) continue;
+                    Wsc[cn.slot] = P.spool.alloc_n<double>(size_t(k) * k);
+                    B.gemm(Wsc[cn.slot], k, k, k, 1.0, 0.0, cn.U, m, 1, cn.U, m, 0, m);
+                    flops += 2.0 * m * k * k;
+                }
+                B.flush_gemm(P);
+                for (CompNode& cn : comp) {
+                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
+                    if (k < 2) continue;
+                    double* Un = P.spool.alloc_n<double>(size_t(m) * k);
+                    B.copy(cn.U, m, Un, m, m, k, 0);
+                    B.gemm(Un, m, m, k, -0.5, 1.5, cn.U, m, 0, Wsc[cn.slot], k, 0, k);
+                    flops += 2.0 * m * k * k;
+                    cn.U = Un;
+                }
+                B.flush_copies(P);
+                B.flush_gemm(P);
+            }
             std::vector<const CompNode*> compof(nd, nullptr);
             for (const CompNode& cn : comp) compof[cn.s] = &cn;
 
