@@ -69,6 +69,12 @@ enum { HSOLVE_PCG = 0, HSOLVE_FPCG = 1, HSOLVE_GMRES = 2, HSOLVE_STATIONARY = 3 
    GROW      eps h 2^{(lmax - d)/3}, h = n^{-1/dim}: small at the leaves, larger toward the root
              (the paper's adaptive choice for LoRaSp) */
 enum { HSOLVE_EPS_CONSTANT = 0, HSOLVE_EPS_SHRINK = 1, HSOLVE_EPS_GROW = 2 };
+/* which clusters are neighbours (their interaction is never compressed):
+   FOOTPRINT  clusters joined by a nonzero of A (§3.1: the original graph's adjacency);
+   GEOMETRIC  the rule of §7's experiments: with every unknown a unit cell at its coordinates,
+              clusters (boxes of their cells) are well separated when the Euclidean gap
+              between the boxes exceeds the larger box side, and neighbours otherwise */
+enum { HSOLVE_NEIGHBOURS_FOOTPRINT = 0, HSOLVE_NEIGHBOURS_GEOMETRIC = 1 };
 
 typedef struct {
     int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
@@ -107,6 +113,7 @@ typedef struct {
     int apply_graph;        /* 1 (default): the forward and backward sweeps of an apply are
                                captured once per workspace as a HIP graph and replayed; 0: the
                                launches are issued one by one */
+    int neighbours;         /* HSOLVE_NEIGHBOURS_FOOTPRINT (default) or HSOLVE_NEIGHBOURS_GEOMETRIC */
 } hsolve_options;
 
 typedef struct {

@@ -23,13 +23,13 @@ What it follows (sections, equations and algorithms of arXiv:1611.03189):
 Readings where the paper is silent or ambiguous are listed in ``hsolver.py`` next to
 the code that takes them.
 """
-from .tree import tree_depth, cluster_leaves, footprint_adjacency
+from .tree import tree_depth, cluster_leaves, footprint_adjacency, GeometricNeighbours
 from .hsolver import (Factorization, NotSPDError, compress, pivot, eliminate_node,
                       factor, apply, apply_matrix, level_eps, LORASP, GC)
 from .krylov import pcg, fpcg, gmres, stationary
 
 __all__ = [
-    "tree_depth", "cluster_leaves", "footprint_adjacency",
+    "tree_depth", "cluster_leaves", "footprint_adjacency", "GeometricNeighbours",
     "Factorization", "NotSPDError", "compress", "pivot", "eliminate_node", "factor",
     "apply", "apply_matrix", "level_eps", "LORASP", "GC", "pcg", "gmres", "stationary",
 ]

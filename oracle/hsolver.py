@@ -57,7 +57,7 @@ from dataclasses import dataclass, field
 import numpy as np
 import scipy.linalg as sla
 
-from .tree import tree_depth, cluster_leaves, leaf_index, footprint_adjacency
+from .tree import tree_depth, cluster_leaves, leaf_index, footprint_adjacency, GeometricNeighbours
 
 LORASP = 0
 GC = 1          # preserve the given vectors (constant vector by default)
@@ -360,12 +360,14 @@ def _leaf_blocks(row_ptr, col_idx, values, leaves, leaf_of, n):
 
 def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1e-2,
            variant: int = GC, phi: np.ndarray | None = None,
-           eps_schedule: str = "constant") -> Factorization:
+           eps_schedule: str = "constant", neighbours: str = "footprint") -> Factorization:
     """Algorithm "Setup": build the hierarchical factorization of the SPD matrix A.
 
     ``phi`` (n x p) are the vectors GC preserves; default is the constant vector
     (GC-constant). Ignored for LoRaSp. ``eps_schedule`` picks the per-level tolerance
     (see ``level_eps``; dim is the coordinate dimension, 1 without coordinates).
+    ``neighbours``: "footprint" (R6, the original graph's adjacency, §3.1) or "geometric"
+    (R6g, the distance rule of §7's experiments, ``GeometricNeighbours``).
     """
     n = len(row_ptr) - 1
     L = tree_depth(n, leaf)
@@ -403,7 +405,10 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
         eps_d = level_eps(eps, eps_schedule, d, L, n, dim)
         eps_at[d] = eps_d
         cur, child_size = _merge(red, d, variant)
-        adj = footprint_adjacency(row_ptr, col_idx, leaf_of, L, d)
+        if neighbours == "geometric":
+            adj = GeometricNeighbours(coords, leaves, L, d)
+        else:
+            adj = footprint_adjacency(row_ptr, col_idx, leaf_of, L, d)
         super_size = dict(cur.size)
         remaining = [s for s in range(1 << d) if cur.size[s] > 0]
         colours, nodes = [], {}

@@ -73,3 +73,33 @@ def footprint_adjacency(row_ptr, col_idx, leaf_of: np.ndarray, L: int, d: int) -
     off = ci != cj
     code = np.unique(ci[off] * (1 << 32) + cj[off])
     return set(zip((code >> 32).tolist(), (code & 0xFFFFFFFF).tolist()))
+
+
+class GeometricNeighbours:
+    """Neighbour test of §7's experiments: two clusters are well separated when their distance
+    is larger than the size of the clusters (reading R6g). Every unknown is a unit cell at its
+    coordinates (the unknown's index as a 1-D coordinate when there are none); a cluster is the
+    bounding box of its cells, [min, max + 1) per axis; its size is the largest side; the
+    distance of two clusters is the Euclidean gap between their boxes. Clusters i != j at
+    depth d are neighbours iff gap <= max(size_i, size_j). ``(i, j) in obj`` answers for
+    depth-d cluster indices."""
+
+    def __init__(self, coords, leaves: list, L: int, d: int):
+        n = sum(len(c) for c in leaves)
+        if coords is None:
+            coords = np.arange(n, dtype=np.float64)[:, None]
+        coords = np.asarray(coords, dtype=np.float64).reshape(n, -1)
+        k = 1 << (L - d)
+        groups = [np.concatenate(leaves[i * k:(i + 1) * k]) for i in range(1 << d)]
+        self.lo = np.array([coords[g].min(axis=0) if len(g) else np.full(coords.shape[1], np.inf)
+                            for g in groups])
+        self.hi = np.array([coords[g].max(axis=0) + 1.0 if len(g) else np.full(coords.shape[1], -np.inf)
+                            for g in groups])
+        self.size = np.max(self.hi - self.lo, axis=1)
+
+    def __contains__(self, pair) -> bool:
+        i, j = pair
+        if i == j:
+            return False
+        gap = np.maximum(0.0, np.maximum(self.lo[j] - self.hi[i], self.lo[i] - self.hi[j]))
+        return bool(np.sqrt(np.sum(gap * gap)) <= max(self.size[i], self.size[j]))

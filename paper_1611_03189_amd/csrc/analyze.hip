@@ -20,6 +20,8 @@
 //  * elimination order inside a level: greedy colours in index order, a node joins the
 //    current colour only if it has no block to a node already in it.
 #include <algorithm>
+#include <cmath>
+#include <limits>
 #include <numeric>
 
 #include <string>
@@ -185,6 +187,53 @@ void analyze(Plan& P) {
         return adj;
     };
 
+    // Geometric neighbours (opt.neighbours = HSOLVE_NEIGHBOURS_GEOMETRIC, the rule of §7's
+    // experiments): every unknown is a unit cell at its coordinates (its index when there are
+    // none), a cluster the box [min, max + 1) of its cells, its size the box's largest side;
+    // clusters are well separated when the Euclidean gap between their boxes exceeds the larger
+    // size. Boxes of depth d are unions of the boxes of depth d + 1.
+    const bool geometric = P.opt.neighbours == HSOLVE_NEIGHBOURS_GEOMETRIC;
+    const int dim = (P.coords.empty() || P.opt.dim < 1) ? 1 : P.opt.dim;
+    std::vector<std::vector<double>> box_lo, box_hi;   // [depth][cluster * dim + t]
+    if (geometric) {
+        box_lo.assign(L + 1, {});
+        box_hi.assign(L + 1, {});
+        box_lo[L].assign(size_t(1 << L) * dim, std::numeric_limits<double>::infinity());
+        box_hi[L].assign(size_t(1 << L) * dim, -std::numeric_limits<double>::infinity());
+        for (int i = 0; i < (1 << L); ++i)
+            for (int q = P.leaf_off[i]; q < P.leaf_off[i + 1]; ++q)
+                for (int t = 0; t < dim; ++t) {
+                    const double x = P.coords.empty() ? double(P.perm[q]) : P.coords[size_t(P.perm[q]) * dim + t];
+                    box_lo[L][size_t(i) * dim + t] = std::min(box_lo[L][size_t(i) * dim + t], x);
+                    box_hi[L][size_t(i) * dim + t] = std::max(box_hi[L][size_t(i) * dim + t], x + 1.0);
+                }
+        for (int d = L - 1; d >= 0; --d) {
+            box_lo[d].resize(size_t(1 << d) * dim);
+            box_hi[d].resize(size_t(1 << d) * dim);
+            for (int c = 0; c < (1 << d); ++c)
+                for (int t = 0; t < dim; ++t) {
+                    box_lo[d][size_t(c) * dim + t] =
+                        std::min(box_lo[d + 1][size_t(2 * c) * dim + t], box_lo[d + 1][size_t(2 * c + 1) * dim + t]);
+                    box_hi[d][size_t(c) * dim + t] =
+                        std::max(box_hi[d + 1][size_t(2 * c) * dim + t], box_hi[d + 1][size_t(2 * c + 1) * dim + t]);
+                }
+        }
+    }
+    auto geo_near = [&](int d, int i, int j) {
+        const double* li = &box_lo[d][size_t(i) * dim];
+        const double* hi_ = &box_hi[d][size_t(i) * dim];
+        const double* lj = &box_lo[d][size_t(j) * dim];
+        const double* hj = &box_hi[d][size_t(j) * dim];
+        double g2 = 0.0, si = 0.0, sj = 0.0;
+        for (int t = 0; t < dim; ++t) {
+            const double g = std::max(0.0, std::max(lj[t] - hi_[t], li[t] - hj[t]));
+            g2 += g * g;
+            si = std::max(si, hi_[t] - li[t]);
+            sj = std::max(sj, hj[t] - lj[t]);
+        }
+        return std::sqrt(g2) <= std::max(si, sj);
+    };
+
     // pattern of the first level = footprint adjacency of depth L-1 (all nodes non-empty)
     std::vector<std::vector<int>> partners = adjacency(L - 1);
     std::vector<uint8_t> nonempty(size_t(1) << (L - 1), 1);
@@ -201,7 +250,8 @@ void analyze(Plan& P) {
         S.super_nonempty = nonempty;
         S.red_nonempty.assign(nd, 0);
         S.init_partners = partners;
-        std::vector<std::vector<int>> adj = adjacency(d);
+        std::vector<std::vector<int>> adj;
+        if (!geometric) adj = adjacency(d);
         std::vector<uint8_t> is_red(nd, 0);
         std::vector<int> remaining;
         for (int s = 0; s < nd; ++s)
@@ -221,7 +271,8 @@ void analyze(Plan& P) {
                 std::vector<int>& Ns = S.N[s];
                 std::vector<int>& Ws = S.W[s];
                 for (int j : partners[s]) {
-                    bool nb = std::binary_search(adj[s].begin(), adj[s].end(), j);
+                    const bool nb = geometric ? geo_near(d, s, j)
+                                              : std::binary_search(adj[s].begin(), adj[s].end(), j);
                     (nb ? Ns : Ws).push_back(j);
                     (nb ? S.Nred[s] : S.Wred[s]).push_back(is_red[j]);
                 }

@@ -41,13 +41,15 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("neighbours", ["footprint", "geometric"])
 @pytest.mark.parametrize("name,make,leaf,eps,variant", CASES, ids=[c[0] for c in CASES])
-def test_schedule_matches_oracle(name, make, leaf, eps, variant):
+def test_schedule_matches_oracle(name, make, leaf, eps, variant, neighbours):
     p = make()
     coords = None if name.endswith("nocoords") else p.coords
     F = O.factor(p.row_ptr, p.col_idx, p.values, coords, leaf=leaf, eps=eps,
-                 variant=O.GC if variant == "gc" else O.LORASP)
-    with H.HSolver(p.row_ptr, p.col_idx, coords=coords, leaf=leaf, eps=eps, variant=variant) as S:
+                 variant=O.GC if variant == "gc" else O.LORASP, neighbours=neighbours)
+    with H.HSolver(p.row_ptr, p.col_idx, coords=coords, leaf=leaf, eps=eps, variant=variant,
+                   neighbours=neighbours) as S:
         assert S.depth == F.L
         perm, off = S.leaf_order()
         assert np.array_equal(perm, np.concatenate(F.leaves))

@@ -141,3 +141,34 @@ def test_eps_schedules_match_oracle(schedule, eps, variant):
     F, S, r, z_ref, z = run_pair(p, 8, eps, variant, eps_schedule=schedule)
     check_parity(F, S, z, z_ref, f"{schedule}/{eps}/{variant}")
     S.close()
+
+
+GEO_CASES = [
+    ("poisson2d_32_eps0.1_gc", lambda: pb.poisson(32, 2), 0.1, "gc"),
+    ("poisson2d_32_eps0.1_lorasp", lambda: pb.poisson(32, 2), 0.1, "lorasp"),
+    ("inclusion2d_32_eps0.2_gc", lambda: pb.piecewise_inclusion(32), 0.2, "gc"),
+    ("uniform2d_32_eps0.3_gc", lambda: pb.uniform_random(32, 2, 1005), 0.3, "gc"),
+    ("poisson3d_12_eps0.2_gc", lambda: pb.poisson(12, 3), 0.2, "gc"),
+]
+
+
+@pytest.mark.parametrize("name,make,eps,variant", GEO_CASES, ids=[c[0] for c in GEO_CASES])
+def test_geometric_rule_matches_oracle(name, make, eps, variant):
+    """The paper's experiment settings (leaf 8, eps 0.1 - 0.3, §7) under its geometric
+    well-separation rule: ranks, z, and the GMRES count (the paper's outer loop)."""
+    say("geometric", name)
+    p = make()
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=eps,
+                 variant=O.GC if variant == "gc" else O.LORASP, neighbours="geometric")
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8, eps=eps, variant=variant,
+                  neighbours="geometric", krylov="gmres")
+    S.factor(torch.from_numpy(p.values).cuda())
+    r = pb.rhs(p.n, 2, 7)
+    z = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+    check_parity(F, S, z, O.apply(F, r), name)
+    b = pb.rhs(p.n, 1, 11)[:, 0]
+    x_ref, it_ref, rel_ref = O.gmres(p.to_scipy(), b, lambda v: O.apply(F, v), tol=TOL)
+    x, st = S.solve(torch.from_numpy(b).cuda())
+    say(name, "gmres", st["iterations"], it_ref)
+    assert st["converged"] and abs(st["iterations"] - it_ref) <= 1
+    S.close()

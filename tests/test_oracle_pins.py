@@ -685,3 +685,55 @@ def test_shrink_schedule_leaf_level_equals_constant_and_bounds_hold(monkeypatch)
     assert np.allclose(O.apply(F1, p.to_scipy() @ one), one, atol=1e-10)
     # smaller tolerances toward the root keep at least as many directions in total
     assert sum(map(sum, (F1.ranks(d) for d in F1.levels))) >= sum(map(sum, (F0.ranks(d) for d in F0.levels)))
+
+
+# ---------------------------------------------------------------------------
+# Geometric neighbour rule of §7 (reading R6g)
+# ---------------------------------------------------------------------------
+def test_geometric_neighbours_on_a_worked_layout():
+    """16 x 16 grid cut into 4 x 4 boxes (depth 4 of leaves of 16): with boxes of side 4, a
+    cluster's neighbours are the boxes touching it (gap 0) and the boxes one box away along
+    one axis while touching along the other (gap 4 = the side); one box away along both axes
+    (gap 4 sqrt 2) or two away (gap 8) are well separated."""
+    p = pb.poisson(16, 2)
+    L = O.tree_depth(p.n, 16)
+    leaves = O.cluster_leaves(p.coords, p.n, L)
+    G = O.GeometricNeighbours(p.coords, leaves, L, L)
+    corner = {tuple(p.coords[c].min(0).astype(int)): i for i, c in enumerate(leaves)}
+    c = corner[(4, 4)]
+    near = {(0, 0), (4, 0), (8, 0), (0, 4), (8, 4), (0, 8), (4, 8), (8, 8),
+            (12, 0), (12, 4), (12, 8), (0, 12), (4, 12), (8, 12)}
+    for xy, j in corner.items():
+        if j == c:
+            continue
+        assert ((c, j) in G) == (xy in near), xy
+    # symmetric, and never a neighbour of itself
+    assert all(((i, j) in G) == ((j, i) in G) for i in range(16) for j in range(16))
+    assert (c, c) not in G
+
+
+@pytest.mark.parametrize("variant", [O.LORASP, O.GC])
+def test_geometric_rule_eps_zero_exact_and_gc_invariant(variant):
+    p = pb.lognormal(12, 2, 1.0, 9)
+    F0 = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=4, eps=0.0, variant=variant,
+                  neighbours="geometric")
+    b = pb.rhs(p.n, 1, 3)[:, 0]
+    x = np.linalg.solve(p.dense(), b)
+    assert np.linalg.norm(O.apply(F0, b) - x) <= 1e-12 * np.linalg.cond(p.dense()) * np.linalg.norm(x)
+    if variant == O.GC:
+        F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=4, eps=0.3, variant=variant,
+                     neighbours="geometric")
+        one = np.ones(p.n)
+        assert np.allclose(O.apply(F, p.to_scipy() @ one), one, atol=1e-10)
+
+
+@pytest.mark.parametrize("eps", [0.1, 0.3])
+@pytest.mark.parametrize("variant", [O.LORASP, O.GC])
+def test_geometric_rule_preconditioner_spd_at_the_papers_tolerances(variant, eps):
+    """Leaf 8, eps 0.1 / 0.3 (Tables 1-5): A_H^-1 symmetric positive definite (brute force)."""
+    p = pb.poisson(16, 2)
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=eps, variant=variant,
+                 neighbours="geometric")
+    M = O.apply_matrix(F)
+    assert np.linalg.norm(M - M.T) <= 1e-12 * np.linalg.norm(M)
+    assert np.linalg.eigvalsh((M + M.T) / 2).min() > 0
