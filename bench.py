@@ -161,6 +161,54 @@ def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
     return out
 
 
+def paper_tables(H, pb, np, torch) -> dict:
+    """The iteration counts of the paper's experiments (§7, Tables 1-5) on the GPU, with its
+    settings: leaf red nodes of 8, the geometric well-separation rule, FD Poisson problems.
+    Table 1: stationary iteration (the library stops on the true relative residual 1e-6; the
+    paper stops on the relative error 1e-6). Table 2: GMRES to 1e-10, eps 0.1 (0.2, 0.3 on the
+    largest grid). Table 3: 3-D GMRES, eps 0.2 / 0.3. Tables 4-5: 1e-5 inclusion and
+    U(0,1] coefficients, eps 0.1 / 0.2 / 0.3 (on 512^2 instead of the paper's 1024^2).
+    Columns: LoRaSp, GC-constant, GC with the smallest eigenvector (constant problems)."""
+    def its(prob, eps, variant, krylov, tol=1e-10, phi=None):
+        S = H.HSolver(prob.row_ptr, prob.col_idx, coords=prob.coords, leaf=8, eps=eps, variant=variant,
+                      phi=phi, tol=tol, krylov=krylov, neighbours="geometric", max_iter=2000)
+        try:
+            S.factor(torch.from_numpy(prob.values).cuda())
+            b = torch.from_numpy(pb.rhs(prob.n, 1, 7)[:, 0]).cuda()
+            _, st = S.solve(b)
+            return st["iterations"] if st["converged"] else f">{st['iterations']}"
+        except H.NotSPD:
+            return "not SPD"
+        finally:
+            S.close()
+
+    out = {"settings": "leaf 8, geometric well-separation rule, GMRES tol 1e-10 (stationary: residual 1e-6)"}
+    sizes = [32, 64, 128, 256, 512]
+    t1, t2 = {}, {}
+    for N in sizes:
+        p = pb.poisson(N, 2)
+        ev = pb.poisson_smallest_eigenvector(N, 2)
+        t1[f"{N}^2"] = [its(p, 0.1, "lorasp", "stationary", 1e-6), its(p, 0.1, "gc", "stationary", 1e-6),
+                        its(p, 0.1, "gc", "stationary", 1e-6, ev)]
+        t2[f"{N}^2"] = [its(p, 0.1, "lorasp", "gmres"), its(p, 0.1, "gc", "gmres"), its(p, 0.1, "gc", "gmres", phi=ev)]
+    p = pb.poisson(sizes[-1], 2)
+    for e in (0.2, 0.3):
+        t2[f"{sizes[-1]}^2 eps {e}"] = [its(p, e, "lorasp", "gmres"), its(p, e, "gc", "gmres")]
+    out["table1_stationary_2d_eps0.1 [lorasp, gc_const, gc_eig]"] = t1
+    out["table2_gmres_2d [lorasp, gc_const, gc_eig]"] = t2
+    t3 = {}
+    for N in (8, 16, 32):
+        p = pb.poisson(N, 3)
+        t3[f"{N}^3"] = [its(p, 0.2, "lorasp", "gmres"), its(p, 0.3, "lorasp", "gmres"),
+                        its(p, 0.2, "gc", "gmres"), its(p, 0.3, "gc", "gmres")]
+    out["table3_gmres_3d [lorasp 0.2, lorasp 0.3, gc 0.2, gc 0.3]"] = t3
+    for key, prob in (("table4_inclusion_512^2", pb.piecewise_inclusion(512)),
+                      ("table5_uniform_512^2", pb.uniform_random(512, 2, 1005))):
+        out[key + " [lorasp, gc_const] per eps"] = {str(e): [its(prob, e, "lorasp", "gmres"), its(prob, e, "gc", "gmres")]
+                                                   for e in (0.1, 0.2, 0.3)}
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -172,6 +220,8 @@ def main() -> int:
     ap.add_argument("--serve-requests", type=int, default=64,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--no-paper-tables", action="store_true",
+                    help="skip the iteration counts of the paper's experiment settings")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one elementwise copy of 256 MiB first (counter calibration)")
     args = ap.parse_args()
@@ -298,6 +348,8 @@ def main() -> int:
     }
     if not args.no_variants:
         out["variants"] = variants(H, pb, np, torch, p, w, vals, b_host, xs)
+    if not args.no_paper_tables:
+        out["paper_tables"] = paper_tables(H, pb, np, torch)
     if args.serve_requests > 0:
         out["serving"] = serving(args.serve_requests, args.serve_slots)
     if not args.no_cpu_baseline:
