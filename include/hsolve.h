@@ -56,7 +56,10 @@ typedef enum {
                                       stats.fail_level / fail_node name it */
 } hsolve_status;
 
-enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1 };
+/* compression: LoRaSp (truncated SVD of A_sw, §3.2); GC (keeps the given vectors exactly, §6);
+   GC_PROJ1 (keeps them approximately: the first-order one-sided projection of Appendix B, where
+   U1 holds the singular directions of [X_s, A_sw X_w] above eps1 times the largest, X = phi) */
+enum { HSOLVE_LORASP = 0, HSOLVE_GC = 1, HSOLVE_GC_PROJ1 = 2 };
 /* outer iteration of hsolve_solve (§7): conjugate gradients with the standard or the
    flexible beta, right-preconditioned restarted GMRES, or the stationary iteration
    x <- x + A_H^{-1} (b - A x) of §7.1 */
@@ -81,10 +84,11 @@ typedef struct {
                                depth L is the integer nearest log2(n / leaf_size) */
     double eps;             /* relative compression tolerance (>= 0; 0 = no truncation):
                                keep singular values > eps * ||A_sw||_2 */
-    int variant;            /* HSOLVE_LORASP or HSOLVE_GC (default GC) */
+    int variant;            /* HSOLVE_LORASP, HSOLVE_GC (default) or HSOLVE_GC_PROJ1 */
     int nvec;               /* GC: number of preserved vectors in phi (<= 8) */
     const double* phi;      /* GC, host: n x nvec column-major, or NULL for the constant
-                               vector (GC-constant) */
+                               vector (GC-constant); for GC_PROJ1 the vectors X of Appendix B
+                               (low-frequency eigenvectors divided by their eigenvalues) */
     int dim;                /* coordinate dimension 0..3 */
     const double* coords;   /* host: n x dim, row-major (coords[i*dim + t]); NULL = use
                                the unknown index as a 1-D coordinate */
@@ -114,6 +118,8 @@ typedef struct {
                                captured once per workspace as a HIP graph and replayed; 0: the
                                launches are issued one by one */
     int neighbours;         /* HSOLVE_NEIGHBOURS_FOOTPRINT (default) or HSOLVE_NEIGHBOURS_GEOMETRIC */
+    double eps1;            /* HSOLVE_GC_PROJ1: relative truncation of [X_s, A_sw X_w] (0 <= eps1 < 1;
+                               0 keeps its whole range, as GC) */
 } hsolve_options;
 
 typedef struct {

@@ -25,11 +25,13 @@ the code that takes them.
 """
 from .tree import tree_depth, cluster_leaves, footprint_adjacency, GeometricNeighbours
 from .hsolver import (Factorization, NotSPDError, compress, pivot, eliminate_node,
-                      factor, apply, apply_matrix, level_eps, LORASP, GC)
+                      factor, apply, apply_matrix, level_eps, truncated_left_basis,
+                      LORASP, GC, GC_PROJ1)
 from .krylov import pcg, fpcg, gmres, stationary
 
 __all__ = [
     "tree_depth", "cluster_leaves", "footprint_adjacency", "GeometricNeighbours",
     "Factorization", "NotSPDError", "compress", "pivot", "eliminate_node", "factor",
-    "apply", "apply_matrix", "level_eps", "LORASP", "GC", "pcg", "gmres", "stationary",
+    "apply", "apply_matrix", "level_eps", "truncated_left_basis", "LORASP", "GC", "GC_PROJ1",
+    "pcg", "gmres", "stationary",
 ]

@@ -61,6 +61,7 @@ from .tree import tree_depth, cluster_leaves, leaf_index, footprint_adjacency, G
 
 LORASP = 0
 GC = 1          # preserve the given vectors (constant vector by default)
+GC_PROJ1 = 2    # approximately preserve them: first-order one-sided projection (Appendix B)
 
 ORTH_DROP_TOL = 1e-10
 
@@ -96,9 +97,25 @@ def orth_columns(Z: np.ndarray, tol: float = ORTH_DROP_TOL) -> np.ndarray:
     return np.column_stack(basis)
 
 
+def truncated_left_basis(Z: np.ndarray, eps1: float, margins: list | None = None) -> np.ndarray:
+    """Leading left singular vectors of Z with sigma_j > eps1 sigma_1(Z) (Appendix B, first
+    step of the first-order one-sided projection); eps1 = 0 gives an orthonormal basis of Z's
+    range (reading R4, as GC)."""
+    if eps1 == 0.0:
+        return orth_columns(Z)
+    keep = [j for j in range(Z.shape[1]) if np.linalg.norm(Z[:, j]) > 0.0]
+    Z = Z[:, keep]
+    if Z.shape[1] == 0:
+        return np.zeros((Z.shape[0], 0))
+    Uz, sz, _ = np.linalg.svd(Z, full_matrices=False)
+    if margins is not None and sz[0] > 0.0:
+        margins.append(float(np.min(np.abs(sz / sz[0] - eps1))))
+    return Uz[:, :int(np.count_nonzero(sz > eps1 * sz[0]))]
+
+
 def compress(A_sw: np.ndarray, eps: float, variant: int,
              phi_s: np.ndarray | None = None, phi_w: np.ndarray | None = None,
-             margins: list | None = None) -> np.ndarray:
+             margins: list | None = None, eps1: float = 0.0) -> np.ndarray:
     """Orthonormal U (m x k) for the low-rank part of the well-separated block A_sw.
 
     LoRaSp: U = leading left singular vectors of A_sw with sigma_j > eps * sigma_1.
@@ -118,7 +135,7 @@ def compress(A_sw: np.ndarray, eps: float, variant: int,
         Qc = np.eye(m)
     else:
         Z = np.hstack([phi_s.reshape(m, -1), (A_sw @ phi_w).reshape(m, -1)])
-        U1 = orth_columns(Z)
+        U1 = truncated_left_basis(Z, eps1, margins) if variant == GC_PROJ1 else orth_columns(Z)
         q = U1.shape[1]
         Qc = np.linalg.qr(U1, mode="complete")[0][:, q:] if q > 0 else np.eye(m)
     Bc = Qc.T @ A_sw                                   # (I - U1 U1^T) A_sw in complement coords
@@ -276,7 +293,7 @@ def level_eps(eps: float, schedule: str, d: int, L: int, n: int, dim: int) -> fl
 
 
 def eliminate_node(st: LevelState, s: int, adj: set, eps: float, variant: int,
-                   margins: list | None = None) -> NodeFactor:
+                   margins: list | None = None, eps1: float = 0.0) -> NodeFactor:
     """Compress, extend and eliminate super node s of the current level state.
 
     §3.2: N(s) are the current nodes with a block to s that are neighbours of s, W(s)
@@ -292,7 +309,7 @@ def eliminate_node(st: LevelState, s: int, adj: set, eps: float, variant: int,
         A_sW = np.hstack([st.blocks[(s, w)] for w in W])
         phi_s = st.phi.get(s)
         phi_W = np.vstack([st.phi[w] for w in W]) if variant != LORASP else None
-        U = compress(A_sW, eps, variant, phi_s, phi_W, margins=margins)
+        U = compress(A_sW, eps, variant, phi_s, phi_W, margins=margins, eps1=eps1)
         RT = U.T @ A_sW                               # R^T = U^T A_sw (eq. compression_sw)
     else:
         A_sW = np.zeros((m, 0))
@@ -360,7 +377,8 @@ def _leaf_blocks(row_ptr, col_idx, values, leaves, leaf_of, n):
 
 def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1e-2,
            variant: int = GC, phi: np.ndarray | None = None,
-           eps_schedule: str = "constant", neighbours: str = "footprint") -> Factorization:
+           eps_schedule: str = "constant", neighbours: str = "footprint",
+           eps1: float = 0.0) -> Factorization:
     """Algorithm "Setup": build the hierarchical factorization of the SPD matrix A.
 
     ``phi`` (n x p) are the vectors GC preserves; default is the constant vector
@@ -368,6 +386,9 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
     (see ``level_eps``; dim is the coordinate dimension, 1 without coordinates).
     ``neighbours``: "footprint" (R6, the original graph's adjacency, §3.1) or "geometric"
     (R6g, the distance rule of §7's experiments, ``GeometricNeighbours``).
+    ``variant = GC_PROJ1`` approximately preserves ``phi`` (the vectors X of Appendix B, e.g.
+    eigenvectors divided by their eigenvalues): U1 keeps the singular directions of
+    [X_s, A_sw X_w] above eps1 times the largest, then U2 is chosen as for GC.
     """
     n = len(row_ptr) - 1
     L = tree_depth(n, leaf)
@@ -419,7 +440,7 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
                     colour.append(s)
             for s in colour:
                 before = {j: cur.state[j] for j in cur.partners.get(s, ())}
-                nf = eliminate_node(cur, s, adj, eps_d, variant, margins)
+                nf = eliminate_node(cur, s, adj, eps_d, variant, margins, eps1)
                 nf.nbrs = [(nb, before[nb], A) for (nb, _, A) in nf.nbrs]
                 nf.Wstate = [before[w] for w in nf.W]
                 nodes[s] = nf

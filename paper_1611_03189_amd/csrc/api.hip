@@ -78,6 +78,7 @@ void hsolve_default_options(hsolve_options* o) {
     o->cmp_vectors = 0;
     o->apply_graph = 1;
     o->neighbours = HSOLVE_NEIGHBOURS_FOOTPRINT;
+    o->eps1 = 0.0;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -90,7 +91,8 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
     if (opt) o = *opt;
     else hsolve_default_options(&o);
     if (!(o.eps >= 0.0) || !std::isfinite(o.eps) || o.leaf_size < 1 ||
-        (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC) || o.dim < 0 || o.dim > 3 ||
+        (o.variant != HSOLVE_LORASP && o.variant != HSOLVE_GC && o.variant != HSOLVE_GC_PROJ1) ||
+        !(o.eps1 >= 0.0 && o.eps1 < 1.0) || o.dim < 0 || o.dim > 3 ||
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
         !(o.tol >= 0.0) || (o.krylov < HSOLVE_PCG || o.krylov > HSOLVE_STATIONARY) ||
         (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1 ||
@@ -120,7 +122,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
                 if (!std::isfinite(c)) throw Error{HSOLVE_ERR_INVALID, "non-finite coordinate"};
         }
         P.opt.coords = P.coords.empty() ? nullptr : P.coords.data();
-        if (o.variant == HSOLVE_GC) {
+        if (o.variant == HSOLVE_GC || o.variant == HSOLVE_GC_PROJ1) {
             if (o.phi) {
                 P.nphi = o.nvec;
                 P.phi.assign(o.phi, o.phi + size_t(n) * o.nvec);

@@ -1643,6 +1643,115 @@ __global__ __launch_bounds__(NT) void k_comp_bt(const CompressTask* tasks, int v
     }
 }
 
+// ---------------------------------------------------------------------------------
+// First step of the first-order one-sided projection (Appendix B): Z = [X_s, A_sw X_w]
+// (m x nz, nz <= 16) is replaced by its left singular vectors with sigma_j > eps1 sigma_1(Z)
+// in its first columns and zeros after them, so that the GC basis step that follows keeps
+// exactly that truncated basis. Per node: the nz x nz Gram matrix Z^T Z (one wave per pair of
+// columns), its eigen-decomposition by cyclic Jacobi rotations (one lane; nz is at most 16),
+// then every row of Z times V_kept / sigma_kept.
+// ---------------------------------------------------------------------------------
+constexpr int TRUNC_MAXZ = 16;
+
+__global__ __launch_bounds__(NT) void k_gc_truncate(const CompressTask* tasks, double eps1) {
+    const CompressTask T = tasks[blockIdx.x];
+    const int m = T.m, nz = T.nz;
+    if (nz <= 0 || nz > TRUNC_MAXZ) return;
+    __shared__ double Gm[TRUNC_MAXZ][TRUNC_MAXZ], Vm[TRUNC_MAXZ][TRUNC_MAXZ];
+    __shared__ double lam[TRUNC_MAXZ];
+    __shared__ int order[TRUNC_MAXZ];
+    __shared__ int nkeep;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    HS_G double* Z = gp(const_cast<double*>(T.Z));
+    const int npair = nz * (nz + 1) / 2;
+    for (int pr = wv; pr < npair; pr += NT / WAVE) {
+        int a = 0, r = pr;
+        while (r >= nz - a) { r -= nz - a; ++a; }
+        const int b = a + r;
+        double part = 0.0;
+        for (int i = lane; i < m; i += WAVE) part += Z[i + size_t(a) * m] * Z[i + size_t(b) * m];
+        const double dot = wave_sum(part);
+        if (lane == 0) { Gm[a][b] = dot; Gm[b][a] = dot; }
+    }
+    __syncthreads();
+    if (tid == 0) {
+        for (int a = 0; a < nz; ++a)
+            for (int b = 0; b < nz; ++b) Vm[a][b] = (a == b) ? 1.0 : 0.0;
+        double fro = 0.0;
+        for (int a = 0; a < nz; ++a)
+            for (int b = 0; b < nz; ++b) fro += Gm[a][b] * Gm[a][b];
+        for (int sweep = 0; sweep < 60; ++sweep) {
+            double off = 0.0;
+            for (int a = 0; a < nz; ++a)
+                for (int b = a + 1; b < nz; ++b) off += Gm[a][b] * Gm[a][b];
+            if (!(off > 1e-34 * fro)) break;
+            for (int a = 0; a < nz; ++a)
+                for (int b = a + 1; b < nz; ++b) {
+                    const double apq = Gm[a][b];
+                    if (apq == 0.0) continue;
+                    // rotation that zeroes (a, b): t = tan, from theta = (G_bb - G_aa) / (2 G_ab)
+                    const double theta = (Gm[b][b] - Gm[a][a]) / (2.0 * apq);
+                    const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                    const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+                    for (int k = 0; k < nz; ++k) {         // columns a, b
+                        const double ga = Gm[k][a], gb = Gm[k][b];
+                        Gm[k][a] = c * ga - sn * gb;
+                        Gm[k][b] = sn * ga + c * gb;
+                    }
+                    for (int k = 0; k < nz; ++k) {         // rows a, b
+                        const double ga = Gm[a][k], gb = Gm[b][k];
+                        Gm[a][k] = c * ga - sn * gb;
+                        Gm[b][k] = sn * ga + c * gb;
+                    }
+                    for (int k = 0; k < nz; ++k) {
+                        const double va = Vm[k][a], vb = Vm[k][b];
+                        Vm[k][a] = c * va - sn * vb;
+                        Vm[k][b] = sn * va + c * vb;
+                    }
+                }
+        }
+        for (int a = 0; a < nz; ++a) {
+            lam[a] = Gm[a][a];
+            order[a] = a;
+        }
+        for (int a = 1; a < nz; ++a)             // descending eigenvalues
+            for (int b = a; b > 0 && lam[order[b]] > lam[order[b - 1]]; --b) {
+                const int tmp = order[b];
+                order[b] = order[b - 1];
+                order[b - 1] = tmp;
+            }
+        const double top = lam[order[0]];
+        int kp = 0;
+        while (kp < nz && top > 0.0 && lam[order[kp]] > eps1 * eps1 * top) ++kp;
+        nkeep = kp;
+    }
+    __syncthreads();
+    const int kp = nkeep;
+    for (int i = tid; i < m; i += NT) {
+        double zr[TRUNC_MAXZ];
+#pragma unroll
+        for (int a = 0; a < TRUNC_MAXZ; ++a) zr[a] = (a < nz) ? Z[i + size_t(a) * m] : 0.0;
+        for (int c = 0; c < nz; ++c) {
+            double v = 0.0;
+            if (c < kp) {
+                const int j = order[c];
+#pragma unroll
+                for (int a = 0; a < TRUNC_MAXZ; ++a)
+                    if (a < nz) v += zr[a] * Vm[a][j];
+                v /= sqrt(lam[j]);
+            }
+            Z[i + size_t(c) * m] = v;
+        }
+    }
+}
+
+void launch_gc_truncate(const CompressTask* d_tasks, int ntasks, double eps1, hipStream_t s) {
+    if (ntasks <= 0) return;
+    ProfScope ps("k_gc_truncate", 0.0, s);
+    hipLaunchKernelGGL(k_gc_truncate, dim3(ntasks), dim3(NT), 0, s, d_tasks, eps1);
+    check_launch("k_gc_truncate");
+}
+
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps, int* d_rank,
                      double flops, bool lds, int max_m, int force_lpe, int force_vectors, hipStream_t s) {
     if (ntasks <= 0) return;

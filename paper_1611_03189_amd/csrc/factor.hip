@@ -190,7 +190,11 @@ void factor(Plan& P, const double* values_in) {
     hipStream_t st = P.stream;
     const int L = P.L;
     const int nlev = std::max(L, 1);
-    const bool gc = P.opt.variant == HSOLVE_GC;
+    // GC_PROJ1 is GC whose kept vectors are first truncated (Appendix B); the compression
+    // kernels then run the GC path
+    const bool proj1 = P.opt.variant == HSOLVE_GC_PROJ1 && P.opt.eps1 > 0.0;
+    const bool gc = P.opt.variant == HSOLVE_GC || P.opt.variant == HSOLVE_GC_PROJ1;
+    const int cmp_variant = gc ? HSOLVE_GC : HSOLVE_LORASP;
     const int p = P.nphi;
     const int q_gc = gc ? 2 * p : 0;   // columns of [phi_s, A_sw phi_w]
     const bool overlap = P.opt.overlap_pivots != 0 && !dry;
@@ -460,6 +464,10 @@ void factor(Plan& P, const double* values_in) {
             }
             B.flush_copies(P);
             B.flush_gemm(P);
+            if (proj1 && !ctasks.empty()) {
+                const CompressTask* d_all = P.stage.upload_vec(ctasks, P.spool, st);
+                if (!dry) launch_gc_truncate(d_all, int(ctasks.size()), P.opt.eps1, st);
+            }
             for (int big = 0; big < 2; ++big) {
                 // counted work of the reduction kernel: one Householder tridiagonalisation,
                 // 4/3 m^3 (two when GC keeps more than four vectors)
@@ -476,7 +484,7 @@ void factor(Plan& P, const double* values_in) {
                 if (part.empty()) continue;
                 const CompressTask* d_part = P.stage.upload_vec(part, P.spool, st);
                 if (!dry)
-                    launch_compress(d_part, int(part.size()), P.opt.variant, eps, d_rank, cflops, !big, max_m,
+                    launch_compress(d_part, int(part.size()), cmp_variant, eps, d_rank, cflops, !big, max_m,
                                     P.opt.cmp_lpe, P.opt.cmp_vectors, st);
             }
             if (!dry) {

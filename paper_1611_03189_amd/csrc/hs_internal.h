@@ -388,6 +388,9 @@ void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double fl
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
                      int* d_rank, double flops, bool lds, int max_m, int force_lpe, int force_vectors,
                      hipStream_t s);
+// Appendix B first-order one-sided projection: Z (m x nz <= 16) becomes its left singular
+// vectors above eps1 sigma_1(Z), zero columns after them
+void launch_gc_truncate(const CompressTask* d_tasks, int ntasks, double eps1, hipStream_t s);
 constexpr int LDS_MAX_M = 128;   // compression blocks up to this size work in LDS
 constexpr int CMP_WY_NB = 16;     // reflectors per block in the compression back-transformation
 // doubles of the per-node compression work buffer for a super node of m unknowns

@@ -22,6 +22,7 @@ HEADER = os.path.join(os.path.dirname(HERE), "include", "hsolve.h")
 
 LORASP = 0
 GC = 1
+GC_PROJ1 = 2
 KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2, "stationary": 3}
 EPS_SCHEDULE = {"constant": 0, "shrink": 1, "grow": 2}
 
@@ -50,6 +51,7 @@ class Options(ctypes.Structure):
         ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
         ("factor_prec", c_int), ("max_super", c_int), ("max_nrhs", c_int), ("eps_schedule", c_int),
         ("cmp_lpe", c_int), ("cmp_vectors", c_int), ("apply_graph", c_int), ("neighbours", c_int),
+        ("eps1", c_double),
     ]
 
 
@@ -206,7 +208,8 @@ class HSolver:
                  stream=None, krylov: str = "pcg", apply_prec: int = 64, restart: int = 200,
                  overlap_pivots: bool = True, factor_prec: int = 64, max_super: int = 512,
                  max_nrhs: int = 32, eps_schedule: str = "constant", cmp_lpe: int = 0,
-                 cmp_vectors: int = 0, apply_graph: bool = True, neighbours: str = "footprint"):
+                 cmp_vectors: int = 0, apply_graph: bool = True, neighbours: str = "footprint",
+                 eps1: float = 0.0):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -217,7 +220,9 @@ class HSolver:
         lib.hsolve_default_options(ctypes.byref(opt))
         opt.leaf_size = int(leaf)
         opt.eps = float(eps)
-        opt.variant = {"gc": GC, "lorasp": LORASP}[variant] if isinstance(variant, str) else int(variant)
+        opt.variant = ({"gc": GC, "lorasp": LORASP, "gc_proj1": GC_PROJ1}[variant] if isinstance(variant, str)
+                       else int(variant))
+        opt.eps1 = float(eps1)
         opt.tol = float(tol)
         opt.max_iter = int(max_iter)
         opt.krylov = KRYLOV[krylov] if isinstance(krylov, str) else int(krylov)

@@ -50,7 +50,7 @@ def _oracle_case(key):
 
 def compression_kernels(S):
     """Names of the compression kernels the last factorization ran (from the kernel timer)."""
-    return sorted({e["name"] for e in S.profile_end() if e["name"].startswith("k_comp")})
+    return sorted({e["name"] for e in S.profile_end() if e["name"].startswith(("k_comp", "k_gc"))})
 
 
 @pytest.mark.parametrize("vectors", [1, 2], ids=["lane_per_eigenvalue", "wave_per_eigenvalue"])
@@ -171,4 +171,27 @@ def test_geometric_rule_matches_oracle(name, make, eps, variant):
     x, st = S.solve(torch.from_numpy(b).cuda())
     say(name, "gmres", st["iterations"], it_ref)
     assert st["converged"] and abs(st["iterations"] - it_ref) <= 1
+    S.close()
+
+
+@pytest.mark.parametrize("eps1,neighbours", [(1e-2, "geometric"), (1e-1, "footprint")])
+def test_first_order_projection_matches_oracle(eps1, neighbours):
+    """Appendix B's first-order one-sided projection (GC_PROJ1) with X = the two smallest
+    eigenvectors over their eigenvalues: ranks and z against the oracle."""
+    say("gc_proj1", eps1, neighbours)
+    p = pb.poisson(24, 2)
+    lam, V = np.linalg.eigh(p.dense())
+    X = np.asfortranarray(V[:, :2] / lam[:2])
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=0.1, variant=O.GC_PROJ1, phi=X,
+                 eps1=eps1, neighbours=neighbours)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=8, eps=0.1, variant="gc_proj1", phi=X,
+                  eps1=eps1, neighbours=neighbours)
+    S.profile_begin()
+    S.factor(torch.from_numpy(p.values).cuda())
+    kernels = compression_kernels(S)
+    say("kernels", kernels)
+    assert "k_gc_truncate" in kernels
+    r = pb.rhs(p.n, 2, 7)
+    z = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+    check_parity(F, S, z, O.apply(F, r), f"proj1/{eps1}/{neighbours}")
     S.close()

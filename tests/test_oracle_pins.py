@@ -737,3 +737,74 @@ def test_geometric_rule_preconditioner_spd_at_the_papers_tolerances(variant, eps
     M = O.apply_matrix(F)
     assert np.linalg.norm(M - M.T) <= 1e-12 * np.linalg.norm(M)
     assert np.linalg.eigvalsh((M + M.T) / 2).min() > 0
+
+
+# ---------------------------------------------------------------------------
+# Appendix B: first-order one-sided projection (approximate preservation)
+# ---------------------------------------------------------------------------
+def _proj1_bounds(A_sw, X_s, X_w, eps1, eps2):
+    """The Appendix B statements for B = A_ws (B^T = A_sw), Z = [X_s, B^T X_w]:
+    ||B^T - B~^T|| <= eps2 ||B||;  ||(B^T - B~^T) X_w|| <= min(eps1 ||Z||, eps2 ||B|| ||X_w||);
+    ||(B - B~) X_s|| <= eps1 eps2 ||B|| ||Z||; and U1 is the minimal truncation of Z."""
+    U = O.compress(A_sw, eps2, O.GC_PROJ1, X_s, X_w, eps1=eps1)
+    assert np.allclose(U.T @ U, np.eye(U.shape[1]), atol=1e-12)
+    Bt_err = A_sw - U @ (U.T @ A_sw)                  # B^T - B~^T
+    nB = np.linalg.norm(A_sw, 2)
+    Z = np.column_stack([X_s, A_sw @ X_w])
+    nZ = np.linalg.norm(Z, 2)
+    tol = 1 + 1e-10
+    assert np.linalg.norm(Bt_err, 2) <= eps2 * nB * tol
+    assert np.linalg.norm(Bt_err @ X_w, 2) <= min(eps1 * nZ, eps2 * nB * np.linalg.norm(X_w, 2)) * tol + 1e-14 * nZ
+    assert np.linalg.norm(Bt_err.T @ X_s, 2) <= eps1 * eps2 * nB * nZ * tol + 1e-14 * nB * nZ
+    U1 = O.truncated_left_basis(Z, eps1)
+    q = U1.shape[1]
+    assert np.linalg.norm(Z - U1 @ (U1.T @ Z), 2) <= eps1 * nZ * tol
+    if q >= 1 and eps1 > 0:
+        Ud = U1[:, :-1]
+        assert np.linalg.norm(Z - Ud @ (Ud.T @ Z), 2) > eps1 * nZ
+    return U, q
+
+
+@pytest.mark.parametrize("eps1,eps2", [(1e-1, 1e-1), (1e-2, 1e-1), (1e-3, 1e-2)])
+def test_proj1_meets_appendix_b_bounds(eps1, eps2):
+    B = _smooth_block(40, 60, 8)
+    rng = np.random.default_rng(9)
+    X_s = rng.standard_normal((40, 3)) * np.array([1.0, 1e-1, 1e-3])
+    X_w = rng.standard_normal((60, 3)) * np.array([1.0, 1e-1, 1e-3])
+    U, q = _proj1_bounds(B, X_s, X_w, eps1, eps2)
+    assert 1 <= q < 6                          # Z has 6 columns; the small ones were truncated
+
+
+def test_proj1_with_eps1_zero_is_gc():
+    B = _smooth_block(30, 45, 2)
+    rng = np.random.default_rng(3)
+    phi_s, phi_w = rng.standard_normal((30, 2)), rng.standard_normal((45, 2))
+    U0 = O.compress(B, 1e-2, O.GC, phi_s, phi_w)
+    U1 = O.compress(B, 1e-2, O.GC_PROJ1, phi_s, phi_w, eps1=0.0)
+    assert U0.shape == U1.shape and np.allclose(U0 @ U0.T, U1 @ U1.T, atol=1e-12)
+
+
+def test_proj1_bounds_on_poisson_blocks(monkeypatch):
+    """Every block of a 2-D Poisson factorization with X = (first eigenvectors) / eigenvalues."""
+    import oracle.hsolver as OH
+    seen = []
+    orig = OH.compress
+
+    def rec(A_sw, eps, variant, phi_s=None, phi_w=None, **kw):
+        seen.append((A_sw.copy(), eps, np.array(phi_s, copy=True), np.array(phi_w, copy=True), kw.get("eps1")))
+        return orig(A_sw, eps, variant, phi_s, phi_w, **kw)
+
+    monkeypatch.setattr(OH, "compress", rec)
+    p = pb.poisson(24, 2)
+    lam, V = np.linalg.eigh(p.dense())
+    X = V[:, :2] / lam[:2]
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=8, eps=0.1, variant=O.GC_PROJ1, phi=X,
+                 eps1=1e-2, neighbours="geometric")
+    checked = 0
+    for A_sw, eps, ps, pw, e1 in seen:
+        if A_sw.shape[1] and np.any(A_sw):
+            _proj1_bounds(A_sw, ps, pw, e1, eps)
+            checked += 1
+    assert checked > 10
+    M = O.apply_matrix(F)                      # still symmetric positive definite
+    assert np.linalg.eigvalsh((M + M.T) / 2).min() > 0
