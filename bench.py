@@ -96,7 +96,7 @@ def cpu_baseline(seconds_hint: float = 20.0) -> dict:
     }
 
 
-def serving(count: int, slots: int) -> dict:
+def serving(count: int, slots: int, mixed: bool = True) -> dict:
     """The serving stream (mixed 2-D / 3-D lognormal systems, 1..8 right-hand sides each):
     first closed loop (every request waiting at t = 0, saturation), then open loop with
     Poisson arrivals at 0.7 x the closed-loop request rate. Latency runs from arrival to the
@@ -105,7 +105,7 @@ def serving(count: int, slots: int) -> dict:
     from paper_1611_03189_amd.serve import RequestLoop, requests_from_stream
     specs = pb.serving_stream(count, seed=4)
     reqs = requests_from_stream(specs)
-    loop = RequestLoop(slots=slots)
+    loop = RequestLoop(slots=slots, mixed=mixed)
     loop.run(reqs[:min(4, len(reqs))], realtime=False)          # warm-up
     closed = loop.run(reqs, realtime=False).stats()
     rate = 0.7 * closed["requests_per_s"]
@@ -115,8 +115,9 @@ def serving(count: int, slots: int) -> dict:
     opened = loop.run(reqs, realtime=True).stats()
     opened["arrival_rate_per_s"] = round(rate, 3)
     return {"workload": f"{count} systems: 2-D N~U{{64..256}} / 3-D N~U{{16..48}}, lognormal sigma 1, "
-                        f"1-8 rhs, GC eps 1e-2, PCG 1e-10", "slots": slots,
-            "closed_loop": closed, "open_loop": opened}
+                        f"1-8 rhs, GC eps 1e-2, " + ("FP32 factorization + FP64 flexible PCG" if mixed
+                                                     else "FP64 factorization + PCG") + " to 1e-10",
+            "slots": slots, "closed_loop": closed, "open_loop": opened}
 
 
 def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
@@ -148,6 +149,9 @@ def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
         return r, xh
 
     out = {}
+    # the mixed form: FP32 factorization (blocks, pivots, GEMMs on the FP32 matrix cores) inside
+    # FP64 flexible PCG, against the FP64 PCG solution of the same system
+    out["c3_fp32_factor_fpcg"], _ = run(p, w, vals, A3, b_host, b3, x64, factor_prec=32, krylov="fpcg")
     out["c3_fp32_solve_fpcg"], _ = run(p, w, vals, A3, b_host, b3, x64, apply_prec=32, krylov="fpcg")
     out["c3_gmres"], _ = run(p, w, vals, A3, b_host, b3, x64, krylov="gmres")
     p2, w2 = pb.workload("c2_lognormal2d_256")
@@ -158,6 +162,8 @@ def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
     out["c2_lognormal2d_256_fp64_pcg"], x2 = run(p2, w2, v2, A2, b2h, b2)
     out["c2_lognormal2d_256_fp32_solve_fpcg"], _ = run(p2, w2, v2, A2, b2h, b2, x2, apply_prec=32,
                                                        krylov="fpcg")
+    out["c2_lognormal2d_256_fp32_factor_fpcg"], _ = run(p2, w2, v2, A2, b2h, b2, x2, factor_prec=32,
+                                                        krylov="fpcg")
     return out
 
 
@@ -217,7 +223,7 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the other solver settings (FP32 solve phase, GMRES, 2-D lognormal 256^2)")
-    ap.add_argument("--serve-requests", type=int, default=64,
+    ap.add_argument("--serve-requests", type=int, default=512,
                     help="requests of the serving stream (0: skip the serving measurement)")
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--no-paper-tables", action="store_true",

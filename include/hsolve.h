@@ -104,7 +104,13 @@ typedef struct {
     int overlap_pivots;     /* 1 (default): the pivot blocks of a colour are factored on a
                                second stream of the plan while the colour is compressed; 0: in
                                order on opt.stream (for callers that run many plans at once) */
-    int factor_prec;        /* 64 (default): arithmetic of the factorization */
+    int factor_prec;        /* 64 (default) or 32: storage and arithmetic of the factorization. With
+                               32 the blocks, pivots (Cholesky and inverse), Schur updates, Gram
+                               matrices and the products of the elimination run in FP32 on the
+                               matrix cores; the symmetric eigen-solver of the compression reads the
+                               FP32 Gram matrix in FP64 and its basis is rounded back to FP32. The
+                               solve phase then runs in FP32 (apply_prec is 32); pair it with
+                               HSOLVE_FPCG or HSOLVE_GMRES, whose FP64 loop refines to opt.tol. */
     int max_super;          /* largest super node, in unknowns, the plan admits (1..512, default
                                512); it caps the ranks the arena bound of hsolve_analyze assumes */
     int max_nrhs;           /* right-hand sides per batch the arena bound covers (default 32);
@@ -226,12 +232,13 @@ hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream);
  * 16, 1: 64x64/32, 2: 128x64/16, 3: 128x128/16); every shape gives the same bits. A launch
  * falls into one of HSOLVE_GEMM_BUCKETS buckets: its number of 64x64 output tiles (< 32,
  * < 256, < 2048, more) times its mean inner dimension (<= 64, <= 256, more), bucket =
- * 3 * tile_class + k_class. hsolve_tune_gemm times every shape on a synthetic launch of each
- * bucket and keeps the fastest for the process: d_work is caller device memory of at least
- * hsolve_tune_workspace_bytes(); choice (HSOLVE_GEMM_BUCKETS entries) and ms
- * (HSOLVE_GEMM_BUCKETS x HSOLVE_GEMM_VARIANTS, best of three) may be NULL. Untuned, every
- * bucket uses shape 0. hsolve_set_gemm_choice installs a saved choice. Neither may run
- * while a factorization is in flight. */
+ * 3 * tile_class + k_class; FP64 and FP32 GEMMs are tuned apart. hsolve_tune_gemm times every
+ * shape on a synthetic launch of each bucket and type and keeps the fastest for the process:
+ * d_work is caller device memory of at least hsolve_tune_workspace_bytes(); choice
+ * (2 x HSOLVE_GEMM_BUCKETS entries: FP64 buckets, then FP32) and ms (2 x HSOLVE_GEMM_BUCKETS x
+ * HSOLVE_GEMM_VARIANTS, best of three) may be NULL. Untuned, every bucket uses shape 0.
+ * hsolve_set_gemm_choice installs a saved choice (2 x HSOLVE_GEMM_BUCKETS entries). Neither
+ * may run while a factorization is in flight. */
 #define HSOLVE_GEMM_VARIANTS 4
 #define HSOLVE_GEMM_BUCKETS 12
 size_t hsolve_tune_workspace_bytes(void);

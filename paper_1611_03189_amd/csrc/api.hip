@@ -96,7 +96,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         o.nvec < 0 || o.nvec > 8 || (o.phi && o.nvec < 1) || o.max_iter < 0 ||
         !(o.tol >= 0.0) || (o.krylov < HSOLVE_PCG || o.krylov > HSOLVE_STATIONARY) ||
         (o.apply_prec != 64 && o.apply_prec != 32) || o.restart < 1 ||
-        (o.overlap_pivots != 0 && o.overlap_pivots != 1) || o.factor_prec != 64 ||
+        (o.overlap_pivots != 0 && o.overlap_pivots != 1) || (o.factor_prec != 64 && o.factor_prec != 32) ||
         o.max_super < 1 || o.max_super > hs::MAX_SUPER || o.max_nrhs < 1 ||
         o.eps_schedule < HSOLVE_EPS_CONSTANT || o.eps_schedule > HSOLVE_EPS_GROW ||
         !(o.cmp_lpe == 0 || (o.cmp_lpe >= 1 && o.cmp_lpe <= 64 && (o.cmp_lpe & (o.cmp_lpe - 1)) == 0)) ||
@@ -112,7 +112,9 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         P.n = n;
         P.nnz = row_ptr[n];
         P.opt = o;
-        P.apply32 = o.apply_prec == 32;
+        P.f32 = o.factor_prec == 32;
+        P.apply32 = o.apply_prec == 32 || P.f32;      // an FP32 factor is applied in FP32
+        if (P.f32) P.opt.apply_prec = 32;
         P.stream = static_cast<hipStream_t>(o.stream);
         P.row_ptr.assign(row_ptr, row_ptr + n + 1);
         P.col_idx.assign(col_idx, col_idx + P.nnz);
@@ -259,18 +261,18 @@ size_t hsolve_tune_workspace_bytes(void) { return hs::tune_workspace_bytes(); }
 hsolve_status hsolve_tune_gemm(void* d_work, size_t work_bytes, void* stream, int32_t* choice, double* ms) {
     if (!d_work) return HSOLVE_ERR_INVALID;
     return run(nullptr, "tune_gemm", [&] {
-        std::vector<int> c(hs::GEMM_BUCKETS, 0);
+        std::vector<int> c(2 * hs::GEMM_BUCKETS, 0);
         hs::tune_gemm(d_work, work_bytes, static_cast<hipStream_t>(stream), c.data(), ms);
         if (choice)
-            for (int b = 0; b < hs::GEMM_BUCKETS; ++b) choice[b] = c[b];
+            for (int b = 0; b < 2 * hs::GEMM_BUCKETS; ++b) choice[b] = c[b];
     });
 }
 
 hsolve_status hsolve_set_gemm_choice(const int32_t* choice) {
     if (!choice) return HSOLVE_ERR_INVALID;
-    for (int b = 0; b < hs::GEMM_BUCKETS; ++b)
+    for (int b = 0; b < 2 * hs::GEMM_BUCKETS; ++b)
         if (choice[b] < 0 || choice[b] >= hs::GEMM_VARIANTS) return HSOLVE_ERR_INVALID;
-    for (int b = 0; b < hs::GEMM_BUCKETS; ++b) hs::set_gemm_variant(b, choice[b]);
+    for (int b = 0; b < 2 * hs::GEMM_BUCKETS; ++b) hs::set_gemm_variant(b % hs::GEMM_BUCKETS, b >= hs::GEMM_BUCKETS, choice[b]);
     return HSOLVE_OK;
 }
 
@@ -401,7 +403,13 @@ hsolve_status hsolve_node_factor(hsolve_plan plan, int depth, int node, int32_t*
     if (!G || !nn.Gm || count == 0) return HSOLVE_OK;
     if (cap < count) return HSOLVE_ERR_INVALID;
     return run(plan, "node_factor", [&] {
-        HS_HIP(hipMemcpy(G, nn.Gm, sizeof(double) * count, hipMemcpyDeviceToHost));
+        if (P.f32) {       // the FP32 factor, widened on the host
+            std::vector<float> h(static_cast<size_t>(count));
+            HS_HIP(hipMemcpy(h.data(), nn.Gm, sizeof(float) * count, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < count; ++i) G[i] = double(h[size_t(i)]);
+        } else {
+            HS_HIP(hipMemcpy(G, nn.Gm, sizeof(double) * count, hipMemcpyDeviceToHost));
+        }
     });
 }
 

@@ -19,6 +19,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <map>
+#include <type_traits>
 
 #include "hs_internal.h"
 
@@ -36,6 +37,7 @@ struct Live {
     void erase(int i, int j) { map.erase(i <= j ? bkey(i, j) : bkey(j, i)); }
 };
 
+template <typename R>
 struct Batch {
     bool trace_pivots = false;
     bool dry = false;                 // replay: tables are counted, nothing is launched
@@ -45,20 +47,20 @@ struct Batch {
     std::vector<GemmTile> tiles;
     std::vector<CholTask> chol;
 
-    void copy(const double* src, int lds, double* dst, int ldd, int rows, int cols, int trans) {
+    void copy(const R* src, int lds, R* dst, int ldd, int rows, int cols, int trans) {
         if (rows > 0 && cols > 0) copies.push_back(CopyTask{src, dst, lds, ldd, rows, cols, trans, 0});
     }
-    void open(double* C, int ldc, int M, int N, double alpha, double beta) {
+    void open(R* C, int ldc, int M, int N, double alpha, double beta) {
         gt.push_back(GemmTask{C, ldc, M, N, int(terms.size()), int(terms.size()), 0, alpha, beta});
     }
-    void term(const double* A, int lda, int tA, const double* B, int ldb, int tB, int K) {
+    void term(const R* A, int lda, int tA, const R* B, int ldb, int tB, int K) {
         if (K <= 0) return;
         terms.push_back(GemmTerm{A, B, lda, ldb, K, tA, tB, 0});
         gt.back().t_end = int(terms.size());
     }
     void close() {}   // output tiles are laid out at flush time, in the launch's tile shape
-    void gemm(double* C, int ldc, int M, int N, double alpha, double beta, const double* A,
-              int lda, int tA, const double* B, int ldb, int tB, int K) {
+    void gemm(R* C, int ldc, int M, int N, double alpha, double beta, const R* A,
+              int lda, int tA, const R* B, int ldb, int tB, int K) {
         if (M <= 0 || N <= 0) return;
         open(C, ldc, M, N, alpha, beta);
         term(A, lda, tA, B, ldb, tB, K);
@@ -69,11 +71,11 @@ struct Batch {
         double bytes = 0.0;
         int max_cols = 0;
         for (const CopyTask& c : copies) {
-            bytes += 16.0 * c.rows * c.cols;
+            bytes += 2.0 * sizeof(R) * c.rows * c.cols;
             max_cols = std::max(max_cols, c.cols);
         }
         CopyTask* d = P.stage.upload_vec(copies, P.spool, P.stream);
-        if (!dry) launch_copy(d, int(copies.size()), max_cols, bytes, P.stream);
+        if (!dry) launch_copy<R>(d, int(copies.size()), max_cols, bytes, P.stream);
         copies.clear();
     }
     // The tables always travel on the plan's stream; with side set, the launch goes to the
@@ -93,7 +95,8 @@ struct Batch {
         }
         // tile shape: the autotuned choice for this launch's size bucket; the replay lays out
         // the 64 x 64 tiles, the most of any shape, so its table bounds every choice
-        const int variant = dry ? 0 : gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0));
+        const int variant =
+            dry ? 0 : gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0), sizeof(R) == 4);
         const GemmShape sh = GEMM_SHAPES[variant];
         for (size_t id = 0; id < gt.size(); ++id)
             for (int ti = 0; ti * sh.tm < gt[id].M; ++ti)
@@ -111,7 +114,7 @@ struct Batch {
             GemmTask* dt = reinterpret_cast<GemmTask*>(dbase);
             GemmTerm* dterm = reinterpret_cast<GemmTerm*>(dbase + o1);
             GemmTile* dtile = reinterpret_cast<GemmTile*>(dbase + o2);
-            if (!dry) launch_gemm(dt, dterm, dtile, int(tiles.size()), flops, variant, to_side(P, side));
+            if (!dry) launch_gemm<R>(dt, dterm, dtile, int(tiles.size()), flops, variant, to_side(P, side));
         }
         gt.clear();
         terms.clear();
@@ -125,7 +128,7 @@ struct Batch {
             int max_m = 0;
             for (CholTask c : chol) {
                 if ((c.m > PIV_LDS_MAX_M) != bool(big)) continue;
-                if (big) c.work = P.spool.alloc_n<double>(size_t(c.m) * c.m);
+                if (big) c.work = P.spool.alloc_n<R>(size_t(c.m) * c.m);
                 // potrf m^3/3 + triangular inverse m^3/3 (+ X^T X, m^3/3, in the LDS kernel)
                 flops += (big ? 2.0 / 3.0 : 1.0) * double(c.m) * c.m * c.m;
                 max_m = std::max(max_m, c.m);
@@ -138,7 +141,7 @@ struct Batch {
                 for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 4 * q;
             }
             CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
-            if (!dry) launch_chol_inv(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
+            if (!dry) launch_chol_inv<R>(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
             if (d_stamp && !dry) {
                 if (side) HS_HIP(hipStreamSynchronize(P.side));
                 std::vector<long long> h(4 * part.size());
@@ -150,8 +153,9 @@ struct Batch {
                              part.size(), max_m, ph[0] / 1000, ph[1] / 1000, ph[2] / 1000);
             }
             if (big) {      // A^{-1} = X^T X, X = L^{-1} left in the work matrices
-                for (const CholTask& c : part) gemm(c.Ainv, c.ldi, c.m, c.m, 1.0, 0.0, c.work, c.m, 1,
-                                                    c.work, c.m, 0, c.m);
+                for (const CholTask& c : part)
+                    gemm(static_cast<R*>(c.Ainv), c.ldi, c.m, c.m, 1.0, 0.0, static_cast<const R*>(c.work), c.m, 1,
+                         static_cast<const R*>(c.work), c.m, 0, c.m);
                 flush_gemm(P, side);
             }
         }
@@ -159,7 +163,8 @@ struct Batch {
     }
 };
 
-size_t blk_bytes(int r, int c) { return ((size_t(r) * c * sizeof(double)) + 255) & ~size_t(255); }
+template <typename R>
+size_t blk_bytes(int r, int c) { return ((size_t(r) * c * sizeof(R)) + 255) & ~size_t(255); }
 
 }  // namespace
 
@@ -183,8 +188,15 @@ double level_eps(const Plan& P, int d) {
     }
 }
 
-void factor(Plan& P, const double* values_in) {
+// The factorization in the storage type R: double (factor_prec = 64), or float
+// (factor_prec = 32: blocks, factors, pivots and GEMMs in FP32 on the matrix cores; the Gram
+// matrices and kept vectors are promoted to FP64 for the symmetric eigen-solver and its basis
+// is rounded back to FP32 after the orthonormalisation).
+template <typename R>
+static void factor_t(Plan& P, const double* values_in) {
+    constexpr bool F32 = std::is_same<R, float>::value;
     using clk = std::chrono::steady_clock;
+    auto gm = [](const NodeNum& nn) { return static_cast<R*>(nn.Gm); };
     const auto t0 = clk::now();
     const bool dry = P.dry;
     hipStream_t st = P.stream;
@@ -239,7 +251,7 @@ void factor(Plan& P, const double* values_in) {
 
     P.num.assign(nlev, LevelNum{});
     Live lives[2];
-    std::vector<std::vector<double*>> phi_sup(nlev), phi_red(nlev);
+    std::vector<std::vector<R*>> phi_sup(nlev), phi_red(nlev);
     double flops = 0.0;
     int max_rank = 0;
     int* h_flags = P.h_flags;   // fail flags of the level + ranks of the colour
@@ -282,7 +294,7 @@ void factor(Plan& P, const double* values_in) {
         P.spool.reset();
         int* d_fail = lp.alloc_n<int>(nd);
         if (!dry) HS_HIP(hipMemsetAsync(d_fail, 0, sizeof(int) * nd, st));
-        Batch B;
+        Batch<R> B;
         B.trace_pivots = trace;
         B.dry = dry;
 
@@ -290,28 +302,28 @@ void factor(Plan& P, const double* values_in) {
         size_t region = 0;
         for (int s = 0; s < nd; ++s) {
             if (!S.super_nonempty[s]) continue;
-            region += blk_bytes(LN.msz[s], LN.msz[s]);
+            region += blk_bytes<R>(LN.msz[s], LN.msz[s]);
             for (int j : S.init_partners[s])
-                if (j > s) region += blk_bytes(LN.msz[s], LN.msz[j]);
+                if (j > s) region += blk_bytes<R>(LN.msz[s], LN.msz[j]);
         }
         char* base = static_cast<char*>(lp.alloc(region));
-        if (!dry) launch_fill(reinterpret_cast<double*>(base), 0.0, int64_t(region / sizeof(double)), st);
+        if (!dry) launch_fill<R>(reinterpret_cast<R*>(base), R(0), int64_t(region / sizeof(R)), st);
         std::vector<int32_t> blk_begin(nd + 1, 0), blk_col, blk_ld;
-        std::vector<double*> blk_ptr;
+        std::vector<void*> blk_ptr;
         {
             size_t off = 0;
             for (int s = 0; s < nd; ++s) {
                 blk_begin[s] = int32_t(blk_col.size());
                 if (!S.super_nonempty[s]) continue;
                 const int m = LN.msz[s];
-                Block b{reinterpret_cast<double*>(base + off), m, m, m};
-                off += blk_bytes(m, m);
+                Block b{base + off, m, m, m};
+                off += blk_bytes<R>(m, m);
                 live.put(s, s, b);
                 blk_col.push_back(s); blk_ld.push_back(m); blk_ptr.push_back(b.p);
                 for (int j : S.init_partners[s]) {
                     if (j <= s) continue;
-                    Block c{reinterpret_cast<double*>(base + off), m, LN.msz[j], m};
-                    off += blk_bytes(m, LN.msz[j]);
+                    Block c{base + off, m, LN.msz[j], m};
+                    off += blk_bytes<R>(m, LN.msz[j]);
                     live.put(s, j, c);
                     blk_col.push_back(j); blk_ld.push_back(m); blk_ptr.push_back(c.p);
                 }
@@ -323,15 +335,15 @@ void factor(Plan& P, const double* values_in) {
             if (L > 0)
                 for (int s = 0; s < nd; ++s) super_first[s] = P.leaf_off[2 * s];
             const int32_t* d_sf = P.stage.upload_vec(super_first, P.spool, st);
-            double* const* d_bp = P.stage.upload_vec(blk_ptr, P.spool, st);
+            void* const* d_bp = P.stage.upload_vec(blk_ptr, P.spool, st);
             const int32_t* d_bl = P.stage.upload_vec(blk_ld, P.spool, st);
             const int32_t* d_bc = P.stage.upload_vec(blk_col, P.spool, st);
             const int32_t* d_bb = P.stage.upload_vec(blk_begin, P.spool, st);
             if (!dry)
-                launch_leaf_scatter(P.d_row_ptr, P.d_col_idx, P.d_values, P.d_iperm, P.d_pos_super, d_sf, d_bp,
+                launch_leaf_scatter<R>(P.d_row_ptr, P.d_col_idx, P.d_values, P.d_iperm, P.d_pos_super, d_sf, d_bp,
                                     d_bl, d_bc, d_bb, P.n, st);
             if (gc) {
-                std::vector<double> h(size_t(P.n) * p);
+                std::vector<R> h(size_t(P.n) * p);
                 size_t off = 0;
                 std::vector<size_t> node_off(nd, 0);
                 for (int s = 0; s < nd; ++s) {
@@ -340,10 +352,10 @@ void factor(Plan& P, const double* values_in) {
                     const int p0 = (L == 0) ? 0 : P.leaf_off[2 * s];
                     for (int c = 0; c < p; ++c)
                         for (int i = 0; i < m; ++i)
-                            h[off + size_t(c) * m + i] = P.phi[size_t(P.perm[p0 + i]) + size_t(c) * P.n];
+                            h[off + size_t(c) * m + i] = R(P.phi[size_t(P.perm[p0 + i]) + size_t(c) * P.n]);
                     off += size_t(m) * p;
                 }
-                double* dphi = P.stage.upload_vec(h, lp, st);
+                R* dphi = P.stage.upload_vec(h, lp, st);
                 for (int s = 0; s < nd; ++s) phi_sup[d][s] = dphi + node_off[s];
             }
         } else {
@@ -366,16 +378,17 @@ void factor(Plan& P, const double* values_in) {
                             const int coff = b ? kc[2 * J] : 0;
                             Block* ch = prev.find(ca, cb);
                             if (!ch) continue;
-                            B.copy(ch->p, ch->ld, C->p + roff + size_t(coff) * C->ld, C->ld, ch->rows,
-                                   ch->cols, 0);
+                            B.copy(static_cast<R*>(ch->p), ch->ld, static_cast<R*>(C->p) + roff + size_t(coff) * C->ld,
+                                   C->ld, ch->rows, ch->cols, 0);
                             if (I == J && a == 0 && b == 1)
-                                B.copy(ch->p, ch->ld, C->p + kc[2 * I], C->ld, ch->cols, ch->rows, 1);
+                                B.copy(static_cast<R*>(ch->p), ch->ld, static_cast<R*>(C->p) + kc[2 * I], C->ld, ch->cols,
+                                       ch->rows, 1);
                         }
                     }
                 }
                 if (gc) {
                     const int m = LN.msz[I];
-                    double* f = lp.alloc_n<double>(size_t(m) * p);
+                    R* f = lp.alloc_n<R>(size_t(m) * p);
                     phi_sup[d][I] = f;
                     int r0 = 0;
                     for (int a = 0; a < 2; ++a) {
@@ -398,20 +411,23 @@ void factor(Plan& P, const double* values_in) {
             // --- pivot blocks: Cholesky and inverse of every A_ss of the colour on the side
             // stream, overlapped with the compression below (which does not read A_ss); the
             // inverses land in Ainv (ld m) and join the plan's stream in phase B
-            std::vector<double*> Ainv(nodes.size(), nullptr);
+            std::vector<R*> Ainv(nodes.size(), nullptr);
             for (size_t q = 0; q < nodes.size(); ++q) {
                 const int s = nodes[q];
                 const int m = LN.msz[s];
                 Block* dg = live.find(s, s);
                 if (!dg) throw Error{HSOLVE_ERR_DEVICE, "internal: missing diagonal block"};
-                Ainv[q] = P.spool.alloc_n<double>(size_t(m) * m);
+                Ainv[q] = P.spool.alloc_n<R>(size_t(m) * m);
                 B.chol.push_back(CholTask{dg->p, Ainv[q], nullptr, nullptr, dg->ld, m, m, s});
                 flops += double(m) * m * m;      // Cholesky (m^3/3) + inverse (2m^3/3)
             }
             B.flush_chol(P, d_fail, overlap);
             if (overlap) HS_HIP(hipEventRecord(P.ev_done, P.side));
             // --- phase A: compression of the nodes with well-separated blocks
-            struct CompNode { int s, slot, wt; double *Asw, *U; };
+            // Asw: the gathered A_sw (R); U: the basis in double from the eigen-solver, Ur: the
+            // basis the elimination uses (R; the same buffer in FP64)
+            struct CompNode { int s, slot, wt; R* Asw; double* U; R* Ur; };
+            std::vector<PromoteTask> promote;
             std::vector<CompNode> comp;
             std::vector<CompressTask> ctasks;
             for (int s : nodes) {
@@ -419,23 +435,23 @@ void factor(Plan& P, const double* values_in) {
                 const int m = LN.msz[s];
                 int wt = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) wt += cursize(S.W[s][t], S.Wred[s][t]);
-                double* Asw = P.spool.alloc_n<double>(size_t(m) * wt);
-                double* G = P.spool.alloc_n<double>(size_t(m) * m);
+                R* Asw = P.spool.alloc_n<R>(size_t(m) * wt);
+                R* G = P.spool.alloc_n<R>(size_t(m) * m);
                 double* U = P.spool.alloc_n<double>(size_t(m) * m);
                 double* work = P.spool.alloc_n<double>(cmp_work_doubles(m));
-                double* Z = nullptr;
+                R* Z = nullptr;
                 int off = 0;
                 for (size_t t = 0; t < S.W[s].size(); ++t) {
                     const int w = S.W[s][t];
                     const int ws = cursize(w, S.Wred[s][t]);
                     Block* b = live.find(s, w);
                     if (!b) throw Error{HSOLVE_ERR_DEVICE, "internal: missing well-separated block"};
-                    if (s < w) B.copy(b->p, b->ld, Asw + size_t(off) * m, m, m, ws, 0);
-                    else B.copy(b->p, b->ld, Asw + size_t(off) * m, m, m, ws, 1);
+                    if (s < w) B.copy(static_cast<R*>(b->p), b->ld, Asw + size_t(off) * m, m, m, ws, 0);
+                    else B.copy(static_cast<R*>(b->p), b->ld, Asw + size_t(off) * m, m, m, ws, 1);
                     off += ws;
                 }
                 if (gc) {
-                    double* phiW = P.spool.alloc_n<double>(size_t(wt) * p);
+                    R* phiW = P.spool.alloc_n<R>(size_t(wt) * p);
                     int r0 = 0;
                     for (size_t t = 0; t < S.W[s].size(); ++t) {
                         const int w = S.W[s][t];
@@ -444,7 +460,7 @@ void factor(Plan& P, const double* values_in) {
                         B.copy(red ? phi_red[d][w] : phi_sup[d][w], ws, phiW + r0, wt, ws, p, 0);
                         r0 += ws;
                     }
-                    Z = P.spool.alloc_n<double>(size_t(m) * 2 * p);
+                    Z = P.spool.alloc_n<R>(size_t(m) * 2 * p);
                     B.copy(phi_sup[d][s], m, Z, m, m, p, 0);
                     B.gemm(Z + size_t(p) * m, m, m, p, 1.0, 0.0, Asw, m, 0, phiW, wt, 0, wt);
                     flops += 2.0 * m * wt * p;
@@ -452,8 +468,20 @@ void factor(Plan& P, const double* values_in) {
                 B.gemm(G, m, m, m, 1.0, 0.0, Asw, m, 0, Asw, m, 1, wt);
                 flops += 2.0 * m * m * wt;
                 const int slot = int(comp.size());
-                comp.push_back(CompNode{s, slot, wt, Asw, U});
-                ctasks.push_back(CompressTask{G, Z, work, U, nullptr, m, gc ? 2 * p : 0, wt, slot});
+                const double* Gd = reinterpret_cast<const double*>(G);
+                const double* Zd = reinterpret_cast<const double*>(Z);
+                if constexpr (F32) {      // the eigen-solver reads FP64
+                    double* g64 = P.spool.alloc_n<double>(size_t(m) * m);
+                    promote.push_back(PromoteTask{G, g64, (long long)m * m});
+                    Gd = g64;
+                    if (Z) {
+                        double* z64 = P.spool.alloc_n<double>(size_t(m) * 2 * p);
+                        promote.push_back(PromoteTask{Z, z64, (long long)m * 2 * p});
+                        Zd = z64;
+                    }
+                }
+                comp.push_back(CompNode{s, slot, wt, Asw, U, nullptr});
+                ctasks.push_back(CompressTask{Gd, Zd, work, U, nullptr, m, gc ? 2 * p : 0, wt, slot});
             }
             int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
             long long* d_stamp = nullptr;
@@ -464,6 +492,12 @@ void factor(Plan& P, const double* values_in) {
             }
             B.flush_copies(P);
             B.flush_gemm(P);
+            if (!promote.empty()) {
+                double elems = 0.0;
+                for (const PromoteTask& t : promote) elems += double(t.count);
+                const PromoteTask* d_pr = P.stage.upload_vec(promote, P.spool, st);
+                if (!dry) launch_promote(d_pr, int(promote.size()), elems, st);
+            }
             if (proj1 && !ctasks.empty()) {
                 const CompressTask* d_all = P.stage.upload_vec(ctasks, P.spool, st);
                 if (!dry) launch_gc_truncate(d_all, int(ctasks.size()), P.opt.eps1, st);
@@ -531,32 +565,56 @@ void factor(Plan& P, const double* values_in) {
             // towards the polar factor, U <- U (3 I - U^T U) / 2, restores U^T U = I to second
             // order on the matrix cores; it keeps span(U), so the GC vectors stay in it.
             {
+                // in double: the eigen-solver's basis (for FP32, rounded once afterwards)
+                Batch<double> Bd;
+                Batch<double>& B64 = [&]() -> Batch<double>& {
+                    if constexpr (F32) return Bd;
+                    else return B;
+                }();
+                Bd.dry = dry;
                 std::vector<double*> Wsc(comp.size(), nullptr);
                 for (CompNode& cn : comp) {
                     const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
                     if (k < 2) continue;
                     Wsc[cn.slot] = P.spool.alloc_n<double>(size_t(k) * k);
-                    B.gemm(Wsc[cn.slot], k, k, k, 1.0, 0.0, cn.U, m, 1, cn.U, m, 0, m);
+                    B64.gemm(Wsc[cn.slot], k, k, k, 1.0, 0.0, cn.U, m, 1, cn.U, m, 0, m);
                     flops += 2.0 * m * k * k;
                 }
-                B.flush_gemm(P);
+                B64.flush_gemm(P);
                 for (CompNode& cn : comp) {
                     const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
                     if (k < 2) continue;
                     double* Un = P.spool.alloc_n<double>(size_t(m) * k);
-                    B.copy(cn.U, m, Un, m, m, k, 0);
-                    B.gemm(Un, m, m, k, -0.5, 1.5, cn.U, m, 0, Wsc[cn.slot], k, 0, k);
+                    B64.copy(cn.U, m, Un, m, m, k, 0);
+                    B64.gemm(Un, m, m, k, -0.5, 1.5, cn.U, m, 0, Wsc[cn.slot], k, 0, k);
                     flops += 2.0 * m * k * k;
                     cn.U = Un;
                 }
-                B.flush_copies(P);
-                B.flush_gemm(P);
+                B64.flush_copies(P);
+                B64.flush_gemm(P);
+                if constexpr (F32) {
+                    std::vector<DemoteTask> dt;
+                    double elems = 0.0;
+                    for (CompNode& cn : comp) {
+                        const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
+                        if (!k) continue;
+                        cn.Ur = P.spool.alloc_n<R>(size_t(m) * k);
+                        dt.push_back(DemoteTask{cn.U, reinterpret_cast<float*>(cn.Ur), (long long)m * k});
+                        elems += double(m) * k;
+                    }
+                    if (!dt.empty()) {
+                        const DemoteTask* d_dt = P.stage.upload_vec(dt, P.spool, st);
+                        if (!dry) launch_demote(d_dt, int(dt.size()), elems, st);
+                    }
+                } else {
+                    for (CompNode& cn : comp) cn.Ur = reinterpret_cast<R*>(cn.U);
+                }
             }
             std::vector<const CompNode*> compof(nd, nullptr);
             for (const CompNode& cn : comp) compof[cn.s] = &cn;
 
             // --- phase B: elimination
-            std::vector<double*> AN(nodes.size()), Ysc(nodes.size());
+            std::vector<R*> AN(nodes.size()), Ysc(nodes.size());
             for (size_t q = 0; q < nodes.size(); ++q) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
@@ -571,18 +629,18 @@ void factor(Plan& P, const double* values_in) {
                     nn.ntot += cursize(S.N[s][t], S.Nred[s][t]);
                 }
                 nn.ldG = nn.m + nn.ntot + nn.k;
-                nn.Gm = P.fpool.alloc_n<double>(size_t(nn.ldG) * nn.m);
+                nn.Gm = P.fpool.alloc_n<R>(size_t(nn.ldG) * nn.m);
                 const int m = nn.m;
-                AN[q] = nn.ntot ? P.spool.alloc_n<double>(size_t(nn.ntot) * m) : nullptr;
+                AN[q] = nn.ntot ? P.spool.alloc_n<R>(size_t(nn.ntot) * m) : nullptr;
                 for (size_t t = 0; t < S.N[s].size(); ++t) {
                     const int nb = S.N[s][t];
                     const int ns = cursize(nb, S.Nred[s][t]);
                     Block* b = live.find(nb, s);
                     if (!b) throw Error{HSOLVE_ERR_DEVICE, "internal: missing neighbour block"};
-                    if (nb < s) B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 0);
-                    else B.copy(b->p, b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
+                    if (nb < s) B.copy(static_cast<R*>(b->p), b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 0);
+                    else B.copy(static_cast<R*>(b->p), b->ld, AN[q] + nn.noff[t], nn.ntot, ns, m, 1);
                 }
-                B.copy(Ainv[q], m, nn.Gm, nn.ldG, m, m, 0);      // A_ss^-1 into rows 0..m-1 of Gm
+                B.copy(Ainv[q], m, gm(nn), nn.ldG, m, m, 0);      // A_ss^-1 into rows 0..m-1 of Gm
             }
             B.flush_copies(P);
             // Y = A_ss^-1 U, S = U^T Y
@@ -590,18 +648,18 @@ void factor(Plan& P, const double* values_in) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
-                Ysc[q] = P.spool.alloc_n<double>(size_t(nn.m) * nn.k);
-                B.gemm(Ysc[q], nn.m, nn.m, nn.k, 1.0, 0.0, nn.Gm, nn.ldG, 0, compof[s]->U, nn.m, 0, nn.m);
+                Ysc[q] = P.spool.alloc_n<R>(size_t(nn.m) * nn.k);
+                B.gemm(Ysc[q], nn.m, nn.m, nn.k, 1.0, 0.0, gm(nn), nn.ldG, 0, compof[s]->Ur, nn.m, 0, nn.m);
                 flops += 2.0 * nn.m * nn.m * nn.k;
             }
             B.flush_gemm(P);
-            std::vector<double*> Ssc(nodes.size()), Sinv(nodes.size());
+            std::vector<R*> Ssc(nodes.size()), Sinv(nodes.size());
             for (size_t q = 0; q < nodes.size(); ++q) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
-                Ssc[q] = P.spool.alloc_n<double>(size_t(nn.k) * nn.k);
-                B.gemm(Ssc[q], nn.k, nn.k, nn.k, 1.0, 0.0, compof[s]->U, nn.m, 1, Ysc[q], nn.m, 0, nn.m);
+                Ssc[q] = P.spool.alloc_n<R>(size_t(nn.k) * nn.k);
+                B.gemm(Ssc[q], nn.k, nn.k, nn.k, 1.0, 0.0, compof[s]->Ur, nn.m, 1, Ysc[q], nn.m, 0, nn.m);
                 flops += 2.0 * nn.m * nn.k * nn.k;
             }
             B.flush_gemm(P);
@@ -609,7 +667,7 @@ void factor(Plan& P, const double* values_in) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
-                Sinv[q] = static_cast<double*>(lp.alloc(blk_bytes(nn.k, nn.k)));
+                Sinv[q] = static_cast<R*>(lp.alloc(blk_bytes<R>(nn.k, nn.k)));
                 B.chol.push_back(CholTask{Ssc[q], Sinv[q], nullptr, nullptr, nn.k, nn.k, nn.k, s});
                 flops += double(nn.k) * nn.k * nn.k;
             }
@@ -619,7 +677,7 @@ void factor(Plan& P, const double* values_in) {
                 const int s = nodes[q];
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
-                B.gemm(nn.Gm + nn.m + nn.ntot, nn.ldG, nn.k, nn.m, 1.0, 0.0, Sinv[q], nn.k, 0, Ysc[q],
+                B.gemm(gm(nn) + nn.m + nn.ntot, nn.ldG, nn.k, nn.m, 1.0, 0.0, Sinv[q], nn.k, 0, Ysc[q],
                        nn.m, 1, nn.k);
                 flops += 2.0 * nn.k * nn.k * nn.m;
             }
@@ -630,11 +688,11 @@ void factor(Plan& P, const double* values_in) {
                 NodeNum& nn = LN.node[s];
                 if (!nn.k) continue;
                 if (nn.k == nn.m) {
-                    B.open(nn.Gm, nn.ldG, nn.m, nn.m, 0.0, 0.0);
+                    B.open(gm(nn), nn.ldG, nn.m, nn.m, 0.0, 0.0);
                     B.close();
                     continue;
                 }
-                B.gemm(nn.Gm, nn.ldG, nn.m, nn.m, -1.0, 1.0, Ysc[q], nn.m, 0, nn.Gm + nn.m + nn.ntot,
+                B.gemm(gm(nn), nn.ldG, nn.m, nn.m, -1.0, 1.0, Ysc[q], nn.m, 0, gm(nn) + nn.m + nn.ntot,
                        nn.ldG, 0, nn.k);
                 flops += 2.0 * nn.m * nn.m * nn.k;
             }
@@ -645,7 +703,7 @@ void factor(Plan& P, const double* values_in) {
                 NodeNum& nn = LN.node[s];
                 const int m = nn.m, k = nn.k;
                 if (nn.ntot) {
-                    B.gemm(nn.Gm + m, nn.ldG, nn.ntot, m, 1.0, 0.0, AN[q], nn.ntot, 0, nn.Gm, nn.ldG, 0, m);
+                    B.gemm(gm(nn) + m, nn.ldG, nn.ntot, m, 1.0, 0.0, AN[q], nn.ntot, 0, gm(nn), nn.ldG, 0, m);
                     flops += 2.0 * nn.ntot * m * m;
                 }
                 if (!k) {
@@ -654,16 +712,16 @@ void factor(Plan& P, const double* values_in) {
                     live.erase(s, s);
                     continue;
                 }
-                const double* Pm = nn.Gm + m + nn.ntot;
+                const R* Pm = gm(nn) + m + nn.ntot;
                 for (size_t t = 0; t < S.N[s].size(); ++t) {
                     const int nb = S.N[s][t];
                     const int ns = cursize(nb, S.Nred[s][t]);
                     if (nb < s) {
-                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(ns, k)));
+                        R* blk = static_cast<R*>(lp.alloc(blk_bytes<R>(ns, k)));
                         live.put(nb, s, Block{blk, ns, k, ns});
                         B.gemm(blk, ns, ns, k, 1.0, 0.0, AN[q] + nn.noff[t], nn.ntot, 0, Pm, nn.ldG, 1, m);
                     } else {
-                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(k, ns)));
+                        R* blk = static_cast<R*>(lp.alloc(blk_bytes<R>(k, ns)));
                         live.put(s, nb, Block{blk, k, ns, k});
                         B.gemm(blk, k, k, ns, 1.0, 0.0, Pm, nn.ldG, 0, AN[q] + nn.noff[t], nn.ntot, 1, m);
                     }
@@ -674,24 +732,24 @@ void factor(Plan& P, const double* values_in) {
                 for (size_t t = 0; t < S.W[s].size(); ++t) {
                     const int w = S.W[s][t];
                     const int ws = cursize(w, S.Wred[s][t]);
-                    const double* Aw = cn->Asw + size_t(off) * m;
+                    const R* Aw = cn->Asw + size_t(off) * m;
                     if (s < w) {
-                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(k, ws)));
+                        R* blk = static_cast<R*>(lp.alloc(blk_bytes<R>(k, ws)));
                         live.put(s, w, Block{blk, k, ws, k});
-                        B.gemm(blk, k, k, ws, 1.0, 0.0, cn->U, m, 1, Aw, m, 0, m);
+                        B.gemm(blk, k, k, ws, 1.0, 0.0, cn->Ur, m, 1, Aw, m, 0, m);
                     } else {
-                        double* blk = static_cast<double*>(lp.alloc(blk_bytes(ws, k)));
+                        R* blk = static_cast<R*>(lp.alloc(blk_bytes<R>(ws, k)));
                         live.put(w, s, Block{blk, ws, k, ws});
-                        B.gemm(blk, ws, ws, k, 1.0, 0.0, Aw, m, 1, cn->U, m, 0, m);
+                        B.gemm(blk, ws, ws, k, 1.0, 0.0, Aw, m, 1, cn->Ur, m, 0, m);
                     }
                     flops += 2.0 * ws * m * k;
                     off += ws;
                 }
                 live.put(s, s, Block{Sinv[q], k, k, k});
                 if (gc) {
-                    double* f = lp.alloc_n<double>(size_t(k) * p);
+                    R* f = lp.alloc_n<R>(size_t(k) * p);
                     phi_red[d][s] = f;
-                    B.gemm(f, k, k, p, 1.0, 0.0, cn->U, m, 1, phi_sup[d][s], m, 0, m);
+                    B.gemm(f, k, k, p, 1.0, 0.0, cn->Ur, m, 1, phi_sup[d][s], m, 0, m);
                 }
             }
             B.flush_gemm(P);
@@ -713,16 +771,16 @@ void factor(Plan& P, const double* values_in) {
                 Block* C = live.find(a, b);
                 bool fresh = false;
                 if (!C) {
-                    double* blk = static_cast<double*>(lp.alloc(blk_bytes(sa, sb)));
+                    R* blk = static_cast<R*>(lp.alloc(blk_bytes<R>(sa, sb)));
                     live.put(a, b, Block{blk, sa, sb, sa});
                     C = live.find(a, b);
                     fresh = true;
                 }
-                B.open(C->p, C->ld, sa, sb, -1.0, fresh ? 0.0 : 1.0);
+                B.open(static_cast<R*>(C->p), C->ld, sa, sb, -1.0, fresh ? 0.0 : 1.0);
                 for (const auto& ct : contrib) {
                     const int s = nodes[ct[0]];
                     const NodeNum& nn = LN.node[s];
-                    B.term(nn.Gm + nn.m + nn.noff[ct[1]], nn.ldG, 0, AN[ct[0]] + nn.noff[ct[2]], nn.ntot, 1,
+                    B.term(gm(nn) + nn.m + nn.noff[ct[1]], nn.ldG, 0, AN[ct[0]] + nn.noff[ct[2]], nn.ntot, 1,
                            nn.m);
                     flops += 2.0 * sa * sb * nn.m;
                 }
@@ -766,7 +824,11 @@ void factor(Plan& P, const double* values_in) {
         }
         P.stage.reset();
     }
-    if (P.apply32) {
+    if constexpr (F32) {
+        // the FP32 factor is what the single-precision solve phase reads
+        for (int d = 0; d < nlev; ++d)
+            for (NodeNum& nn : P.num[d].node) nn.Gm32 = reinterpret_cast<float*>(nn.Gm);
+    } else if (P.apply32) {
         // single-precision copies of the solve-phase blocks, rounded once from the FP64 factor
         std::vector<DemoteTask> dt;
         double elems = 0.0;
@@ -776,7 +838,7 @@ void factor(Plan& P, const double* values_in) {
                 if (!nn.Gm || nn.m == 0) continue;
                 const long long cnt = (long long)nn.ldG * nn.m;
                 nn.Gm32 = P.fpool.alloc_n<float>(size_t(cnt));
-                dt.push_back(DemoteTask{nn.Gm, nn.Gm32, cnt});
+                dt.push_back(DemoteTask{static_cast<const double*>(nn.Gm), nn.Gm32, cnt});
                 elems += double(cnt);
             }
         for (size_t i = 0; i < dt.size(); i += 65535) {
@@ -800,6 +862,11 @@ void factor(Plan& P, const double* values_in) {
     P.stats.fail_level = -1;
     P.stats.fail_node = -1;
     P.stats.t_factor = std::chrono::duration<double>(clk::now() - t0).count();
+}
+
+void factor(Plan& P, const double* values) {
+    if (P.f32) factor_t<float>(P, values);
+    else factor_t<double>(P, values);
 }
 
 // Arena bound (hsolve_analyze): replay the factorization on the host with every rank at its

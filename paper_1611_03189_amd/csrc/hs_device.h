@@ -33,6 +33,25 @@ inline void check_launch(const char* name) {
 
 // operand / accumulator type of v_mfma_f64_16x16x4f64
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+// One 16 x 16 x 4 matrix-core product per wave in the storage type T: lane l supplies
+// A(l % 16, l / 16) and B(l / 16, l % 16); result register r holds C(row(l, r), l % 16). The
+// FP64 and FP32 instructions take the same operand lanes but place their result rows
+// differently (measured on gfx950).
+template <typename T> struct Mma;
+template <> struct Mma<double> {
+    typedef dbl4 acc;
+    __device__ static acc zero() { return dbl4{0.0, 0.0, 0.0, 0.0}; }
+    __device__ static acc mac(double a, double b, acc c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return lane / 16 + 4 * r; }
+};
+template <> struct Mma<float> {
+    typedef flt4 acc;
+    __device__ static acc zero() { return flt4{0.f, 0.f, 0.f, 0.f}; }
+    __device__ static acc mac(float a, float b, acc c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    __device__ static int row(int lane, int r) { return 4 * (lane / 16) + r; }
+};
 
 // Wave-wide reductions with DPP: two quad permutations and two rotations by 4 and 8 leave
 // every lane with the total of its row of 16; two row broadcasts (lane 15 into rows 1 and 3,

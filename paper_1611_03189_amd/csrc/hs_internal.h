@@ -139,8 +139,8 @@ struct LevelSym {
 // ---------------------------------------------------------------------------------
 // Dense blocks of the current matrix (column-major, canonical orientation i <= j)
 // ---------------------------------------------------------------------------------
-struct Block {
-    double* p = nullptr;
+struct Block {               // elements of the factorization's storage type (double or float)
+    void* p = nullptr;
     int rows = 0, cols = 0, ld = 0;
 };
 
@@ -155,8 +155,9 @@ inline uint64_t bkey(int i, int j) {
 // ---------------------------------------------------------------------------------
 struct NodeNum {
     int m = 0, k = 0, ntot = 0, ka = 0;
-    double* Gm = nullptr;
-    float* Gm32 = nullptr;     // single-precision copy for the FP32 solve phase
+    void* Gm = nullptr;        // in the factorization's storage type
+    float* Gm32 = nullptr;     // what the FP32 solve phase reads: a rounded copy of an FP64 factor,
+                               // or the FP32 factor itself
     int ldG = 0;
     std::vector<int> noff;     // row offset of each neighbour inside T_N
 };
@@ -170,21 +171,21 @@ struct LevelNum {
 // ---------------------------------------------------------------------------------
 // Kernel task records (shared layout with kernels.hip)
 // ---------------------------------------------------------------------------------
-struct CopyTask {            // dst(i,j) = src(i,j) or src(j,i) (trans)
-    const double* src;
-    double* dst;
+struct CopyTask {            // dst(i,j) = src(i,j) or src(j,i) (trans), in the launch's type
+    const void* src;
+    void* dst;
     int lds, ldd, rows, cols, trans, pad;
 };
 
-struct GemmTask {            // C = beta C + alpha sum_t op(A_t) op(B_t), C is M x N
-    double* C;
+struct GemmTask {            // C = beta C + alpha sum_t op(A_t) op(B_t), C is M x N (launch's type)
+    void* C;
     int ldc, M, N, t_begin, t_end, pad;
     double alpha, beta;
 };
 
 struct GemmTerm {
-    const double* A;
-    const double* B;
+    const void* A;
+    const void* B;
     int lda, ldb, K, transA, transB, pad;
 };
 
@@ -203,15 +204,15 @@ constexpr int GEMM_TILE_BUCKETS = 4;       // 64x64 tiles: < 32, < 256, < 2048, 
 constexpr int GEMM_K_BUCKETS = 3;          // mean K: <= 64, <= 256, more
 constexpr int GEMM_BUCKETS = GEMM_TILE_BUCKETS * GEMM_K_BUCKETS;
 int gemm_bucket(double tiles64, double mean_k);
-int gemm_variant(int bucket);              // the tuned choice (0 until tuned)
-void set_gemm_variant(int bucket, int variant);
+int gemm_variant(int bucket, bool f32);    // the tuned choice (0 until tuned)
+void set_gemm_variant(int bucket, bool f32, int variant);
 size_t tune_workspace_bytes();
 void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* ms);
 
-struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1}
-    double* A;
-    double* Ainv;
-    double* work;            // m x m scratch for blocks too large for LDS (else null)
+struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1} (launch's type)
+    void* A;
+    void* Ainv;
+    void* work;              // m x m scratch for blocks too large for LDS (else null)
     long long* tstamp;       // optional: 4 clock stamps at phase boundaries (trace only)
     int lda, ldi, m, id;
 };
@@ -245,6 +246,12 @@ struct BwdNode {             // x_s = Gm^T [phi_s; -x_N; x_r], written at dst of
 struct DemoteTask {          // dst[i] = float(src[i]), i < count
     const double* src;
     float* dst;
+    long long count;
+};
+
+struct PromoteTask {         // dst[i] = double(src[i]), i < count
+    const float* src;
+    double* dst;
     long long count;
 };
 
@@ -320,6 +327,7 @@ struct Plan {
     };
     std::vector<std::vector<ColourSched>> sched;   // sched[d][c]
     bool apply32 = false;                           // solve phase in single precision
+    bool f32 = false;                               // factorization in single precision
     void* d_V = nullptr;                            // forward right-hand sides (phi)
     void* d_X = nullptr;                            // backward solutions (x)
     int V_cols = 0;
@@ -380,11 +388,16 @@ void gmres(Plan& P, int nrhs, const double* b, int ldb, double* x, int ldx, doub
 void spmv(Plan& P, const double* x, double* y);
 
 // kernels.hip: launch wrappers (all asynchronous on stream s)
+// the factorization's kernels in its storage type T (double, or float with factor_prec = 32)
+template <typename T>
 void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s);
+template <typename T>
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
                  int ntiles, double flops, int variant, hipStream_t s);
+template <typename T>
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s);
+void launch_promote(const PromoteTask* d_tasks, int ntasks, double elems, hipStream_t s);
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
                      int* d_rank, double flops, bool lds, int max_m, int force_lpe, int force_vectors,
                      hipStream_t s);
@@ -400,9 +413,10 @@ inline size_t cmp_work_doubles(int m) {
 }
 constexpr int PIV_LDS_MAX_M = 64; // pivot blocks up to this size are factored in LDS; larger
                                   // ones by the blocked kernel (panels of 32 columns)
+template <typename T>
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const int32_t* iperm, const int32_t* pos_super,
-                         const int32_t* super_first, double* const* blk_ptr,
+                         const int32_t* super_first, void* const* blk_ptr,
                          const int32_t* blk_ld, const int32_t* blk_col,
                          const int32_t* blk_begin, int n, hipStream_t s);
 // solve phase in the storage type T of the factor copy it reads (double, or float for the

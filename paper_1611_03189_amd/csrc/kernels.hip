@@ -18,14 +18,15 @@ namespace hs {
 // large blocks spread over many CUs.
 constexpr int COPY_COLS = 32;
 
+template <typename T>
 __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
     const CopyTask t = tasks[blockIdx.x];
     const int j0 = blockIdx.y * COPY_COLS;
     if (j0 >= t.cols) return;
     const int nc = min(COPY_COLS, t.cols - j0);
-    const HS_G double* src = gp(t.src);
-    HS_G double* dst = gp(t.dst);
-    __shared__ double tile[32][33];
+    const HS_G T* src = gp(static_cast<const T*>(t.src));
+    HS_G T* dst = gp(static_cast<T*>(t.dst));
+    __shared__ T tile[32][33];
     if (!t.trans) {
         copy_block(dst + size_t(j0) * t.ldd, t.ldd, src + size_t(j0) * t.lds, t.lds, t.rows, nc);
         return;
@@ -46,11 +47,30 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyTask* tasks) {
     }
 }
 
+template <typename T>
 void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s) {
     if (ntasks <= 0 || max_cols <= 0) return;
-    ProfScope ps("k_copy", bytes, s);
-    hipLaunchKernelGGL(k_copy, dim3(ntasks, (max_cols + COPY_COLS - 1) / COPY_COLS), dim3(NT), 0, s, d_tasks);
+    ProfScope ps(sizeof(T) == 8 ? "k_copy" : "k_copy_f32", bytes, s);
+    hipLaunchKernelGGL(k_copy<T>, dim3(ntasks, (max_cols + COPY_COLS - 1) / COPY_COLS), dim3(NT), 0, s, d_tasks);
     check_launch("k_copy");
+}
+template void launch_copy<double>(const CopyTask*, int, int, double, hipStream_t);
+template void launch_copy<float>(const CopyTask*, int, int, double, hipStream_t);
+
+// dst[i] = double(src[i]) for each task (the FP32 factorization's Gram matrices and kept
+// vectors, read by the FP64 eigen-solver)
+__global__ void k_promote(const PromoteTask* tasks) {
+    const PromoteTask t = tasks[blockIdx.y];
+    for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < t.count;
+         i += (long long)gridDim.x * blockDim.x)
+        t.dst[i] = double(t.src[i]);
+}
+
+void launch_promote(const PromoteTask* d_tasks, int ntasks, double elems, hipStream_t s) {
+    if (ntasks <= 0) return;
+    ProfScope ps("k_promote", 12.0 * elems, s);
+    hipLaunchKernelGGL(k_promote, dim3(64, ntasks), dim3(NT), 0, s, d_tasks);
+    check_launch("k_promote");
 }
 
 // ---------------------------------------------------------------------------------
@@ -69,37 +89,38 @@ struct GemmStep {            // position in the concatenated K loop of a task's 
     int term, k0;
 };
 
-template <int TM, int TN, int TK>
+template <typename T, int TM, int TN, int TK>
 __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
                                              const GemmTile* tiles) {
+    typedef Mma<T> MM;
     constexpr int BX = TM / 32, BY = TN / 32;              // 16 x 16 blocks per wave
     constexpr int LA = TM * TK / NT, LB = TN * TK / NT;    // loads per thread and K step
     static_assert(LA * NT == TM * TK && LB * NT == TN * TK, "tile");
     const GemmTile tl = tiles[blockIdx.x];
-    const GemmTask T = tasks[tl.task];
+    const GemmTask Tk = tasks[tl.task];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    __shared__ double As[2][TK][TM + 1];
-    __shared__ double Bs[2][TK][TN + 1];
+    __shared__ T As[2][TK][TM + 1];
+    __shared__ T Bs[2][TK][TN + 1];
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
-    dbl4 acc[BX][BY];
+    typename MM::acc acc[BX][BY];
 #pragma unroll
     for (int x = 0; x < BX; ++x)
 #pragma unroll
-        for (int y = 0; y < BY; ++y) acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
+        for (int y = 0; y < BY; ++y) acc[x][y] = MM::zero();
 
-    double ra[LA], rb[LB];
+    T ra[LA], rb[LB];
     auto load_step = [&](GemmStep st) {
         const GemmTerm g = terms[st.term];
-        const HS_G double* gA = gp(g.A);
-        const HS_G double* gB = gp(g.B);
+        const HS_G T* gA = gp(static_cast<const T*>(g.A));
+        const HS_G T* gB = gp(static_cast<const T*>(g.B));
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int e = tid + NT * q;
             int ii, kk;
             if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
             const int gi = i0 + ii, gk = st.k0 + kk;
-            ra[q] = (gi < T.M && gk < g.K) ? (g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda])
-                                           : 0.0;
+            ra[q] = (gi < Tk.M && gk < g.K) ? (g.transA ? gA[gk + size_t(gi) * g.lda] : gA[gi + size_t(gk) * g.lda])
+                                            : T(0);
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
@@ -107,8 +128,8 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
             int jj, kb;
             if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
             const int gj = j0 + jj, gkb = st.k0 + kb;
-            rb[q] = (gj < T.N && gkb < g.K) ? (g.transB ? gB[gj + size_t(gkb) * g.ldb] : gB[gkb + size_t(gj) * g.ldb])
-                                            : 0.0;
+            rb[q] = (gj < Tk.N && gkb < g.K) ? (g.transB ? gB[gj + size_t(gkb) * g.ldb] : gB[gkb + size_t(gj) * g.ldb])
+                                             : T(0);
         }
     };
     auto store_step = [&](GemmStep st, int buf) {
@@ -130,26 +151,26 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
     };
     auto next_step = [&](GemmStep st) {
         st.k0 += TK;
-        while (st.term < T.t_end && st.k0 >= terms[st.term].K) {
+        while (st.term < Tk.t_end && st.k0 >= terms[st.term].K) {
             ++st.term;
             st.k0 = 0;
         }
         return st;
     };
-    GemmStep cur{T.t_begin, 0};
-    while (cur.term < T.t_end && terms[cur.term].K <= 0) ++cur.term;
+    GemmStep cur{Tk.t_begin, 0};
+    while (cur.term < Tk.t_end && terms[cur.term].K <= 0) ++cur.term;
     const int wr = (wv / 2) * (TM / 2), wc = (wv % 2) * (TN / 2);    // this wave's sub-tile
     const int fr = lane % 16, fk = lane / 16;
     int buf = 0;
-    if (cur.term < T.t_end) load_step(cur);
-    while (cur.term < T.t_end) {
+    if (cur.term < Tk.t_end) load_step(cur);
+    while (cur.term < Tk.t_end) {
         store_step(cur, buf);
         __syncthreads();
         const GemmStep nxt = next_step(cur);
-        if (nxt.term < T.t_end) load_step(nxt);
+        if (nxt.term < Tk.t_end) load_step(nxt);
 #pragma unroll
         for (int kk = 0; kk < TK; kk += 4) {
-            double af[BX], bf[BY];
+            T af[BX], bf[BY];
 #pragma unroll
             for (int x = 0; x < BX; ++x) af[x] = As[buf][kk + fk][wr + 16 * x + fr];
 #pragma unroll
@@ -158,49 +179,54 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
             for (int x = 0; x < BX; ++x)
 #pragma unroll
                 for (int y = 0; y < BY; ++y)
-                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(af[x], bf[y], acc[x][y], 0, 0, 0);
+                    acc[x][y] = MM::mac(af[x], bf[y], acc[x][y]);
         }
         cur = nxt;
         buf ^= 1;
     }
-    HS_G double* C = gp(T.C);
+    HS_G T* C = gp(static_cast<T*>(Tk.C));
+    const T alpha = T(Tk.alpha), beta = T(Tk.beta);
 #pragma unroll
     for (int x = 0; x < BX; ++x)
 #pragma unroll
         for (int y = 0; y < BY; ++y)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int i = i0 + wr + 16 * x + fk + 4 * r, j = j0 + wc + 16 * y + fr;
-                if (i < T.M && j < T.N) {
-                    HS_G double* c = C + i + size_t(j) * T.ldc;
-                    const double old = (T.beta == 0.0) ? 0.0 : T.beta * (*c);
-                    *c = old + T.alpha * acc[x][y][r];
+                const int i = i0 + wr + 16 * x + MM::row(lane, r), j = j0 + wc + 16 * y + fr;
+                if (i < Tk.M && j < Tk.N) {
+                    HS_G T* c = C + i + size_t(j) * Tk.ldc;
+                    const T old = (Tk.beta == 0.0) ? T(0) : beta * (*c);
+                    *c = old + alpha * acc[x][y][r];
                 }
             }
 }
 
 const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16}, {64, 64, 32}, {128, 64, 16}, {128, 128, 16}};
 
+template <typename T>
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
                  int ntiles, double flops, int variant, hipStream_t s) {
     if (ntiles <= 0) return;
-    ProfScope ps("k_gemm", flops, s);
+    ProfScope ps(sizeof(T) == 8 ? "k_gemm" : "k_gemm_f32", flops, s);
     switch (variant) {
-        case 1: hipLaunchKernelGGL((k_gemm<64, 64, 32>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 2: hipLaunchKernelGGL((k_gemm<128, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 3: hipLaunchKernelGGL((k_gemm<128, 128, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        default: hipLaunchKernelGGL((k_gemm<64, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 1: hipLaunchKernelGGL((k_gemm<T, 64, 64, 32>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 2: hipLaunchKernelGGL((k_gemm<T, 128, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 3: hipLaunchKernelGGL((k_gemm<T, 128, 128, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        default: hipLaunchKernelGGL((k_gemm<T, 64, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
     }
     check_launch("k_gemm");
 }
+template void launch_gemm<double>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t);
+template void launch_gemm<float>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t);
 
 // ---------------------------------------------------------------------------------
 // Initial blocks of the first level from the CSR values
 // ---------------------------------------------------------------------------------
+template <typename T>
 __global__ void k_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx,
                                const double* vals, const int32_t* iperm,
                                const int32_t* pos_super, const int32_t* super_first,
-                               double* const* blk_ptr, const int32_t* blk_ld,
+                               void* const* blk_ptr, const int32_t* blk_ld,
                                const int32_t* blk_col, const int32_t* blk_begin, int n) {
     const int u = blockIdx.x * blockDim.x + threadIdx.x;
     if (u >= n) return;
@@ -211,23 +237,30 @@ __global__ void k_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx,
         const int lv = pv - super_first[sv];
         for (int b = blk_begin[su]; b < blk_begin[su + 1]; ++b)
             if (blk_col[b] == sv) {
-                blk_ptr[b][lu + size_t(lv) * blk_ld[b]] = vals[t];
+                static_cast<T*>(blk_ptr[b])[lu + size_t(lv) * blk_ld[b]] = T(vals[t]);
                 break;
             }
     }
 }
 
+template <typename T>
 void launch_leaf_scatter(const int64_t* row_ptr, const int32_t* col_idx, const double* vals,
                          const int32_t* iperm, const int32_t* pos_super,
-                         const int32_t* super_first, double* const* blk_ptr,
+                         const int32_t* super_first, void* const* blk_ptr,
                          const int32_t* blk_ld, const int32_t* blk_col,
                          const int32_t* blk_begin, int n, hipStream_t s) {
     if (n <= 0) return;
-    hipLaunchKernelGGL(k_leaf_scatter, dim3((n + NT - 1) / NT), dim3(NT), 0, s, row_ptr,
+    hipLaunchKernelGGL(k_leaf_scatter<T>, dim3((n + NT - 1) / NT), dim3(NT), 0, s, row_ptr,
                        col_idx, vals, iperm, pos_super, super_first, blk_ptr, blk_ld, blk_col,
                        blk_begin, n);
     check_launch("k_leaf_scatter");
 }
+template void launch_leaf_scatter<double>(const int64_t*, const int32_t*, const double*, const int32_t*,
+                                          const int32_t*, const int32_t*, void* const*, const int32_t*,
+                                          const int32_t*, const int32_t*, int, hipStream_t);
+template void launch_leaf_scatter<float>(const int64_t*, const int32_t*, const double*, const int32_t*,
+                                         const int32_t*, const int32_t*, void* const*, const int32_t*,
+                                         const int32_t*, const int32_t*, int, hipStream_t);
 
 // ---------------------------------------------------------------------------------
 // Solve phase: forward (gather form) and backward sweeps of one colour

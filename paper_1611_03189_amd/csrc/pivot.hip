@@ -19,37 +19,38 @@ namespace hs {
 constexpr int PIV_LDS_MAX = 128;
 constexpr int PIV_MAX = 512;
 constexpr int PIV_NB = 32;
-constexpr int PIV_PANEL = PIV_MAX * PIV_NB;     // doubles of the LDS panel buffer
+constexpr int PIV_PANEL = PIV_MAX * PIV_NB;     // elements of the LDS panel buffer
 
+template <typename R>
 __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fail) {
-    extern __shared__ double lds[];
+    extern __shared__ double lds_raw[];             // typed double: 8-byte aligned LDS accesses
     __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
-    double* W = lds;
+    R* W = reinterpret_cast<R*>(lds_raw);
     const int ldw = m + 1;
-    const HS_G double* A = gp(T.A);
-    HS_G double* Ainv = gp(T.Ainv);
+    const HS_G R* A = gp(static_cast<const R*>(T.A));
+    HS_G R* Ainv = gp(static_cast<R*>(T.Ainv));
     copy_block(W, ldw, A, T.lda, m, m);
     if (tid == 0) bad = 0;
     __syncthreads();
     for (int j = 0; j < m; ++j) {
         if (tid == 0) {
-            const double d = W[j + j * ldw];
-            if (!(d > 0.0) || !isfinite(d)) bad = 1;
+            const R d = W[j + j * ldw];
+            if (!(d > R(0)) || !isfinite(d)) bad = 1;
             else W[j + j * ldw] = sqrt(d);
         }
         __syncthreads();
         if (bad) break;
-        const double piv = W[j + j * ldw];
+        const R piv = W[j + j * ldw];
         for (int i = j + 1 + tid; i < m; i += NT) W[i + j * ldw] /= piv;
         __syncthreads();
         // trailing update, rows over threads (the column-j entry of a row stays in a register)
         for (int i = j + 1 + tid; i < m; i += NT) {
-            const double lij = W[i + j * ldw];
+            const R lij = W[i + j * ldw];
             int k = j + 1;
             for (; k + 4 <= i + 1; k += 4) {
-                double t[4];
+                R t[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) t[u] = W[(k + u) + j * ldw];
 #pragma unroll
@@ -65,13 +66,13 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     }
     // X = L^{-1} in place, columns right to left
     for (int j = m - 1; j >= 0; --j) {
-        if (tid == 0) W[j + j * ldw] = 1.0 / W[j + j * ldw];
+        if (tid == 0) W[j + j * ldw] = R(1) / W[j + j * ldw];
         __syncthreads();
-        const double ajj = -W[j + j * ldw];
-        double y = 0.0;
+        const R ajj = -W[j + j * ldw];
+        R y = R(0);
         const int i = j + 1 + tid;         // m <= PIV_LDS_MAX < NT: at most one row per thread
         if (i < m) {
-            double a[4] = {0, 0, 0, 0};
+            R a[4] = {0, 0, 0, 0};
             int l = j + 1;
             for (; l + 4 <= i + 1; l += 4) {
 #pragma unroll
@@ -88,7 +89,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     for (int e = tid; e < m * m; e += NT) {
         const int i = e % m, j = e / m;
         if (i < j) continue;
-        double s = 0.0;
+        R s = R(0);
         for (int k = i; k < m; ++k) s += W[k + i * ldw] * W[k + j * ldw];
         Ainv[i + size_t(j) * T.ldi] = s;
         Ainv[j + size_t(i) * T.ldi] = s;
@@ -102,17 +103,18 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
 // factorisation keeps each column unscaled until the end (updates use a_rj a_cj / d_j),
 // and the inverse solves L X = I by columns, one barrier per step. Sets *bad on a
 // non-positive pivot (every thread sees the same pivot, so all leave together).
-__device__ void block_potrf_trinv32(double* P, int ldp, int nb, double* X11, int* bad) {
+template <typename R>
+__device__ void block_potrf_trinv32(R* P, int ldp, int nb, R* X11, int* bad) {
     constexpr int l11 = PIV_NB + 1;
     const int r = threadIdx.x % PIV_NB, cb = threadIdx.x / PIV_NB;
     for (int j = 0; j < nb; ++j) {
-        const double dj = P[j + j * ldp];
-        if (!(dj > 0.0) || !isfinite(dj)) {
+        const R dj = P[j + j * ldp];
+        if (!(dj > R(0)) || !isfinite(dj)) {
             if (threadIdx.x == 0) *bad = 1;
             return;                                 // uniform: every thread read the same dj
         }
-        const double idj = 1.0 / dj;
-        const double arj = (r < nb) ? P[r + j * ldp] : 0.0;
+        const R idj = R(1) / dj;
+        const R arj = (r < nb) ? P[r + j * ldp] : R(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int c = cb + 8 * k;
@@ -121,11 +123,11 @@ __device__ void block_potrf_trinv32(double* P, int ldp, int nb, double* X11, int
         __syncthreads();
     }
     // scale: L(r, c) = a_rc / sqrt(d_c), L(c, c) = sqrt(d_c); X11 = I
-    double l[4];
+    R l[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = cb + 8 * k;
-        l[k] = 0.0;
+        l[k] = R(0);
         if (r < nb && c < nb && c <= r) l[k] = (r == c) ? sqrt(P[c + c * ldp]) : P[r + c * ldp] / sqrt(P[c + c * ldp]);
     }
     __syncthreads();
@@ -133,13 +135,13 @@ __device__ void block_potrf_trinv32(double* P, int ldp, int nb, double* X11, int
     for (int k = 0; k < 4; ++k) {
         const int c = cb + 8 * k;
         if (r < nb && c < nb && c <= r) P[r + c * ldp] = l[k];
-        X11[r + c * l11] = (r == c && r < nb) ? 1.0 : 0.0;
+        X11[r + c * l11] = (r == c && r < nb) ? R(1) : R(0);
     }
     __syncthreads();
     // forward substitution L X = I, columns in parallel; row j of X is scaled at the end
     for (int j = 0; j < nb; ++j) {
-        const double ilj = 1.0 / P[j + j * ldp];
-        const double lrj = (r > j && r < nb) ? P[r + j * ldp] : 0.0;
+        const R ilj = R(1) / P[j + j * ldp];
+        const R lrj = (r > j && r < nb) ? P[r + j * ldp] : R(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int c = cb + 8 * k;
@@ -157,16 +159,16 @@ __device__ void block_potrf_trinv32(double* P, int ldp, int nb, double* X11, int
 
 // rows [i_begin, i_end) of P (column-major, ld ldp): P(i, :) <- P(i, :) X11^T (trans) or
 // P(i, :) X11, X11 a full PIV_NB x PIV_NB matrix in LDS; the row is held in registers
-template <bool TRANS>
-__device__ inline void rows_times_x11(double* P, int ldp, int i_begin, int i_end, int nb, const double* X11) {
+template <bool TRANS, typename R>
+__device__ inline void rows_times_x11(R* P, int ldp, int i_begin, int i_end, int nb, const R* X11) {
     constexpr int l11 = PIV_NB + 1;
     for (int i = i_begin + threadIdx.x; i < i_end; i += NT) {
-        double a[PIV_NB];
+        R a[PIV_NB];
 #pragma unroll
-        for (int l = 0; l < PIV_NB; ++l) a[l] = (l < nb) ? P[i + l * ldp] : 0.0;
+        for (int l = 0; l < PIV_NB; ++l) a[l] = (l < nb) ? P[i + l * ldp] : R(0);
 #pragma unroll 1
         for (int c = 0; c < nb; ++c) {
-            double s = 0.0;
+            R s = R(0);
 #pragma unroll
             for (int l = 0; l < PIV_NB; ++l) s += a[l] * (TRANS ? X11[c + l * l11] : X11[l + c * l11]);
             P[i + c * ldp] = s;
@@ -174,15 +176,18 @@ __device__ inline void rows_times_x11(double* P, int ldp, int i_begin, int i_end
     }
 }
 
+template <typename R>
 __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int* fail) {
-    extern __shared__ double Pn[];                  // panel / Y buffer, PIV_PANEL doubles
-    __shared__ double X11[PIV_NB * (PIV_NB + 1)];
+    typedef Mma<R> MM;
+    extern __shared__ double lds_raw[];             // typed double: 8-byte aligned LDS accesses
+    R* Pn = reinterpret_cast<R*>(lds_raw);          // panel / Y buffer, PIV_PANEL elements
+    __shared__ R X11[PIV_NB * (PIV_NB + 1)];
     __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
     constexpr int l11 = PIV_NB + 1;
-    HS_G double* W = gp(T.work);                   // m x m, ld m
-    const HS_G double* A = gp(T.A);
+    HS_G R* W = gp(static_cast<R*>(T.work));       // m x m, ld m
+    const HS_G R* A = gp(static_cast<const R*>(T.A));
     auto stamp = [&](int k) {
         if (T.tstamp && tid == 0) T.tstamp[k] = clock64();
     };
@@ -224,9 +229,9 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             const int li = lane % 16, lk = lane / 16;
             const int qr = 32 * (wv % 2), qc = 32 * (wv / 2);
             const int ksteps = (nb + 3) / 4;
-            HS_G double* W22 = W + (jb + nb) + (jb + nb) * ld;
-            int rr[2], cc[2][4];
-            dbl4 nxt[2][2];
+            HS_G R* W22 = W + (jb + nb) + (jb + nb) * ld;
+            int rr[2], cc[2][4], cbase[2];
+            typename MM::acc nxt[2][2];
             auto tile_pos = [&](int bt) {
                 int bj = 0, rem = bt;                 // column-major order of the lower tiles
                 while (rem >= Tb - bj) {
@@ -237,9 +242,11 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
 #pragma unroll
                 for (int x = 0; x < 2; ++x) rr[x] = 64 * bi + qr + 16 * x + li;
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < 2; ++y) {
+                    cbase[y] = 64 * bj + qc + 16 * y;
 #pragma unroll
-                    for (int u = 0; u < 4; ++u) cc[y][u] = 64 * bj + qc + 16 * y + lk + 4 * u;
+                    for (int u = 0; u < 4; ++u) cc[y][u] = cbase[y] + MM::row(lane, u);
+                }
             };
             auto load_tile = [&]() {
 #pragma unroll
@@ -255,8 +262,8 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                 load_tile();
             }
             for (int bt = 0; bt < ntile; ++bt) {
-                dbl4 acc[2][2];
-                int r_cur[2], c_cur[2][4];
+                typename MM::acc acc[2][2];
+                int r_cur[2], c_cur[2][4], cb_cur[2];
 #pragma unroll
                 for (int x = 0; x < 2; ++x) {
                     r_cur[x] = rr[x];
@@ -264,12 +271,14 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                     for (int y = 0; y < 2; ++y) acc[x][y] = nxt[x][y];
                 }
 #pragma unroll
-                for (int y = 0; y < 2; ++y)
+                for (int y = 0; y < 2; ++y) {
+                    cb_cur[y] = cbase[y];
 #pragma unroll
                     for (int u = 0; u < 4; ++u) c_cur[y][u] = cc[y][u];
+                }
                 int sa[2], rb[2];                       // panel rows of this lane's operands
 #pragma unroll
-                for (int y = 0; y < 2; ++y) sa[y] = nb + min(c_cur[y][0] - lk + li, t - 1);
+                for (int y = 0; y < 2; ++y) sa[y] = nb + min(cb_cur[y] + li, t - 1);
 #pragma unroll
                 for (int x = 0; x < 2; ++x) rb[x] = nb + min(r_cur[x], t - 1);
                 if (bt + 1 < ntile) {
@@ -280,16 +289,15 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                     const int k = 4 * ks + lk;
                     const bool kv = k < nb;
                     const int kc = kv ? k : 0;
-                    double a[2], b[2];
+                    R a[2], b[2];
 #pragma unroll
-                    for (int y = 0; y < 2; ++y) a[y] = kv ? -Pn[sa[y] + kc * r] : 0.0;
+                    for (int y = 0; y < 2; ++y) a[y] = kv ? -Pn[sa[y] + kc * r] : R(0);
 #pragma unroll
-                    for (int x = 0; x < 2; ++x) b[x] = kv ? Pn[rb[x] + kc * r] : 0.0;
+                    for (int x = 0; x < 2; ++x) b[x] = kv ? Pn[rb[x] + kc * r] : R(0);
 #pragma unroll
                     for (int x = 0; x < 2; ++x)
 #pragma unroll
-                        for (int y = 0; y < 2; ++y)
-                            acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[y], b[x], acc[x][y], 0, 0, 0);
+                        for (int y = 0; y < 2; ++y) acc[x][y] = MM::mac(a[y], b[x], acc[x][y]);
                 }
 #pragma unroll
                 for (int x = 0; x < 2; ++x)
@@ -316,7 +324,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
         if (t == 0) continue;                      // the last diagonal block holds X11 already
         for (int e = tid; e < PIV_NB * PIV_NB; e += NT) {
             const int i = e % PIV_NB, c = e / PIV_NB;
-            X11[i + c * l11] = (i < nb && c < nb && i >= c) ? W[(jb + i) + (jb + c) * ld] : 0.0;
+            X11[i + c * l11] = (i < nb && c < nb && i >= c) ? W[(jb + i) + (jb + c) * ld] : R(0);
         }
         copy_block(Pn, t, W + (jb + nb) + jb * ld, ld, t, nb);
         __syncthreads();
@@ -331,22 +339,22 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
         {
             const int lane = tid % WAVE, wv = tid / WAVE;
             const int li = lane % 16, lk = lane / 16;
-            const HS_G double* X22 = W + (jb + nb) + (jb + nb) * ld;
+            const HS_G R* X22 = W + (jb + nb) + (jb + nb) * ld;
             for (int i0 = 0; i0 < t; i0 += 64) {
                 const int i = i0 + 16 * wv + li;             // this lane's row (operand B)
                 const int ic = min(i, t - 1);
                 const int kend = min(i0 + 64, t);
                 const int nks = (kend + 3) / 4;
-                dbl4 acc[2] = {dbl4{0.0, 0.0, 0.0, 0.0}, dbl4{0.0, 0.0, 0.0, 0.0}};
+                typename MM::acc acc[2] = {MM::zero(), MM::zero()};
                 auto ldb = [&](int ks) {
                     const int l = 4 * ks + lk;
-                    return (l < kend && l <= i && i < t) ? X22[ic + size_t(min(l, t - 1)) * ld] : 0.0;
+                    return (l < kend && l <= i && i < t) ? X22[ic + size_t(min(l, t - 1)) * ld] : R(0);
                 };
-                double bq[4];
+                R bq[4];
 #pragma unroll
                 for (int q = 0; q < 4; ++q) bq[q] = ldb(q);
                 for (int ks0 = 0; ks0 < nks; ks0 += 4) {
-                    double bc[4];
+                    R bc[4];
 #pragma unroll
                     for (int q = 0; q < 4; ++q) bc[q] = bq[q];
 #pragma unroll
@@ -358,8 +366,8 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
 #pragma unroll
                         for (int y = 0; y < 2; ++y) {
                             const int c = 16 * y + li;
-                            const double av = (l < kend && c < nb) ? Pn[lc + min(c, nb - 1) * t] : 0.0;
-                            acc[y] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bc[q], acc[y], 0, 0, 0);
+                            const R av = (l < kend && c < nb) ? Pn[lc + min(c, nb - 1) * t] : R(0);
+                            acc[y] = MM::mac(av, bc[q], acc[y]);
                         }
                     }
                 }
@@ -367,7 +375,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                 for (int y = 0; y < 2; ++y)
 #pragma unroll
                     for (int u = 0; u < 4; ++u) {
-                        const int c = 16 * y + lk + 4 * u;
+                        const int c = 16 * y + MM::row(lane, u);
                         if (i < t && c < nb) W[(jb + nb + i) + (jb + c) * ld] = -acc[y][u];
                     }
             }
@@ -377,31 +385,36 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     // upper triangle of X is zero for the product X^T X
     for (size_t e = tid; e < ld * m; e += NT) {
         const size_t i = e % ld, j = e / ld;
-        if (i < j) W[e] = 0.0;
+        if (i < j) W[e] = R(0);
     }
     stamp(3);
 }
 
+template <typename R>
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s) {
     if (ntasks <= 0) return;
     if (max_m > PIV_MAX) throw Error{HSOLVE_ERR_INVALID, "pivot block larger than 512"};
-    ProfScope ps(lds ? "k_chol_inv" : "k_chol_inv_blk", flops, s);
+    const bool f32 = sizeof(R) == 4;
+    ProfScope ps(lds ? (f32 ? "k_chol_inv_f32" : "k_chol_inv") : (f32 ? "k_chol_inv_blk_f32" : "k_chol_inv_blk"),
+                 flops, s);
     if (lds) {
         if (max_m > PIV_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS pivot too large"};
-        const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(double);
+        const size_t bytes = size_t(max_m) * (max_m + 1) * sizeof(R);
         static std::once_flag once;
-        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv),
-                      size_t(PIV_LDS_MAX) * (PIV_LDS_MAX + 1) * sizeof(double));
-        hipLaunchKernelGGL(k_chol_inv, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
+        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv<R>),
+                      size_t(PIV_LDS_MAX) * (PIV_LDS_MAX + 1) * sizeof(R));
+        hipLaunchKernelGGL(k_chol_inv<R>, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
         check_launch("k_chol_inv");
     } else {
-        const size_t bytes = size_t(PIV_PANEL) * sizeof(double);
+        const size_t bytes = size_t(PIV_PANEL) * sizeof(R);
         static std::once_flag once;
-        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv_blk), bytes);
-        hipLaunchKernelGGL(k_chol_inv_blk, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
+        set_lds_limit(once, reinterpret_cast<const void*>(&k_chol_inv_blk<R>), bytes);
+        hipLaunchKernelGGL(k_chol_inv_blk<R>, dim3(ntasks), dim3(NT), bytes, s, d_tasks, d_fail);
         check_launch("k_chol_inv_blk");
     }
 }
+template void launch_chol_inv<double>(const CholTask*, int, int*, double, bool, int, hipStream_t);
+template void launch_chol_inv<float>(const CholTask*, int, int*, double, bool, int, hipStream_t);
 
 }  // namespace hs

@@ -47,7 +47,7 @@ void build_apply_schedule(Plan& P) {
     const double w = P.apply32 ? 4.0 : 8.0;
     auto grow = [&](const NodeNum& nn, int row) -> const void* {
         if (P.apply32) return nn.Gm32 + row;
-        return nn.Gm + row;
+        return static_cast<const double*>(nn.Gm) + row;
     };
     double bytes = 0.0;
     P.sched.assign(nlev, {});

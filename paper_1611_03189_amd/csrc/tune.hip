@@ -14,7 +14,7 @@
 namespace hs {
 
 namespace {
-std::atomic<int> g_variant[GEMM_BUCKETS];   // zero-initialised: the 64 x 64 x 16 shape
+std::atomic<int> g_variant[2][GEMM_BUCKETS];   // [FP64, FP32]; zero-initialised: 64 x 64 x 16
 
 constexpr int TILE_REP[GEMM_TILE_BUCKETS] = {16, 128, 1024, 4096};   // 64 x 64 tiles per launch
 constexpr int K_REP[GEMM_K_BUCKETS] = {32, 160, 512};
@@ -27,14 +27,14 @@ int gemm_bucket(double tiles64, double mean_k) {
     return tb * GEMM_K_BUCKETS + kb;
 }
 
-int gemm_variant(int bucket) {
+int gemm_variant(int bucket, bool f32) {
     if (bucket < 0 || bucket >= GEMM_BUCKETS) return 0;
-    return g_variant[bucket].load(std::memory_order_relaxed);
+    return g_variant[f32][bucket].load(std::memory_order_relaxed);
 }
 
-void set_gemm_variant(int bucket, int variant) {
+void set_gemm_variant(int bucket, bool f32, int variant) {
     if (bucket >= 0 && bucket < GEMM_BUCKETS && variant >= 0 && variant < GEMM_VARIANTS)
-        g_variant[bucket].store(variant, std::memory_order_relaxed);
+        g_variant[f32][bucket].store(variant, std::memory_order_relaxed);
 }
 
 size_t tune_workspace_bytes() {
@@ -44,18 +44,17 @@ size_t tune_workspace_bytes() {
            (size_t(4) << 20);
 }
 
-// Times every shape on every bucket; ms[b * GEMM_VARIANTS + v] receives the best of three
-// launches, choice[b] the fastest shape (also stored for the process).
+// Times every shape on every bucket, in FP64 and then in FP32 (the FP32 factorization's
+// GEMMs); ms[(t * GEMM_BUCKETS + b) * GEMM_VARIANTS + v] receives the best of three launches,
+// choice[t * GEMM_BUCKETS + b] the fastest shape (also stored for the process), t = 0 FP64,
+// 1 FP32.
+template <typename T>
+static void tune_type(char* w, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int* choice, double* ms);
+
 void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* ms) {
     if (bytes < tune_workspace_bytes())
         throw Error{HSOLVE_ERR_OOM, "tuning workspace too small: needs " + std::to_string(tune_workspace_bytes())};
     char* w = static_cast<char*>(d_work);
-    const int kmax = K_REP[GEMM_K_BUCKETS - 1];
-    double* A = reinterpret_cast<double*>(w);
-    double* B = A + 32 * size_t(TASK_M) * kmax;
-    double* C = B + 32 * size_t(TASK_M) * kmax;
-    char* tables = reinterpret_cast<char*>(C + size_t(TILE_REP[GEMM_TILE_BUCKETS - 1]) / 4 * TASK_M * TASK_M);
-    launch_fill<double>(A, 0.5, 64 * int64_t(TASK_M) * kmax, st);
     hipEvent_t e0, e1;
     HS_HIP(hipEventCreate(&e0));
     HS_HIP(hipEventCreate(&e1));
@@ -63,6 +62,23 @@ void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* 
         hipEvent_t a, b;
         ~Ev() { (void)hipEventDestroy(a); (void)hipEventDestroy(b); }
     } ev{e0, e1};
+    tune_type<double>(w, st, e0, e1, choice, ms);
+    tune_type<float>(w, st, e0, e1, choice ? choice + GEMM_BUCKETS : nullptr,
+                     ms ? ms + GEMM_BUCKETS * GEMM_VARIANTS : nullptr);
+    HS_HIP(hipStreamSynchronize(st));
+}
+
+
+template <typename T>
+static void tune_type(char* w, hipStream_t st, hipEvent_t e0, hipEvent_t e1, int* choice, double* ms) {
+    constexpr bool F32 = sizeof(T) == 4;
+    const int kmax = K_REP[GEMM_K_BUCKETS - 1];
+    T* A = reinterpret_cast<T*>(w);
+    T* B = A + 32 * size_t(TASK_M) * kmax;
+    T* C = B + 32 * size_t(TASK_M) * kmax;
+    char* tables = reinterpret_cast<char*>(C + size_t(TILE_REP[GEMM_TILE_BUCKETS - 1]) / 4 * TASK_M * TASK_M);
+    launch_fill<T>(A, T(0.5), 64 * int64_t(TASK_M) * kmax, st);
+    launch_fill<T>(C, T(0), int64_t(TILE_REP[GEMM_TILE_BUCKETS - 1]) / 4 * TASK_M * TASK_M, st);
     for (int tb = 0; tb < GEMM_TILE_BUCKETS; ++tb)
         for (int kb = 0; kb < GEMM_K_BUCKETS; ++kb) {
             const int bucket = tb * GEMM_K_BUCKETS + kb;
@@ -90,11 +106,11 @@ void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* 
                 const auto* dt = reinterpret_cast<const GemmTask*>(tables);
                 const auto* dm = reinterpret_cast<const GemmTerm*>(tables + o1);
                 const auto* dl = reinterpret_cast<const GemmTile*>(tables + o2);
-                launch_gemm(dt, dm, dl, int(tl.size()), 0.0, v, st);      // warm-up
+                launch_gemm<T>(dt, dm, dl, int(tl.size()), 0.0, v, st);      // warm-up
                 float t_best = 1e30f;
                 for (int rep = 0; rep < 3; ++rep) {
                     HS_HIP(hipEventRecord(e0, st));
-                    launch_gemm(dt, dm, dl, int(tl.size()), 0.0, v, st);
+                    launch_gemm<T>(dt, dm, dl, int(tl.size()), 0.0, v, st);
                     HS_HIP(hipEventRecord(e1, st));
                     HS_HIP(hipEventSynchronize(e1));
                     float t = 0.f;
@@ -107,10 +123,9 @@ void tune_gemm(void* d_work, size_t bytes, hipStream_t st, int* choice, double* 
                     arg = v;
                 }
             }
-            set_gemm_variant(bucket, arg);
+            set_gemm_variant(bucket, F32, arg);
             if (choice) choice[bucket] = arg;
         }
-    HS_HIP(hipStreamSynchronize(st));
 }
 
 }  // namespace hs

@@ -175,21 +175,24 @@ def tune_gemm(stream=None) -> dict:
     import torch
     lib = load()
     work = torch.empty(int(lib.hsolve_tune_workspace_bytes()), dtype=torch.uint8, device="cuda")
-    choice = np.zeros(GEMM_BUCKETS, dtype=np.int32)
-    ms = np.zeros(GEMM_BUCKETS * len(GEMM_SHAPES))
+    choice = np.zeros(2 * GEMM_BUCKETS, dtype=np.int32)
+    ms = np.zeros(2 * GEMM_BUCKETS * len(GEMM_SHAPES))
     _check(lib.hsolve_tune_gemm(c_void_p(work.data_ptr()), work.numel(),
                                 c_void_p(stream.cuda_stream) if stream is not None else None,
                                 _i32p(choice), ms.ctypes.data_as(POINTER(c_double))), "hsolve_tune_gemm")
     torch.cuda.synchronize()
     del work
-    return {"choice": choice.tolist(), "shapes": [list(x) for x in GEMM_SHAPES],
-            "ms": ms.reshape(GEMM_BUCKETS, len(GEMM_SHAPES)).round(4).tolist()}
+    return {"choice": choice[:GEMM_BUCKETS].tolist(), "choice_f32": choice[GEMM_BUCKETS:].tolist(),
+            "shapes": [list(x) for x in GEMM_SHAPES],
+            "ms": ms[:GEMM_BUCKETS * len(GEMM_SHAPES)].reshape(GEMM_BUCKETS, len(GEMM_SHAPES)).round(4).tolist(),
+            "ms_f32": ms[GEMM_BUCKETS * len(GEMM_SHAPES):].reshape(GEMM_BUCKETS, len(GEMM_SHAPES)).round(4).tolist()}
 
 
-def set_gemm_choice(choice) -> None:
-    """Install a tile-shape choice per bucket (e.g. one saved from tune_gemm)."""
-    c = np.ascontiguousarray(choice, dtype=np.int32)
-    if c.shape != (GEMM_BUCKETS,):
+def set_gemm_choice(choice, choice_f32=None) -> None:
+    """Install a tile-shape choice per bucket (e.g. one saved from tune_gemm) for the FP64
+    GEMMs and, given or else the same, the FP32 ones."""
+    c = np.ascontiguousarray(list(choice) + list(choice if choice_f32 is None else choice_f32), dtype=np.int32)
+    if c.shape != (2 * GEMM_BUCKETS,):
         raise ValueError(f"expected {GEMM_BUCKETS} entries")
     _check(load().hsolve_set_gemm_choice(_i32p(c)), "hsolve_set_gemm_choice")
 

@@ -93,8 +93,9 @@ class RequestLoop:
     run the symbolic analyses as requests arrive."""
 
     def __init__(self, slots: int = 4, memory_budget: int | None = None, overlap_pivots: bool = False,
-                 analysers: int = 2, solver_factory=None):
+                 analysers: int = 2, solver_factory=None, mixed: bool = False):
         self.slots = slots
+        self.mixed = mixed          # FP32 factorization inside FP64 flexible PCG
         self.overlap_pivots = overlap_pivots
         self.analysers = max(1, analysers)
         self._factory = solver_factory
@@ -108,8 +109,9 @@ class RequestLoop:
     def _solver(self, r: Request):
         if self._factory is not None:
             return self._factory(r)
+        kw = dict(factor_prec=32, krylov="fpcg") if self.mixed else {}
         return H.HSolver(r.row_ptr, r.col_idx, coords=r.coords, leaf=r.leaf, eps=r.eps, variant=r.variant,
-                         tol=1e-10, overlap_pivots=self.overlap_pivots, max_nrhs=max(1, r.b.shape[1]))
+                         tol=1e-10, overlap_pivots=self.overlap_pivots, max_nrhs=max(1, r.b.shape[1]), **kw)
 
     def _execute(self, S, r: Request, stream):
         """Factor and solve one admitted request on `stream`; returns (x, stats, device bytes)."""

@@ -128,7 +128,8 @@ def test_new_options_are_checked(lib):
         assert e.value.status == -1, kw
     for kw in ({"eps_schedule": "shrink"}, {"eps_schedule": "grow"}, {"cmp_lpe": 8, "cmp_vectors": 1},
                {"cmp_lpe": 1, "cmp_vectors": 2}, {"max_super": 64, "max_nrhs": 4},
-               {"variant": "gc_proj1", "eps1": 1e-2}, {"neighbours": "geometric"}):
+               {"variant": "gc_proj1", "eps1": 1e-2}, {"neighbours": "geometric"},
+               {"factor_prec": 32, "krylov": "fpcg"}):
         with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
             assert S.arena_bound > 0
 

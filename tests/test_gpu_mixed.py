@@ -197,3 +197,58 @@ def test_stationary_iteration(name, N, dim, leaf):
         assert np.linalg.norm(b[:, c] - A @ x[:, c]) <= 2 * TOL * np.linalg.norm(b[:, c])
     assert st["converged"] and abs(st["iterations"] - max(its_ref)) <= 1, (st, its_ref)
     S.close()
+
+
+@pytest.mark.parametrize("name,make,leaf,N,dim", [
+    ("c1_poisson2d_32_leaf16", lambda: pb.poisson(32, 2), 16, 32, 2),
+    ("poisson3d_16_leaf64", lambda: pb.poisson(16, 3), 64, 16, 3),
+    ("poisson2d_64_leaf256", lambda: pb.poisson(64, 2), 256, 64, 2),
+])
+def test_fp32_factorization_against_oracle(name, make, leaf, N, dim):
+    """factor_prec = 32: blocks, pivots and GEMMs in FP32 (the eigen-solver reads the FP32
+    Gram matrix in FP64). Stated per case: the ranks (equal to the oracle's on these cases),
+    ||z32 - z_oracle|| / ||z_oracle|| within 20 kappa(A) u32 (the FP32 chain of dense products,
+    kappa(A_H) ~ kappa(A) by Example 1) and above FP64 rounding, and flexible PCG in FP64
+    reaching the 1e-10 true residual in at most two more iterations than FP64 PCG."""
+    say("fp32 factor", name)
+    p = make()
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=1e-2, variant=O.GC)
+    r = pb.rhs(p.n, 2, 31)
+    z_ref = O.apply(F, r)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2, factor_prec=32, krylov="fpcg")
+    S.profile_begin()
+    S.factor(dev(p.values))
+    names = {e["name"] for e in S.profile_end()}
+    assert {"k_gemm_f32", "k_promote"} <= names and "k_gemm" in names     # FP64 only in the basis step
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), (name, d)
+    z = S.apply(dev(r)).cpu().numpy()
+    bar = 20.0 * kappa_poisson(N, dim) * U32
+    e = rel(z, z_ref)
+    say("fp32 factor", name, "rel", e, "bar", bar)
+    assert 1e-12 < e <= bar, (e, bar)
+    b = pb.rhs(p.n, 1, 2001)[:, 0]
+    x, st = S.solve(dev(b))
+    true_rel = np.linalg.norm(b - p.to_scipy() @ x.cpu().numpy()) / np.linalg.norm(b)
+    S64 = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2)
+    S64.factor(dev(p.values))
+    x64, st64 = S64.solve(dev(b))
+    say("fp32 factor", name, "fpcg", st["iterations"], "fp64 pcg", st64["iterations"], "true", true_rel)
+    assert st["converged"] and true_rel <= 2 * TOL and st["iterations"] <= st64["iterations"] + 2
+    assert rel(x.cpu().numpy(), x64.cpu().numpy()) <= 1e-8
+    S.close()
+    S64.close()
+
+
+def test_fp32_factorization_gmres_and_columns():
+    say("fp32 factor gmres / columns")
+    p = pb.lognormal(40, 2, 1.0, 71)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=16, eps=1e-2, factor_prec=32, krylov="gmres")
+    S.factor(dev(p.values))
+    B = pb.rhs(p.n, 3, 5)
+    X, st = S.solve(dev(B))
+    res = np.linalg.norm(B - p.to_scipy() @ X.cpu().numpy(), axis=0) / np.linalg.norm(B, axis=0)
+    assert st["converged"] and np.all(res <= 2 * TOL)
+    Z = S.apply(dev(B)).cpu().numpy()
+    assert np.array_equal(S.apply(dev(B[:, 2])).cpu().numpy(), Z[:, 2])
+    S.close()

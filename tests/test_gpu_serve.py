@@ -56,3 +56,19 @@ def test_request_loop_admission_respects_budget():
     assert len(out.results) == 3 and all(r.converged for r in out.results)
     spans = sorted((r.t_start, r.t_done) for r in out.results)
     assert all(spans[i][1] <= spans[i + 1][0] + 1e-6 for i in range(len(spans) - 1))
+
+
+def test_request_loop_mixed_precision_alone_and_in_mix():
+    """The served mixed form (FP32 factorization, FP64 flexible PCG): the same bits alone and in
+    the mix, every result at the 1e-10 true residual."""
+    say("serve_mixed")
+    import scipy.sparse as sp
+    from paper_1611_03189_amd.serve import RequestLoop
+    reqs = _requests()
+    alone = RequestLoop(slots=1, mixed=True).run(reqs, realtime=False)
+    mix = RequestLoop(slots=4, mixed=True).run(reqs, realtime=False)
+    for q, a, m in zip(reqs, alone.results, mix.results):
+        assert np.array_equal(a.x, m.x) and a.converged and m.converged
+        A = sp.csr_matrix((q.values, q.col_idx, q.row_ptr), shape=(q.n, q.n))
+        res = np.linalg.norm(q.b - A @ m.x, axis=0) / np.linalg.norm(q.b, axis=0)
+        assert np.all(res <= 2e-10), res
