@@ -240,11 +240,12 @@ __device__ inline double wave_sum_last(double v) {
 // One wave's share of y = A v: columns [cb, ce) of the len x len matrix at A (column
 // stride ld, len >= 2). Lane l takes the row pairs (r, r + 1), r = 2l + rofs + rstep k, k < KM,
 // loaded as one 16-byte access; SB columns are taken at a time with every load issued before
-// the products. Pairs that start past len - 2 are clamped to (len - 2, len - 1).
+// the products (16 / KM columns, at least 4: about 32 values per lane per round). Pairs
+// that start past len - 2 are clamped to (len - 2, len - 1).
 template <int KM>
 __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, int len, int cb, int ce,
                                  int lane, int rofs, int rstep, double* acc) {
-    constexpr int SB = (KM == 1) ? 16 : 8;
+    constexpr int SB = (16 / KM > 4) ? 16 / KM : 4;
 #pragma unroll
     for (int k = 0; k < 8; ++k) acc[k] = 0.0;
     int rr[KM];
@@ -278,12 +279,12 @@ __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, 
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
 // matrix takes the rank-2 nb update once per panel. LDS: Vl, Wl (TRI_NB x nn, column c
-// at c nn, absolute rows) and Pp (4 x nn partial products of the matrix-vector step).
+// at c nn, absolute rows) and Pp (waves x nn partial products of the matrix-vector step).
 template <class SH>
 __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double* Bl, int bst, int nbr,
                                    double* Vl, double* Wl, double* Pp, long long* prof = nullptr) {
-    constexpr int NTH = SH::nth;
-    const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    constexpr int NTH = SH::nth, NW = NTH / WAVE;
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
     const int nref = nn - 2;
     int parity = 0;
     long long pc[8] = {0, 0, 0, 0, 0, 0, 0, 0}, tprev = 0;   // trace: cycles per phase
@@ -347,33 +348,34 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                     a = wave_sum_last(a);
                     if (lane == WAVE - 1) S.tt[g] = a;
                 }
-                // y = A(j+1:, j+1:) v: the columns in 4 groups, the 128-row blocks dealt round
-                // robin to the RG waves of a group, row pairs over the lanes; partial sums of
-                // column group g in Pp(g nn + r)
+                // y = A(j+1:, j+1:) v: the columns in one group per wave, each over all rows
+                // (row pairs over the lanes, 128-row blocks in the same round of loads);
+                // partial sums of column group g in Pp(g nn + r)
                 {
-                    constexpr int RG = NTH / WAVE / 4, KMX = (4 + RG - 1) / RG;
-                    const int cg = wv % 4, rg = wv / 4;
                     const HS_G double* A0 = H + size_t(j + 1) * ld + (j + 1);
-                    const int cw = (len + 3) / 4, cbeg = cg * cw, cend = min(len, cbeg + cw);
+                    const int cw = (len + NW - 1) / NW, cbeg = wv * cw, cend = min(len, cbeg + cw);
                     const int kb = (len + 127) / 128;                // row blocks (at most 4)
-                    const int km = (kb > rg) ? (kb - rg + RG - 1) / RG : 0;   // this wave's, uniform
                     double acc[8];
-                    switch (km) {
-                        case 0: break;
-                        case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
-                        case 2: symv_part<(KMX < 2 ? KMX : 2)>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
-                        case 3: symv_part<(KMX < 3 ? KMX : 3)>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
-                        default: symv_part<KMX>(A0, ld, v, len, cbeg, cend, lane, 128 * rg, 128 * RG, acc); break;
+                    if (cbeg < cend) {
+                        switch (kb) {
+                            case 1: symv_part<1>(A0, ld, v, len, cbeg, cend, lane, 0, 128, acc); break;
+                            case 2: symv_part<2>(A0, ld, v, len, cbeg, cend, lane, 0, 128, acc); break;
+                            case 3: symv_part<3>(A0, ld, v, len, cbeg, cend, lane, 0, 128, acc); break;
+                            default: symv_part<4>(A0, ld, v, len, cbeg, cend, lane, 0, 128, acc); break;
+                        }
+                    } else {
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) acc[k] = 0.0;
                     }
 #pragma unroll
-                    for (int k = 0; k < KMX; ++k) {
-                        const int r0 = 2 * lane + 128 * (rg + RG * k);
-                        if (k < km && r0 < len) {
+                    for (int k = 0; k < 4; ++k) {
+                        const int r0 = 2 * lane + 128 * k;
+                        if (k < kb && r0 < len) {
                             if (r0 <= len - 2) {
-                                Pp[cg * nn + r0] = acc[2 * k];
-                                Pp[cg * nn + r0 + 1] = acc[2 * k + 1];
+                                Pp[wv * nn + r0] = acc[2 * k];
+                                Pp[wv * nn + r0 + 1] = acc[2 * k + 1];
                             } else {                        // last row of an odd length
-                                Pp[cg * nn + r0] = acc[2 * k + 1];
+                                Pp[wv * nn + r0] = acc[2 * k + 1];
                             }
                         }
                     }
@@ -383,7 +385,9 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                 phase(2);
                 double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
                 for (int r = tid; r < len; r += NTH) {
-                    double y = (Pp[r] + Pp[nn + r]) + (Pp[2 * nn + r] + Pp[3 * nn + r]);
+                    double y = 0.0;
+#pragma unroll
+                    for (int g = 0; g < NW; ++g) y += Pp[g * nn + r];
 #pragma unroll
                     for (int c = 0; c < TRI_NB - 1; ++c)
                         if (c < i) y -= Vl[c * nn + j + 1 + r] * S.tt[c] + Wl[c * nn + j + 1 + r] * S.tt[i + c];
@@ -955,6 +959,11 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
     __syncthreads();
 }
 
+// dynamic LDS of the global-matrix compression: the blocked tridiagonalisation's Vl, Wl and
+// per-wave partial products, or the GC block reflection's V, Y, Wm (q <= 8) and q x q blocks
+constexpr int TRI_LDS_DOUBLES = (2 * TRI_NB + CMP_GLOBAL_NT / WAVE + 1) * CMP_MAX;
+static_assert(TRI_LDS_DOUBLES >= 3 * 8 * CMP_MAX + 4 * 64, "GC block reflection does not fit");
+
 template <bool LDS, int MAXN>
 __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
                                                     int* rank) {
@@ -975,7 +984,9 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
     HS_G double* U = gp(T.U);
     const HS_G double* G = gp(T.G);
     // Householder tridiagonalisation: unblocked in LDS, blocked for global matrices
-    auto tri = [&](HPtr A, int n, double* Bl, int nbr) {
+    // inlined, so that sizes and strides stay scalar (an outlined call passes them in vector
+    // registers and every branch on them becomes divergent)
+    auto tri = [&](HPtr A, int n, double* Bl, int nbr) __attribute__((always_inline)) {
         if constexpr (LDS) tridiagonalize(A, LDL, n, S, Bl, MAXN, nbr);
         else tridiagonalize_blk(A, ld, n, S, Bl, MAXN, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN,
                                 T.tstamp ? T.tstamp + 8 : nullptr);
@@ -1769,7 +1780,7 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
                                d_tasks, variant, eps, d_rank);
             check_launch("k_comp_reduce<lds>");
         } else {
-            const size_t bytes = size_t(2 * TRI_NB + 4) * CMP_MAX * sizeof(double);
+            const size_t bytes = size_t(TRI_LDS_DOUBLES) * sizeof(double);
             static std::once_flag once;
             set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>), bytes);
             hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(CMP_GLOBAL_NT), bytes, s, d_tasks,
