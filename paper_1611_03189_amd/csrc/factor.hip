@@ -137,20 +137,25 @@ struct Batch {
             if (part.empty()) continue;
             long long* d_stamp = nullptr;
             if (big && trace_pivots) {
-                d_stamp = P.spool.alloc_n<long long>(4 * part.size());
-                for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 4 * q;
+                d_stamp = P.spool.alloc_n<long long>(9 * part.size());
+                for (size_t q = 0; q < part.size(); ++q) part[q].tstamp = d_stamp + 9 * q;
             }
             CholTask* d = P.stage.upload_vec(part, P.spool, P.stream);
             if (!dry) launch_chol_inv<R>(d, int(part.size()), d_fail, flops, !big, max_m, to_side(P, side));
             if (d_stamp && !dry) {
                 if (side) HS_HIP(hipStreamSynchronize(P.side));
-                std::vector<long long> h(4 * part.size());
+                std::vector<long long> h(9 * part.size());
                 HS_HIP(hipMemcpy(h.data(), d_stamp, sizeof(long long) * h.size(), hipMemcpyDeviceToHost));
-                long long ph[3] = {0, 0, 0};
-                for (size_t q = 0; q < part.size(); ++q)
-                    for (int k = 0; k < 3; ++k) ph[k] = std::max(ph[k], h[4 * q + k + 1] - h[4 * q + k]);
-                std::fprintf(stderr, "    pivot batch n=%zu max_m=%d kcycles copy %lld chol %lld trinv %lld\n",
-                             part.size(), max_m, ph[0] / 1000, ph[1] / 1000, ph[2] / 1000);
+                long long ph[3] = {0, 0, 0}, pp[5] = {0, 0, 0, 0, 0};
+                for (size_t q = 0; q < part.size(); ++q) {
+                    for (int k = 0; k < 3; ++k) ph[k] = std::max(ph[k], h[9 * q + k + 1] - h[9 * q + k]);
+                    for (int k = 0; k < 5; ++k) pp[k] = std::max(pp[k], h[9 * q + 4 + k]);
+                }
+                std::fprintf(stderr,
+                             "    pivot batch n=%zu max_m=%d kcycles copy %lld chol %lld trinv %lld | panel: copy %lld "
+                             "l11 %lld l21 %lld wb %lld trail %lld\n",
+                             part.size(), max_m, ph[0] / 1000, ph[1] / 1000, ph[2] / 1000, pp[0] / 1000, pp[1] / 1000,
+                             pp[2] / 1000, pp[3] / 1000, pp[4] / 1000);
             }
             if (big) {      // A^{-1} = X^T X, X = L^{-1} left in the work matrices
                 for (const CholTask& c : part)

@@ -213,7 +213,7 @@ struct CholTask {            // in: A (m x m, SPD); out: Ainv (m x m) = A^{-1} (
     void* A;
     void* Ainv;
     void* work;              // m x m scratch for blocks too large for LDS (else null)
-    long long* tstamp;       // optional: 4 clock stamps at phase boundaries (trace only)
+    long long* tstamp;       // optional: 4 clock stamps at phase boundaries and 5 per-phase cycle sums of the panels (trace only)
     int lda, ldi, m, id;
 };
 

@@ -7,11 +7,13 @@
 //                inverse X = L^{-1} (column j = -(X22 l_j) / l_jj, right to left), then
 //                A^{-1} = X^T X written to both triangles.
 // k_chol_inv_blk larger blocks (up to PIV_MAX rows) in a global work matrix, blocked by
-//                PIV_NB columns: the current panel is factored in LDS, the trailing
-//                matrix is updated on the FP64 matrix cores; the inverse is blocked the
-//                same way (X21 = -X22 L21 X11, right to left, also on the matrix cores). X = L^{-1} is left in the
-//                work matrix (upper triangle zeroed) for the product A^{-1} = X^T X, which
-//                the caller forms with the grouped GEMM over many workgroups.
+//                PIV_NB columns: the panel's diagonal block is factored and inverted in
+//                one pass of steps in LDS, the panel below it (L21 = A21 L11^{-T}) and
+//                the trailing update run on the matrix cores; the inverse is blocked the same
+//                way (X21 = -X22 L21 X11, right to left, also on the matrix cores). X =
+//                L^{-1} is left in the work matrix (upper triangle zeroed) for the product
+//                A^{-1} = X^T X, which the caller forms with the grouped GEMM over many
+//                workgroups.
 #include "hs_device.h"
 
 namespace hs {
@@ -96,17 +98,24 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     }
 }
 
-
 // Cholesky of the nb x nb diagonal block at P (column-major, ld ldp, nb <= PIV_NB) in place
 // and its inverse in X11 (full PIV_NB x PIV_NB, zeros above the diagonal and outside nb), by
-// the whole workgroup: thread t owns the entries (t % 32, t / 32 + 8k), k < 4. The
-// factorisation keeps each column unscaled until the end (updates use a_rj a_cj / d_j),
-// and the inverse solves L X = I by columns, one barrier per step. Sets *bad on a
-// non-positive pivot (every thread sees the same pivot, so all leave together).
+// the whole workgroup: thread t owns the entries (t % 32, t / 32 + 8k), k < 4, of both. The
+// factorisation keeps each column unscaled until the end (updates use a_rj a_cj / d_j); the
+// forward substitution L X = I runs in the same steps, one barrier per step: at step j the
+// column l_j = a_j / sqrt(d_j) is final, so the rows r > j of X take -l_rj X(j, :) / l_jj,
+// and row r of X is divided by l_rr at the end. Sets *bad on a non-positive pivot (every
+// thread sees the same pivot, so all leave together).
 template <typename R>
 __device__ void block_potrf_trinv32(R* P, int ldp, int nb, R* X11, int* bad) {
     constexpr int l11 = PIV_NB + 1;
     const int r = threadIdx.x % PIV_NB, cb = threadIdx.x / PIV_NB;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const int c = cb + 8 * k;
+        X11[r + c * l11] = (r == c && r < nb) ? R(1) : R(0);
+    }
+    __syncthreads();
     for (int j = 0; j < nb; ++j) {
         const R dj = P[j + j * ldp];
         if (!(dj > R(0)) || !isfinite(dj)) {
@@ -115,64 +124,69 @@ __device__ void block_potrf_trinv32(R* P, int ldp, int nb, R* X11, int* bad) {
         }
         const R idj = R(1) / dj;
         const R arj = (r < nb) ? P[r + j * ldp] : R(0);
+        const R sdj = sqrt(dj), ilj = R(1) / sdj;
+        const R lrj = (r > j && r < nb) ? arj / sdj : R(0);
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
             const int c = cb + 8 * k;
             if (c > j && c <= r && r < nb) P[r + c * ldp] -= arj * P[c + j * ldp] * idj;
+            if (r > j && r < nb && c <= j) X11[r + c * l11] -= lrj * X11[j + c * l11] * ilj;
         }
         __syncthreads();
     }
-    // scale: L(r, c) = a_rc / sqrt(d_c), L(c, c) = sqrt(d_c); X11 = I
+    // scale: L(r, c) = a_rc / sqrt(d_c), L(c, c) = sqrt(d_c); X's rows by 1 / L(r, r)
+    const R sdr = (r < nb) ? sqrt(P[r + r * ldp]) : R(1);
     R l[4];
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = cb + 8 * k;
         l[k] = R(0);
-        if (r < nb && c < nb && c <= r) l[k] = (r == c) ? sqrt(P[c + c * ldp]) : P[r + c * ldp] / sqrt(P[c + c * ldp]);
+        if (r < nb && c < nb && c <= r) l[k] = (r == c) ? sdr : P[r + c * ldp] / sqrt(P[c + c * ldp]);
+        if (r < nb) X11[r + c * l11] /= sdr;
     }
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
         const int c = cb + 8 * k;
         if (r < nb && c < nb && c <= r) P[r + c * ldp] = l[k];
-        X11[r + c * l11] = (r == c && r < nb) ? R(1) : R(0);
-    }
-    __syncthreads();
-    // forward substitution L X = I, columns in parallel; row j of X is scaled at the end
-    for (int j = 0; j < nb; ++j) {
-        const R ilj = R(1) / P[j + j * ldp];
-        const R lrj = (r > j && r < nb) ? P[r + j * ldp] : R(0);
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const int c = cb + 8 * k;
-            if (r > j && r < nb && c <= j) X11[r + c * l11] -= lrj * X11[j + c * l11] * ilj;
-        }
-        __syncthreads();
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int c = cb + 8 * k;
-        if (r < nb) X11[r + c * l11] /= P[r + r * ldp];
     }
     __syncthreads();
 }
 
-// rows [i_begin, i_end) of P (column-major, ld ldp): P(i, :) <- P(i, :) X11^T (trans) or
-// P(i, :) X11, X11 a full PIV_NB x PIV_NB matrix in LDS; the row is held in registers
+// rows [i_begin, i_end) of P (column-major, ld ldp, nb <= PIV_NB columns): P(i, :) <-
+// P(i, :) X11^T (TRANS) or P(i, :) X11, X11 a full PIV_NB x PIV_NB matrix in LDS (zeros
+// outside nb), on the matrix cores: each wave takes blocks of 16 rows (blocks w, w + 4, ..)
+// as two 16 x 16 output blocks over K = 32 (lane l: operand A = P(i0 + l % 16, k), operand B
+// = the X11 entry of (k, column 16 y + l % 16), k = 4 s + l / 16). A block's rows are read
+// into the products before they are written back; rows past i_end are read clamped and not
+// stored.
 template <bool TRANS, typename R>
 __device__ inline void rows_times_x11(R* P, int ldp, int i_begin, int i_end, int nb, const R* X11) {
+    typedef Mma<R> MM;
     constexpr int l11 = PIV_NB + 1;
-    for (int i = i_begin + threadIdx.x; i < i_end; i += NT) {
-        R a[PIV_NB];
+    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int li = lane % 16, lk = lane / 16;
+    for (int i0 = i_begin + 16 * wv; i0 < i_end; i0 += 16 * (NT / WAVE)) {
+        const int ia = min(i0 + li, i_end - 1);
+        typename MM::acc acc[2] = {MM::zero(), MM::zero()};
 #pragma unroll
-        for (int l = 0; l < PIV_NB; ++l) a[l] = (l < nb) ? P[i + l * ldp] : R(0);
-#pragma unroll 1
-        for (int c = 0; c < nb; ++c) {
-            R s = R(0);
+        for (int s = 0; s < PIV_NB / 4; ++s) {
+            const int k = 4 * s + lk;
+            const R av = (k < nb) ? P[ia + k * ldp] : R(0);
 #pragma unroll
-            for (int l = 0; l < PIV_NB; ++l) s += a[l] * (TRANS ? X11[c + l * l11] : X11[l + c * l11]);
-            P[i + c * ldp] = s;
+            for (int y = 0; y < 2; ++y) {
+                const int c = 16 * y + li;
+                const R bv = TRANS ? X11[c + k * l11] : X11[k + c * l11];
+                acc[y] = MM::mac(av, bv, acc[y]);
+            }
         }
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int i = i0 + MM::row(lane, u), c = 16 * y + li;
+                if (i < i_end && c < nb) P[i + c * ldp] = acc[y][u];
+            }
     }
 }
 
@@ -198,23 +212,38 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
     __syncthreads();
     stamp(1);
 
+    // trace only: cycles of the panel phases (copy, diagonal block, L21, write-back,
+    // trailing update) summed over the panels into tstamp[4..8]
+    long long pcyc[5] = {0, 0, 0, 0, 0}, tprev = 0;
+    auto phase = [&](int k) {
+        if (T.tstamp && tid == 0) {
+            const long long tnow = clock64();
+            if (k >= 0) pcyc[k] += tnow - tprev;
+            tprev = tnow;
+        }
+    };
     // ---- blocked right-looking Cholesky; the diagonal blocks of W receive L11^{-1} ----
     for (int jb = 0; jb < m; jb += PIV_NB) {
         const int nb = min(PIV_NB, m - jb);
         const int r = m - jb;                        // panel rows (diagonal block first)
+        phase(-1);
         copy_block(Pn, r, W + jb + jb * ld, ld, r, nb);
         __syncthreads();
+        phase(0);
         // L11 and its inverse by the whole workgroup
         block_potrf_trinv32(Pn, r, nb, X11, &bad);
         __syncthreads();
+        phase(1);
         if (bad) break;
         // L21 = A21 L11^{-T}, rows in registers
         rows_times_x11<true>(Pn, r, nb, r, nb, X11);
         __syncthreads();
+        phase(2);
         for (int e = tid; e < r * nb; e += NT) {
             const int i = e % r, c = e / r;
             W[(jb + i) + (jb + c) * ld] = (i < nb) ? X11[i + c * l11] : Pn[i + c * r];
         }
+        phase(3);
         // trailing update W22 -= L21 L21^T, L21 = Pn(nb.., :), on the FP64 matrix cores: the
         // 64 x 64 tiles on and below the diagonal (column of tiles by column), wave wv takes
         // the 32 x 32 quarter (rows 32 (wv % 2), columns 32 (wv / 2)) as 2 x 2 blocks of
@@ -309,7 +338,10 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             }
         }
         __syncthreads();
+        phase(4);
     }
+    if (T.tstamp && tid == 0)
+        for (int k = 0; k < 5; ++k) T.tstamp[4 + k] = pcyc[k];
     if (bad) {
         if (tid == 0) fail[T.id] = 1;
         return;

@@ -97,3 +97,31 @@ def test_largest_leaf_pairs():
     z_ref = O.apply(F, r)
     assert np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref) <= TOL
     S.close()
+
+
+def test_largest_leaf_pairs_gc_four_vectors():
+    """The same 512-unknown leaf pairs with GC keeping four vectors (1, x, y, z): Z =
+    [phi_s, A_sw phi_w] has 8 columns, so up to 8 GC reflectors are applied as one block,
+    whose LDS buffers (3 x 8 x 512 doubles) are the largest the global-matrix compression
+    holds. Ranks equal and the apply within the FP64 bar of the oracle."""
+    say("leaf pairs of 512, GC with 4 vectors")
+    p = pb.poisson(16, 3)
+    c = p.coords
+    x = (c - c.mean(0)) / np.ptp(c, 0)
+    phi = np.asfortranarray(np.column_stack([np.ones(p.n), x[:, 0], x[:, 1], x[:, 2]]))
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=256, eps=1e-2, variant=O.GC, phi=phi)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=256, eps=1e-2, phi=phi)
+    S.factor(dev(p.values))
+    assert F.tie_margin > 1e-8
+    for d in F.levels:
+        assert S.ranks(d).tolist() == F.ranks(d), d
+    r = pb.rhs(p.n, 1, 46)
+    z = S.apply(dev(r)).cpu().numpy()
+    z_ref = O.apply(F, r)
+    assert np.linalg.norm(z - z_ref) / np.linalg.norm(z_ref) <= TOL
+    assert np.max(np.abs(z - z_ref)) / np.max(np.abs(z_ref)) <= TOL
+    # each kept vector is preserved exactly: A_H^{-1} A phi_j = phi_j (the GC invariant)
+    for j in range(phi.shape[1]):
+        zj = S.apply(dev(p.dense() @ phi[:, j])).cpu().numpy()
+        assert np.max(np.abs(zj - phi[:, j])) / np.max(np.abs(phi[:, j])) < 1e-10, j
+    S.close()
