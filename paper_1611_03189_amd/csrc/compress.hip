@@ -437,7 +437,6 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
             const int tg = wv / 4, wq = wv % 4;
             const int qr = 32 * (wq % 2), qc = 32 * (wq / 2);
             const int li = lane % 16, lk = lane / 16;
-            const int ksteps = (2 * nb + 3) / 4;
             int rr[2], cc[2][4];
             dbl4 nxt[2][2];
             auto tile_pos = [&](int bt) {
@@ -485,7 +484,10 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
                     tile_pos(bt + NG);
                     load_tile();
                 }
-                for (int ks = 0; ks < ksteps; ++ks) {
+                // all 2 TRI_NB / 4 steps, unrolled (operands past 2 nb are zero: the products
+                // add exact zeros), so that the operand reads of a tile issue together
+#pragma unroll
+                for (int ks = 0; ks < 2 * TRI_NB / 4; ++ks) {
                     const int kk = 4 * ks + lk;           // this lane's K index
                     const bool kv = kk < 2 * nb;
                     const int c = kv ? (kk < nb ? kk : kk - nb) : 0;

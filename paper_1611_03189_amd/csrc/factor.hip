@@ -94,9 +94,15 @@ struct Batch {
             tiles64 += double((t.M + 63) / 64) * double((t.N + 63) / 64);
         }
         // tile shape: the autotuned choice for this launch's size bucket; the replay lays out
-        // the 64 x 64 tiles, the most of any shape, so its table bounds every choice
-        const int variant =
-            dry ? 0 : gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0), sizeof(R) == 4);
+        // the tiles of the smallest shape, the most of any, so its table bounds every choice
+        int variant = 0;
+        if (dry) {
+            for (int v = 1; v < GEMM_VARIANTS; ++v)
+                if (GEMM_SHAPES[v].tm * GEMM_SHAPES[v].tn < GEMM_SHAPES[variant].tm * GEMM_SHAPES[variant].tn)
+                    variant = v;
+        } else {
+            variant = gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0), sizeof(R) == 4);
+        }
         const GemmShape sh = GEMM_SHAPES[variant];
         for (size_t id = 0; id < gt.size(); ++id)
             for (int ti = 0; ti * sh.tm < gt[id].M; ++ti)

@@ -198,7 +198,7 @@ struct GemmTile {            // one output tile of a task (the launch's tile sha
 struct GemmShape {
     int tm, tn, tk;
 };
-constexpr int GEMM_VARIANTS = 4;
+constexpr int GEMM_VARIANTS = 6;
 extern const GemmShape GEMM_SHAPES[GEMM_VARIANTS];
 constexpr int GEMM_TILE_BUCKETS = 4;       // 64x64 tiles: < 32, < 256, < 2048, more
 constexpr int GEMM_K_BUCKETS = 3;          // mean K: <= 64, <= 256, more

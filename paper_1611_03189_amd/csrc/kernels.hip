@@ -201,7 +201,10 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
             }
 }
 
-const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16}, {64, 64, 32}, {128, 64, 16}, {128, 128, 16}};
+// 32 x 32 tiles with long K steps: four times the workgroups of a 64 x 64 tiling for launches
+// with fewer tiles than compute units, each with a quarter of the tile's matrix-core work
+const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16},  {64, 64, 32}, {128, 64, 16},
+                                              {128, 128, 16}, {32, 32, 64}, {32, 32, 128}};
 
 template <typename T>
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
@@ -212,6 +215,8 @@ void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTil
         case 1: hipLaunchKernelGGL((k_gemm<T, 64, 64, 32>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
         case 2: hipLaunchKernelGGL((k_gemm<T, 128, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
         case 3: hipLaunchKernelGGL((k_gemm<T, 128, 128, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 4: hipLaunchKernelGGL((k_gemm<T, 32, 32, 64>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 5: hipLaunchKernelGGL((k_gemm<T, 32, 32, 128>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
         default: hipLaunchKernelGGL((k_gemm<T, 64, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
     }
     check_launch("k_gemm");

@@ -257,7 +257,6 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
             const int lane = tid % WAVE, wv = tid / WAVE;
             const int li = lane % 16, lk = lane / 16;
             const int qr = 32 * (wv % 2), qc = 32 * (wv / 2);
-            const int ksteps = (nb + 3) / 4;
             HS_G R* W22 = W + (jb + nb) + (jb + nb) * ld;
             int rr[2], cc[2][4], cbase[2];
             typename MM::acc nxt[2][2];
@@ -314,7 +313,10 @@ __global__ __launch_bounds__(NT) void k_chol_inv_blk(const CholTask* tasks, int*
                     tile_pos(bt + 1);
                     load_tile();
                 }
-                for (int ks = 0; ks < ksteps; ++ks) {
+                // all PIV_NB / 4 steps, unrolled (operands past nb are zero: the products
+                // add exact zeros), so that the operand reads of a tile issue together
+#pragma unroll
+                for (int ks = 0; ks < PIV_NB / 4; ++ks) {
                     const int k = 4 * ks + lk;
                     const bool kv = k < nb;
                     const int kc = kv ? k : 0;

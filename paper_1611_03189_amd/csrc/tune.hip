@@ -1,5 +1,5 @@
 // Autotuner of the grouped GEMM's tile shape. A launch is classified by its number of
-// 64 x 64 output tiles (how many workgroups the smallest shape gives it) and by its mean
+// 64 x 64 output tiles (its size in workgroups of the default shape) and by its mean
 // inner dimension (how long each tile accumulates). For each such bucket the tuner times
 // every tile shape on a synthetic launch of that size (groups of 128 x 128 products with the
 // bucket's inner dimension, operands spread over the caller's workspace) and keeps the

@@ -165,7 +165,7 @@ def _cols(t, n, torch, what):
     return M.t().contiguous(), vec
 
 
-GEMM_SHAPES = [(64, 64, 16), (64, 64, 32), (128, 64, 16), (128, 128, 16)]
+GEMM_SHAPES = [(64, 64, 16), (64, 64, 32), (128, 64, 16), (128, 128, 16), (32, 32, 64), (32, 32, 128)]
 GEMM_BUCKETS = 12
 
 
