@@ -3,9 +3,9 @@
 //
 // k_chol_inv     blocks up to PIV_LDS_MAX rows, held in LDS with leading dimension m+1
 //                (odd stride: the column walks of the inverse and of the product hit
-//                distinct banks): right-looking Cholesky, in-place lower-triangular
-//                inverse X = L^{-1} (column j = -(X22 l_j) / l_jj, right to left), then
-//                A^{-1} = X^T X written to both triangles.
+//                distinct banks): right-looking Cholesky and in-place lower-triangular
+//                inverse X = L^{-1} (column j = -(X22 l_j) / l_jj, right to left), two
+//                barriers per column each, then A^{-1} = X^T X written to both triangles.
 // k_chol_inv_blk larger blocks (up to PIV_MAX rows) in a global work matrix, blocked by
 //                PIV_NB columns: the panel's diagonal block is factored and inverted in
 //                one pass of steps in LDS, the panel below it (L21 = A21 L11^{-T}) and
@@ -26,7 +26,6 @@ constexpr int PIV_PANEL = PIV_MAX * PIV_NB;     // elements of the LDS panel buf
 template <typename R>
 __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fail) {
     extern __shared__ double lds_raw[];             // typed double: 8-byte aligned LDS accesses
-    __shared__ int bad;
     const CholTask T = tasks[blockIdx.x];
     const int m = T.m, tid = threadIdx.x;
     R* W = reinterpret_cast<R*>(lds_raw);
@@ -34,19 +33,20 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
     const HS_G R* A = gp(static_cast<const R*>(T.A));
     HS_G R* Ainv = gp(static_cast<R*>(T.Ainv));
     copy_block(W, ldw, A, T.lda, m, m);
-    if (tid == 0) bad = 0;
     __syncthreads();
+    // two barriers per column: every thread takes the pivot sqrt(d_j) itself, the diagonal
+    // entry is stored once the column is scaled (nobody reads it any more in this step)
+    bool failed = false;
     for (int j = 0; j < m; ++j) {
-        if (tid == 0) {
-            const R d = W[j + j * ldw];
-            if (!(d > R(0)) || !isfinite(d)) bad = 1;
-            else W[j + j * ldw] = sqrt(d);
+        const R d = W[j + j * ldw];
+        if (!(d > R(0)) || !isfinite(d)) {
+            failed = true;                              // uniform: every thread read the same d
+            break;
         }
-        __syncthreads();
-        if (bad) break;
-        const R piv = W[j + j * ldw];
+        const R piv = sqrt(d);
         for (int i = j + 1 + tid; i < m; i += NT) W[i + j * ldw] /= piv;
         __syncthreads();
+        if (tid == 0) W[j + j * ldw] = piv;
         // trailing update, rows over threads (the column-j entry of a row stays in a register)
         for (int i = j + 1 + tid; i < m; i += NT) {
             const R lij = W[i + j * ldw];
@@ -62,15 +62,16 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
         }
         __syncthreads();
     }
-    if (bad) {
+    if (failed) {
         if (tid == 0) fail[T.id] = 1;
         return;
     }
-    // X = L^{-1} in place, columns right to left
+    __syncthreads();
+    // X = L^{-1} in place, columns right to left, two barriers per column: every thread takes
+    // -1 / l_jj itself; X's column j and diagonal entry are stored once the column of L and
+    // the old diagonal entry have been read
     for (int j = m - 1; j >= 0; --j) {
-        if (tid == 0) W[j + j * ldw] = R(1) / W[j + j * ldw];
-        __syncthreads();
-        const R ajj = -W[j + j * ldw];
+        const R ajj = -(R(1) / W[j + j * ldw]);
         R y = R(0);
         const int i = j + 1 + tid;         // m <= PIV_LDS_MAX < NT: at most one row per thread
         if (i < m) {
@@ -85,6 +86,7 @@ __global__ __launch_bounds__(NT) void k_chol_inv(const CholTask* tasks, int* fai
         }
         __syncthreads();
         if (i < m) W[i + j * ldw] = ajj * y;
+        if (tid == 0) W[j + j * ldw] = -ajj;
         __syncthreads();
     }
     // A^{-1} = X^T X
