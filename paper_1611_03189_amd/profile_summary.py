@@ -5,6 +5,10 @@
     python -m paper_1611_03189_amd.profile_summary --pmc FETCH_CSV WRITE_CSV CALIB_KERNEL BYTES "COMMANDS"
         per-kernel HBM bytes per dispatch from FETCH_SIZE / WRITE_SIZE counter runs, scaled by
         a copy of known size; prints JSON with the source hashes of the kernels
+    python -m paper_1611_03189_amd.profile_summary --mfma COUNTER_CSV "COMMAND" [TITLE]
+        per-kernel FP64 matrix-core work from one counter run (SQ_INSTS_VALU_MFMA_MOPS_F64,
+        SQ_VALU_MFMA_BUSY_CYCLES, GRBM_GUI_ACTIVE): flops, rate over the dispatches' own
+        durations and the fraction of the FP64 matrix peak
 """
 import csv
 import sys
@@ -63,6 +67,48 @@ def pmc_summary(fetch_csv: str, write_csv: str, calib_kernel: str, calib_bytes: 
     return out
 
 
+PEAK_FP64_TFLOPS = 78.6          # MI355X dense FP64 (matrix and vector)
+
+
+def mfma_summary(path: str, command: str, title: str = "") -> str:
+    """One line per kernel that issues FP64 MFMA: dispatches, summed dispatch time of the
+    counter run, MFMA flops (MOPS_F64 x 512, padding included), their rate over that time, the
+    fraction of the FP64 peak, and the MFMA busy cycles over the GUI-active cycles as the
+    counters report them (busy summed over the chip's 1024 SIMDs, GUI-active over its 8
+    XCDs), and that ratio over 128 SIMDs per XCD: the matrix cores' busy fraction, which the
+    flop-based fraction should match."""
+    per = {}
+    for r in csv.DictReader(open(path)):
+        d = per.setdefault(r["Dispatch_Id"], {"name": r["Kernel_Name"],
+                                              "ns": int(r["End_Timestamp"]) - int(r["Start_Timestamp"])})
+        d[r["Counter_Name"]] = float(r["Counter_Value"])
+    acc = {}
+    for d in per.values():
+        name = d["name"]
+        if "(" in name:
+            name = name[:name.index("(")]
+        name = name.replace("void ", "")
+        a = acc.setdefault(name, [0, 0.0, 0.0, 0.0, 0.0])
+        a[0] += 1
+        a[1] += d["ns"]
+        a[2] += d.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512.0
+        a[3] += d.get("SQ_VALU_MFMA_BUSY_CYCLES", 0.0)
+        a[4] += d.get("GRBM_GUI_ACTIVE", 0.0)
+    out = []
+    if title:
+        out.append(f"# {title}")
+    out.append(f"# command: {command}")
+    out.append(f"# {'kernel':50s} {'calls':>6s} {'ms':>9s} {'mfma_gflop':>11s} {'tflop/s':>8s} "
+               f"{'frac':>7s} {'busy/gui':>9s} {'simd_busy':>9s}")
+    for name, a in sorted(acc.items(), key=lambda kv: -kv[1][2]):
+        if a[2] <= 0.0:
+            continue
+        rate = a[2] / a[1] / 1e3
+        out.append(f"  {name[:50]:50s} {a[0]:6d} {a[1] / 1e6:9.2f} {a[2] / 1e9:11.2f} {rate:8.2f} "
+                   f"{rate / PEAK_FP64_TFLOPS:7.4f} {a[3] / max(a[4], 1.0):9.3f} {a[3] / max(a[4], 1.0) / 128:9.4f}")
+    return "\n".join(out) + "\n"
+
+
 def source_hashes() -> dict:
     """sha256 of every HIP source of the library: counters are valid for this code only."""
     import hashlib
@@ -73,7 +119,9 @@ def source_hashes() -> dict:
 
 
 if __name__ == "__main__":
-    if sys.argv[1] == "--pmc":
+    if sys.argv[1] == "--mfma":
+        print(mfma_summary(sys.argv[2], sys.argv[3], sys.argv[4] if len(sys.argv) > 4 else ""), end="")
+    elif sys.argv[1] == "--pmc":
         import json
         res = pmc_summary(sys.argv[2], sys.argv[3], sys.argv[4], float(sys.argv[5]))
         res["command"] = sys.argv[6]
