@@ -229,8 +229,9 @@ hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream);
 
 /* ---- Autotuning of the grouped GEMM (Schur updates, Gram matrices, pivot products) ----
  * The GEMM runs in one of HSOLVE_GEMM_VARIANTS output-tile shapes (0: 64x64 with K steps of
- * 16, 1: 64x64/32, 2: 128x64/16, 3: 128x128/16, 4: 32x32/64, 5: 32x32/128); every shape gives
- * the same bits. A launch
+ * 16, 1: 64x64/32, 2: 128x64/16, 3: 128x128/16, 4: 32x32/64, 5: 32x32/128, 6: 64x64/16 and
+ * 7: 32x32/64 persistent, i.e. a grid of resident workgroups looping over the tiles); every
+ * shape gives the same bits. A launch
  * falls into one of HSOLVE_GEMM_BUCKETS buckets: its number of 64x64 output tiles (< 32,
  * < 256, < 2048, more) times its mean inner dimension (<= 64, <= 256, more), bucket =
  * 3 * tile_class + k_class; FP64 and FP32 GEMMs are tuned apart. hsolve_tune_gemm times every
@@ -240,7 +241,7 @@ hsolve_status hsolve_set_stream(hsolve_plan plan, void* stream);
  * HSOLVE_GEMM_VARIANTS, best of three) may be NULL. Untuned, every bucket uses shape 0.
  * hsolve_set_gemm_choice installs a saved choice (2 x HSOLVE_GEMM_BUCKETS entries). Neither
  * may run while a factorization is in flight. */
-#define HSOLVE_GEMM_VARIANTS 6
+#define HSOLVE_GEMM_VARIANTS 8
 #define HSOLVE_GEMM_BUCKETS 12
 size_t hsolve_tune_workspace_bytes(void);
 hsolve_status hsolve_tune_gemm(void* d_work, size_t work_bytes, void* stream, int32_t* choice, double* ms);

@@ -197,8 +197,9 @@ struct GemmTile {            // one output tile of a task (the launch's tile sha
 // is decided by its number of 64 x 64 output tiles and its mean inner dimension.
 struct GemmShape {
     int tm, tn, tk;
+    int persistent;          // 1: a grid of resident workgroups loops over the tiles
 };
-constexpr int GEMM_VARIANTS = 6;
+constexpr int GEMM_VARIANTS = 8;
 extern const GemmShape GEMM_SHAPES[GEMM_VARIANTS];
 constexpr int GEMM_TILE_BUCKETS = 4;       // 64x64 tiles: < 32, < 256, < 2048, more
 constexpr int GEMM_K_BUCKETS = 3;          // mean K: <= 64, <= 256, more

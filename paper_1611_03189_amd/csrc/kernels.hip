@@ -7,6 +7,9 @@
 //  k_spmv, gathers/scatters (batched PCG kernels: krylov.hip)             outer PCG
 #include <cfloat>
 
+#include <algorithm>
+#include <atomic>
+
 #include "hs_device.h"
 
 namespace hs {
@@ -90,17 +93,14 @@ struct GemmStep {            // position in the concatenated K loop of a task's 
 };
 
 template <typename T, int TM, int TN, int TK>
-__global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
-                                             const GemmTile* tiles) {
+__device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, const GemmTile tl,
+                                 T (&As)[2][TK][TM + 1], T (&Bs)[2][TK][TN + 1]) {
     typedef Mma<T> MM;
     constexpr int BX = TM / 32, BY = TN / 32;              // 16 x 16 blocks per wave
     constexpr int LA = TM * TK / NT, LB = TN * TK / NT;    // loads per thread and K step
     static_assert(LA * NT == TM * TK && LB * NT == TN * TK, "tile");
-    const GemmTile tl = tiles[blockIdx.x];
     const GemmTask Tk = tasks[tl.task];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
-    __shared__ T As[2][TK][TM + 1];
-    __shared__ T Bs[2][TK][TN + 1];
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
     typename MM::acc acc[BX][BY];
 #pragma unroll
@@ -201,23 +201,63 @@ __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTe
             }
 }
 
+// One workgroup per tile, or, in the persistent form, a grid of resident workgroups that take
+// tiles w, w + grid, .. of the list (the same computation per tile).
+template <typename T, int TM, int TN, int TK>
+__global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
+                                             const GemmTile* tiles, int ntiles) {
+    __shared__ T As[2][TK][TM + 1];
+    __shared__ T Bs[2][TK][TN + 1];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        gemm_tile<T, TM, TN, TK>(tasks, terms, tiles[t], As, Bs);
+        __syncthreads();                           // the next tile refills the LDS buffers
+    }
+}
+
 // 32 x 32 tiles with long K steps: four times the workgroups of a 64 x 64 tiling for launches
-// with fewer tiles than compute units, each with a quarter of the tile's matrix-core work
-const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16},  {64, 64, 32}, {128, 64, 16},
-                                              {128, 128, 16}, {32, 32, 64}, {32, 32, 128}};
+// with fewer tiles than compute units, each with a quarter of the tile's matrix-core work.
+// The last two shapes run persistent: as many workgroups as fit on the chip at once, each
+// looping over the tile list.
+const GemmShape GEMM_SHAPES[GEMM_VARIANTS] = {{64, 64, 16, 0},   {64, 64, 32, 0}, {128, 64, 16, 0},
+                                              {128, 128, 16, 0}, {32, 32, 64, 0}, {32, 32, 128, 0},
+                                              {64, 64, 16, 1},   {32, 32, 64, 1}};
+
+// resident workgroups of a kernel on this device (the persistent grid), found once per kernel
+template <typename T, int TM, int TN, int TK>
+static int resident_grid() {
+    static std::atomic<int> cached{0};
+    int g = cached.load(std::memory_order_relaxed);
+    if (g > 0) return g;
+    int dev = 0, cus = 0, per_cu = 0;
+    HS_HIP(hipGetDevice(&dev));
+    HS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_gemm<T, TM, TN, TK>),
+                                                        NT, 0));
+    g = std::max(1, cus * std::max(1, per_cu));
+    cached.store(g, std::memory_order_relaxed);
+    return g;
+}
+
+template <typename T, int TM, int TN, int TK>
+static void launch_shape(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles, int ntiles,
+                         bool persistent, hipStream_t s) {
+    const int grid = persistent ? std::min(ntiles, resident_grid<T, TM, TN, TK>()) : ntiles;
+    hipLaunchKernelGGL((k_gemm<T, TM, TN, TK>), dim3(grid), dim3(NT), 0, s, d_tasks, d_terms, d_tiles, ntiles);
+}
 
 template <typename T>
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
                  int ntiles, double flops, int variant, hipStream_t s) {
     if (ntiles <= 0) return;
     ProfScope ps(sizeof(T) == 8 ? "k_gemm" : "k_gemm_f32", flops, s);
+    const bool pers = GEMM_SHAPES[variant].persistent != 0;
     switch (variant) {
-        case 1: hipLaunchKernelGGL((k_gemm<T, 64, 64, 32>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 2: hipLaunchKernelGGL((k_gemm<T, 128, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 3: hipLaunchKernelGGL((k_gemm<T, 128, 128, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 4: hipLaunchKernelGGL((k_gemm<T, 32, 32, 64>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        case 5: hipLaunchKernelGGL((k_gemm<T, 32, 32, 128>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
-        default: hipLaunchKernelGGL((k_gemm<T, 64, 64, 16>), dim3(ntiles), dim3(NT), 0, s, d_tasks, d_terms, d_tiles); break;
+        case 1: launch_shape<T, 64, 64, 32>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        case 2: launch_shape<T, 128, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        case 3: launch_shape<T, 128, 128, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        case 4: case 7: launch_shape<T, 32, 32, 64>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        case 5: launch_shape<T, 32, 32, 128>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        default: launch_shape<T, 64, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
     }
     check_launch("k_gemm");
 }

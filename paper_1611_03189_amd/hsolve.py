@@ -165,7 +165,9 @@ def _cols(t, n, torch, what):
     return M.t().contiguous(), vec
 
 
-GEMM_SHAPES = [(64, 64, 16), (64, 64, 32), (128, 64, 16), (128, 128, 16), (32, 32, 64), (32, 32, 128)]
+# (tile rows, tile columns, K step, persistent grid)
+GEMM_SHAPES = [(64, 64, 16, 0), (64, 64, 32, 0), (128, 64, 16, 0), (128, 128, 16, 0), (32, 32, 64, 0),
+               (32, 32, 128, 0), (64, 64, 16, 1), (32, 32, 64, 1)]
 GEMM_BUCKETS = 12
 
 
