@@ -120,7 +120,9 @@ def serving(count: int, slots: int, mixed: bool = True) -> dict:
     """The serving stream (mixed 2-D / 3-D lognormal systems, 1..8 right-hand sides each):
     first closed loop (every request waiting at t = 0, saturation), then open loop with
     Poisson arrivals at 0.7 x the closed-loop request rate. Latency runs from arrival to the
-    last right-hand side solved; the systems are generated before the timed runs."""
+    last right-hand side solved; the systems are generated before the timed runs. With the
+    mixed form, the same requests also run closed loop in plain FP64 (FP64 factorization and
+    PCG), for the comparison on the same matrices."""
     from paper_1611_03189_amd import problems as pb
     from paper_1611_03189_amd.serve import RequestLoop, requests_from_stream
     specs = pb.serving_stream(count, seed=4)
@@ -134,10 +136,19 @@ def serving(count: int, slots: int, mixed: bool = True) -> dict:
         r.arrival = sp["arrival"]
     opened = loop.run(reqs, realtime=True).stats()
     opened["arrival_rate_per_s"] = round(rate, 3)
-    return {"workload": f"{count} systems: 2-D N~U{{64..256}} / 3-D N~U{{16..48}}, lognormal sigma 1, "
-                        f"1-8 rhs, GC eps 1e-2, " + ("FP32 factorization + FP64 flexible PCG" if mixed
-                                                     else "FP64 factorization + PCG") + " to 1e-10",
-            "slots": slots, "closed_loop": closed, "open_loop": opened}
+    out = {"workload": f"{count} systems: 2-D N~U{{64..256}} / 3-D N~U{{16..48}}, lognormal sigma 1, "
+                       f"1-8 rhs, GC eps 1e-2, " + ("FP32 factorization + FP64 flexible PCG" if mixed
+                                                    else "FP64 factorization + PCG") + " to 1e-10",
+           "slots": slots, "closed_loop": closed, "open_loop": opened}
+    if mixed:
+        for r in reqs:
+            r.arrival = 0.0
+        loop64 = RequestLoop(slots=slots, mixed=False)
+        loop64.run(reqs[:min(4, len(reqs))], realtime=False)
+        closed64 = loop64.run(reqs, realtime=False).stats()
+        out["fp64_closed_loop"] = closed64
+        out["mixed_speedup_closed_loop"] = round(closed64["makespan_s"] / closed["makespan_s"], 3)
+    return out
 
 
 def variants(H, pb, np, torch, p, w, vals, b_host, x64) -> dict:
