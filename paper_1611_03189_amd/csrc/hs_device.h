@@ -17,6 +17,11 @@ constexpr int WAVE = 64;
 #define HS_G __attribute__((address_space(1)))
 template <class T> __device__ inline HS_G T* gp(T* p) { return (HS_G T*)p; }
 template <class T> __device__ inline const HS_G T* gp(const T* p) { return (const HS_G T*)p; }
+// Read-only view of global memory that no thread of the running kernel writes: loads at
+// wave-uniform addresses through it become scalar loads (the scalar cache starts every
+// dispatch clean). Used only for such reads.
+#define HS_C __attribute__((address_space(4)))
+template <class T> __device__ inline const HS_C T* cp(const T* p) { return (const HS_C T*)p; }
 
 // Raise the dynamic LDS limit of a kernel once per process (safe from several host threads)
 inline void set_lds_limit(std::once_flag& flag, const void* kernel, size_t bytes) {

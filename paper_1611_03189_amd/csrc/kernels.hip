@@ -320,7 +320,7 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
     const FwdTarget t = targets[blockIdx.y];
     const int r0 = blockIdx.x * FWD_ROWS;
     if (r0 >= t.len) return;
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int i = r0 + lane;
     __shared__ T part[NT / WAVE][WAVE];
     for (int c = 0; c < nrhs; ++c) {
@@ -329,7 +329,8 @@ __global__ __launch_bounds__(NT) void k_fwd(const FwdTarget* targets, const FwdC
         if (i < t.len) {
             for (int q = t.c_begin; q < t.c_end; ++q) {
                 const FwdContrib f = contrib[q];
-                const T* x = Vc + f.src;
+                // the source segment (a node of this colour) is not a target of the launch
+                const HS_C T* x = cp(Vc + f.src);
                 const HS_G T* g = gp(static_cast<const T*>(f.G)) + i;
                 int j = wv;
                 for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_fwd_m(const FwdTarget* targets, const Fw
     const int r0 = blockIdx.x * FWD_ROWS, c0 = blockIdx.z * APPLY_RC;
     if (r0 >= t.len) return;
     const int nc = min(APPLY_RC, nrhs - c0);
-    const int lane = threadIdx.x % WAVE, wv = threadIdx.x / WAVE;
+    const int lane = threadIdx.x % WAVE, wv = __builtin_amdgcn_readfirstlane(threadIdx.x / WAVE);
     const int i = r0 + lane;
     __shared__ T part[APPLY_RC][NT / WAVE][WAVE];
     T acc[APPLY_RC][4];
@@ -376,7 +377,8 @@ __global__ __launch_bounds__(NT) void k_fwd_m(const FwdTarget* targets, const Fw
     if (i < t.len) {
         for (int q = t.c_begin; q < t.c_end; ++q) {
             const FwdContrib f = contrib[q];
-            const T* x = V + size_t(c0) * ldv + f.src;
+            // the source segment (a node of this colour) is not a target of the launch
+            const HS_C T* x = cp(V + size_t(c0) * ldv + f.src);
             const HS_G T* g = gp(static_cast<const T*>(f.G)) + i;
             int j = wv;
             for (; j + 3 * (NT / WAVE) < f.m; j += 4 * (NT / WAVE)) {
