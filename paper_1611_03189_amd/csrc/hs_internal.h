@@ -177,16 +177,21 @@ struct CopyTask {            // dst(i,j) = src(i,j) or src(j,i) (trans), in the 
     int lds, ldd, rows, cols, trans, pad;
 };
 
+// Flags of a GEMM task (for C) and term (for B): GEMM_REL, the pointer field holds an element
+// offset from one of the two base pointers the launch passes (GEMM_BASE1 picks the second);
+// GEMM_NEG (term), the term enters with a minus sign.
+enum { GEMM_NEG = 1, GEMM_REL = 2, GEMM_BASE1 = 4 };
+
 struct GemmTask {            // C = beta C + alpha sum_t op(A_t) op(B_t), C is M x N (launch's type)
     void* C;
-    int ldc, M, N, t_begin, t_end, pad;
+    int ldc, M, N, t_begin, t_end, flags;
     double alpha, beta;
 };
 
 struct GemmTerm {
     const void* A;
     const void* B;
-    int lda, ldb, K, transA, transB, pad;
+    int lda, ldb, K, transA, transB, flags;
 };
 
 struct GemmTile {            // one output tile of a task (the launch's tile shape)
@@ -319,12 +324,20 @@ struct Plan {
     Staging stage;
 
     // apply schedule (device), per level and colour
+    struct ApplyGemm {      // one sweep of a colour as grouped-GEMM tables (vector-relative)
+        GemmTask* tasks = nullptr;
+        GemmTerm* terms = nullptr;
+        GemmTile* tiles = nullptr;
+        int ntiles = 0;
+        double flops = 0.0;  // per right-hand side
+    };
     struct ColourSched {
         double fwd_bytes = 0.0, bwd_bytes = 0.0;   // algorithmic bytes per rhs
         FwdTarget* fwd_t = nullptr; int nfwd = 0; int max_len = 0;
         FwdContrib* fwd_c = nullptr;
         BwdNode* bwd_n = nullptr; int nbwd = 0; int max_m = 0;
         BwdSeg* bwd_s = nullptr;
+        ApplyGemm gf, gb;   // the same sweeps for several right-hand sides
     };
     std::vector<std::vector<ColourSched>> sched;   // sched[d][c]
     bool apply32 = false;                           // solve phase in single precision
@@ -393,8 +406,11 @@ void spmv(Plan& P, const double* x, double* y);
 template <typename T>
 void launch_copy(const CopyTask* d_tasks, int ntasks, int max_cols, double bytes, hipStream_t s);
 template <typename T>
+// base0, base1: the bases of GEMM_REL pointers; ncols > 0 overrides every task's N (the
+// launch then covers columns [0, ncols) of relative operands); name: the profiler's label
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, double flops, int variant, hipStream_t s);
+                 int ntiles, double flops, int variant, hipStream_t s, T* base0 = nullptr,
+                 T* base1 = nullptr, int ncols = 0, const char* name = nullptr);
 template <typename T>
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s);

@@ -92,9 +92,12 @@ struct GemmStep {            // position in the concatenated K loop of a task's 
     int term, k0;
 };
 
-template <typename T, int TM, int TN, int TK>
+// REL: the flagged form of the apply sweeps (relative B and C addresses, negated terms, a
+// column count per launch); without it the flags are ignored and none of that is compiled in.
+template <typename T, int TM, int TN, int TK, bool REL>
 __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, const GemmTile tl,
-                                 T (&As)[2][TK][TM + 1], T (&Bs)[2][TK][TN + 1]) {
+                                 T (&As)[2][TK][TM + 1], T (&Bs)[2][TK][TN + 1], T* base0, T* base1,
+                                 int ncols) {
     typedef Mma<T> MM;
     constexpr int BX = TM / 32, BY = TN / 32;              // 16 x 16 blocks per wave
     constexpr int LA = TM * TK / NT, LB = TN * TK / NT;    // loads per thread and K step
@@ -102,6 +105,8 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
     const GemmTask Tk = tasks[tl.task];
     const int tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     const int i0 = tl.ti * TM, j0 = tl.tj * TN;
+    const int Nc = (REL && ncols > 0) ? ncols : Tk.N;      // columns of this launch
+    if (REL && j0 >= Nc) return;
     typename MM::acc acc[BX][BY];
 #pragma unroll
     for (int x = 0; x < BX; ++x)
@@ -112,7 +117,9 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
     auto load_step = [&](GemmStep st) {
         const GemmTerm g = terms[st.term];
         const HS_G T* gA = gp(static_cast<const T*>(g.A));
-        const HS_G T* gB = gp(static_cast<const T*>(g.B));
+        const HS_G T* gB = gp((REL && (g.flags & GEMM_REL))
+                                  ? ((g.flags & GEMM_BASE1) ? base1 : base0) + reinterpret_cast<uintptr_t>(g.B)
+                                  : static_cast<const T*>(g.B));
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int e = tid + NT * q;
@@ -128,18 +135,21 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
             int jj, kb;
             if (g.transB) { jj = e % TN; kb = e / TN; } else { kb = e % TK; jj = e / TK; }
             const int gj = j0 + jj, gkb = st.k0 + kb;
-            rb[q] = (gj < Tk.N && gkb < g.K) ? (g.transB ? gB[gj + size_t(gkb) * g.ldb] : gB[gkb + size_t(gj) * g.ldb])
-                                             : T(0);
+            rb[q] = (gj < Nc && gkb < g.K) ? (g.transB ? gB[gj + size_t(gkb) * g.ldb] : gB[gkb + size_t(gj) * g.ldb])
+                                           : T(0);
         }
     };
     auto store_step = [&](GemmStep st, int buf) {
         const GemmTerm g = terms[st.term];
+        // a negative term's sign goes on at the store, when the prefetched values are in
+        // (on the load it would make the prefetch wait)
+        const bool neg = REL && (g.flags & GEMM_NEG) != 0;
 #pragma unroll
         for (int q = 0; q < LA; ++q) {
             const int e = tid + NT * q;
             int ii, kk;
             if (!g.transA) { ii = e % TM; kk = e / TM; } else { kk = e % TK; ii = e / TK; }
-            As[buf][kk][ii] = ra[q];
+            As[buf][kk][ii] = neg ? -ra[q] : ra[q];
         }
 #pragma unroll
         for (int q = 0; q < LB; ++q) {
@@ -184,7 +194,8 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
         cur = nxt;
         buf ^= 1;
     }
-    HS_G T* C = gp(static_cast<T*>(Tk.C));
+    HS_G T* C = gp((REL && (Tk.flags & GEMM_REL)) ? ((Tk.flags & GEMM_BASE1) ? base1 : base0) + reinterpret_cast<uintptr_t>(Tk.C)
+                                          : static_cast<T*>(Tk.C));
     const T alpha = T(Tk.alpha), beta = T(Tk.beta);
 #pragma unroll
     for (int x = 0; x < BX; ++x)
@@ -193,7 +204,7 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int i = i0 + wr + 16 * x + MM::row(lane, r), j = j0 + wc + 16 * y + fr;
-                if (i < Tk.M && j < Tk.N) {
+                if (i < Tk.M && j < Nc) {
                     HS_G T* c = C + i + size_t(j) * Tk.ldc;
                     const T old = (Tk.beta == 0.0) ? T(0) : beta * (*c);
                     *c = old + alpha * acc[x][y][r];
@@ -203,13 +214,13 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
 
 // One workgroup per tile, or, in the persistent form, a grid of resident workgroups that take
 // tiles w, w + grid, .. of the list (the same computation per tile).
-template <typename T, int TM, int TN, int TK>
+template <typename T, int TM, int TN, int TK, bool REL>
 __global__ __launch_bounds__(NT) void k_gemm(const GemmTask* tasks, const GemmTerm* terms,
-                                             const GemmTile* tiles, int ntiles) {
+                                             const GemmTile* tiles, int ntiles, T* base0, T* base1, int ncols) {
     __shared__ T As[2][TK][TM + 1];
     __shared__ T Bs[2][TK][TN + 1];
     for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
-        gemm_tile<T, TM, TN, TK>(tasks, terms, tiles[t], As, Bs);
+        gemm_tile<T, TM, TN, TK, REL>(tasks, terms, tiles[t], As, Bs, base0, base1, ncols);
         __syncthreads();                           // the next tile refills the LDS buffers
     }
 }
@@ -231,7 +242,7 @@ static int resident_grid() {
     int dev = 0, cus = 0, per_cu = 0;
     HS_HIP(hipGetDevice(&dev));
     HS_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_gemm<T, TM, TN, TK>),
+    HS_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_gemm<T, TM, TN, TK, false>),
                                                         NT, 0));
     g = std::max(1, cus * std::max(1, per_cu));
     cached.store(g, std::memory_order_relaxed);
@@ -240,29 +251,37 @@ static int resident_grid() {
 
 template <typename T, int TM, int TN, int TK>
 static void launch_shape(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles, int ntiles,
-                         bool persistent, hipStream_t s) {
+                         bool persistent, hipStream_t s, T* base0, T* base1, int ncols) {
     const int grid = persistent ? std::min(ntiles, resident_grid<T, TM, TN, TK>()) : ntiles;
-    hipLaunchKernelGGL((k_gemm<T, TM, TN, TK>), dim3(grid), dim3(NT), 0, s, d_tasks, d_terms, d_tiles, ntiles);
+    if (base0 || base1 || ncols > 0)
+        hipLaunchKernelGGL((k_gemm<T, TM, TN, TK, true>), dim3(grid), dim3(NT), 0, s, d_tasks, d_terms, d_tiles,
+                           ntiles, base0, base1, ncols);
+    else
+        hipLaunchKernelGGL((k_gemm<T, TM, TN, TK, false>), dim3(grid), dim3(NT), 0, s, d_tasks, d_terms, d_tiles,
+                           ntiles, base0, base1, ncols);
 }
 
 template <typename T>
 void launch_gemm(const GemmTask* d_tasks, const GemmTerm* d_terms, const GemmTile* d_tiles,
-                 int ntiles, double flops, int variant, hipStream_t s) {
+                 int ntiles, double flops, int variant, hipStream_t s, T* base0, T* base1, int ncols,
+                 const char* name) {
     if (ntiles <= 0) return;
-    ProfScope ps(sizeof(T) == 8 ? "k_gemm" : "k_gemm_f32", flops, s);
+    ProfScope ps(name ? name : (sizeof(T) == 8 ? "k_gemm" : "k_gemm_f32"), flops, s);
     const bool pers = GEMM_SHAPES[variant].persistent != 0;
     switch (variant) {
-        case 1: launch_shape<T, 64, 64, 32>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
-        case 2: launch_shape<T, 128, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
-        case 3: launch_shape<T, 128, 128, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
-        case 4: case 7: launch_shape<T, 32, 32, 64>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
-        case 5: launch_shape<T, 32, 32, 128>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
-        default: launch_shape<T, 64, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s); break;
+        case 1: launch_shape<T, 64, 64, 32>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
+        case 2: launch_shape<T, 128, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
+        case 3: launch_shape<T, 128, 128, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
+        case 4: case 7: launch_shape<T, 32, 32, 64>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
+        case 5: launch_shape<T, 32, 32, 128>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
+        default: launch_shape<T, 64, 64, 16>(d_tasks, d_terms, d_tiles, ntiles, pers, s, base0, base1, ncols); break;
     }
     check_launch("k_gemm");
 }
-template void launch_gemm<double>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t);
-template void launch_gemm<float>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t);
+template void launch_gemm<double>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t,
+                                  double*, double*, int, const char*);
+template void launch_gemm<float>(const GemmTask*, const GemmTerm*, const GemmTile*, int, double, int, hipStream_t,
+                                 float*, float*, int, const char*);
 
 // ---------------------------------------------------------------------------------
 // Initial blocks of the first level from the CSR values

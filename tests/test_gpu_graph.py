@@ -22,7 +22,7 @@ def say(*a):
     print("[gpu-case]", *a, file=sys.stderr, flush=True)
 
 
-@pytest.mark.parametrize("apply_prec,nrhs", [(64, 1), (64, 3), (32, 2)])
+@pytest.mark.parametrize("apply_prec,nrhs", [(64, 1), (64, 3), (32, 2), (64, 8), (32, 6)])
 def test_graph_replays_equal_eager(apply_prec, nrhs):
     say("graph replays", apply_prec, nrhs)
     p = pb.poisson(14, 3)
