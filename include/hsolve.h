@@ -126,6 +126,12 @@ typedef struct {
     int neighbours;         /* HSOLVE_NEIGHBOURS_FOOTPRINT (default) or HSOLVE_NEIGHBOURS_GEOMETRIC */
     double eps1;            /* HSOLVE_GC_PROJ1: relative truncation of [X_s, A_sw X_w] (0 <= eps1 < 1;
                                0 keeps its whole range, as GC) */
+    int cmp_ritz;           /* 1 (default): the last kept directions of each compression are
+                               refined by Rayleigh-Ritz on A_sw itself (FP64 factorization, eps > 0):
+                               the eigen-solver also returns up to 8 eigenvectors past the
+                               threshold, and the window of up to 8 kept plus those is rotated by
+                               the eigenvectors of (W^T A_sw)(W^T A_sw)^T; 0: the Gram matrix's
+                               eigenvectors as they are */
 } hsolve_options;
 
 typedef struct {

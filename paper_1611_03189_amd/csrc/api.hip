@@ -79,6 +79,7 @@ void hsolve_default_options(hsolve_options* o) {
     o->apply_graph = 1;
     o->neighbours = HSOLVE_NEIGHBOURS_FOOTPRINT;
     o->eps1 = 0.0;
+    o->cmp_ritz = 1;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -101,6 +102,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         o.eps_schedule < HSOLVE_EPS_CONSTANT || o.eps_schedule > HSOLVE_EPS_GROW ||
         !(o.cmp_lpe == 0 || (o.cmp_lpe >= 1 && o.cmp_lpe <= 64 && (o.cmp_lpe & (o.cmp_lpe - 1)) == 0)) ||
         o.cmp_vectors < 0 || o.cmp_vectors > 2 || (o.apply_graph != 0 && o.apply_graph != 1) ||
+        (o.cmp_ritz != 0 && o.cmp_ritz != 1) ||
         (o.neighbours != HSOLVE_NEIGHBOURS_FOOTPRINT && o.neighbours != HSOLVE_NEIGHBOURS_GEOMETRIC))
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;

@@ -133,89 +133,171 @@ __device__ inline void block_sums_1b(double* v, int nv, SH& S, int& parity) {
     }
 }
 
-// Householder tridiagonalisation of the symmetric nn x nn matrix H (column-major, ld):
-// reflector j acts on rows j+1.., its vector (first entry 1, implicit) is kept in
-// H(j+2.., j) with tau[j]; diagonal -> d, sub-diagonal -> e (e[nn-1] = 0).
-// With nbr > 0, the nbr border rows in LDS (Bl[r bst + l] = entry (r, l), l < nn) are
-// multiplied on the right by every reflector, so [D, B; B^T, H] stays similar to the bordered
-// result.
-template <class SH>
-__device__ void tridiagonalize(double* H, int ld, int nn, SH& S, double* Bl = nullptr, int bst = 0,
-                               int nbr = 0) {
-    constexpr int NTH = SH::nth;
-    const int tid = threadIdx.x;
+// Householder tridiagonalisation of a symmetric matrix (column-major, ld), unblocked, for the
+// trailing part T = H(j0.., j0..) of an nn x nn matrix, n = nn - j0 <= NG RB = 16 CB:
+// reflector j acts on rows j+1.., its vector (first entry 1, implicit) is kept in H(j+2.., j)
+// with tau[j]; diagonal -> d, sub-diagonal -> e (e[nn-1] = 0). With nbr > 0, the nbr border
+// rows in LDS (Bl[r bst + l] = entry (r, l), l < nn) are multiplied on the right by every
+// reflector, so [D, B; B^T, H] stays similar to the bordered result.
+// Thread (row group rg, column block cb) keeps T(RB rg + a, CB cb + b) in registers for the
+// whole reduction; the 16 column blocks of a row group are the 16 lanes of one DPP row, so a
+// row of T v is summed in four DPP steps. Per reflector: its column is staged in LDS (colb,
+// two buffers by the parity of the column: the update phase still reads one while the next
+// column is written to the other) and every wave forms the reflector from it (the same
+// arithmetic in each); the products p = tau T v go to LDS (pbuf) for the column side of the
+// rank-2 update, with p^T v (and the border rows' products with v) in one block reduction.
+// Two barriers per reflector. LDS scratch: 3 NG RB doubles.
+template <int RB, int CB, class SH, class PH>
+__device__ void tridiag_regs(PH H, int ld, int j0, int nn, SH& S, double* Bl, int bst, int nbr, double* scratch) {
+    constexpr int NTH = SH::nth, NG = NTH / 16, RTN = NG * RB;
+    static_assert(RTN == 16 * CB, "the register tiles cover a square");
+    const int tid = threadIdx.x, lane = tid % WAVE, wv = __builtin_amdgcn_readfirstlane(tid / WAVE);
+    const int cb = lane % 16, rg = wv * (WAVE / 16) + lane / 16;
+    const int r0 = RB * rg, c0 = CB * cb;
+    const int n = nn - j0;
+    if (n <= 0) return;
+    PH T = H + j0 + size_t(j0) * ld;
+    double A[RB][CB];
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b)
+            A[a][b] = (r0 + a < n && c0 + b < n) ? T[(r0 + a) + size_t(c0 + b) * ld] : 0.0;
     int parity = 0;
-    for (int j = 0; j + 2 < nn; ++j) {
-        double* col = H + size_t(j) * ld;
-        double nrm[1] = {0.0};
-        for (int i = j + 2 + tid; i < nn; i += NTH) nrm[0] += col[i] * col[i];
-        block_sums_1b(nrm, 1, S, parity);
-        const double xn2 = nrm[0];
-        const double alpha = col[j + 1];
+    // rows of this wave: once all of them precede the reflector, its products and updates are
+    // exact zeros and the wave skips them
+    const int wave_last_row = RB * (wv + 1) * (WAVE / 16) - 1;
+    constexpr int XL = (RTN + WAVE - 1) / WAVE, BL = (RTN + NTH - 1) / NTH;
+    // All LDS reads below are unconditional (indexes stay inside the buffers) and the
+    // conditions select among loaded values, so that the reads of a step issue together.
+    for (int jl = 0; jl + 2 < n; ++jl) {
+        const int j = j0 + jl;
+        double* colb = scratch + (jl & 1) * RTN;
+        double* pbuf = scratch + 2 * RTN;
+        // column jl (all rows; zeros past n) into LDS by its column block
+        if (cb == jl / CB) {
+            const int bs = jl % CB;
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+                if (b == bs) {
+#pragma unroll
+                    for (int a = 0; a < RB; ++a) colb[r0 + a] = A[a][b];
+                }
+        }
+        __syncthreads();
+        double xs = 0.0;
+#pragma unroll
+        for (int u = 0; u < XL; ++u) {
+            const int r = jl + 2 + lane + u * WAVE;
+            const double x = colb[min(r, RTN - 1)];
+            xs += (r < n) ? x * x : 0.0;
+        }
+        const double xn2 = wave_sum(xs);
+        const double alpha = colb[jl + 1], dj = colb[jl];
         double tau = 0.0, beta = alpha, scal = 0.0;
         if (xn2 > 0.0) {
             beta = -copysign(sqrt(alpha * alpha + xn2), alpha);
             tau = (beta - alpha) / beta;
             scal = 1.0 / (alpha - beta);
         }
-        const int len = nn - j - 1;
-        // the reflector, kept scaled in col(j+2..) and in S.v (each thread its own entries)
-        for (int i = tid; i < len; i += NTH) {
-            const double v = (i == 0) ? 1.0 : col[j + 1 + i] * scal;
-            if (i > 0) col[j + 1 + i] = v;
-            S.v[i] = v;
-        }
         if (tid == 0) {
-            S.tau[j] = tau;
+            S.d[j] = dj;
             S.e[j] = beta;
+            S.tau[j] = tau;
         }
-        __syncthreads();
-        if (tau != 0.0) {
-            double* T22 = H + size_t(j + 1) * ld + (j + 1);
-            // w = tau A v (two adjacent lanes per row, each over half of the columns), then
-            // v^T w and the border rows' products with v in one reduction
-            double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-            const int hl = len / 2;
-            for (int tb = 0; tb < 2 * len; tb += NTH) {       // uniform trip count (the shuffle)
-                const int t = tb + tid;
-                const int i = min(t >> 1, len - 1), c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
-                double acc = (t < 2 * len) ? dot_rows(T22 + i + size_t(c0) * ld, ld, S.v + c0, c1 - c0) : 0.0;
-                acc += __shfl_xor(acc, 1, WAVE);
-                if (t < 2 * len && !(t & 1)) {
-                    acc *= tau;
-                    S.w[i] = acc;
-                    pv[0] += acc * S.v[i];
+        for (int r = jl + 2 + tid; r < n; r += NTH) T[r + size_t(jl) * ld] = colb[r] * scal;
+        if (tau == 0.0) continue;             // uniform: no barrier is skipped by part of the group
+        // reflector entries of this thread's rows and columns (v(jl+1) = 1, zero above)
+        double vr[RB], vc[CB], xr[RB], xc[CB];
+#pragma unroll
+        for (int a = 0; a < RB; ++a) xr[a] = colb[r0 + a];
+#pragma unroll
+        for (int b = 0; b < CB; ++b) xc[b] = colb[c0 + b];
+#pragma unroll
+        for (int a = 0; a < RB; ++a) vr[a] = (r0 + a == jl + 1) ? 1.0 : (r0 + a > jl + 1 ? xr[a] * scal : 0.0);
+#pragma unroll
+        for (int b = 0; b < CB; ++b) vc[b] = (c0 + b == jl + 1) ? 1.0 : (c0 + b > jl + 1 ? xc[b] * scal : 0.0);
+        // (with one wave per SIMD the last wave sets the pace: skipping gains nothing there)
+        const bool active = NTH <= 256 || wave_last_row > jl;
+        double p[RB];
+#pragma unroll
+        for (int a = 0; a < RB; ++a) p[a] = 0.0;
+        if (active) {
+#pragma unroll
+            for (int b = 0; b < CB; ++b)
+#pragma unroll
+                for (int a = 0; a < RB; ++a) p[a] += A[a][b] * vc[b];
+#pragma unroll
+            for (int a = 0; a < RB; ++a) {
+                const double y = row16_sum(p[a]) * tau;
+                p[a] = (r0 + a > jl) ? y : 0.0;
+            }
+        }
+        double pv[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        if (cb == 0) {
+#pragma unroll
+            for (int a = 0; a < RB; ++a) {
+                pbuf[r0 + a] = p[a];
+                pv[0] += p[a] * vr[a];
+            }
+        }
+        // border rows: entries (r, j + 1 + l) of Bl times v(l), l over the trailing coordinates
+        double vb[BL];
+#pragma unroll
+        for (int u = 0; u < BL; ++u) {
+            const int l = jl + 1 + tid + u * NTH;
+            const double x = colb[min(l, RTN - 1)];
+            vb[u] = (l == jl + 1) ? 1.0 : (l < n ? x * scal : 0.0);
+        }
+        if (nbr > 0) {
+#pragma unroll
+            for (int u = 0; u < BL; ++u) {
+                const int l = jl + 1 + tid + u * NTH;
+                if (l < n) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < nbr) pv[1 + r] += Bl[r * bst + j0 + l] * vb[u];
                 }
             }
-            double* B1 = nbr ? Bl + (j + 1) : nullptr;
-            for (int l = tid; l < len; l += NTH) {
+        }
+        block_sums_1b(pv, 1 + nbr, S, parity);
+        const double K = 0.5 * tau * pv[0];
+        if (active) {
+            double wc[CB];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < nbr) pv[1 + r] += B1[r * bst + l] * S.v[l];
-            }
-            block_sums_1b(pv, 1 + nbr, S, parity);
-            const double K = 0.5 * tau * pv[0];
-            for (int t = tid; t < 2 * len; t += NTH)        // the owners of S.w finish it
-                if (!(t & 1)) S.w[t >> 1] -= K * S.v[t >> 1];
-            for (int l = tid; l < len; l += NTH) {
+            for (int b = 0; b < CB; ++b) wc[b] = pbuf[c0 + b];
 #pragma unroll
-                for (int r = 0; r < 4; ++r)
-                    if (r < nbr) B1[r * bst + l] -= tau * pv[1 + r] * S.v[l];
+            for (int b = 0; b < CB; ++b) wc[b] -= K * vc[b];
+#pragma unroll
+            for (int a = 0; a < RB; ++a) {
+                const double wr = p[a] - K * vr[a];
+#pragma unroll
+                for (int b = 0; b < CB; ++b) A[a][b] = fma(-vr[a], wc[b], fma(-wr, vc[b], A[a][b]));
             }
-            __syncthreads();
-            for (int t = tid; t < 2 * len; t += NTH) {
-                const int i = t >> 1, c0 = (t & 1) ? hl : 0, c1 = (t & 1) ? len : hl;
-                rank2_row(T22 + i + size_t(c0) * ld, ld, S.v[i], S.w[i], S.v + c0, S.w + c0, c1 - c0);
+        }
+        if (nbr > 0) {
+#pragma unroll
+            for (int u = 0; u < BL; ++u) {
+                const int l = jl + 1 + tid + u * NTH;
+                if (l < n) {
+#pragma unroll
+                    for (int r = 0; r < 4; ++r)
+                        if (r < nbr) Bl[r * bst + j0 + l] -= tau * pv[1 + r] * vb[u];
+                }
             }
-            __syncthreads();
         }
     }
-    for (int j = tid; j < nn; j += NTH) S.d[j] = H[j + size_t(j) * ld];
-    if (tid == 0) {
-        if (nn >= 2) {
-            S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
-            S.tau[nn - 2] = 0.0;
+    // the last diagonal entries and sub-diagonal entry, from their owners' registers
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+        for (int b = 0; b < CB; ++b) {
+            const int r = r0 + a, c = c0 + b;
+            if (r == c && r < n && r + 2 >= n) S.d[j0 + r] = A[a][b];
+            if (n >= 2 && r == n - 1 && c == n - 2) S.e[j0 + n - 2] = A[a][b];
         }
+    if (tid == 0) {
+        if (n >= 2) S.tau[j0 + n - 2] = 0.0;
         S.e[nn - 1] = 0.0;
         S.tau[nn - 1] = 0.0;
     }
@@ -274,7 +356,7 @@ __device__ inline void symv_part(const HS_G double* A, int ld, const double* v, 
     }
 }
 
-// Blocked form of tridiagonalize for matrices in global memory (same outputs): reflectors
+// Blocked form of the tridiagonalisation for matrices in global memory (same outputs): reflectors
 // are generated TRI_NB columns at a time; inside a panel the trailing matrix is not
 // updated, its product with each new reflector is corrected with the panel's earlier
 // reflectors V and update vectors W (A_cur = A - V W^T - W V^T), and the whole trailing
@@ -296,7 +378,10 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
         }
     };
     phase(-1);
-    for (int j0 = 0; j0 < nref; j0 += TRI_NB) {
+    // panels while the trailing matrix is larger than the register-resident form holds
+    constexpr int RT_RB = 5, RT_CB = 10, RT_N = (NTH / 16) * RT_RB;
+    int j0 = 0;
+    for (; j0 < nref && nn - j0 > RT_N; j0 += TRI_NB) {
         const int nb = min(TRI_NB, nref - j0);
         for (int i = 0; i < nb; ++i) {
             const int j = j0 + i;
@@ -519,16 +604,9 @@ __device__ void tridiagonalize_blk(HS_G double* H, int ld, int nn, SH& S, double
     }
     if (prof && tid == 0)
         for (int k = 0; k < 8; ++k) prof[k] = pc[k];
-    for (int j = tid; j < nn; j += NTH) S.d[j] = H[j + size_t(j) * ld];
-    if (tid == 0) {
-        if (nn >= 2) {
-            S.e[nn - 2] = H[(nn - 1) + size_t(nn - 2) * ld];
-            S.tau[nn - 2] = 0.0;
-        }
-        S.e[nn - 1] = 0.0;
-        S.tau[nn - 1] = 0.0;
-    }
-    __syncthreads();
+    for (int j = tid; j < j0; j += NTH) S.d[j] = H[j + size_t(j) * ld];
+    // the rest in registers (the panel buffers are free now)
+    tridiag_regs<RT_RB, RT_CB>(H, ld, j0, nn, S, Bl, bst, nbr, Vl);
 }
 
 // number of eigenvalues of the tridiagonal (d, e) below x
@@ -968,7 +1046,7 @@ static_assert(TRI_LDS_DOUBLES >= 3 * 8 * CMP_MAX + 4 * 64, "GC block reflection 
 
 template <bool LDS, int MAXN>
 __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,
-                                                    int* rank) {
+                                                    int* rank, int* extra, int kx_max) {
     constexpr int NTH = LDS ? NT : CMP_GLOBAL_NT;
     extern __shared__ double lds[];
     __shared__ CmpShared<MAXN, NTH> S;
@@ -989,7 +1067,7 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
     // inlined, so that sizes and strides stay scalar (an outlined call passes them in vector
     // registers and every branch on them becomes divergent)
     auto tri = [&](HPtr A, int n, double* Bl, int nbr) __attribute__((always_inline)) {
-        if constexpr (LDS) tridiagonalize(A, LDL, n, S, Bl, MAXN, nbr);
+        if constexpr (LDS) tridiag_regs<8, 8>(A, LDL, 0, n, S, Bl, MAXN, nbr, lds + size_t(m) * LDL);
         else tridiagonalize_blk(A, ld, n, S, Bl, MAXN, nbr, lds, lds + TRI_NB * MAXN, lds + 2 * TRI_NB * MAXN,
                                 T.tstamp ? T.tstamp + 8 : nullptr);
     };
@@ -1149,6 +1227,9 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
         k2 = 0;
         q = 1;
     }
+    // eigenvectors past the threshold for the Rayleigh-Ritz refinement of the last kept
+    // directions (none when nothing is truncated); the later kernels compute k2 + kx vectors
+    const int kx = (kx_max > 0 && eps > 0.0 && gmax > 0.0 && k2 > 0) ? max(0, min(kx_max, cap - k2)) : 0;
     for (int i = tid; i < nn; i += NTH) {
         Wk.d[i] = S.d[i];
         Wk.e[i] = S.e[i];
@@ -1158,13 +1239,14 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
         for (int e = tid; e < m * m; e += NTH) Wk.H[e] = H[(e % m) + (e / m) * ld];
     if (tid == 0) {
         Wk.info[INF_Q] = q;
-        Wk.info[INF_K2] = k2;
+        Wk.info[INF_K2] = k2 + kx;
         Wk.info[INF_NN] = nn;
         Wk.info[INF_TNORM] = S.scal[3];
         Wk.info[INF_PIVMIN] = S.scal[2];
         Wk.info[INF_LO] = S.scal[0];
         Wk.info[INF_HI] = S.scal[1];
         rank[T.id] = q + k2;
+        if (extra) extra[T.id] = kx;
     }
     stamp(6);
 }
@@ -1765,8 +1847,138 @@ void launch_gc_truncate(const CompressTask* d_tasks, int ntasks, double eps1, hi
     check_launch("k_gc_truncate");
 }
 
+// Rayleigh-Ritz on a window W (m x s, s <= 16) of the basis: the last kept directions and the
+// first ones past the threshold. One workgroup per node:
+//   C = B B^T (s x s) from B = W^T A_sw (s x wt, ld s) on the FP64 matrix cores: the 16 x 16
+//     product with K = 4 takes B's rows as both operands; the four waves take every fourth
+//     group of four columns of B and their partial products are summed in LDS;
+//   the eigenvectors of C by Jacobi in tournament order (eight disjoint rotations per step,
+//     15 steps per sweep): rotation (p, q) zeroes c_pq (tan of the angle from
+//     (c_qq - c_pp) / 2 c_pq, the smaller root); pairs with |c_pq| <= eps_mach sqrt(|c_pp c_qq|)
+//     are skipped; sweeps end when none rotates (at most 30);
+//   W's first w columns <- W times the eigenvectors of the w largest eigenvalues (each thread
+//     reads and rewrites whole rows of W, so the product is in place).
+__global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
+    typedef Mma<double> MM;
+    constexpr int R = RITZ_MAX;
+    static_assert(R == 16 && NT == 4 * WAVE, "one 16 x 16 matrix-core block per wave");
+    __shared__ double cp[NT / WAVE][R][R + 1];
+    __shared__ double a[R][R + 1], v[R][R + 1];
+    __shared__ double rc[R / 2], rs[R / 2];
+    __shared__ int rp[R / 2], rq[R / 2], inv[R], anyf;
+    const RitzTask T = tasks[blockIdx.x];
+    const int s = T.s, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
+    {
+        const HS_G double* B = gp(T.B);
+        typename MM::acc acc = MM::zero();
+        const int i = lane % 16;
+        for (int k0 = 4 * wv; k0 < T.wt; k0 += 4 * (NT / WAVE)) {
+            const int kk = k0 + lane / 16;
+            const double x = (i < s && kk < T.wt) ? B[i + size_t(kk) * s] : 0.0;
+            acc = MM::mac(x, x, acc);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cp[wv][MM::row(lane, r)][i] = acc[r];
+    }
+    __syncthreads();
+    {
+        const int i = tid % R, j = tid / R;                 // NT = R * R entries
+        double c = 0.0;
+#pragma unroll
+        for (int w = 0; w < NT / WAVE; ++w) c += (i >= j) ? cp[w][i][j] : cp[w][j][i];
+        a[i][j] = c;
+        v[i][j] = (i == j) ? 1.0 : 0.0;
+    }
+    __syncthreads();
+    // round r of the tournament: position 0 stays, the others rotate; pair i = (pos i, pos 15 - i)
+    auto player = [](int pos, int r) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (R - 1); };
+    for (int sweep = 0; sweep < 30; ++sweep) {
+        if (tid == 0) anyf = 0;
+        __syncthreads();
+        for (int r = 0; r < R - 1; ++r) {
+            if (tid < R / 2) {
+                const int pa = player(tid, r), pb = player(R - 1 - tid, r);
+                const int p = min(pa, pb), q = max(pa, pb);
+                double c = 1.0, sn = 0.0;
+                if (q < s) {
+                    const double apq = a[p][q], app = a[p][p], aqq = a[q][q];
+                    if (apq != 0.0 && fabs(apq) > DBL_EPSILON * sqrt(fabs(app * aqq))) {
+                        const double theta = (aqq - app) / (2.0 * apq);
+                        const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
+                        c = 1.0 / sqrt(t * t + 1.0);
+                        sn = t * c;
+                        anyf = 1;
+                    }
+                }
+                rp[tid] = p;
+                rq[tid] = q;
+                rc[tid] = c;
+                rs[tid] = sn;
+            }
+            __syncthreads();
+            if (tid < R * R / 2) {                      // columns p, q of A and V, row j
+                const int pi = tid / R, j = tid % R;
+                const double c = rc[pi], sn = rs[pi];
+                if (sn != 0.0) {
+                    const int p = rp[pi], q = rq[pi];
+                    const double ajp = a[j][p], ajq = a[j][q];
+                    a[j][p] = c * ajp - sn * ajq;
+                    a[j][q] = sn * ajp + c * ajq;
+                    const double vjp = v[j][p], vjq = v[j][q];
+                    v[j][p] = c * vjp - sn * vjq;
+                    v[j][q] = sn * vjp + c * vjq;
+                }
+            }
+            __syncthreads();
+            if (tid < R * R / 2) {                      // rows p, q of A, column j
+                const int pi = tid / R, j = tid % R;
+                const double c = rc[pi], sn = rs[pi];
+                if (sn != 0.0) {
+                    const int p = rp[pi], q = rq[pi];
+                    const double apj = a[p][j], aqj = a[q][j];
+                    a[p][j] = c * apj - sn * aqj;
+                    a[q][j] = sn * apj + c * aqj;
+                }
+            }
+            __syncthreads();
+        }
+        if (anyf == 0) break;                           // uniform: read after the barrier
+    }
+    if (tid < s) {
+        const double li = a[tid][tid];
+        int r = 0;
+        for (int j = 0; j < s; ++j) {
+            const double lj = a[j][j];
+            r += (lj > li || (lj == li && j < tid)) ? 1 : 0;
+        }
+        inv[r] = tid;                                   // eigenvector of the r-th largest
+    }
+    __syncthreads();
+    HS_G double* W = gp(T.W);
+    for (int row = tid; row < T.m; row += NT) {
+        double x[R];
+#pragma unroll
+        for (int c = 0; c < R; ++c) x[c] = (c < s) ? W[row + size_t(c) * T.ldw] : 0.0;
+        for (int o = 0; o < T.w; ++o) {
+            const int e = inv[o];
+            double y = 0.0;
+#pragma unroll
+            for (int c = 0; c < R; ++c) y += x[c] * v[c][e];
+            W[row + size_t(o) * T.ldw] = y;
+        }
+    }
+}
+
+void launch_comp_ritz(const RitzTask* d_tasks, int ntasks, hipStream_t s) {
+    if (ntasks <= 0) return;
+    ProfScope ps("k_comp_ritz", 0.0, s);
+    hipLaunchKernelGGL(k_comp_ritz, dim3(ntasks), dim3(NT), 0, s, d_tasks);
+    check_launch("k_comp_ritz");
+}
+
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps, int* d_rank,
-                     double flops, bool lds, int max_m, int force_lpe, int force_vectors, hipStream_t s) {
+                     int* d_extra, int kx_max, double flops, bool lds, int max_m, int force_lpe,
+                     int force_vectors, hipStream_t s) {
     if (ntasks <= 0) return;
     if (max_m > CMP_MAX)
         throw Error{HSOLVE_ERR_INVALID, "super node larger than 512 unknowns at compression"};
@@ -1776,17 +1988,18 @@ void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, doubl
             if (max_m > CMP_LDS_MAX) throw Error{HSOLVE_ERR_INVALID, "internal: LDS compression too large"};
             static std::once_flag once;
             set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<true, CMP_LDS_MAX>),
-                          size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) * sizeof(double));
-            const size_t bytes = size_t(max_m) * (CMP_LDS_MAX + 1) * sizeof(double);
+                          (size_t(CMP_LDS_MAX) * (CMP_LDS_MAX + 1) + 3 * CMP_LDS_MAX) * sizeof(double));
+            // the matrix, then the register-resident tridiagonalisation's scratch
+            const size_t bytes = (size_t(max_m) * (CMP_LDS_MAX + 1) + 3 * CMP_LDS_MAX) * sizeof(double);
             hipLaunchKernelGGL((k_comp_reduce<true, CMP_LDS_MAX>), dim3(ntasks), dim3(NT), bytes, s,
-                               d_tasks, variant, eps, d_rank);
+                               d_tasks, variant, eps, d_rank, d_extra, kx_max);
             check_launch("k_comp_reduce<lds>");
         } else {
             const size_t bytes = size_t(TRI_LDS_DOUBLES) * sizeof(double);
             static std::once_flag once;
             set_lds_limit(once, reinterpret_cast<const void*>(&k_comp_reduce<false, CMP_MAX>), bytes);
             hipLaunchKernelGGL((k_comp_reduce<false, CMP_MAX>), dim3(ntasks), dim3(CMP_GLOBAL_NT), bytes, s, d_tasks,
-                               variant, eps, d_rank);
+                               variant, eps, d_rank, d_extra, kx_max);
             check_launch("k_comp_reduce<global>");
         }
     }

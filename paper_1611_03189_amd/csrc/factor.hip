@@ -240,7 +240,7 @@ static void factor_t(Plan& P, const double* values_in) {
             HS_HIP(hipEventCreateWithFlags(&P.ev_done, hipEventDisableTiming));
         }
         if (!P.h_flags)
-            HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_flags), sizeof(int) * (size_t(2) << nlev) + 64,
+            HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_flags), sizeof(int) * (size_t(4) << nlev) + 64,
                                  hipHostMallocDefault));
         HS_HIP(hipStreamSynchronize(P.side));
         HS_HIP(hipStreamSynchronize(st));
@@ -494,7 +494,10 @@ static void factor_t(Plan& P, const double* values_in) {
                 comp.push_back(CompNode{s, slot, wt, Asw, U, nullptr});
                 ctasks.push_back(CompressTask{Gd, Zd, work, U, nullptr, m, gc ? 2 * p : 0, wt, slot});
             }
-            int* d_rank = P.spool.alloc_n<int>(std::max<size_t>(1, comp.size()));
+            // kept count per node, then (with the refinement) the extra eigenvectors computed past it
+            const bool ritz = !F32 && eps > 0.0 && P.opt.cmp_ritz != 0;
+            int* d_rank = P.spool.alloc_n<int>(2 * std::max<size_t>(1, comp.size()));
+            int* d_extra = ritz ? d_rank + comp.size() : nullptr;
             long long* d_stamp = nullptr;
             if (trace && !ctasks.empty()) {
                 d_stamp = P.spool.alloc_n<long long>(16 * ctasks.size());
@@ -529,8 +532,9 @@ static void factor_t(Plan& P, const double* values_in) {
                 if (part.empty()) continue;
                 const CompressTask* d_part = P.stage.upload_vec(part, P.spool, st);
                 if (!dry)
-                    launch_compress(d_part, int(part.size()), cmp_variant, eps, d_rank, cflops, !big, max_m,
-                                    P.opt.cmp_lpe, P.opt.cmp_vectors, st);
+                    launch_compress(d_part, int(part.size()), cmp_variant, eps, d_rank, d_extra,
+                                    ritz ? RITZ_EXTRA : 0, cflops, !big, max_m, P.opt.cmp_lpe, P.opt.cmp_vectors,
+                                    st);
             }
             if (!dry) {
                 // the pivot blocks of this colour may still run on the side stream: their failure
@@ -538,7 +542,7 @@ static void factor_t(Plan& P, const double* values_in) {
                 if (overlap) HS_HIP(hipStreamWaitEvent(st, P.ev_done, 0));
                 HS_HIP(hipMemcpyAsync(h_flags, d_fail, sizeof(int) * nd, hipMemcpyDeviceToHost, st));
                 if (!comp.empty())
-                    HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size(),
+                    HS_HIP(hipMemcpyAsync(h_flags + nd, d_rank, sizeof(int) * comp.size() * (ritz ? 2 : 1),
                                           hipMemcpyDeviceToHost, st));
                 HS_HIP(hipStreamSynchronize(st));
                 P.stage.reset();
@@ -549,6 +553,7 @@ static void factor_t(Plan& P, const double* values_in) {
                         throw Error{HSOLVE_ERR_NOT_SPD, "pivot block not positive definite"};
                     }
             }
+            std::vector<int> kxs(comp.size(), 0);
             for (const CompNode& cn : comp) {
                 // the replay takes the largest rank the compression can return:
                 // |U1| + k2 <= min(m, 2p + |W|) (R5: at least one column)
@@ -560,6 +565,13 @@ static void factor_t(Plan& P, const double* values_in) {
                                     ", |W| " + std::to_string(cn.wt) + ", k " + std::to_string(k) + ")"};
                 LN.ksz[cn.s] = k;
                 max_rank = std::max(max_rank, k);
+                if (ritz) {
+                    const int kx = dry ? std::min(RITZ_EXTRA, LN.msz[cn.s] - k)
+                                       : h_flags[nd + comp.size() + cn.slot];
+                    if (kx < 0 || k + kx > LN.msz[cn.s])
+                        throw Error{HSOLVE_ERR_DEVICE, "internal: extra eigenvectors out of range"};
+                    kxs[cn.slot] = kx;
+                }
             }
             double tc1 = 0.0;
             std::vector<long long> stamps;
@@ -583,9 +595,11 @@ static void factor_t(Plan& P, const double* values_in) {
                     else return B;
                 }();
                 Bd.dry = dry;
+                // (with the refinement the extra eigenvectors join the step: the window below
+                // must be orthonormal as a whole)
                 std::vector<double*> Wsc(comp.size(), nullptr);
                 for (CompNode& cn : comp) {
-                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
+                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s] + kxs[cn.slot];
                     if (k < 2) continue;
                     Wsc[cn.slot] = P.spool.alloc_n<double>(size_t(k) * k);
                     B64.gemm(Wsc[cn.slot], k, k, k, 1.0, 0.0, cn.U, m, 1, cn.U, m, 0, m);
@@ -593,7 +607,7 @@ static void factor_t(Plan& P, const double* values_in) {
                 }
                 B64.flush_gemm(P);
                 for (CompNode& cn : comp) {
-                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s];
+                    const int m = LN.msz[cn.s], k = LN.ksz[cn.s] + kxs[cn.slot];
                     if (k < 2) continue;
                     double* Un = P.spool.alloc_n<double>(size_t(m) * k);
                     B64.copy(cn.U, m, Un, m, m, k, 0);
@@ -603,6 +617,41 @@ static void factor_t(Plan& P, const double* values_in) {
                 }
                 B64.flush_copies(P);
                 B64.flush_gemm(P);
+                // Rayleigh-Ritz on the window W of the last kept directions and the extra ones
+                // (w + kx <= RITZ_MAX columns): the eigenvectors of C = (W^T A_sw)(W^T A_sw)^T
+                // rotate W, and the first w replace the kept ones. The eigenvectors of the Gram
+                // matrix separate two singular values sigma_k > eps sigma_1 > sigma_k+1 only to
+                // about u sigma_1 / (2 eps (sigma_k - sigma_k+1)); C's entries carry errors of
+                // u sigma_1 sigma_k, which resolves the pair to u sigma_1 / (sigma_k - sigma_k+1),
+                // the accuracy of an SVD of A_sw itself.
+                if constexpr (!F32) {
+                    if (ritz) {
+                        struct Win { double* W; const double* A; double* Bw; int m, wt, w, s; };
+                        std::vector<Win> win;
+                        for (CompNode& cn : comp) {
+                            const int m = LN.msz[cn.s], k = LN.ksz[cn.s], kx = kxs[cn.slot];
+                            // window: kept directions past the GC vectors (at most q_gc of them)
+                            const int w = std::min(RITZ_KEEP, k - q_gc);
+                            if (!dry && (kx <= 0 || w <= 0)) continue;
+                            // the replay counts every node at the largest window
+                            const int ss = dry ? std::min(RITZ_MAX, m) : w + kx;
+                            Win x{cn.U + (dry ? size_t(0) : size_t(k - w) * m), reinterpret_cast<const double*>(cn.Asw),
+                                  P.spool.alloc_n<double>(size_t(ss) * cn.wt), m, cn.wt, dry ? 0 : w, ss};
+                            win.push_back(x);
+                        }
+                        std::vector<RitzTask> rt;
+                        for (const Win& x : win) {
+                            B64.gemm(x.Bw, x.s, x.s, x.wt, 1.0, 0.0, x.W, x.m, 1, x.A, x.m, 0, x.m);
+                            flops += 2.0 * x.s * x.m * x.wt;
+                            rt.push_back(RitzTask{x.Bw, x.W, x.s, x.w, x.wt, x.m, x.m});
+                        }
+                        B64.flush_gemm(P);
+                        if (!rt.empty()) {
+                            const RitzTask* d_rt = P.stage.upload_vec(rt, P.spool, st);
+                            if (!dry) launch_comp_ritz(d_rt, int(rt.size()), st);
+                        }
+                    }
+                }
                 if constexpr (F32) {
                     std::vector<DemoteTask> dt;
                     double elems = 0.0;

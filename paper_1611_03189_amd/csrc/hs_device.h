@@ -86,7 +86,25 @@ __device__ inline float lane63(float v) {
 }
 
 constexpr int DPP_QUAD_1032 = 0xB1, DPP_QUAD_2301 = 0x4E, DPP_ROR4 = 0x124, DPP_ROR8 = 0x128,
-              DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+              DPP_ROW_MIRROR = 0x140, DPP_ROW_HALF_MIRROR = 0x141, DPP_BCAST15 = 0x142, DPP_BCAST31 = 0x143;
+
+// Sum over the 16 lanes of each DPP row, the same bits in every lane: a butterfly whose
+// partners swap equal partial sums (pairs, quads, then the halves of the row by mirroring),
+// so each addition is the same pair of operands in either order.
+// (Every lane's source is inside its row, so the moves need no fill value.)
+template <int CTRL>
+__device__ inline double dpp_row_move(double v) {
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
+    return __hiloint2double(hi, lo);
+}
+__device__ inline double row16_sum(double v) {
+    v += dpp_row_move<DPP_QUAD_1032>(v);
+    v += dpp_row_move<DPP_QUAD_2301>(v);
+    v += dpp_row_move<DPP_ROW_HALF_MIRROR>(v);
+    v += dpp_row_move<DPP_ROW_MIRROR>(v);
+    return v;
+}
 
 template <class T>
 __device__ inline T wave_sum(T v) {

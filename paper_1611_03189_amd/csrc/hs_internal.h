@@ -415,9 +415,22 @@ template <typename T>
 void launch_chol_inv(const CholTask* d_tasks, int ntasks, int* d_fail, double flops, bool lds,
                      int max_m, hipStream_t s);
 void launch_promote(const PromoteTask* d_tasks, int ntasks, double elems, hipStream_t s);
+// d_rank[id] = |U1| + k2 (the kept count); with kx_max > 0 also d_extra[id] = kx, the
+// eigenvectors past the threshold written after the kept ones (U columns rank .. rank + kx)
 void launch_compress(const CompressTask* d_tasks, int ntasks, int variant, double eps,
-                     int* d_rank, double flops, bool lds, int max_m, int force_lpe, int force_vectors,
-                     hipStream_t s);
+                     int* d_rank, int* d_extra, int kx_max, double flops, bool lds, int max_m,
+                     int force_lpe, int force_vectors, hipStream_t s);
+// Rayleigh-Ritz on a window W (m x s, ld ldw, s <= RITZ_MAX) of the basis, given B = W^T A_sw
+// (s x wt, ld s): W's first w columns become the eigenvectors of B B^T of the w largest
+// eigenvalues, mapped by W
+constexpr int RITZ_MAX = 16;
+constexpr int RITZ_KEEP = 8, RITZ_EXTRA = 8;   // window: kept directions, and those past the threshold
+struct RitzTask {
+    const double* B;
+    double* W;
+    int s, w, wt, m, ldw;
+};
+void launch_comp_ritz(const RitzTask* d_tasks, int ntasks, hipStream_t s);
 // Appendix B first-order one-sided projection: Z (m x nz <= 16) becomes its left singular
 // vectors above eps1 sigma_1(Z), zero columns after them
 void launch_gc_truncate(const CompressTask* d_tasks, int ntasks, double eps1, hipStream_t s);

@@ -51,7 +51,7 @@ class Options(ctypes.Structure):
         ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
         ("factor_prec", c_int), ("max_super", c_int), ("max_nrhs", c_int), ("eps_schedule", c_int),
         ("cmp_lpe", c_int), ("cmp_vectors", c_int), ("apply_graph", c_int), ("neighbours", c_int),
-        ("eps1", c_double),
+        ("eps1", c_double), ("cmp_ritz", c_int),
     ]
 
 
@@ -214,7 +214,7 @@ class HSolver:
                  overlap_pivots: bool = True, factor_prec: int = 64, max_super: int = 512,
                  max_nrhs: int = 32, eps_schedule: str = "constant", cmp_lpe: int = 0,
                  cmp_vectors: int = 0, apply_graph: bool = True, neighbours: str = "footprint",
-                 eps1: float = 0.0):
+                 eps1: float = 0.0, cmp_ritz: bool = True):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -241,6 +241,7 @@ class HSolver:
         opt.cmp_lpe = int(cmp_lpe)
         opt.cmp_vectors = int(cmp_vectors)
         opt.apply_graph = 1 if apply_graph else 0
+        opt.cmp_ritz = 1 if cmp_ritz else 0
         opt.neighbours = {"footprint": 0, "geometric": 1}[neighbours] if isinstance(neighbours, str) else int(neighbours)
         self._keep = []
         if coords is not None:
