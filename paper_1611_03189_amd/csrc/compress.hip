@@ -1872,10 +1872,17 @@ __global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
         const HS_G double* B = gp(T.B);
         typename MM::acc acc = MM::zero();
         const int i = lane % 16;
-        for (int k0 = 4 * wv; k0 < T.wt; k0 += 4 * (NT / WAVE)) {
-            const int kk = k0 + lane / 16;
-            const double x = (i < s && kk < T.wt) ? B[i + size_t(kk) * s] : 0.0;
-            acc = MM::mac(x, x, acc);
+        // eight groups of four columns per round, their loads issued before the products
+        constexpr int UR = 8, STEP = 4 * (NT / WAVE);
+        for (int k0 = 4 * wv; k0 < T.wt; k0 += UR * STEP) {
+            double x[UR];
+#pragma unroll
+            for (int u = 0; u < UR; ++u) {
+                const int kk = k0 + u * STEP + lane / 16;
+                x[u] = (i < s && kk < T.wt) ? B[i + size_t(kk) * s] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < UR; ++u) acc = MM::mac(x[u], x[u], acc);
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) cp[wv][MM::row(lane, r)][i] = acc[r];

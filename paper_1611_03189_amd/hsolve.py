@@ -241,7 +241,7 @@ class HSolver:
         opt.cmp_lpe = int(cmp_lpe)
         opt.cmp_vectors = int(cmp_vectors)
         opt.apply_graph = 1 if apply_graph else 0
-        opt.cmp_ritz = 1 if cmp_ritz else 0
+        opt.cmp_ritz = int(cmp_ritz)
         opt.neighbours = {"footprint": 0, "geometric": 1}[neighbours] if isinstance(neighbours, str) else int(neighbours)
         self._keep = []
         if coords is not None:

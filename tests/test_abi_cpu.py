@@ -122,14 +122,14 @@ def test_new_options_are_checked(lib):
     p = pb.poisson(6, 2)
     for kw in ({"factor_prec": 16}, {"max_super": 0}, {"max_super": 513}, {"max_nrhs": 0},
                {"eps_schedule": 3}, {"cmp_lpe": 3}, {"cmp_lpe": 128}, {"cmp_vectors": 3},
-               {"variant": 3}, {"eps1": -0.1}, {"eps1": 1.0}, {"neighbours": 2}):
+               {"variant": 3}, {"eps1": -0.1}, {"eps1": 1.0}, {"neighbours": 2}, {"cmp_ritz": 2}):
         with pytest.raises(H.HSolveError) as e:
             H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
         assert e.value.status == -1, kw
     for kw in ({"eps_schedule": "shrink"}, {"eps_schedule": "grow"}, {"cmp_lpe": 8, "cmp_vectors": 1},
                {"cmp_lpe": 1, "cmp_vectors": 2}, {"max_super": 64, "max_nrhs": 4},
                {"variant": "gc_proj1", "eps1": 1e-2}, {"neighbours": "geometric"},
-               {"factor_prec": 32, "krylov": "fpcg"}):
+               {"factor_prec": 32, "krylov": "fpcg"}, {"cmp_ritz": False}):
         with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
             assert S.arena_bound > 0
 

@@ -105,6 +105,29 @@ def test_c2_lognormal_256_matches_oracle():
     S.close()
 
 
+def test_ritz_refinement_on_and_off_match_oracle():
+    """The Rayleigh-Ritz refinement of the last kept directions (option cmp_ritz): on the 256^2
+    lognormal case both settings meet the FP64 bar against the oracle (whose compression is an
+    SVD of A_sw), the refinement's kernel runs only when it is on, and it changes the basis."""
+    say("ritz on/off c2_lognormal2d_256")
+    p, w = pb.workload("c2_lognormal2d_256")
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=w["leaf"], eps=w["eps"], variant=O.GC)
+    r = pb.rhs(p.n, 1, 7)
+    z_ref = O.apply(F, r)
+    zs = {}
+    for on in (True, False):
+        S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=w["leaf"], eps=w["eps"], cmp_ritz=on)
+        S.profile_begin()
+        S.factor(torch.from_numpy(p.values).cuda())
+        kernels = compression_kernels(S)
+        say("cmp_ritz", on, kernels)
+        assert ("k_comp_ritz" in kernels) == on
+        zs[on] = S.apply(torch.from_numpy(np.ascontiguousarray(r)).cuda()).cpu().numpy()
+        check_parity(F, S, zs[on], z_ref, f"c2 cmp_ritz={on}")
+        S.close()
+    assert not np.array_equal(zs[True], zs[False])
+
+
 @pytest.mark.slow
 def test_c3_poisson_64_matches_stored_oracle():
     say("c3_poisson3d_64 vs stored oracle")
