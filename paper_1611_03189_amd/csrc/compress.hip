@@ -18,7 +18,8 @@
 //                  most four kept vectors by multisection on the tridiagonal form bordered
 //                  by the kept directions, which is similar to G; otherwise G itself is
 //                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
-//   k_comp_bisect  (1 to 64 lanes per kept eigenvalue) multisection to eps ||T||;
+//   k_comp_bisect  (1 to 64 lanes per kept eigenvalue) multisection until the bracket stops
+//                  shrinking in floating point;
 //   k_comp_vectors (one lane per kept eigenvalue) / k_comp_vectors_wave (one wave each)
 //                  inverse iteration;
 //   k_comp_orth    the vectors of each cluster of eigenvalues closer than 1e-7 ||T|| made
@@ -1302,10 +1303,14 @@ __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
     const bool active = j < k2;
     const int a = nn - 1 - (active ? j : k2 - 1);                // a-th smallest
     const double pivmin = Wk.info[INF_PIVMIN];
-    const double tol = 2.0 * DBL_EPSILON * fmax(Wk.info[INF_TNORM], 1e-300);
+    // Each eigenvalue is bracketed to the resolution of the floating-point Sturm count: the
+    // group stops when its bracket no longer shrinks (adjacent numbers), not at an absolute
+    // tolerance. The kept eigenvalues near eps^2 lambda_max are small against ||T||, and a
+    // bracket of width u ||T|| would leave their last digits to the launch shape; inverse
+    // iteration carries those digits into the basis. So the result does not depend on LPE.
     constexpr int NP = BIS_NX * LPE;
     double lo = Wk.info[INF_LO], hi = Wk.info[INF_HI];
-    bool need = hi - lo > tol;
+    bool need = hi > lo;
     for (int round = 0; round < 64; ++round) {
         // every lane of the wave stays in the loop until all groups have converged
         int any = need ? 1 : 0;
@@ -1327,7 +1332,7 @@ __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
             if (xl == lo && xh == hi) need = false;       // no progress in floating point
             lo = xl;
             hi = xh;
-            if (!(hi - lo > tol)) need = false;
+            if (!(hi > lo)) need = false;
         }
     }
     if (active && g == 0) Wk.lam[j] = 0.5 * (lo + hi);

@@ -105,6 +105,23 @@ def test_c2_lognormal_256_matches_oracle():
     S.close()
 
 
+@pytest.mark.parametrize("case", sorted(SHAPE_CASES))
+def test_eigenvalues_do_not_depend_on_launch_shape(case):
+    """The multisection brackets every eigenvalue to adjacent floating-point numbers, so the
+    factorization is the same bits for 1, 8 and 64 lanes per eigenvalue."""
+    say("lpe-invariance", case)
+    p, F = _oracle_case(case)
+    _, leaf, eps = SHAPE_CASES[case]
+    r = torch.from_numpy(np.ascontiguousarray(pb.rhs(p.n, 1, 7))).cuda()
+    zs = []
+    for lpe in (1, 8, 64):
+        S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=eps, cmp_lpe=lpe)
+        S.factor(torch.from_numpy(p.values).cuda())
+        zs.append(S.apply(r).cpu().numpy())
+        S.close()
+    assert np.array_equal(zs[0], zs[1]) and np.array_equal(zs[0], zs[2])
+
+
 def test_ritz_refinement_on_and_off_match_oracle():
     """The Rayleigh-Ritz refinement of the last kept directions (option cmp_ritz): on the 256^2
     lognormal case both settings meet the FP64 bar against the oracle (whose compression is an
