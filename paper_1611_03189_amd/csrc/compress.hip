@@ -1339,12 +1339,16 @@ __global__ __launch_bounds__(NT) void k_comp_bisect(const CompressTask* tasks) {
 }
 
 // Inverse iteration for the kept eigenvalues, one lane per eigenvalue (VL per workgroup), in
-// trailing coordinates: three times, the LU factorisation with partial pivoting of T - lambda I
+// trailing coordinates: INV_ITERS times, the LU factorisation with partial pivoting of T - lambda I
 // (the steps of tridiag_shift_factor) with the forward elimination applied to y on the way,
 // then the back substitution and the normalisation. Each lane keeps its vector and factors in
 // the node's work buffer, lane-interleaved (row i of all lanes is one coalesced access), and
 // reads eight rows ahead of its sequential recurrence.
 constexpr int VL = 64;
+// Passes of inverse iteration. The shifts are the eigenvalues to the last bit, so one solve
+// already damps a neighbour at distance g by about ulp(lambda) / g; the second leaves it far
+// below rounding.
+constexpr int INV_ITERS = 2;
 
 __global__ __launch_bounds__(VL) void k_comp_vectors(const CompressTask* tasks) {
     __shared__ double d[CMP_MAX], e[CMP_MAX];
@@ -1368,7 +1372,7 @@ __global__ __launch_bounds__(VL) void k_comp_vectors(const CompressTask* tasks) 
     auto at = [&](int f, int i) -> HS_G double& { return base[(size_t(f) * m + i) * VL]; };   // 0 y, 1 r0, 2 u1, 3 u2
     for (int i = 0; i < nn; ++i) at(0, i) = start_value(i, c);
     double inv = 1.0;
-    for (int it = 0; it < 3; ++it) {
+    for (int it = 0; it < INV_ITERS; ++it) {
         double p0 = d[0] - lamc, p1 = nn > 1 ? e[0] : 0.0, p2 = 0.0;
         double yc = at(0, 0) * inv;                 // current y_i after the earlier eliminations
         for (int i0 = 0; i0 + 1 < nn; i0 += 8) {
@@ -1491,7 +1495,7 @@ __global__ __launch_bounds__(VNT) void k_comp_vectors_wave(const CompressTask* t
     for (int i = lane; i < nn; i += WAVE) y[i] = start_value(i, c);
     wave_sync();
     if (lane == 0) tridiag_shift_factor(d, e, nn, lam[c], tiny, u0, u1, u2, mult, swp);
-    for (int it = 0; it < 3; ++it) {
+    for (int it = 0; it < INV_ITERS; ++it) {
         wave_sync();
         if (lane == 0) tridiag_shift_apply(nn, u0, u1, u2, mult, swp, y);
         wave_sync();
