@@ -645,6 +645,12 @@ __device__ void tridiag_bounds(int nn, SH& S) {
     __syncthreads();
 }
 
+// Rounds of the 257-point multisections for lambda_max. It only sets the threshold
+// eps^2 lambda_max of the kept count, so 5 rounds suffice: the bracket is 257^-5 < 2^-40 of
+// its start interval (at most ||G||_F <= sqrt(m) lambda_max wide), a relative error below
+// 2e-11, and a rank decided closer than that to the threshold is a tie in any arithmetic.
+constexpr int BL_ROUNDS = 5;
+
 // largest eigenvalue by parallel multisection (after tridiag_bounds)
 template <class SH>
 __device__ double largest_eigenvalue(int nn, SH& S) {
@@ -653,7 +659,7 @@ __device__ double largest_eigenvalue(int nn, SH& S) {
     double lo = S.scal[0], hi = S.scal[1];
     const double pivmin = S.scal[2];
     constexpr int NP = NTH < 256 ? NTH : 256;          // points per round (threads taking part)
-    for (int round = 0; round < 10; ++round) {
+    for (int round = 0; round < BL_ROUNDS; ++round) {
         const double x = lo + (hi - lo) * double(tid + 1) / double(NP + 1);
         if (tid < NP) S.pts[tid] = sturm_count(S.d, S.e, nn, x, pivmin) == nn ? 1 : 0;
         __syncthreads();
@@ -786,7 +792,7 @@ __device__ inline int block_min_int(int v, SH& S) {
 // largest eigenvalue of the bordered matrix by multisection of [lo, hi] (lo below it): each
 // round evaluates one point per thread on up to 256 threads (more waves per SIMD would slow
 // the latency-bound recurrences) and keeps the subinterval where the count above x drops to
-// zero
+// zero (BL_ROUNDS rounds).
 template <class SH>
 __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
     constexpr int NTH = SH::nth;
@@ -797,7 +803,7 @@ __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
         // one point per thread: with one wave per SIMD the interleaved recurrences of several
         // points are bound by instruction issue, one recurrence by its latency only
         constexpr int NX = 1, NP = NX * NPT;
-        for (int round = 0; round < 7; ++round) {      // (NP + 1)^7 > 2^56
+        for (int round = 0; round < BL_ROUNDS; ++round) {
             double x[NX];
             int cnt[NX];
 #pragma unroll
@@ -817,7 +823,7 @@ __device__ double bordered_largest(int nn, int q, double lo, double hi, SH& S) {
         }
         return 0.5 * (lo + hi);
     }
-    for (int round = 0; round < 7; ++round) {      // (NPT + 1)^7 > 2^56
+    for (int round = 0; round < BL_ROUNDS; ++round) {
         const double x = lo + (hi - lo) * double(tid + 1) / double(NPT + 1);
         const int first =
             (tid < NPT && bordered_count_above(S.d, S.e, nn, S.bord, S.dq, q, x, pivmin) == 0) ? tid : NPT;
