@@ -925,7 +925,7 @@ __device__ void reflect_two_sided(PH H, int ld, int m, PV v, double tau, SH& S) 
 template <class SH>
 __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_G double* gcv,
                                  const HS_G double* gct, double* buf, SH& S) {
-    constexpr int NTH = SH::nth;
+    constexpr int NTH = SH::nth, GR = 16;
     const int tid = threadIdx.x;
     double* Vs = buf;
     double* Y = Vs + size_t(q) * m;
@@ -943,13 +943,14 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
         const int i = min(t >> 1, m - 1), c0 = (t & 1) ? hm : 0, c1 = (t & 1) ? m : hm;
         double acc[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (t < 2 * m) {
+            // GR columns per round: their loads are in flight together (same order of sums)
             int l = c0;
-            for (; l + 4 <= c1; l += 4) {
-                double h[4];
+            for (; l + GR <= c1; l += GR) {
+                double h[GR];
 #pragma unroll
-                for (int u = 0; u < 4; ++u) h[u] = H[i + size_t(l + u) * ld];
+                for (int u = 0; u < GR; ++u) h[u] = H[i + size_t(l + u) * ld];
 #pragma unroll
-                for (int u = 0; u < 4; ++u)
+                for (int u = 0; u < GR; ++u)
 #pragma unroll
                     for (int b = 0; b < 8; ++b)
                         if (b < q) acc[b] += h[u] * Vs[(l + u) + b * m];
@@ -1023,12 +1024,12 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
             vi[b] = (b < q) ? Vs[i + b * m] : 0.0;
         }
         int l = c0;
-        for (; l + 4 <= c1; l += 4) {
-            double h[4];
+        for (; l + GR <= c1; l += GR) {
+            double h[GR];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) h[u] = H[i + size_t(l + u) * ld];
+            for (int u = 0; u < GR; ++u) h[u] = H[i + size_t(l + u) * ld];
 #pragma unroll
-            for (int u = 0; u < 4; ++u) {
+            for (int u = 0; u < GR; ++u) {
 #pragma unroll
                 for (int b = 0; b < 8; ++b)
                     if (b < q) h[u] -= wi[b] * Vs[(l + u) + b * m] + vi[b] * Wm[(l + u) + b * m];
