@@ -66,6 +66,15 @@ struct Batch {
         term(A, lda, tA, B, ldb, tB, K);
         close();
     }
+    // C (M x M) = alpha A op(A) for a symmetric result: only the tiles on or below the
+    // diagonal are computed, and their lower values are mirrored (GEMM_MIRROR)
+    void gemm_sym(R* C, int ldc, int M, double alpha, const R* A, int lda, int tA, int K) {
+        if (M <= 0) return;
+        open(C, ldc, M, M, alpha, 0.0);
+        gt.back().flags |= GEMM_MIRROR;
+        term(A, lda, tA, A, lda, 1 - tA, K);
+        close();
+    }
     void flush_copies(Plan& P) {
         if (copies.empty()) return;
         double bytes = 0.0;
@@ -89,9 +98,11 @@ struct Batch {
     void flush_gemm(Plan& P, bool side = false) {
         double flops = 0.0, mn = 0.0, tiles64 = 0.0;
         for (const GemmTask& t : gt) {
-            for (int q = t.t_begin; q < t.t_end; ++q) flops += 2.0 * t.M * t.N * terms[q].K;
-            mn += double(t.M) * t.N;
-            tiles64 += double((t.M + 63) / 64) * double((t.N + 63) / 64);
+            // a mirrored (symmetric) result is about half the work: its lower triangle
+            const double part = (t.flags & GEMM_MIRROR) ? 0.5 * (1.0 + 1.0 / std::max(1, t.M)) : 1.0;
+            for (int q = t.t_begin; q < t.t_end; ++q) flops += part * 2.0 * t.M * t.N * terms[q].K;
+            mn += part * double(t.M) * t.N;
+            tiles64 += part * double((t.M + 63) / 64) * double((t.N + 63) / 64);
         }
         // tile shape: the autotuned choice for this launch's size bucket; the replay lays out
         // the tiles of the smallest shape, the most of any, so its table bounds every choice
@@ -104,9 +115,14 @@ struct Batch {
             variant = gemm_variant(gemm_bucket(tiles64, mn > 0.0 ? flops / (2.0 * mn) : 0.0), sizeof(R) == 4);
         }
         const GemmShape sh = GEMM_SHAPES[variant];
-        for (size_t id = 0; id < gt.size(); ++id)
+        for (size_t id = 0; id < gt.size(); ++id) {
+            const bool mirror = (gt[id].flags & GEMM_MIRROR) != 0;
             for (int ti = 0; ti * sh.tm < gt[id].M; ++ti)
-                for (int tj = 0; tj * sh.tn < gt[id].N; ++tj) tiles.push_back(GemmTile{int(id), ti, tj, 0});
+                for (int tj = 0; tj * sh.tn < gt[id].N; ++tj) {
+                    if (mirror && tj * sh.tn >= ti * sh.tm + sh.tm) continue;   // wholly above the diagonal
+                    tiles.push_back(GemmTile{int(id), ti, tj, 0});
+                }
+        }
         if (!tiles.empty()) {
             // the three tables in one upload (one copy on the stream instead of three)
             auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
@@ -476,8 +492,8 @@ static void factor_t(Plan& P, const double* values_in) {
                     B.gemm(Z + size_t(p) * m, m, m, p, 1.0, 0.0, Asw, m, 0, phiW, wt, 0, wt);
                     flops += 2.0 * m * wt * p;
                 }
-                B.gemm(G, m, m, m, 1.0, 0.0, Asw, m, 0, Asw, m, 1, wt);
-                flops += 2.0 * m * m * wt;
+                B.gemm_sym(G, m, m, 1.0, Asw, m, 0, wt);
+                flops += double(m) * (m + 1) * wt;
                 const int slot = int(comp.size());
                 const double* Gd = reinterpret_cast<const double*>(G);
                 const double* Zd = reinterpret_cast<const double*>(Z);

@@ -179,8 +179,11 @@ struct CopyTask {            // dst(i,j) = src(i,j) or src(j,i) (trans), in the 
 
 // Flags of a GEMM task (for C) and term (for B): GEMM_REL, the pointer field holds an element
 // offset from one of the two base pointers the launch passes (GEMM_BASE1 picks the second);
-// GEMM_NEG (term), the term enters with a minus sign.
-enum { GEMM_NEG = 1, GEMM_REL = 2, GEMM_BASE1 = 4 };
+// GEMM_NEG (term), the term enters with a minus sign. GEMM_MIRROR (task, square and
+// symmetric C such as A A^T): the tiles wholly above the diagonal (tj TN >= ti TM + TM) are not
+// listed, and every element (i, j) whose transposed position lies in one of them is also
+// written to (j, i).
+enum { GEMM_NEG = 1, GEMM_REL = 2, GEMM_BASE1 = 4, GEMM_MIRROR = 8 };
 
 struct GemmTask {            // C = beta C + alpha sum_t op(A_t) op(B_t), C is M x N (launch's type)
     void* C;

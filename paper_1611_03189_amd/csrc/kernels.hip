@@ -207,7 +207,11 @@ __device__ inline void gemm_tile(const GemmTask* tasks, const GemmTerm* terms, c
                 if (i < Tk.M && j < Nc) {
                     HS_G T* c = C + i + size_t(j) * Tk.ldc;
                     const T old = (Tk.beta == 0.0) ? T(0) : beta * (*c);
-                    *c = old + alpha * acc[x][y][r];
+                    const T val = old + alpha * acc[x][y][r];
+                    *c = val;
+                    // (j, i) lies in a tile that is not listed: write its value there too
+                    if ((Tk.flags & GEMM_MIRROR) && (i / TN) * TN >= (j / TM) * TM + TM)
+                        C[j + size_t(i) * Tk.ldc] = val;
                 }
             }
 }
