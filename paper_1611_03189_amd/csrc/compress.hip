@@ -13,15 +13,17 @@
 //   k_comp_reduce  (one workgroup per node: 256 threads when the matrix sits in LDS, 512
 //                  when it stays in global memory) scale G by its largest entry (decisions are
 //                  relative); GC basis and projection; Householder tridiagonalisation of the
-//                  projected matrix (unblocked in LDS when m <= CMP_LDS_MAX, blocked by
-//                  panels of TRI_NB reflectors for larger m). lambda_max(G): for GC with at
+//                  projected matrix (unblocked, the matrix in registers, when m <= CMP_LDS_MAX;
+//                  for larger m blocked by panels of TRI_NB reflectors until the trailing
+//                  matrix fits the register form). lambda_max(G): for GC with at
 //                  most four kept vectors by multisection on the tridiagonal form bordered
 //                  by the kept directions, which is similar to G; otherwise G itself is
 //                  tridiagonalised first. Number k2 of kept eigenvalues by a Sturm count;
 //   k_comp_bisect  (1 to 64 lanes per kept eigenvalue) multisection until the bracket stops
 //                  shrinking in floating point;
 //   k_comp_vectors (one lane per kept eigenvalue) / k_comp_vectors_wave (one wave each)
-//                  inverse iteration;
+//                  inverse iteration (also for up to RITZ_EXTRA eigenvalues past the
+//                  threshold, for the refinement of the kept subspace's last directions);
 //   k_comp_orth    the vectors of each cluster of eigenvalues closer than 1e-7 ||T|| made
 //                  orthonormal (they span the cluster's invariant subspace);
 //   k_comp_wy      block reflector factors T of the tridiagonalisation (compact WY form);
@@ -1071,7 +1073,8 @@ __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const 
     else H = Wk.H;
     HS_G double* U = gp(T.U);
     const HS_G double* G = gp(T.G);
-    // Householder tridiagonalisation: unblocked in LDS, blocked for global matrices
+    // Householder tridiagonalisation: in registers for a matrix in LDS; blocked panels for a
+    // global matrix until its trailing part fits the register form
     // inlined, so that sizes and strides stay scalar (an outlined call passes them in vector
     // registers and every branch on them becomes divergent)
     auto tri = [&](HPtr A, int n, double* Bl, int nbr) __attribute__((always_inline)) {
@@ -1286,7 +1289,7 @@ __device__ __forceinline__ void sturm_counts(const double* d, const double* e, i
 
 // Kept eigenvalues (largest first) by multisection of the Gershgorin interval: a group of LPE
 // lanes per eigenvalue, each lane evaluating BIS_NX points per round (BIS_NX LPE points in
-// all), until the bracket is narrower than 2 eps ||T|| (the accuracy of the counts). Wide
+// all), until the bracket stops shrinking (adjacent floating-point numbers). Wide
 // groups finish in few rounds (latency) for few nodes; narrow groups do less total work
 // (throughput) when a launch holds many nodes. A lane's BIS_NX recurrences are interleaved:
 // several hide the latency of one division chain when the groups are narrow, while wide

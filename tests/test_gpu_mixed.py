@@ -74,6 +74,32 @@ def test_fp32_apply_close_to_oracle(name, N, dim, leaf):
     S.close()
 
 
+def test_fp32_gemm_sweeps_close_to_oracle():
+    """FP32 sweeps with six right-hand sides run as grouped GEMMs: within the FP32 bar of the
+    oracle, close to the single-column FP32 sweep, and each column independent of the others
+    (bitwise)."""
+    say("fp32 gemm sweeps")
+    N, dim, leaf = 32, 2, 16
+    p = pb.poisson(N, dim)
+    F = O.factor(p.row_ptr, p.col_idx, p.values, p.coords, leaf=leaf, eps=1e-2, variant=O.GC)
+    B = pb.rhs(p.n, 6, 37)
+    S = H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, leaf=leaf, eps=1e-2, apply_prec=32,
+                  krylov="fpcg")
+    S.factor(dev(p.values))
+    Z = S.apply(dev(B)).cpu().numpy()
+    bar = 20.0 * kappa_poisson(N, dim) * U32
+    e = rel(Z, O.apply(F, B))
+    say("fp32 gemm sweeps rel", e, "bar", bar)
+    assert 1e-12 < e <= bar, (e, bar)
+    z5 = S.apply(dev(B[:, 5])).cpu().numpy()
+    assert rel(Z[:, 5], z5) <= bar
+    B2 = B.copy()
+    B2[:, 1:] = pb.rhs(p.n, 5, 38)
+    Z2 = S.apply(dev(B2)).cpu().numpy()
+    assert np.array_equal(Z2[:, 0], Z[:, 0])
+    S.close()
+
+
 @pytest.mark.parametrize("name,make,leaf,eps", [
     ("c1_poisson2d_32", lambda: pb.poisson(32, 2), 16, 1e-2),
     ("lognormal2d_64_s2", lambda: pb.lognormal(64, 2, 2.0, 1002), 16, 1e-2),

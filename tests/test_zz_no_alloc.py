@@ -47,7 +47,8 @@ def test_static_apply_equals_apply_twice_then_smaller(apply_prec):
     S1.factor(torch.from_numpy(big.values).cuda())
     S2 = H.HSolver(small.row_ptr, small.col_idx, coords=small.coords, leaf=8, eps=1e-2, apply_prec=apply_prec)
     S2.factor(torch.from_numpy(small.values).cuda())
-    calls = [(S1, 3, 41), (S1, 1, 42), (S2, 2, 43), (S2, 1, 44)]
+    # six columns first: the sweeps run as grouped GEMMs on the static vectors
+    calls = [(S1, 6, 40), (S1, 3, 41), (S1, 1, 42), (S2, 2, 43), (S2, 1, 44)]
     for S, nrhs, seed in calls:
         R = torch.from_numpy(np.ascontiguousarray(pb.rhs(S.n, nrhs, seed).T)).cuda()
         st_s, Zs = _static(S, R)
