@@ -1884,7 +1884,7 @@ __global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
     __shared__ double cp[NT / WAVE][R][R + 1];
     __shared__ double a[R][R + 1], v[R][R + 1];
     __shared__ double rc[R / 2], rs[R / 2];
-    __shared__ int rp[R / 2], rq[R / 2], inv[R], anyf;
+    __shared__ int rp[R / 2], rq[R / 2], inv[R], anyf[2];
     const RitzTask T = tasks[blockIdx.x];
     const int s = T.s, tid = threadIdx.x, lane = tid % WAVE, wv = tid / WAVE;
     {
@@ -1918,8 +1918,12 @@ __global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
     __syncthreads();
     // round r of the tournament: position 0 stays, the others rotate; pair i = (pos i, pos 15 - i)
     auto player = [](int pos, int r) { return pos == 0 ? 0 : 1 + (pos - 1 + r) % (R - 1); };
+    // the "any rotation" flag of a sweep alternates between two slots: a slot is cleared again
+    // only after every thread has passed the next sweep's first barrier, that is after its
+    // read of the slot
     for (int sweep = 0; sweep < 30; ++sweep) {
-        if (tid == 0) anyf = 0;
+        int* anyr = &anyf[sweep & 1];
+        if (tid == 0) *anyr = 0;
         __syncthreads();
         for (int r = 0; r < R - 1; ++r) {
             if (tid < R / 2) {
@@ -1933,7 +1937,7 @@ __global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
                         const double t = copysign(1.0, theta) / (fabs(theta) + sqrt(theta * theta + 1.0));
                         c = 1.0 / sqrt(t * t + 1.0);
                         sn = t * c;
-                        anyf = 1;
+                        *anyr = 1;
                     }
                 }
                 rp[tid] = p;
@@ -1968,7 +1972,7 @@ __global__ __launch_bounds__(NT) void k_comp_ritz(const RitzTask* tasks) {
             }
             __syncthreads();
         }
-        if (anyf == 0) break;                           // uniform: read after the barrier
+        if (*anyr == 0) break;                          // uniform: read after the barrier
     }
     if (tid < s) {
         const double li = a[tid][tid];
