@@ -936,6 +936,7 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
     double* VV = Ts + 64;
     double* VY = VV + 64;
     double* Z = VY + 64;
+    double* TM = Z + 64;                     // (V^T Y) T, in LDS (a private array would need scratch)
     for (int e = tid; e < q * m; e += NTH) Vs[e] = gcv[e];
     __syncthreads();
     // Y = H V: two adjacent lanes per row, each over half of the columns
@@ -993,7 +994,7 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
             Ts[b + 8 * b] = tb;
             for (int a = b + 1; a < q; ++a) Ts[a + 8 * b] = 0.0;
         }
-        double TM[64];                                    // (V^T Y) T, then Z = T^T (V^T Y) T
+        // TM = (V^T Y) T, then Z = T^T (V^T Y) T
         for (int a = 0; a < q; ++a)
             for (int b = 0; b < q; ++b) {
                 double acc = 0.0;
@@ -1052,7 +1053,7 @@ __device__ void gc_block_reflect(HS_G double* H, int ld, int m, int q, const HS_
 // dynamic LDS of the global-matrix compression: the blocked tridiagonalisation's Vl, Wl and
 // per-wave partial products, or the GC block reflection's V, Y, Wm (q <= 8) and q x q blocks
 constexpr int TRI_LDS_DOUBLES = (2 * TRI_NB + CMP_GLOBAL_NT / WAVE + 1) * CMP_MAX;
-static_assert(TRI_LDS_DOUBLES >= 3 * 8 * CMP_MAX + 4 * 64, "GC block reflection does not fit");
+static_assert(TRI_LDS_DOUBLES >= 3 * 8 * CMP_MAX + 5 * 64, "GC block reflection does not fit");
 
 template <bool LDS, int MAXN>
 __global__ __launch_bounds__(LDS ? NT : CMP_GLOBAL_NT) void k_comp_reduce(const CompressTask* tasks, int variant, double eps,

@@ -106,6 +106,19 @@ class RequestLoop:
         self.budget = memory_budget
         self.streams = None
 
+    def _trim_cache(self):
+        """Arenas of finished requests go back to PyTorch's caching allocator, which keeps them
+        per stream. With arenas of many sizes on several streams its reserve can grow until the
+        device is full, and then an allocation of the HIP runtime itself (the scratch memory a
+        kernel's queue needs) fails. So the unused cache is released whenever less than a tenth
+        of the device is free."""
+        if self._factory is not None:
+            return
+        import torch
+        free, total = torch.cuda.mem_get_info()
+        if free < total // 10:
+            torch.cuda.empty_cache()
+
     def _solver(self, r: Request):
         if self._factory is not None:
             return self._factory(r)
@@ -216,6 +229,7 @@ class RequestLoop:
                     summary.results.append(Result(r.rid, x.reshape(r.n, -1), st["iterations"], st["converged"],
                                                   st["rel_residual"], dev, r.arrival, t_start, t_done, slot))
                     lock.notify_all()
+                self._trim_cache()
 
         threads = [threading.Thread(target=analyser, daemon=True) for _ in range(self.analysers)]
         threads += [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.slots)]
