@@ -28,6 +28,9 @@ import numpy as np
 
 from . import hsolve as H
 
+# device memory kept free for the HIP runtime's own allocations (queue scratch, internal buffers)
+RUNTIME_HEADROOM = 4 << 30
+
 
 @dataclass
 class Request:
@@ -106,19 +109,6 @@ class RequestLoop:
         self.budget = memory_budget
         self.streams = None
 
-    def _trim_cache(self):
-        """Arenas of finished requests go back to PyTorch's caching allocator, which keeps them
-        per stream. With arenas of many sizes on several streams its reserve can grow until the
-        device is full, and then an allocation of the HIP runtime itself (the scratch memory a
-        kernel's queue needs) fails. So the unused cache is released whenever less than a tenth
-        of the device is free."""
-        if self._factory is not None:
-            return
-        import torch
-        free, total = torch.cuda.mem_get_info()
-        if free < total // 10:
-            torch.cuda.empty_cache()
-
     def _solver(self, r: Request):
         if self._factory is not None:
             return self._factory(r)
@@ -131,7 +121,15 @@ class RequestLoop:
         import torch
         with torch.cuda.stream(stream):
             S.set_stream(stream)
-            arena = torch.empty(max(S.arena_bound, 256), dtype=torch.uint8, device="cuda")
+            need = max(S.arena_bound, 256)
+            # Arenas of finished requests stay in PyTorch's caching allocator, per stream; with
+            # many sizes on several streams its reserve can fill the device, and then an
+            # allocation of the HIP runtime itself (a queue's scratch memory) fails. Unless this
+            # arena fits with RUNTIME_HEADROOM left free, the unused cache is released first.
+            free, _ = torch.cuda.mem_get_info()
+            if free < need + RUNTIME_HEADROOM:
+                torch.cuda.empty_cache()
+            arena = torch.empty(need, dtype=torch.uint8, device="cuda")
             B = torch.from_numpy(np.ascontiguousarray(r.b)).to("cuda")
             stream.synchronize()
             S.factor(r.values, arena=arena)          # host values: copied into the arena
@@ -229,7 +227,6 @@ class RequestLoop:
                     summary.results.append(Result(r.rid, x.reshape(r.n, -1), st["iterations"], st["converged"],
                                                   st["rel_residual"], dev, r.arrival, t_start, t_done, slot))
                     lock.notify_all()
-                self._trim_cache()
 
         threads = [threading.Thread(target=analyser, daemon=True) for _ in range(self.analysers)]
         threads += [threading.Thread(target=worker, args=(i,), daemon=True) for i in range(self.slots)]
