@@ -78,6 +78,14 @@ enum { HSOLVE_EPS_CONSTANT = 0, HSOLVE_EPS_SHRINK = 1, HSOLVE_EPS_GROW = 2 };
               clusters (boxes of their cells) are well separated when the Euclidean gap
               between the boxes exceeds the larger box side, and neighbours otherwise */
 enum { HSOLVE_NEIGHBOURS_FOOTPRINT = 0, HSOLVE_NEIGHBOURS_GEOMETRIC = 1 };
+/* order in which the super nodes of a level are eliminated (§3.2 leaves it open); both rules
+   eliminate colour by colour, a colour being a set of nodes without blocks between them, built
+   by one greedy pass over the nodes not yet eliminated and then eliminated in index order:
+   INDEX    the pass visits the nodes in index order;
+   WAITING  the pass visits first the nodes with the most partners (nodes with a block to
+            them) not yet eliminated at the level, ties by index. It packs the colours
+            tighter: fewer colours per level, so fewer batched steps in the factorization */
+enum { HSOLVE_ORDER_INDEX = 0, HSOLVE_ORDER_WAITING = 1 };
 
 typedef struct {
     int leaf_size;          /* target unknowns per leaf red node (default 16); the tree
@@ -132,6 +140,7 @@ typedef struct {
                                threshold, and the window of up to 8 kept plus those is rotated by
                                the eigenvectors of (W^T A_sw)(W^T A_sw)^T; 0: the Gram matrix's
                                eigenvectors as they are */
+    int order;              /* HSOLVE_ORDER_WAITING (default) or HSOLVE_ORDER_INDEX */
 } hsolve_options;
 
 typedef struct {

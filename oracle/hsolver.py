@@ -40,9 +40,11 @@ R6  Neighbour = footprint adjacency in the original graph (§3.1); a red node ha
     footprint of its super node; N(s) / W(s) are the nodes with a block to s that are /
     are not neighbours.
 R8  Elimination order inside a level (§3.2 only asks for "a given ordering"): colour
-    by colour; each colour is chosen greedily in index order among the remaining super
-    nodes, taking a node only if it has no block to a node already in the colour. Inside
-    a colour, nodes are eliminated in index order.
+    by colour; each colour is chosen greedily among the remaining super nodes, taking a
+    node only if it has no block to a node already in the colour. The pass visits the
+    nodes in index order (order="index") or (order="waiting", the default) first the
+    nodes with the most partners (nodes with a block to them) still remaining, ties by
+    lower index. Inside a colour, nodes are eliminated in index order.
 R10 The parent-level super node I is the merge of red nodes 2I and 2I+1 of the level
     below (the two halves of its bisection).
 R11 A_nb in the formula for A~~_nn is A_ns A_ss^-1 U, so A~~_nn = A_nn - A_ns M_ss A_sn.
@@ -125,7 +127,7 @@ def compress(A_sw: np.ndarray, eps: float, variant: int,
             U U^T A_sw phi_w = A_sw phi_w and R U^T phi_s = A_ws phi_s (eq. compression_xy).
 
     ``margins``, when given, receives min_j |sigma_j / sigma_1(A_sw) - eps| over the singular
-    values the threshold decides on (reading R16: a rank decided within ~1e-8 of the
+    values the threshold decides on (reading R16: a rank decided within 1e-9 of the
     threshold can flip under rounding, so a parity case must keep clear of it).
     """
     m, wt = A_sw.shape
@@ -378,7 +380,7 @@ def _leaf_blocks(row_ptr, col_idx, values, leaves, leaf_of, n):
 def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1e-2,
            variant: int = GC, phi: np.ndarray | None = None,
            eps_schedule: str = "constant", neighbours: str = "footprint",
-           eps1: float = 0.0) -> Factorization:
+           eps1: float = 0.0, order: str = "waiting") -> Factorization:
     """Algorithm "Setup": build the hierarchical factorization of the SPD matrix A.
 
     ``phi`` (n x p) are the vectors GC preserves; default is the constant vector
@@ -386,6 +388,8 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
     (see ``level_eps``; dim is the coordinate dimension, 1 without coordinates).
     ``neighbours``: "footprint" (R6, the original graph's adjacency, §3.1) or "geometric"
     (R6g, the distance rule of §7's experiments, ``GeometricNeighbours``).
+    ``order``: how each colour's greedy pass visits the remaining nodes (R8): "waiting"
+    (most partners still remaining first) or "index".
     ``variant = GC_PROJ1`` approximately preserves ``phi`` (the vectors X of Appendix B, e.g.
     eigenvectors divided by their eigenvalues): U1 keeps the singular directions of
     [X_s, A_sw X_w] above eps1 times the largest, then U2 is chosen as for GC.
@@ -434,10 +438,18 @@ def factor(row_ptr, col_idx, values, coords=None, leaf: int = 16, eps: float = 1
         remaining = [s for s in range(1 << d) if cur.size[s] > 0]
         colours, nodes = [], {}
         while remaining:
+            # R8: the greedy pass in index order, or the nodes with the most partners still
+            # waiting first (ties by index)
+            if order == "waiting":
+                waiting = set(remaining)
+                visit = sorted(remaining, key=lambda s: (-len(cur.partners.get(s, set()) & waiting), s))
+            else:
+                visit = remaining
             colour = []
-            for s in remaining:
+            for s in visit:
                 if all((s, c) not in cur.blocks for c in colour):
                     colour.append(s)
+            colour.sort()
             for s in colour:
                 before = {j: cur.state[j] for j in cur.partners.get(s, ())}
                 nf = eliminate_node(cur, s, adj, eps_d, variant, margins, eps1)

@@ -17,8 +17,10 @@
 //    unknowns in ascending index;
 //  * a red node is empty exactly when its super node had no well-separated block; empty
 //    nodes carry no blocks;
-//  * elimination order inside a level: greedy colours in index order, a node joins the
-//    current colour only if it has no block to a node already in it.
+//  * elimination order inside a level: colour by colour; each colour is a greedy pass over
+//    the remaining nodes (in index order, or most partners still waiting first with ties by
+//    index, opt.order), a node joining only if it has no block to a node already in the
+//    colour; a colour is eliminated in index order.
 #include <algorithm>
 #include <cmath>
 #include <limits>
@@ -259,13 +261,27 @@ void analyze(Plan& P) {
         std::vector<int> mark(nd, -1);
         while (!remaining.empty()) {
             const int cid = int(S.colours.size());
+            // the greedy pass: in index order, or (HSOLVE_ORDER_WAITING) the nodes with the most
+            // partners still waiting at this level first, ties by index; either way the colour
+            // itself is eliminated in index order
+            std::vector<int> order(remaining.size());
+            std::iota(order.begin(), order.end(), 0);
+            if (P.opt.order == HSOLVE_ORDER_WAITING) {
+                std::vector<int> waiting(remaining.size(), 0);
+                for (size_t q = 0; q < remaining.size(); ++q)
+                    for (int j : partners[remaining[q]]) waiting[q] += S.colour_of[j] < 0;
+                std::stable_sort(order.begin(), order.end(),
+                                 [&](int a, int b) { return waiting[a] > waiting[b]; });
+            }
             std::vector<int> colour;
-            for (int s : remaining) {
+            for (int q : order) {
+                const int s = remaining[q];
                 bool ok = true;
                 for (int j : partners[s])
                     if (mark[j] == cid) { ok = false; break; }
                 if (ok) { colour.push_back(s); mark[s] = cid; }
             }
+            std::sort(colour.begin(), colour.end());
             for (int s : colour) {
                 S.colour_of[s] = cid;
                 std::vector<int>& Ns = S.N[s];

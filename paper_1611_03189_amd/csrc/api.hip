@@ -80,6 +80,7 @@ void hsolve_default_options(hsolve_options* o) {
     o->neighbours = HSOLVE_NEIGHBOURS_FOOTPRINT;
     o->eps1 = 0.0;
     o->cmp_ritz = 1;
+    o->order = HSOLVE_ORDER_WAITING;
 }
 
 hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_idx,
@@ -103,6 +104,7 @@ hsolve_status hsolve_analyze(int n, const int64_t* row_ptr, const int32_t* col_i
         !(o.cmp_lpe == 0 || (o.cmp_lpe >= 1 && o.cmp_lpe <= 64 && (o.cmp_lpe & (o.cmp_lpe - 1)) == 0)) ||
         o.cmp_vectors < 0 || o.cmp_vectors > 2 || (o.apply_graph != 0 && o.apply_graph != 1) ||
         (o.cmp_ritz != 0 && o.cmp_ritz != 1) ||
+        (o.order != HSOLVE_ORDER_INDEX && o.order != HSOLVE_ORDER_WAITING) ||
         (o.neighbours != HSOLVE_NEIGHBOURS_FOOTPRINT && o.neighbours != HSOLVE_NEIGHBOURS_GEOMETRIC))
         return HSOLVE_ERR_INVALID;
     if (row_ptr[0] != 0 || row_ptr[n] < 0) return HSOLVE_ERR_INVALID;

@@ -25,6 +25,7 @@ GC = 1
 GC_PROJ1 = 2
 KRYLOV = {"pcg": 0, "fpcg": 1, "gmres": 2, "stationary": 3}
 EPS_SCHEDULE = {"constant": 0, "shrink": 1, "grow": 2}
+ORDER = {"index": 0, "waiting": 1}
 
 STATUS = {
     0: "HSOLVE_OK", 1: "HSOLVE_NOT_CONVERGED", -1: "HSOLVE_ERR_INVALID",
@@ -51,7 +52,7 @@ class Options(ctypes.Structure):
         ("apply_prec", c_int), ("restart", c_int), ("overlap_pivots", c_int),
         ("factor_prec", c_int), ("max_super", c_int), ("max_nrhs", c_int), ("eps_schedule", c_int),
         ("cmp_lpe", c_int), ("cmp_vectors", c_int), ("apply_graph", c_int), ("neighbours", c_int),
-        ("eps1", c_double), ("cmp_ritz", c_int),
+        ("eps1", c_double), ("cmp_ritz", c_int), ("order", c_int),
     ]
 
 
@@ -214,7 +215,7 @@ class HSolver:
                  overlap_pivots: bool = True, factor_prec: int = 64, max_super: int = 512,
                  max_nrhs: int = 32, eps_schedule: str = "constant", cmp_lpe: int = 0,
                  cmp_vectors: int = 0, apply_graph: bool = True, neighbours: str = "footprint",
-                 eps1: float = 0.0, cmp_ritz: bool = True):
+                 eps1: float = 0.0, cmp_ritz: bool = True, order: str = "waiting"):
         lib = load()
         self._lib = lib
         self.row_ptr = np.ascontiguousarray(row_ptr, dtype=np.int64)
@@ -242,6 +243,7 @@ class HSolver:
         opt.cmp_vectors = int(cmp_vectors)
         opt.apply_graph = 1 if apply_graph else 0
         opt.cmp_ritz = int(cmp_ritz)
+        opt.order = ORDER[order] if isinstance(order, str) else int(order)
         opt.neighbours = {"footprint": 0, "geometric": 1}[neighbours] if isinstance(neighbours, str) else int(neighbours)
         self._keep = []
         if coords is not None:

@@ -41,15 +41,16 @@ CASES = [
 ]
 
 
+@pytest.mark.parametrize("order", ["waiting", "index"])
 @pytest.mark.parametrize("neighbours", ["footprint", "geometric"])
 @pytest.mark.parametrize("name,make,leaf,eps,variant", CASES, ids=[c[0] for c in CASES])
-def test_schedule_matches_oracle(name, make, leaf, eps, variant, neighbours):
+def test_schedule_matches_oracle(name, make, leaf, eps, variant, neighbours, order):
     p = make()
     coords = None if name.endswith("nocoords") else p.coords
     F = O.factor(p.row_ptr, p.col_idx, p.values, coords, leaf=leaf, eps=eps,
-                 variant=O.GC if variant == "gc" else O.LORASP, neighbours=neighbours)
+                 variant=O.GC if variant == "gc" else O.LORASP, neighbours=neighbours, order=order)
     with H.HSolver(p.row_ptr, p.col_idx, coords=coords, leaf=leaf, eps=eps, variant=variant,
-                   neighbours=neighbours) as S:
+                   neighbours=neighbours, order=order) as S:
         assert S.depth == F.L
         perm, off = S.leaf_order()
         assert np.array_equal(perm, np.concatenate(F.leaves))
@@ -122,14 +123,15 @@ def test_new_options_are_checked(lib):
     p = pb.poisson(6, 2)
     for kw in ({"factor_prec": 16}, {"max_super": 0}, {"max_super": 513}, {"max_nrhs": 0},
                {"eps_schedule": 3}, {"cmp_lpe": 3}, {"cmp_lpe": 128}, {"cmp_vectors": 3},
-               {"variant": 3}, {"eps1": -0.1}, {"eps1": 1.0}, {"neighbours": 2}, {"cmp_ritz": 2}):
+               {"variant": 3}, {"eps1": -0.1}, {"eps1": 1.0}, {"neighbours": 2}, {"cmp_ritz": 2},
+               {"order": 2}, {"order": -1}):
         with pytest.raises(H.HSolveError) as e:
             H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw)
         assert e.value.status == -1, kw
     for kw in ({"eps_schedule": "shrink"}, {"eps_schedule": "grow"}, {"cmp_lpe": 8, "cmp_vectors": 1},
                {"cmp_lpe": 1, "cmp_vectors": 2}, {"max_super": 64, "max_nrhs": 4},
                {"variant": "gc_proj1", "eps1": 1e-2}, {"neighbours": "geometric"},
-               {"factor_prec": 32, "krylov": "fpcg"}, {"cmp_ritz": False}):
+               {"factor_prec": 32, "krylov": "fpcg"}, {"cmp_ritz": False}, {"order": "index"}):
         with H.HSolver(p.row_ptr, p.col_idx, coords=p.coords, **kw) as S:
             assert S.arena_bound > 0
 
