@@ -18,7 +18,6 @@
 #include <chrono>
 #include <cstdio>
 #include <cstdlib>
-#include <map>
 #include <type_traits>
 
 #include "hs_internal.h"
@@ -552,6 +551,20 @@ static void factor_t(Plan& P, const double* values_in) {
                                     ritz ? RITZ_EXTRA : 0, cflops, !big, max_m, P.opt.cmp_lpe, P.opt.cmp_vectors,
                                     st);
             }
+            // The contributions to the Schur complement of phase B, gathered per target block:
+            // targets in ascending key order, the contributions to one target in node order (a
+            // stable sort of one flat list). They depend on the schedule only, so the host
+            // sorts them while the compression runs.
+            struct Contrib { uint64_t key; int q, a, b; };
+            std::vector<Contrib> contribs;
+            for (size_t q = 0; q < nodes.size(); ++q) {
+                const std::vector<int>& Nl = S.N[nodes[q]];
+                for (size_t a = 0; a < Nl.size(); ++a)
+                    for (size_t b = a; b < Nl.size(); ++b)
+                        contribs.push_back(Contrib{bkey(Nl[a], Nl[b]), int(q), int(a), int(b)});
+            }
+            std::stable_sort(contribs.begin(), contribs.end(),
+                             [](const Contrib& x, const Contrib& y) { return x.key < y.key; });
             if (!dry) {
                 // the pivot blocks of this colour may still run on the side stream: their failure
                 // flags are read only after it has finished (the compression keeps overlapping)
@@ -829,21 +842,15 @@ static void factor_t(Plan& P, const double* values_in) {
                 }
             }
             B.flush_gemm(P);
-            // Schur complement on the neighbours, gathered per target block
-            std::map<uint64_t, std::vector<std::array<int, 3>>> targets;
-            for (size_t q = 0; q < nodes.size(); ++q) {
-                const int s = nodes[q];
-                const std::vector<int>& Nl = S.N[s];
-                for (size_t a = 0; a < Nl.size(); ++a)
-                    for (size_t b = a; b < Nl.size(); ++b)
-                        targets[bkey(Nl[a], Nl[b])].push_back({int(q), int(a), int(b)});
-            }
-            for (auto& [key, contrib] : targets) {
+            // Schur complement on the neighbours, gathered per target block (contribs)
+            for (size_t i0 = 0, i1 = 0; i0 < contribs.size(); i0 = i1) {
+                const uint64_t key = contribs[i0].key;
+                for (i1 = i0 + 1; i1 < contribs.size() && contribs[i1].key == key; ++i1) {}
                 const int a = int(key >> 32), b = int(key & 0xffffffffu);
-                const int q0 = contrib[0][0];
-                const int s0 = nodes[q0];
-                const int sa = cursize(a, S.Nred[s0][contrib[0][1]]);
-                const int sb = cursize(b, S.Nred[s0][contrib[0][2]]);
+                const Contrib& first = contribs[i0];
+                const int s0 = nodes[first.q];
+                const int sa = cursize(a, S.Nred[s0][first.a]);
+                const int sb = cursize(b, S.Nred[s0][first.b]);
                 Block* C = live.find(a, b);
                 bool fresh = false;
                 if (!C) {
@@ -853,10 +860,10 @@ static void factor_t(Plan& P, const double* values_in) {
                     fresh = true;
                 }
                 B.open(static_cast<R*>(C->p), C->ld, sa, sb, -1.0, fresh ? 0.0 : 1.0);
-                for (const auto& ct : contrib) {
-                    const int s = nodes[ct[0]];
-                    const NodeNum& nn = LN.node[s];
-                    B.term(gm(nn) + nn.m + nn.noff[ct[1]], nn.ldG, 0, AN[ct[0]] + nn.noff[ct[2]], nn.ntot, 1,
+                for (size_t i = i0; i < i1; ++i) {
+                    const Contrib& ct = contribs[i];
+                    const NodeNum& nn = LN.node[nodes[ct.q]];
+                    B.term(gm(nn) + nn.m + nn.noff[ct.a], nn.ldG, 0, AN[ct.q] + nn.noff[ct.b], nn.ntot, 1,
                            nn.m);
                     flops += 2.0 * sa * sb * nn.m;
                 }
