@@ -72,12 +72,27 @@ public:
         if (v.empty()) return nullptr;
         return static_cast<T*>(upload(v.data(), v.size() * sizeof(T), pool, s));
     }
-    void reset() { off_ = 0; }   // only after a stream synchronisation
-    bool dry = false;
+    // Batched uploads: between begin_batch and end_batch the copies of uploads that are
+    // contiguous both in pinned memory and on the device merge into one, issued when the run
+    // breaks or at end_batch. Nothing may read the tables before end_batch.
+    void begin_batch() { batch_ = true; }
+    void end_batch(hipStream_t s) {
+        flush_pending(s);
+        batch_ = false;
+    }
+    void reset();   // only after a stream synchronisation; drops a batch an error left open
 
 private:
+    void flush_pending(hipStream_t s);
     char* host_ = nullptr;
     size_t cap_ = 0, off_ = 0;
+    bool batch_ = false;
+    char* pend_h_ = nullptr;
+    char* pend_d_ = nullptr;
+    size_t pend_bytes_ = 0;
+
+public:
+    bool dry = false;
 };
 
 // ---------------------------------------------------------------------------------

@@ -21,13 +21,27 @@ Staging::~Staging() {
     if (host_) (void)hipHostFree(host_);
 }
 
+void Staging::flush_pending(hipStream_t s) {
+    if (!pend_bytes_) return;
+    HS_HIP(hipMemcpyAsync(pend_d_, pend_h_, pend_bytes_, hipMemcpyHostToDevice, s));
+    pend_bytes_ = 0;
+}
+
+// A batch still open here was left by an error: its tables are discarded with it.
+void Staging::reset() {
+    pend_bytes_ = 0;
+    batch_ = false;
+    off_ = 0;
+}
+
 void* Staging::upload(const void* src, size_t bytes, Region& dst_pool, hipStream_t s) {
     if (dry) return dst_pool.alloc(bytes);
     size_t need = align256(bytes);
     if (off_ + need > cap_) {
         // Growing would move memory that queued copies may still read: callers reset the
         // staging only after a synchronisation, so a fresh, larger buffer is safe to use
-        // once the stream has drained.
+        // once the stream has drained (a batch's pending copy is issued first).
+        flush_pending(s);
         HS_HIP(hipStreamSynchronize(s));
         size_t ncap = cap_ ? cap_ : (size_t(8) << 20);
         while (ncap < off_ + need || ncap < need) ncap *= 2;
@@ -40,8 +54,19 @@ void* Staging::upload(const void* src, size_t bytes, Region& dst_pool, hipStream
     char* h = host_ + off_;
     std::memcpy(h, src, bytes);
     off_ += need;
-    void* d = dst_pool.alloc(bytes);
-    HS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+    char* d = static_cast<char*>(dst_pool.alloc(bytes));    // align256(bytes) = need bytes
+    if (!batch_) {
+        HS_HIP(hipMemcpyAsync(d, h, bytes, hipMemcpyHostToDevice, s));
+        return d;
+    }
+    if (pend_bytes_ && pend_h_ + pend_bytes_ == h && pend_d_ + pend_bytes_ == d) {
+        pend_bytes_ += need;
+    } else {
+        flush_pending(s);
+        pend_h_ = h;
+        pend_d_ = d;
+        pend_bytes_ = need;
+    }
     return d;
 }
 

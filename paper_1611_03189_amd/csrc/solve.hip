@@ -61,6 +61,9 @@ void build_apply_schedule(Plan& P) {
     };
     double bytes = 0.0;
     P.sched.assign(nlev, {});
+    // the tables of every colour land one after another in the factor region: their copies
+    // merge into a few large ones, issued before the synchronisation below
+    P.stage.begin_batch();
     for (int d = nlev - 1; d >= 0; --d) {
         const LevelSym& S = P.sym[d];
         const LevelNum& LN = P.num[d];
@@ -187,6 +190,7 @@ void build_apply_schedule(Plan& P) {
         }
     }
     P.stats.apply_bytes = bytes + (8.0 + w) * P.n;
+    P.stage.end_batch(st);
     if (!P.dry) HS_HIP(hipStreamSynchronize(st));
     P.stage.reset();
 }
