@@ -254,10 +254,16 @@ static void factor_t(Plan& P, const double* values_in) {
             HS_HIP(hipEventCreateWithFlags(&P.ev_ready, hipEventDisableTiming));
             HS_HIP(hipEventCreateWithFlags(&P.ev_done, hipEventDisableTiming));
         }
+        if (!P.side2) {     // third stream for the large nodes' compression (default priority)
+            HS_HIP(hipStreamCreateWithFlags(&P.side2, hipStreamNonBlocking));
+            HS_HIP(hipEventCreateWithFlags(&P.ev_ready2, hipEventDisableTiming));
+            HS_HIP(hipEventCreateWithFlags(&P.ev_done2, hipEventDisableTiming));
+        }
         if (!P.h_flags)
             HS_HIP(hipHostMalloc(reinterpret_cast<void**>(&P.h_flags), sizeof(int) * (size_t(4) << nlev) + 64,
                                  hipHostMallocDefault));
         HS_HIP(hipStreamSynchronize(P.side));
+        HS_HIP(hipStreamSynchronize(P.side2));
         HS_HIP(hipStreamSynchronize(st));
         // host or device values (unified addressing decides the direction)
         HS_HIP(hipMemcpyAsync(P.d_values, values_in, size_t(P.nnz) * sizeof(double), hipMemcpyDefault, st));
@@ -531,25 +537,42 @@ static void factor_t(Plan& P, const double* values_in) {
                 const CompressTask* d_all = P.stage.upload_vec(ctasks, P.spool, st);
                 if (!dry) launch_gc_truncate(d_all, int(ctasks.size()), P.opt.eps1, st);
             }
-            for (int big = 0; big < 2; ++big) {
+            // The nodes held in LDS and the larger ones are two independent launch chains. With
+            // overlap the larger nodes' chain runs on the third stream beside the other: both
+            // tables are uploaded first, that stream waits for everything enqueued so far (Gram
+            // matrices, GC bases, tables), and the plan's stream waits for it before the ranks
+            // are read back.
+            struct Part { std::vector<CompressTask> t; double flops = 0.0; int max_m = 0; };
+            Part parts[2];
+            for (const CompressTask& ct : ctasks) {
+                Part& pt = parts[ct.m > LDS_MAX_M ? 1 : 0];
                 // counted work of the reduction kernel: one Householder tridiagonalisation,
                 // 4/3 m^3 (two when GC keeps more than four vectors)
-                std::vector<CompressTask> part;
-                double cflops = 0.0;
-                int max_m = 0;
-                for (const CompressTask& ct : ctasks) {
-                    if ((ct.m > LDS_MAX_M) != bool(big)) continue;
-                    const double m3 = double(ct.m) * ct.m * ct.m;
-                    cflops += ((gc && ct.nz > 4) ? 8.0 / 3.0 : 4.0 / 3.0) * m3;
-                    max_m = std::max(max_m, ct.m);
-                    part.push_back(ct);
+                const double m3 = double(ct.m) * ct.m * ct.m;
+                pt.flops += ((gc && ct.nz > 4) ? 8.0 / 3.0 : 4.0 / 3.0) * m3;
+                pt.max_m = std::max(pt.max_m, ct.m);
+                pt.t.push_back(ct);
+            }
+            const CompressTask* d_part[2] = {nullptr, nullptr};
+            for (int big = 0; big < 2; ++big)
+                if (!parts[big].t.empty()) d_part[big] = P.stage.upload_vec(parts[big].t, P.spool, st);
+            const bool two = overlap && !parts[0].t.empty() && !parts[1].t.empty();
+            if (!dry) {
+                if (two) {
+                    HS_HIP(hipEventRecord(P.ev_ready2, st));
+                    HS_HIP(hipStreamWaitEvent(P.side2, P.ev_ready2, 0));
                 }
-                if (part.empty()) continue;
-                const CompressTask* d_part = P.stage.upload_vec(part, P.spool, st);
-                if (!dry)
-                    launch_compress(d_part, int(part.size()), cmp_variant, eps, d_rank, d_extra,
-                                    ritz ? RITZ_EXTRA : 0, cflops, !big, max_m, P.opt.cmp_lpe, P.opt.cmp_vectors,
-                                    st);
+                for (int big = 0; big < 2; ++big) {
+                    const Part& pt = parts[big];
+                    if (pt.t.empty()) continue;
+                    launch_compress(d_part[big], int(pt.t.size()), cmp_variant, eps, d_rank, d_extra,
+                                    ritz ? RITZ_EXTRA : 0, pt.flops, !big, pt.max_m, P.opt.cmp_lpe,
+                                    P.opt.cmp_vectors, (two && big) ? P.side2 : st);
+                }
+                if (two) {
+                    HS_HIP(hipEventRecord(P.ev_done2, P.side2));
+                    HS_HIP(hipStreamWaitEvent(st, P.ev_done2, 0));
+                }
             }
             // The contributions to the Schur complement of phase B, gathered per target block:
             // targets in ascending key order, the contributions to one target in node order (a

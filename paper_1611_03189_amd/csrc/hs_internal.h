@@ -299,6 +299,8 @@ struct Plan {
     hipStream_t stream = nullptr;
     hipStream_t side = nullptr;        // factorization: pivot blocks beside the compression
     hipEvent_t ev_ready = nullptr, ev_done = nullptr;
+    hipStream_t side2 = nullptr;       // factorization: large nodes' compression beside the small ones'
+    hipEvent_t ev_ready2 = nullptr, ev_done2 = nullptr;
 
     // tree
     int L = 0;

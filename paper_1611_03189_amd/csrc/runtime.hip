@@ -232,8 +232,14 @@ Plan::~Plan() {
         (void)hipStreamSynchronize(side);
         (void)hipStreamDestroy(side);
     }
+    if (side2) {
+        (void)hipStreamSynchronize(side2);
+        (void)hipStreamDestroy(side2);
+    }
     if (ev_ready) (void)hipEventDestroy(ev_ready);
     if (ev_done) (void)hipEventDestroy(ev_done);
+    if (ev_ready2) (void)hipEventDestroy(ev_ready2);
+    if (ev_done2) (void)hipEventDestroy(ev_done2);
     if (h_row_ptr) (void)hipHostFree(h_row_ptr);
     if (h_col_idx) (void)hipHostFree(h_col_idx);
     if (h_perm) (void)hipHostFree(h_perm);
