@@ -110,8 +110,11 @@ typedef struct {
                                enter and leave in FP64). Pair it with HSOLVE_FPCG or GMRES. */
     int restart;            /* HSOLVE_GMRES: Krylov vectors per cycle (200) */
     int overlap_pivots;     /* 1 (default): the pivot blocks of a colour are factored on a
-                               second stream of the plan while the colour is compressed; 0: in
-                               order on opt.stream (for callers that run many plans at once) */
+                               second stream of the plan while the colour is compressed, and the
+                               compression of its nodes above 128 unknowns runs on a third one
+                               beside that of the smaller nodes; 0: all in order on opt.stream
+                               (for callers that run many plans at once). The results are the
+                               same bits either way */
     int factor_prec;        /* 64 (default) or 32: storage and arithmetic of the factorization. With
                                32 the blocks, pivots (Cholesky and inverse), Schur updates, Gram
                                matrices and the products of the elimination run in FP32 on the
