@@ -90,10 +90,10 @@ class RunSummary:
 
 class RequestLoop:
     """Continuous-batching request loop over `slots` concurrent HIP streams. The plans factor
-    their pivot blocks in order on their slot's stream (overlap_pivots=False): with several
-    requests in flight the GPU is already shared, and a second stream per plan only adds
-    queue contention (measured: about 10% fewer solves/s with it). `analysers` host threads
-    run the symbolic analyses as requests arrive."""
+    their pivot blocks and both compression chains in order on their slot's stream
+    (overlap_pivots=False): with several requests in flight the GPU is already shared, and more
+    streams per plan only add queue contention (measured with the pivot stream: about 10%
+    fewer solves/s). `analysers` host threads run the symbolic analyses as requests arrive."""
 
     def __init__(self, slots: int = 4, memory_budget: int | None = None, overlap_pivots: bool = False,
                  analysers: int = 2, solver_factory=None, mixed: bool = False):
