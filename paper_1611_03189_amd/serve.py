@@ -92,8 +92,9 @@ class RequestLoop:
     """Continuous-batching request loop over `slots` concurrent HIP streams. The plans factor
     their pivot blocks and both compression chains in order on their slot's stream
     (overlap_pivots=False): with several requests in flight the GPU is already shared, and more
-    streams per plan only add queue contention (measured with the pivot stream: about 10%
-    fewer solves/s). `analysers` host threads run the symbolic analyses as requests arrive."""
+    streams per plan only add queue contention (measured on the 512-request stream with the
+    pivot and compression streams: 26-30% fewer solves/s). `analysers` host threads run the
+    symbolic analyses as requests arrive."""
 
     def __init__(self, slots: int = 4, memory_budget: int | None = None, overlap_pivots: bool = False,
                  analysers: int = 2, solver_factory=None, mixed: bool = False):
