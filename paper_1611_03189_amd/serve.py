@@ -3,15 +3,16 @@
 Requests (a matrix with 1..8 right-hand sides and an arrival time) are analysed as they
 arrive (host symbolic analysis, which also bounds the device memory the request can need).
 A fixed set of slots, each a host thread with its own HIP stream, take the oldest analysed
-request whose bound fits the free budget, give it an arena of that size, run the
-factorization and one batched solve of all its right-hand sides through the C ABI (the
-factors stay resident for all of them), then destroy the plan and return its arena. Work of
-different slots overlaps on the device; the library calls release the interpreter lock, so
-the slot and analysis threads run concurrently.
+request whose bound fits the free budget, run the factorization and one batched solve of
+all its right-hand sides through the C ABI in the slot's arena (the factors stay resident
+for all of them), then destroy the plan. A slot keeps one arena for a run and grows it when
+a request's bound exceeds it. Work of different slots overlaps on the device; the library
+calls release the interpreter lock, so the slot and analysis threads run concurrently.
 
 Admission: a request is admitted when its arena bound (hsolve_analyze) fits in the budget
 left by the running ones, or when nothing runs; the budget is charged with exactly that
-arena, the device memory the request holds, and the same amount is returned when it ends.
+bound while the request runs, and the same amount is returned when it ends. (Idle slots
+keep their arenas; these are at most the largest bound each slot has served.)
 
 Every result depends only on its own request: the kernels are deterministic and a plan
 shares no device state with another, so a request gives the same bits alone and in the
@@ -109,6 +110,7 @@ class RequestLoop:
             memory_budget = int(0.8 * free)
         self.budget = memory_budget
         self.streams = None
+        self._arenas = {}           # per slot stream, for the duration of a run
 
     def _solver(self, r: Request):
         if self._factory is not None:
@@ -123,14 +125,21 @@ class RequestLoop:
         with torch.cuda.stream(stream):
             S.set_stream(stream)
             need = max(S.arena_bound, 256)
-            # Arenas of finished requests stay in PyTorch's caching allocator, per stream; with
-            # many sizes on several streams its reserve can fill the device, and then an
-            # allocation of the HIP runtime itself (a queue's scratch memory) fails. Unless this
-            # arena fits with RUNTIME_HEADROOM left free, the unused cache is released first.
-            free, _ = torch.cuda.mem_get_info()
-            if free < need + RUNTIME_HEADROOM:
-                torch.cuda.empty_cache()
-            arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+            # One arena per slot, grown when a request needs more: a slot's requests run one
+            # after another on its stream, so its arena is free again when the next one starts.
+            # (An arena per request filled PyTorch's cache with arenas of every size; releasing
+            # that cache synchronises the device.) Unless a new arena fits with
+            # RUNTIME_HEADROOM left free, the unused cache is released first: a full device
+            # leaves the HIP runtime unable to allocate a queue's scratch memory.
+            arena = self._arenas.get(stream)
+            if arena is None or arena.numel() < need:
+                self._arenas.pop(stream, None)
+                arena = None
+                free, _ = torch.cuda.mem_get_info()
+                if free < need + RUNTIME_HEADROOM:
+                    torch.cuda.empty_cache()
+                arena = torch.empty(need, dtype=torch.uint8, device="cuda")
+                self._arenas[stream] = arena
             B = torch.from_numpy(np.ascontiguousarray(r.b)).to("cuda")
             stream.synchronize()
             S.factor(r.values, arena=arena)          # host values: copied into the arena
@@ -237,6 +246,7 @@ class RequestLoop:
             th.join()
         for _, S, _ in waiting:
             S.close()
+        self._arenas = {}
         if state["error"] is not None:
             raise state["error"]
         summary.makespan = now()
